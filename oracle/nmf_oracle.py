@@ -1,0 +1,301 @@
+"""FP64 CPU oracle for beta-NMF by majorization-minimization (MM).
+
+TEST INFRASTRUCTURE ONLY.  This module is the slow, obviously-correct reference
+that the GPU library is checked against.  Only the test suite, the smoke check
+and the CPU-baseline leg of the benchmark may import it; the product path never
+does.  It shares no code with the GPU library (no kernels, headers, helpers or
+constant tables) and imports nothing from it.
+
+Everything is float64 NumPy.  Inputs are taken as given (callers pass the
+float32 data promoted to float64, so both sides see the same numbers).
+
+Paper: "Joint Majorization-Minimization for Nonnegative Matrix Factorization
+with the beta-divergence" (Marmin, Goulart, Fevotte).
+
+Contents, each following the passage cited in its docstring:
+
+* ``beta_divergence`` / ``objective``   -- Sec. 2.1, eqs. (obj_fct) and (beta-div)
+* ``gamma_exponent``                    -- Sec. 2.2, eq. (def_gamma)
+* ``chi1`` / ``chi2``                   -- Sec. 3.2, definitions under eq. (jnt_update)
+* ``bmm_iteration``                     -- Sec. 2.2, eq. (alt_update) and Algorithm 1 (BMM)
+* ``jmm_iteration``                     -- Sec. 3.2, eq. (jnt_update) and Algorithm 2 (JMM)
+* ``normalize``                         -- Sec. 4.1.2 (scaling ambiguity removal)
+* ``gradient``                          -- derivative of eq. (obj_fct); it is the quantity
+                                           inside the KKT residuals of Sec. 4.1.5
+* ``kkt_residuals``                     -- Sec. 4.1.5
+* ``joint_auxiliary``                   -- Sec. 3.1, Table 1, eqs. (simplif) and (jointG)
+* ``relative_decrease``                 -- Sec. 4.1.2 stopping criterion
+
+Smoothing constant kappa (Sec. 4.1.3): the data V is replaced by V + kappa and
+every product WH (or W~H~) by WH + kappa.  The paper gives no value; the
+default here is 0.
+
+Readings where the paper is silent (the same list is kept with the design notes):
+
+* d_beta(0 | y) takes its limit: y for beta = 1, +inf for beta <= 0,
+  y^beta / beta for beta > 0, beta != 1.
+* x^0 is 1 (including 0^0) in every power that appears in the updates.
+* A non-finite or zero-denominator ratio in an update is an error
+  (``FloatingPointError``), never clamped.
+* Normalization leaves a column of W whose norm is zero unchanged.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "gamma_exponent",
+    "beta_divergence",
+    "objective",
+    "chi1",
+    "chi2",
+    "bmm_iteration",
+    "jmm_iteration",
+    "normalize",
+    "gradient",
+    "kkt_residuals",
+    "joint_auxiliary",
+    "relative_decrease",
+]
+
+
+def _f64(a):
+    return np.asarray(a, dtype=np.float64)
+
+
+def _pow(x, p):
+    """Entry-wise x**p with the convention x**0 == 1 (also for x == 0)."""
+    x = _f64(x)
+    if p == 0.0:
+        return np.ones_like(x)
+    with np.errstate(divide="ignore"):
+        return np.power(x, p)
+
+
+def gamma_exponent(beta: float) -> float:
+    """Exponent gamma(beta) of the multiplicative updates, eq. (def_gamma), Sec. 2.2.
+
+    1/(2-beta) below 1, 1 on [1, 2], 1/(beta-1) above 2.
+    """
+    beta = float(beta)
+    if beta < 1.0:
+        return 1.0 / (2.0 - beta)
+    if beta <= 2.0:
+        return 1.0
+    return 1.0 / (beta - 1.0)
+
+
+def beta_divergence(x, y, beta: float):
+    """Entry-wise beta-divergence d_beta(x | y), eq. (beta-div), Sec. 2.1.
+
+    beta = 1: x log(x/y) - x + y (Kullback-Leibler); beta = 0: x/y - log(x/y) - 1
+    (Itakura-Saito); otherwise x^b/(b(b-1)) + y^b/b - x y^(b-1)/(b-1).
+    At x = 0 the limit of the expression is taken (see the module notes).
+    """
+    x = _f64(x)
+    y = _f64(y)
+    x, y = np.broadcast_arrays(x, y)
+    beta = float(beta)
+    out = np.empty(x.shape, dtype=np.float64)
+    pos = x > 0
+    if beta == 1.0:
+        xp, yp = x[pos], y[pos]
+        out[pos] = xp * np.log(xp / yp) - xp + yp
+        out[~pos] = y[~pos]
+    elif beta == 0.0:
+        xp, yp = x[pos], y[pos]
+        out[pos] = xp / yp - np.log(xp / yp) - 1.0
+        out[~pos] = np.inf
+    else:
+        b = beta
+        xp, yp = x[pos], y[pos]
+        out[pos] = xp ** b / (b * (b - 1.0)) + yp ** b / b - xp * yp ** (b - 1.0) / (b - 1.0)
+        if b > 0:
+            out[~pos] = y[~pos] ** b / b
+        else:
+            out[~pos] = np.inf
+    return out
+
+
+def objective(V, W, H, beta: float, kappa: float = 0.0) -> float:
+    """D_beta(V + kappa | WH + kappa): the separable sum of eq. (obj_fct), Sec. 2.1 / 4.1.3."""
+    V = _f64(V)
+    L = _f64(W) @ _f64(H)
+    return float(np.sum(beta_divergence(V + kappa, L + kappa, beta)))
+
+
+def chi1(M, Mt, beta: float):
+    """chi_{1,beta}(M, M~) of Sec. 3.2: M~^(2-beta) / M^(1-beta) for beta <= 2, else M."""
+    M = _f64(M)
+    Mt = _f64(Mt)
+    if beta <= 2.0:
+        return _pow(Mt, 2.0 - beta) / _pow(M, 1.0 - beta)
+    return M.copy()
+
+
+def chi2(M, Mt, beta: float):
+    """chi_{2,beta}(M, M~) of Sec. 3.2: M for beta < 1, else M^beta / M~^(beta-1)."""
+    M = _f64(M)
+    Mt = _f64(Mt)
+    if beta < 1.0:
+        return M.copy()
+    return _pow(M, beta) / _pow(Mt, beta - 1.0)
+
+
+def _ratio(num, den, g):
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        r = num / den
+    if not np.all(np.isfinite(r)) or np.any(den == 0):
+        raise FloatingPointError("multiplicative update ratio is not finite")
+    return _pow(r, g)
+
+
+def normalize(W, H):
+    """Divide each column of W by its l2 norm and scale the rows of H accordingly (Sec. 4.1.2).
+
+    A zero column is left unchanged.  WH is unchanged by construction.
+    """
+    W = _f64(W).copy()
+    H = _f64(H).copy()
+    n = np.sqrt(np.sum(W * W, axis=0))
+    nz = n > 0
+    W[:, nz] /= n[nz]
+    H[nz, :] *= n[nz, None]
+    return W, H
+
+
+def bmm_iteration(V, W, H, beta: float, L_W: int = 1, L_H: int = 1, kappa: float = 0.0,
+                  norm: bool = True, return_parts: bool = False):
+    """One outer iteration of block MM (Algorithm 1, Sec. 2.2), eq. (alt_update).
+
+    L_W multiplicative updates of W against the current H (each recomputes WH),
+    then L_H updates of H against the new W.  Optional column normalization at
+    the end (Sec. 4.1.2).  With ``return_parts`` the numerators/denominators of
+    the last W and H sub-iteration are returned as well.
+    """
+    V = _f64(V) + kappa
+    W = _f64(W).copy()
+    H = _f64(H).copy()
+    g = gamma_exponent(beta)
+    for _ in range(L_W):
+        Lam = W @ H + kappa
+        numW = (_pow(Lam, beta - 2.0) * V) @ H.T
+        denW = _pow(Lam, beta - 1.0) @ H.T
+        W = W * _ratio(numW, denW, g)
+    for _ in range(L_H):
+        Lam = W @ H + kappa
+        numH = W.T @ (_pow(Lam, beta - 2.0) * V)
+        denH = W.T @ _pow(Lam, beta - 1.0)
+        H = H * _ratio(numH, denH, g)
+    Wn, Hn = (normalize(W, H) if norm else (W, H))
+    if return_parts:
+        return Wn, Hn, dict(numW=numW, denW=denW, numH=numH, denH=denH, W_unnorm=W, H_unnorm=H)
+    return Wn, Hn
+
+
+def jmm_iteration(V, Wt, Ht, beta: float, L: int = 1, kappa: float = 0.0, norm: bool = True,
+                  return_parts: bool = False):
+    """One outer iteration of joint MM (Algorithm 2, Sec. 3.2), eq. (jnt_update).
+
+    V~ = W~ H~ (+ kappa) is formed once.  The L sub-iterations update W and then
+    H, always multiplying the *tilde* iterates, with chi_1/chi_2 evaluated at the
+    latest sub-iterate and the tilde iterate.  Optional normalization at the end.
+    """
+    V = _f64(V) + kappa
+    Wt = _f64(Wt)
+    Ht = _f64(Ht)
+    g = gamma_exponent(beta)
+    Vt = Wt @ Ht + kappa
+    P = V / _pow(Vt, 2.0 - beta)          # V / V~^(2-beta)
+    Q = _pow(Vt, beta - 1.0)              # V~^(beta-1)
+    W, H = Wt.copy(), Ht.copy()
+    for _ in range(L):
+        numW = P @ chi1(H, Ht, beta).T
+        denW = Q @ chi2(H, Ht, beta).T
+        W = Wt * _ratio(numW, denW, g)
+        numH = chi1(W, Wt, beta).T @ P
+        denH = chi2(W, Wt, beta).T @ Q
+        H = Ht * _ratio(numH, denH, g)
+    Wn, Hn = (normalize(W, H) if norm else (W, H))
+    if return_parts:
+        return Wn, Hn, dict(numW=numW, denW=denW, numH=numH, denH=denH, W_unnorm=W, H_unnorm=H)
+    return Wn, Hn
+
+
+def gradient(V, W, H, beta: float, kappa: float = 0.0):
+    """Gradient of D_beta(V + kappa | WH + kappa) w.r.t. W and H.
+
+    With Lam = WH + kappa and E = Lam^(beta-2) * (Lam - V - kappa) (the derivative
+    of d_beta in its second argument), grad_W = E H^T and grad_H = W^T E.  These
+    are the bracketed terms of the KKT residuals in Sec. 4.1.5.
+    """
+    V = _f64(V)
+    W = _f64(W)
+    H = _f64(H)
+    Lam = W @ H + kappa
+    E = _pow(Lam, beta - 2.0) * (Lam - (V + kappa))
+    return E @ H.T, W.T @ E
+
+
+def kkt_residuals(V, W, H, beta: float, kappa: float = 0.0):
+    """res(W), res(H) of Sec. 4.1.5: mean |min(X, grad_X D)| over the entries of X."""
+    gW, gH = gradient(V, W, H, beta, kappa)
+    W = _f64(W)
+    H = _f64(H)
+    rW = float(np.sum(np.abs(np.minimum(W, gW)))) / W.size
+    rH = float(np.sum(np.abs(np.minimum(H, gH)))) / H.size
+    return rW, rH
+
+
+def _split_terms(v, y, beta):
+    """Convex, concave and constant parts of d_beta(v | y) in y, Table 1 (Sec. 3.1).
+
+    Returns three callables of y (for fixed v) plus the derivative of the concave part.
+    """
+    b = float(beta)
+    if b == 0.0:
+        conv = lambda t: v / t
+        conc = lambda t: np.log(t)
+        dconc = lambda t: 1.0 / t
+        const = -(np.log(v) + 1.0)
+    elif 1.0 <= b <= 2.0:
+        conv = lambda t: beta_divergence(v, t, b)
+        conc = lambda t: np.zeros_like(_f64(t))
+        dconc = lambda t: np.zeros_like(_f64(t))
+        const = np.zeros_like(_f64(v))
+    elif b < 1.0:
+        conv = lambda t: -v * _pow(t, b - 1.0) / (b - 1.0)
+        conc = lambda t: _pow(t, b) / b
+        dconc = lambda t: _pow(t, b - 1.0)
+        const = _pow(v, b) / (b * (b - 1.0))
+    else:
+        conv = lambda t: _pow(t, b) / b
+        conc = lambda t: -v * _pow(t, b - 1.0) / (b - 1.0)
+        dconc = lambda t: -v * _pow(t, b - 2.0)
+        const = _pow(v, b) / (b * (b - 1.0))
+    return conv, conc, dconc, const
+
+
+def joint_auxiliary(V, W, H, Wt, Ht, beta: float) -> float:
+    """Joint auxiliary function G(W, H | W~, H~) of eq. (jointG), Sec. 3.1.
+
+    Convex part majorized by Jensen's inequality with weights
+    lam~_fnk = w~_fk h~_kn / v~_fn, v~ = [W~H~]_fn (eq. simplif); concave part by
+    its tangent at v~_fn; constant part unchanged.  Materializes an F x N x K
+    array: tiny inputs only.
+    """
+    V = _f64(V)
+    W, H, Wt, Ht = (_f64(a) for a in (W, H, Wt, Ht))
+    Vt = Wt @ Ht
+    lam = Wt[:, None, :] * Ht.T[None, :, :] / Vt[:, :, None]          # F x N x K
+    prod = W[:, None, :] * H.T[None, :, :]                             # w_fk h_kn
+    conv, conc, dconc, const = _split_terms(V[:, :, None], None, beta)
+    Gconv = np.sum(lam * conv(prod / lam), axis=2)
+    conv2, conc2, dconc2, const2 = _split_terms(V, None, beta)
+    Gconc = conc2(Vt) + dconc2(Vt) * (W @ H - Vt)
+    return float(np.sum(Gconv + Gconc + const2))
+
+
+def relative_decrease(D_prev: float, D_cur: float) -> float:
+    """(D(previous iterate) - D(current iterate)) / D(current iterate), Sec. 4.1.2."""
+    return (D_prev - D_cur) / D_cur
