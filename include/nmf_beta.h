@@ -1,0 +1,172 @@
+/*
+ * nmf_beta.h -- C ABI of the MI355X (gfx950) beta-NMF multiplicative-update library.
+ *
+ * Problem (paper Sec. 2.1, eq. (nmf)): given a nonnegative data matrix V (F x N)
+ * and a rank K, find nonnegative W (F x K) and H (K x N) minimizing the separable
+ * beta-divergence D_beta(V | WH) = sum_fn d_beta(v_fn | [WH]_fn), eqs. (obj_fct),
+ * (beta-div).  With the smoothing constant kappa of Sec. 4.1.3 the objective is
+ * D_beta(V + kappa | WH + kappa).
+ *
+ * Conventions shared by every call:
+ *  - Matrices are float32, row-major, in caller-owned DEVICE memory; the leading
+ *    dimension (ld*) is the distance in elements between consecutive rows and must
+ *    be >= the number of columns.  The library never frees caller memory.
+ *  - V is read-only.  W and H are updated in place by nmf_beta_step.
+ *  - V, W, H (and dW, dH) must not overlap; overlap is NMF_ERR_ALIAS.
+ *  - Calls are asynchronous on the given stream (a hipStream_t passed as void*;
+ *    NULL is the null stream).  The returned status covers argument checks and
+ *    launch errors only; numeric trouble (a non-finite or zero-denominator update
+ *    ratio, a non-finite objective) sets sticky device flags read by nmf_get_flags.
+ *  - Device scalars (double* d_objective ...) are caller-owned device memory.
+ *  - A context owns a workspace on one device.  It grows on demand (a blocking
+ *    reallocation) unless the stream is being captured, in which case a too-small
+ *    workspace is NMF_ERR_WORKSPACE; call nmf_reserve first to size it once.
+ *  - A context must not be used by two host threads at the same time, and two
+ *    calls on different streams through one context must not overlap in time
+ *    (they share the workspace).
+ *  - Supported sizes: F, N >= 1, 1 <= K <= 128.
+ */
+#ifndef NMF_BETA_H
+#define NMF_BETA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nmf_ctx_s* nmf_ctx_t;
+
+typedef enum {
+  NMF_OK = 0,
+  NMF_ERR_NULL = 1,        /* a required pointer is NULL */
+  NMF_ERR_SHAPE = 2,       /* F, N or K < 1, or a leading dimension too small */
+  NMF_ERR_BETA = 3,        /* beta or kappa not finite, kappa < 0 */
+  NMF_ERR_ALIAS = 4,       /* two of the matrices overlap in memory */
+  NMF_ERR_WORKSPACE = 5,   /* workspace too small while the stream is captured */
+  NMF_ERR_HIP = 6,         /* a HIP runtime call failed */
+  NMF_ERR_UNSUPPORTED = 7, /* K > 128, inner_iters != 1, unknown precision */
+  NMF_ERR_ARG = 8,         /* other invalid argument (mode, opts field) */
+  NMF_ERR_NO_DEVICE = 9    /* no usable GPU */
+} nmf_status;
+
+typedef enum {
+  NMF_ALTERNATING = 0, /* block MM, Sec. 2.2 eq. (alt_update), Algorithm 1 */
+  NMF_JOINT = 1        /* joint MM, Sec. 3.2 eq. (jnt_update), Algorithm 2 */
+} nmf_mode;
+
+typedef enum {
+  NMF_FP32 = 0, /* every product in float32 (matrix cores, fp32 accumulate) */
+  NMF_BF16 = 1, /* the three products with bfloat16 operands, fp32 accumulate */
+  NMF_FP16 = 2  /* the three products with float16 operands, fp32 accumulate */
+} nmf_precision;
+
+/* sticky numeric flags (nmf_get_flags) */
+#define NMF_FLAG_NONFINITE 1u /* an update ratio num/den was non-finite or den <= 0 */
+#define NMF_FLAG_DOMAIN 2u    /* nmf_beta_validate found data outside the domain */
+
+typedef struct {
+  int32_t precision;   /* nmf_precision; default NMF_FP32 */
+  float kappa;         /* smoothing constant of Sec. 4.1.3, >= 0; default 0 */
+  int32_t inner_iters; /* sub-iterations L of Algorithms 1/2; only 1 is supported */
+  int32_t normalize;   /* 1: divide W's columns by their l2 norm and scale H's rows
+                          (Sec. 4.1.2) at the end of the step; default 1 */
+} nmf_step_opts;
+
+/* Fills *opts with the defaults listed above. */
+void nmf_default_opts(nmf_step_opts* opts);
+
+/* Library version string (static storage). */
+const char* nmf_version(void);
+
+/* Human-readable name of a status code (static storage, never NULL). */
+const char* nmf_status_string(nmf_status status);
+
+/* Creates a context on HIP device `device`.  No workspace is allocated yet.
+ * NMF_ERR_NO_DEVICE if the device does not exist.  *out is NULL on error. */
+nmf_status nmf_create(nmf_ctx_t* out, int device);
+
+/* Releases the context and its workspace (synchronizes the device first). */
+nmf_status nmf_destroy(nmf_ctx_t ctx);
+
+/* Sizes the workspace for every later call with F <= maxF, N <= maxN, K <= maxK,
+ * so that those calls never allocate (required before stream capture). */
+nmf_status nmf_reserve(nmf_ctx_t ctx, int64_t maxF, int64_t maxN, int64_t maxK);
+
+/* Host-only argument check of nmf_beta_step (no HIP call, usable without a GPU).
+ * Returns the status nmf_beta_step would return for these arguments before any
+ * device work.  opts may be NULL (defaults). */
+nmf_status nmf_check_step_args(int64_t F, int64_t N, int64_t K, const float* V, int64_t ldv,
+                               const float* W, int64_t ldw, const float* H, int64_t ldh,
+                               double beta, int32_t mode, const nmf_step_opts* opts);
+
+/* One outer iteration of the multiplicative-update method, in place on W and H.
+ *
+ * mode == NMF_ALTERNATING (paper Sec. 2.2, eq. (alt_update), Algorithm 1 with
+ *   L_W = L_H = 1):  W <- W .* ((( (WH)^(b-2) .* V) H^T) / ((WH)^(b-1) H^T))^gamma,
+ *   then H is updated the same way against the new W (WH is formed again).
+ * mode == NMF_JOINT (paper Sec. 3.2, eq. (jnt_update), Algorithm 2 with L = 1):
+ *   V~ = W~H~ is formed once; W and H are both updated from the tilde iterate,
+ *   the H step using chi_1(W, W~) and chi_2(W, W~) in its contractions.
+ * gamma = gamma(beta) of eq. (def_gamma).  With opts->normalize the columns of W
+ * are scaled to unit l2 norm and the rows of H by the inverse (Sec. 4.1.2).
+ * At L = 1 the W step of both modes is the same computation (Sec. 4.1.1).
+ *
+ * d_objective (device double, may be NULL) receives D_beta(V + kappa | W~H~ + kappa)
+ * at the ENTRY iterate, computed in the same pass over V.
+ */
+nmf_status nmf_beta_step(nmf_ctx_t ctx, void* stream, int64_t F, int64_t N, int64_t K,
+                         const float* V, int64_t ldv, float* W, int64_t ldw, float* H, int64_t ldh,
+                         double beta, int32_t mode, const nmf_step_opts* opts, double* d_objective);
+
+/* D_beta(V + kappa | WH + kappa) (eqs. (obj_fct), (beta-div)) written to the device
+ * double *d_out.  Per-entry terms and the reduction are float64; WH is float32.
+ * At v = 0 the limit is used (beta = 1: the term is [WH]_fn; beta <= 0: +inf). */
+nmf_status nmf_beta_objective(nmf_ctx_t ctx, void* stream, int64_t F, int64_t N, int64_t K,
+                              const float* V, int64_t ldv, const float* W, int64_t ldw,
+                              const float* H, int64_t ldh, double beta, float kappa, double* d_out);
+
+/* Gradient of D_beta(V + kappa | WH + kappa) w.r.t. W and H, times `scale`:
+ *   E = (WH + kappa)^(beta-2) .* (WH - V),  dW = scale * E H^T,  dH = scale * W^T E.
+ * (E is the derivative of d_beta in its second argument; these are the bracketed
+ * terms of the KKT residuals of Sec. 4.1.5.)  dW is F x K (ld lddw), dH is K x N
+ * (ld lddh), both caller-owned device float32.  d_objective (nullable) receives
+ * the objective at (W, H).  No gradient w.r.t. V is computed. */
+nmf_status nmf_beta_grad(nmf_ctx_t ctx, void* stream, int64_t F, int64_t N, int64_t K,
+                         const float* V, int64_t ldv, const float* W, int64_t ldw,
+                         const float* H, int64_t ldh, double beta, float kappa, double scale,
+                         float* dW, int64_t lddw, float* dH, int64_t lddh, double* d_objective);
+
+/* Scans V, W, H once and sets NMF_FLAG_DOMAIN if V has a negative or non-finite
+ * entry, W or H a non-positive or non-finite entry, or (beta <= 0, kappa == 0) V
+ * has a zero (where d_beta is infinite, Sec. 4.1.3). */
+nmf_status nmf_beta_validate(nmf_ctx_t ctx, void* stream, int64_t F, int64_t N, int64_t K,
+                             const float* V, int64_t ldv, const float* W, int64_t ldw,
+                             const float* H, int64_t ldh, double beta, float kappa);
+
+/* Reads (synchronizing `stream`) and optionally clears the sticky flags. */
+nmf_status nmf_get_flags(nmf_ctx_t ctx, void* stream, uint32_t* flags, int32_t clear);
+
+/* Per-kernel timing with HIP events recorded on the launch stream around each
+ * launch of the selected kernels (bit mask of NMF_KERNEL_* values; 0 disables).
+ * nmf_profile_read synchronizes the recorded events and returns the summed
+ * duration in milliseconds and the number of timed launches of one kernel since
+ * the last reset, then resets that kernel's counters. */
+#define NMF_KERNEL_SWEEP_W 0   /* pass over V accumulating the W-step contractions */
+#define NMF_KERNEL_UPDATE_W 1  /* reduction of W partials, W update, chi terms */
+#define NMF_KERNEL_SWEEP_H 2   /* pass over V accumulating the H-step contractions */
+#define NMF_KERNEL_UPDATE_H 3  /* reduction of H partials, H update, normalization */
+#define NMF_KERNEL_FUSED_KL 4  /* single pass for the joint update at beta = 1 */
+#define NMF_KERNEL_COUNT 8
+nmf_status nmf_profile_enable(nmf_ctx_t ctx, uint32_t kernel_mask);
+nmf_status nmf_profile_read(nmf_ctx_t ctx, int32_t kernel, double* total_ms, int64_t* launches);
+
+/* Launch geometry override for tuning: target number of workgroups per sweep
+ * (0 = default, twice the number of compute units) and minimum number of 32-wide
+ * tiles each workgroup walks (0 = default 1).  Applies to later calls. */
+nmf_status nmf_set_launch(nmf_ctx_t ctx, int32_t target_blocks, int32_t min_tiles);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NMF_BETA_H */

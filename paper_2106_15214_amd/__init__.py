@@ -1,0 +1,327 @@
+"""Python binding of the MI355X beta-NMF library (``libnmfbeta.so``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Torch tensors supply device memory and the current HIP stream.
+The library must be built (``python -m paper_2106_15214_amd.build`` or
+``__graft_entry__.build()``); if it is missing, loading raises.
+
+Calls mirror include/nmf_beta.h:
+
+* :func:`step`       -- one outer iteration (alternating or joint MM), in place
+* :func:`objective`  -- D_beta(V + kappa | WH + kappa) as a device float64 scalar
+* :func:`grad`       -- gradient of D_beta w.r.t. W and H
+* :func:`validate`   -- domain scan setting the sticky DOMAIN flag
+* :func:`get_flags`  -- read (and clear) the sticky numeric flags
+* :class:`BetaDivergence` -- ``torch.autograd.Function`` with the GPU backward
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from typing import Optional, Tuple
+
+__all__ = [
+    "NmfError", "lib", "library_path", "Context", "default_context",
+    "ALTERNATING", "JOINT", "FP32", "BF16", "FP16",
+    "FLAG_NONFINITE", "FLAG_DOMAIN", "KERNELS",
+    "step", "objective", "grad", "validate", "get_flags", "check_step_args",
+    "BetaDivergence", "beta_divergence",
+]
+
+ALTERNATING, JOINT = 0, 1
+FP32, BF16, FP16 = 0, 1, 2
+FLAG_NONFINITE, FLAG_DOMAIN = 1, 2
+KERNELS = {"sweep_w": 0, "update_w": 1, "sweep_h": 2, "update_h": 3, "fused_kl": 4}
+MODES = {"alternating": ALTERNATING, "bmm": ALTERNATING, "joint": JOINT, "jmm": JOINT}
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libnmfbeta.so")
+
+
+class NmfError(RuntimeError):
+    """A non-OK status returned by the library."""
+
+    def __init__(self, status: int, where: str = ""):
+        self.status = int(status)
+        msg = _status_string(self.status)
+        super().__init__(f"{where}: {msg}" if where else msg)
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("kappa", ctypes.c_float),
+                ("inner_iters", ctypes.c_int32), ("normalize", ctypes.c_int32)]
+
+
+_lib = None
+_lock = threading.Lock()
+_i64, _i32, _u32, _dbl, _flt, _vp = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
+                                     ctypes.c_double, ctypes.c_float, ctypes.c_void_p)
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libnmfbeta.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(library_path):
+            raise RuntimeError(f"HIP library not built: {library_path} is missing "
+                               "(run python -m paper_2106_15214_amd.build)")
+        L = ctypes.CDLL(library_path)
+        L.nmf_status_string.restype = ctypes.c_char_p
+        L.nmf_status_string.argtypes = [ctypes.c_int]
+        L.nmf_version.restype = ctypes.c_char_p
+        L.nmf_default_opts.argtypes = [ctypes.POINTER(_Opts)]
+        L.nmf_default_opts.restype = None
+        L.nmf_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int]
+        L.nmf_destroy.argtypes = [_vp]
+        L.nmf_reserve.argtypes = [_vp, _i64, _i64, _i64]
+        L.nmf_check_step_args.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
+                                          _dbl, _i32, ctypes.POINTER(_Opts)]
+        L.nmf_beta_step.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
+                                    _dbl, _i32, ctypes.POINTER(_Opts), _vp]
+        L.nmf_beta_objective.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
+                                         _dbl, _flt, _vp]
+        L.nmf_beta_grad.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
+                                    _dbl, _flt, _dbl, _vp, _i64, _vp, _i64, _vp]
+        L.nmf_beta_validate.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
+                                        _dbl, _flt]
+        L.nmf_get_flags.argtypes = [_vp, _vp, ctypes.POINTER(_u32), _i32]
+        L.nmf_profile_enable.argtypes = [_vp, _u32]
+        L.nmf_profile_read.argtypes = [_vp, _i32, ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]
+        L.nmf_set_launch.argtypes = [_vp, _i32, _i32]
+        for name in ("nmf_create", "nmf_destroy", "nmf_reserve", "nmf_check_step_args", "nmf_beta_step",
+                     "nmf_beta_objective", "nmf_beta_grad", "nmf_beta_validate", "nmf_get_flags",
+                     "nmf_profile_enable", "nmf_profile_read", "nmf_set_launch"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _status_string(st: int) -> str:
+    try:
+        return lib().nmf_status_string(int(st)).decode()
+    except Exception:  # pragma: no cover - library absent
+        return f"status {st}"
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise NmfError(st, where)
+
+
+def _opts(precision=FP32, kappa=0.0, inner_iters=1, normalize=True) -> _Opts:
+    o = _Opts()
+    lib().nmf_default_opts(ctypes.byref(o))
+    o.precision = PRECISIONS.get(precision, precision) if isinstance(precision, str) else int(precision)
+    o.kappa = float(kappa)
+    o.inner_iters = int(inner_iters)
+    o.normalize = 1 if normalize else 0
+    return o
+
+
+class Context:
+    """A library context (workspace owner) on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        h = _vp()
+        _check(lib().nmf_create(ctypes.byref(h), int(device)), "nmf_create")
+        self.handle = h
+        self.device = int(device)
+
+    def close(self):
+        if self.handle:
+            lib().nmf_destroy(self.handle)
+            self.handle = _vp()
+
+    def reserve(self, F: int, N: int, K: int):
+        _check(lib().nmf_reserve(self.handle, F, N, K), "nmf_reserve")
+
+    def set_launch(self, target_blocks: int = 0, min_tiles: int = 0):
+        _check(lib().nmf_set_launch(self.handle, target_blocks, min_tiles), "nmf_set_launch")
+
+    def profile(self, kernels) -> None:
+        mask = 0
+        for k in kernels:
+            mask |= 1 << (KERNELS[k] if isinstance(k, str) else int(k))
+        _check(lib().nmf_profile_enable(self.handle, mask), "nmf_profile_enable")
+
+    def profile_read(self, kernel) -> Tuple[float, int]:
+        ms, n = _dbl(), _i64()
+        kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+        _check(lib().nmf_profile_read(self.handle, kid, ctypes.byref(ms), ctypes.byref(n)), "nmf_profile_read")
+        return ms.value, n.value
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_contexts = {}
+
+
+def default_context(device: Optional[int] = None) -> Context:
+    import torch
+    d = torch.cuda.current_device() if device is None else int(device)
+    if d not in _contexts:
+        _contexts[d] = Context(d)
+    return _contexts[d]
+
+
+def _mat(t, name, writable=False):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device (cuda) tensor")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be 2-D with unit column stride")
+    return t.data_ptr(), max(t.stride(0), t.shape[1])
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return _vp(torch.cuda.current_stream().cuda_stream)
+    return _vp(getattr(stream, "cuda_stream", stream))
+
+
+def _ctx(ctx):
+    return (ctx or default_context()).handle
+
+
+def check_step_args(F, N, K, V=0x10000000, ldv=None, W=0x50000000, ldw=None, H=0x90000000, ldh=None,
+                    beta=1.0, mode=JOINT, **kw) -> int:
+    """Host-only argument check (no GPU needed); returns the library's status code."""
+    o = _opts(**kw)
+    return lib().nmf_check_step_args(F, N, K, V, N if ldv is None else ldv, W, K if ldw is None else ldw,
+                                     H, N if ldh is None else ldh, float(beta), int(mode), ctypes.byref(o))
+
+
+def step(V, W, H, beta: float, mode="joint", *, precision="fp32", kappa: float = 0.0, normalize: bool = True,
+         objective_out=None, stream=None, ctx: Optional[Context] = None):
+    """One outer iteration in place on W and H (see nmf_beta_step).
+
+    ``objective_out``: optional float64 device tensor (1 element) receiving the
+    objective at the entry iterate.
+    """
+    m = MODES.get(mode, mode) if isinstance(mode, str) else int(mode)
+    pv, ldv = _mat(V, "V")
+    pw, ldw = _mat(W, "W")
+    ph, ldh = _mat(H, "H")
+    F, N = V.shape
+    K = W.shape[1]
+    if W.shape[0] != F or H.shape != (K, N):
+        raise ValueError("shape mismatch: V (F,N), W (F,K), H (K,N)")
+    o = _opts(precision, kappa, 1, normalize)
+    pobj = None
+    if objective_out is not None:
+        pobj = objective_out.data_ptr()
+    st = lib().nmf_beta_step(_ctx(ctx), _stream(stream), F, N, K, pv, ldv, pw, ldw, ph, ldh,
+                             float(beta), m, ctypes.byref(o), pobj)
+    _check(st, "nmf_beta_step")
+
+
+def objective(V, W, H, beta: float, *, kappa: float = 0.0, out=None, stream=None, ctx=None):
+    """D_beta(V + kappa | WH + kappa) as a 1-element float64 device tensor."""
+    import torch
+    pv, ldv = _mat(V, "V")
+    pw, ldw = _mat(W, "W")
+    ph, ldh = _mat(H, "H")
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=V.device)
+    st = lib().nmf_beta_objective(_ctx(ctx), _stream(stream), V.shape[0], V.shape[1], W.shape[1],
+                                  pv, ldv, pw, ldw, ph, ldh, float(beta), float(kappa), out.data_ptr())
+    _check(st, "nmf_beta_objective")
+    return out
+
+
+def grad(V, W, H, beta: float, *, kappa: float = 0.0, scale: float = 1.0, dW=None, dH=None,
+         objective_out=None, stream=None, ctx=None):
+    """(dW, dH) = scale * gradient of D_beta w.r.t. (W, H); see nmf_beta_grad."""
+    import torch
+    pv, ldv = _mat(V, "V")
+    pw, ldw = _mat(W, "W")
+    ph, ldh = _mat(H, "H")
+    if dW is None:
+        dW = torch.empty_like(W)
+    if dH is None:
+        dH = torch.empty_like(H)
+    pdw, lddw = _mat(dW, "dW")
+    pdh, lddh = _mat(dH, "dH")
+    pobj = objective_out.data_ptr() if objective_out is not None else None
+    st = lib().nmf_beta_grad(_ctx(ctx), _stream(stream), V.shape[0], V.shape[1], W.shape[1], pv, ldv, pw, ldw,
+                             ph, ldh, float(beta), float(kappa), float(scale), pdw, lddw, pdh, lddh, pobj)
+    _check(st, "nmf_beta_grad")
+    return dW, dH
+
+
+def validate(V, W, H, beta: float, *, kappa: float = 0.0, stream=None, ctx=None):
+    pv, ldv = _mat(V, "V")
+    pw, ldw = _mat(W, "W")
+    ph, ldh = _mat(H, "H")
+    st = lib().nmf_beta_validate(_ctx(ctx), _stream(stream), V.shape[0], V.shape[1], W.shape[1],
+                                 pv, ldv, pw, ldw, ph, ldh, float(beta), float(kappa))
+    _check(st, "nmf_beta_validate")
+
+
+def get_flags(clear: bool = False, stream=None, ctx=None) -> int:
+    f = _u32()
+    _check(lib().nmf_get_flags(_ctx(ctx), _stream(stream), ctypes.byref(f), 1 if clear else 0), "nmf_get_flags")
+    return int(f.value)
+
+
+def _make_autograd():
+    import torch
+
+    class BetaDivergence(torch.autograd.Function):
+        """D_beta(V + kappa | WH + kappa) with a GPU backward w.r.t. W and H.
+
+        forward(V, W, H, beta, kappa) returns a 0-d float64 tensor; the backward
+        calls nmf_beta_grad with scale = the incoming gradient.  No gradient is
+        returned for V, beta or kappa.
+        """
+
+        @staticmethod
+        def forward(ctx_, V, W, H, beta, kappa=0.0):
+            Wc, Hc = W.detach().contiguous(), H.detach().contiguous()
+            out = objective(V.detach().contiguous(), Wc, Hc, beta, kappa=kappa)
+            ctx_.save_for_backward(V, W, H)
+            ctx_.beta = float(beta)
+            ctx_.kappa = float(kappa)
+            return out.reshape(())
+
+        @staticmethod
+        def backward(ctx_, g):
+            V, W, H = ctx_.saved_tensors
+            scale = float(g.item())
+            dW, dH = grad(V.detach().contiguous(), W.detach().contiguous(), H.detach().contiguous(),
+                          ctx_.beta, kappa=ctx_.kappa, scale=scale)
+            return None, dW.to(W.dtype), dH.to(H.dtype), None, None
+
+    return BetaDivergence
+
+
+class _LazyAutograd:
+    _cls = None
+
+    def __getattr__(self, item):
+        if _LazyAutograd._cls is None:
+            _LazyAutograd._cls = _make_autograd()
+        return getattr(_LazyAutograd._cls, item)
+
+
+BetaDivergence = _LazyAutograd()
+
+
+def beta_divergence(V, W, H, beta: float, kappa: float = 0.0):
+    """Differentiable D_beta(V + kappa | WH + kappa) (float64 0-d tensor)."""
+    return BetaDivergence.apply(V, W, H, beta, kappa)

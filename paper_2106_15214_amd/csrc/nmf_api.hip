@@ -1,0 +1,533 @@
+// Host side of the beta-NMF library: argument checks, context and workspace,
+// launch planning and the C ABI declared in include/nmf_beta.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "nmf_beta.h"
+#include "nmf_internal.h"
+
+using namespace nmf;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct TimedLaunch {
+  hipEvent_t start, stop;
+};
+
+}  // namespace
+
+struct nmf_ctx_s {
+  int device = 0;
+  int num_cus = 256;
+  char* ws = nullptr;  // workspace base
+  size_t ws_bytes = 0;
+  int target_blocks = 0;  // 0: 2 x CUs
+  int min_tiles = 1;
+  uint32_t profile_mask = 0;
+  std::vector<TimedLaunch> pending[NMF_KERNEL_COUNT];
+  std::vector<hipEvent_t> event_pool;
+  double prof_ms[NMF_KERNEL_COUNT] = {};
+  int64_t prof_count[NMF_KERNEL_COUNT] = {};
+};
+
+namespace {
+
+// Workspace header: flags word and the update_w arrival counter (zeroed at allocation).
+constexpr size_t kHeaderBytes = 256;
+constexpr int kUpdateWBlocks = 128;
+
+struct Plan {
+  int KB, KP;
+  int row_blocks, n_groups, tiles_n;  // sweep_rows grid = row_blocks * n_groups
+  int col_blocks, f_groups, tiles_f;  // sweep_cols grid = col_blocks * f_groups
+  int uw_blocks, uh_blocks;
+  // byte offsets inside the workspace
+  size_t o_pobj, o_pnum, o_pden, o_prs, o_wn, o_c1, o_c2, o_pcol, o_norms, o_csum, o_pnumh, o_pdenh, total;
+};
+
+int kblocks_for(int64_t K) {
+  if (K <= 32) return 1;
+  if (K <= 64) return 2;
+  return 4;
+}
+
+struct Grid {
+  int row_blocks, n_groups, tiles_n;
+  int col_blocks, f_groups, tiles_f;
+};
+
+int64_t target_of(const nmf_ctx_s* c) {
+  return c->target_blocks > 0 ? c->target_blocks : 2 * (int64_t)c->num_cus;
+}
+
+// Splits `tiles` 32-wide tiles over groups so that blocks * groups ~ target.
+void split(int64_t tiles, int64_t blocks, int64_t target, int64_t min_tiles, int* groups, int* per_group) {
+  const int64_t g = std::min<int64_t>(tiles, std::max<int64_t>(1, cdiv(target, blocks)));
+  const int64_t tpg = std::max<int64_t>(min_tiles, cdiv(tiles, g));
+  *per_group = (int)tpg;
+  *groups = (int)cdiv(tiles, tpg);
+}
+
+// Region sizes (bytes) of the workspace; offsets are assigned in this order.
+struct Sizes {
+  size_t pobj, pnum, prs, wn, pcol, kvec, pnumh;
+};
+
+Plan layout(const Sizes& z, Plan p) {
+  size_t o = kHeaderBytes;
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+  p.o_pobj = take(z.pobj);
+  p.o_pnum = take(z.pnum);
+  p.o_pden = take(z.pnum);
+  p.o_prs = take(z.prs);
+  p.o_wn = take(z.wn);
+  p.o_c1 = take(z.wn);
+  p.o_c2 = take(z.wn);
+  p.o_pcol = take(z.pcol);
+  p.o_norms = take(z.kvec);
+  p.o_csum = take(z.kvec);
+  p.o_pnumh = take(z.pnumh);
+  p.o_pdenh = take(z.pnumh);
+  p.total = o;
+  return p;
+}
+
+Plan make_plan(const nmf_ctx_s* c, int64_t F, int64_t N, int64_t K) {
+  Plan p{};
+  p.KB = kblocks_for(K);
+  p.KP = 32 * p.KB;
+  const int64_t target = target_of(c);
+  const int64_t min_tiles = std::max(1, c->min_tiles);
+  p.row_blocks = (int)cdiv(F, kRowsPerBlock);
+  split(cdiv(N, kTile), p.row_blocks, target, min_tiles, &p.n_groups, &p.tiles_n);
+  p.col_blocks = (int)cdiv(N, kRowsPerBlock);
+  split(cdiv(F, kTile), p.col_blocks, target, min_tiles, &p.f_groups, &p.tiles_f);
+  p.uw_blocks = (int)std::min<int64_t>(kUpdateWBlocks, std::max<int64_t>(1, cdiv(F, kBlock / p.KP)));
+  p.uh_blocks = (int)std::max<int64_t>(cdiv(N, kTile), 1);
+  Sizes z;
+  z.pobj = sizeof(double) * (size_t)p.row_blocks * p.n_groups;
+  z.pnum = sizeof(float) * (size_t)p.n_groups * F * p.KP;
+  z.prs = sizeof(float) * (size_t)p.n_groups * p.KP;
+  z.wn = sizeof(float) * (size_t)F * p.KP;
+  z.pcol = sizeof(double) * (size_t)p.uw_blocks * 2 * p.KP;
+  z.kvec = sizeof(float) * p.KP;
+  z.pnumh = sizeof(float) * (size_t)p.f_groups * N * p.KP;
+  return layout(z, p);
+}
+
+// Workspace size that covers every call with F <= maxF, N <= maxN, K <= maxK
+// under the current launch settings: each region at its largest over all shapes.
+size_t plan_bound(const nmf_ctx_s* c, int64_t maxF, int64_t maxN, int64_t maxK) {
+  const int64_t KP = 32 * kblocks_for(maxK);
+  const int64_t target = target_of(c);
+  const int64_t ntmax = cdiv(maxN, kTile), ftmax = cdiv(maxF, kTile);
+  Sizes z{};
+  for (int64_t rb = 1; rb <= cdiv(maxF, kRowsPerBlock); ++rb) {
+    const int64_t groups = std::min<int64_t>(ntmax, std::max<int64_t>(1, cdiv(target, rb)));
+    const int64_t F = std::min<int64_t>(maxF, rb * kRowsPerBlock);
+    z.pobj = std::max(z.pobj, sizeof(double) * (size_t)(rb * groups));
+    z.pnum = std::max(z.pnum, sizeof(float) * (size_t)(groups * F * KP));
+    z.prs = std::max(z.prs, sizeof(float) * (size_t)(groups * KP));
+  }
+  for (int64_t cb = 1; cb <= cdiv(maxN, kRowsPerBlock); ++cb) {
+    const int64_t groups = std::min<int64_t>(ftmax, std::max<int64_t>(1, cdiv(target, cb)));
+    const int64_t N = std::min<int64_t>(maxN, cb * kRowsPerBlock);
+    z.pnumh = std::max(z.pnumh, sizeof(float) * (size_t)(groups * N * KP));
+  }
+  z.wn = sizeof(float) * (size_t)(maxF * KP);
+  z.pcol = sizeof(double) * (size_t)(kUpdateWBlocks * 2 * KP);
+  z.kvec = sizeof(float) * KP;
+  return layout(z, Plan{}).total;
+}
+
+bool is_fin(double x) { return std::isfinite(x); }
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  if (!a || !b || !na || !nb) return false;
+  const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+  return a0 < b0 + nb && b0 < a0 + na;
+}
+
+size_t span_bytes(int64_t rows, int64_t cols, int64_t ld) {
+  return (size_t)(((rows - 1) * ld + cols) * (int64_t)sizeof(float));
+}
+
+nmf_status check_mats(int64_t F, int64_t N, int64_t K, const float* V, int64_t ldv, const float* W, int64_t ldw,
+                      const float* H, int64_t ldh) {
+  if (!V || !W || !H) return NMF_ERR_NULL;
+  if (F < 1 || N < 1 || K < 1) return NMF_ERR_SHAPE;
+  if (F > INT32_MAX || N > INT32_MAX) return NMF_ERR_SHAPE;
+  if (ldv < N || ldw < K || ldh < N) return NMF_ERR_SHAPE;
+  if (K > 128) return NMF_ERR_UNSUPPORTED;
+  const size_t sv = span_bytes(F, N, ldv), sw = span_bytes(F, K, ldw), sh = span_bytes(K, N, ldh);
+  if (overlaps(V, sv, W, sw) || overlaps(V, sv, H, sh) || overlaps(W, sw, H, sh)) return NMF_ERR_ALIAS;
+  return NMF_OK;
+}
+
+nmf_status check_opts(const nmf_step_opts* o) {
+  if (!o) return NMF_OK;
+  if (o->precision != NMF_FP32 && o->precision != NMF_BF16 && o->precision != NMF_FP16) return NMF_ERR_UNSUPPORTED;
+  if (o->precision != NMF_FP32) return NMF_ERR_UNSUPPORTED;
+  if (!is_fin(o->kappa) || o->kappa < 0.f) return NMF_ERR_BETA;
+  if (o->inner_iters != 1) return NMF_ERR_UNSUPPORTED;
+  if (o->normalize != 0 && o->normalize != 1) return NMF_ERR_ARG;
+  return NMF_OK;
+}
+
+nmf_status hip_status(hipError_t e) { return e == hipSuccess ? NMF_OK : NMF_ERR_HIP; }
+
+// Ensures the workspace holds `bytes`; reallocates (blocking) unless capturing.
+nmf_status ensure_ws(nmf_ctx_s* c, hipStream_t s, size_t bytes) {
+  if (c->ws_bytes >= bytes) return NMF_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return NMF_ERR_HIP;
+  if (cs != hipStreamCaptureStatusNone) return NMF_ERR_WORKSPACE;
+  if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
+  uint32_t flags_keep = 0;
+  if (c->ws) {
+    if (hipDeviceSynchronize() != hipSuccess) return NMF_ERR_HIP;
+    (void)hipMemcpy(&flags_keep, c->ws, sizeof(uint32_t), hipMemcpyDeviceToHost);
+    (void)hipFree(c->ws);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  const size_t want = align_up(bytes + bytes / 8);
+  void* p = nullptr;
+  if (hipMalloc(&p, want) != hipSuccess) return NMF_ERR_HIP;
+  if (hipMemset(p, 0, kHeaderBytes) != hipSuccess) { (void)hipFree(p); return NMF_ERR_HIP; }
+  if (flags_keep && hipMemcpy(p, &flags_keep, sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(p);
+    return NMF_ERR_HIP;
+  }
+  c->ws = (char*)p;
+  c->ws_bytes = want;
+  return NMF_OK;
+}
+
+unsigned* flags_ptr(nmf_ctx_s* c) { return (unsigned*)c->ws; }
+unsigned* counter_ptr(nmf_ctx_s* c) { return (unsigned*)(c->ws + 4); }
+
+hipEvent_t get_event(nmf_ctx_s* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+// Runs `launch` between two events when the kernel is selected for timing.
+template <class Fn>
+hipError_t timed(nmf_ctx_s* c, int kernel, hipStream_t s, Fn&& launch) {
+  const bool on = (c->profile_mask >> kernel) & 1u;
+  if (!on) return launch();
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  (void)hipStreamIsCapturing(s, &cs);
+  if (cs != hipStreamCaptureStatusNone) return launch();
+  TimedLaunch t{get_event(c), get_event(c)};
+  (void)hipEventRecord(t.start, s);
+  hipError_t e = launch();
+  (void)hipEventRecord(t.stop, s);
+  c->pending[kernel].push_back(t);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+void nmf_default_opts(nmf_step_opts* o) {
+  if (!o) return;
+  o->precision = NMF_FP32;
+  o->kappa = 0.f;
+  o->inner_iters = 1;
+  o->normalize = 1;
+}
+
+const char* nmf_version(void) { return "nmfbeta 0.1 (gfx950)"; }
+
+const char* nmf_status_string(nmf_status s) {
+  switch (s) {
+    case NMF_OK: return "NMF_OK";
+    case NMF_ERR_NULL: return "NMF_ERR_NULL: required pointer is NULL";
+    case NMF_ERR_SHAPE: return "NMF_ERR_SHAPE: bad size or leading dimension";
+    case NMF_ERR_BETA: return "NMF_ERR_BETA: beta or kappa not finite (or kappa < 0)";
+    case NMF_ERR_ALIAS: return "NMF_ERR_ALIAS: matrices overlap";
+    case NMF_ERR_WORKSPACE: return "NMF_ERR_WORKSPACE: workspace too small during stream capture";
+    case NMF_ERR_HIP: return "NMF_ERR_HIP: HIP runtime error";
+    case NMF_ERR_UNSUPPORTED: return "NMF_ERR_UNSUPPORTED: unsupported size or option";
+    case NMF_ERR_ARG: return "NMF_ERR_ARG: invalid argument";
+    case NMF_ERR_NO_DEVICE: return "NMF_ERR_NO_DEVICE: no usable GPU";
+  }
+  return "unknown nmf_status";
+}
+
+nmf_status nmf_create(nmf_ctx_t* out, int device) {
+  if (!out) return NMF_ERR_NULL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return NMF_ERR_NO_DEVICE;
+  if (device < 0 || device >= n) return NMF_ERR_NO_DEVICE;
+  nmf_ctx_s* c = new (std::nothrow) nmf_ctx_s();
+  if (!c) return NMF_ERR_HIP;
+  c->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->num_cus = prop.multiProcessorCount;
+  *out = c;
+  return NMF_OK;
+}
+
+nmf_status nmf_destroy(nmf_ctx_t c) {
+  if (!c) return NMF_ERR_NULL;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  for (auto& v : c->pending)
+    for (auto& t : v) { (void)hipEventDestroy(t.start); (void)hipEventDestroy(t.stop); }
+  for (auto e : c->event_pool) (void)hipEventDestroy(e);
+  if (c->ws) (void)hipFree(c->ws);
+  delete c;
+  return NMF_OK;
+}
+
+nmf_status nmf_reserve(nmf_ctx_t c, int64_t maxF, int64_t maxN, int64_t maxK) {
+  if (!c) return NMF_ERR_NULL;
+  if (maxF < 1 || maxN < 1 || maxK < 1) return NMF_ERR_SHAPE;
+  if (maxK > 128) return NMF_ERR_UNSUPPORTED;
+  const size_t need = plan_bound(c, maxF, maxN, maxK);
+  return ensure_ws(c, nullptr, need);
+}
+
+nmf_status nmf_check_step_args(int64_t F, int64_t N, int64_t K, const float* V, int64_t ldv, const float* W,
+                               int64_t ldw, const float* H, int64_t ldh, double beta, int32_t mode,
+                               const nmf_step_opts* opts) {
+  nmf_status st = check_mats(F, N, K, V, ldv, W, ldw, H, ldh);
+  if (st != NMF_OK) return st;
+  if (!is_fin(beta)) return NMF_ERR_BETA;
+  if (mode != NMF_ALTERNATING && mode != NMF_JOINT) return NMF_ERR_ARG;
+  return check_opts(opts);
+}
+
+nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K, const float* V, int64_t ldv,
+                         float* W, int64_t ldw, float* H, int64_t ldh, double beta, int32_t mode,
+                         const nmf_step_opts* opts, double* d_objective) {
+  if (!c) return NMF_ERR_NULL;
+  nmf_status st = nmf_check_step_args(F, N, K, V, ldv, W, ldw, H, ldh, beta, mode, opts);
+  if (st != NMF_OK) return st;
+  nmf_step_opts o;
+  nmf_default_opts(&o);
+  if (opts) o = *opts;
+  hipStream_t s = (hipStream_t)stream;
+  const Plan p = make_plan(c, F, N, K);
+  if ((st = ensure_ws(c, s, p.total)) != NMF_OK) return st;
+  if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
+
+  const int bc = beta_class(beta);
+  const bool joint = (mode == NMF_JOINT);
+  const bool beta_one = (bc == BC_B1);
+  char* ws = c->ws;
+  float* Wn = (float*)(ws + p.o_wn);
+  float* C1 = (float*)(ws + p.o_c1);
+  float* C2 = (float*)(ws + p.o_c2);
+  float* norms = (float*)(ws + p.o_norms);
+  float* csum = (float*)(ws + p.o_csum);
+
+  SweepRowsArgs ra{};
+  ra.V = V; ra.ldv = ldv; ra.W = W; ra.ldw = ldw; ra.H = H; ra.ldh = ldh;
+  ra.F = (int)F; ra.N = (int)N; ra.K = (int)K;
+  ra.bm2 = (float)(beta - 2.0); ra.kappa = o.kappa; ra.beta = beta;
+  ra.n_groups = p.n_groups; ra.tiles_per_group = p.tiles_n;
+  ra.pnum = (float*)(ws + p.o_pnum); ra.pden = (float*)(ws + p.o_pden); ra.prs = (float*)(ws + p.o_prs);
+  ra.pobj = (double*)(ws + p.o_pobj);
+  ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
+  const int sw_grid = p.row_blocks * p.n_groups;
+  hipError_t e = timed(c, NMF_KERNEL_SWEEP_W, s, [&] {
+    return launch_sweep_rows(bc, p.KB, KIND_UPDATE, d_objective != nullptr, sw_grid, s, ra);
+  });
+  if (e != hipSuccess) return NMF_ERR_HIP;
+
+  UpdateWArgs ua{};
+  ua.W = W; ua.ldw = ldw; ua.pnum = ra.pnum; ua.pden = ra.pden; ua.prs = ra.prs;
+  ua.F = (int)F; ua.K = (int)K; ua.n_groups = p.n_groups;
+  ua.beta = beta; ua.gamma = gamma_of(beta); ua.joint = joint; ua.beta_one = beta_one;
+  ua.Wn = Wn; ua.C1 = C1; ua.C2 = C2; ua.pcol = (double*)(ws + p.o_pcol);
+  ua.counter = counter_ptr(c); ua.norms = norms; ua.csum = csum;
+  ua.pobj = ra.pobj; ua.nobj = sw_grid; ua.d_obj = d_objective; ua.flags = flags_ptr(c);
+  e = timed(c, NMF_KERNEL_UPDATE_W, s, [&] { return launch_update_w(p.KB, p.uw_blocks, s, ua); });
+  if (e != hipSuccess) return NMF_ERR_HIP;
+
+  SweepColsArgs ca{};
+  ca.V = V; ca.ldv = ldv;
+  if (joint) { ca.WL = W; ca.ldwl = ldw; ca.C1 = C1; ca.C2 = C2; }
+  else { ca.WL = Wn; ca.ldwl = p.KP; ca.C1 = Wn; ca.C2 = Wn; }
+  ca.ldc = p.KP; ca.H = H; ca.ldh = ldh;
+  ca.F = (int)F; ca.N = (int)N; ca.K = (int)K;
+  ca.bm2 = (float)(beta - 2.0); ca.kappa = o.kappa;
+  ca.f_groups = p.f_groups; ca.tiles_per_group = p.tiles_f;
+  ca.pnum = (float*)(ws + p.o_pnumh); ca.pden = (float*)(ws + p.o_pdenh);
+  const int sh_grid = p.col_blocks * p.f_groups;
+  e = timed(c, NMF_KERNEL_SWEEP_H, s, [&] { return launch_sweep_cols(bc, p.KB, KIND_UPDATE, joint, sh_grid, s, ca); });
+  if (e != hipSuccess) return NMF_ERR_HIP;
+
+  UpdateHArgs ha{};
+  ha.H = H; ha.ldh = ldh; ha.pnum = ca.pnum; ha.pden = ca.pden; ha.csum = csum;
+  ha.F = (int)F; ha.N = (int)N; ha.K = (int)K; ha.f_groups = p.f_groups;
+  ha.gamma = gamma_of(beta); ha.beta_one = beta_one; ha.normalize = o.normalize;
+  ha.norms = norms; ha.Wn = Wn; ha.W = W; ha.ldw = ldw; ha.flags = flags_ptr(c);
+  e = timed(c, NMF_KERNEL_UPDATE_H, s, [&] { return launch_update_h(p.KB, p.uh_blocks, s, ha); });
+  return hip_status(e);
+}
+
+nmf_status nmf_beta_objective(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K, const float* V,
+                              int64_t ldv, const float* W, int64_t ldw, const float* H, int64_t ldh, double beta,
+                              float kappa, double* d_out) {
+  if (!c || !d_out) return NMF_ERR_NULL;
+  nmf_status st = check_mats(F, N, K, V, ldv, W, ldw, H, ldh);
+  if (st != NMF_OK) return st;
+  if (!is_fin(beta) || !std::isfinite(kappa) || kappa < 0.f) return NMF_ERR_BETA;
+  hipStream_t s = (hipStream_t)stream;
+  const Plan p = make_plan(c, F, N, K);
+  if ((st = ensure_ws(c, s, p.total)) != NMF_OK) return st;
+  if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
+  SweepRowsArgs ra{};
+  ra.V = V; ra.ldv = ldv; ra.W = W; ra.ldw = ldw; ra.H = H; ra.ldh = ldh;
+  ra.F = (int)F; ra.N = (int)N; ra.K = (int)K;
+  ra.bm2 = (float)(beta - 2.0); ra.kappa = kappa; ra.beta = beta;
+  ra.n_groups = p.n_groups; ra.tiles_per_group = p.tiles_n;
+  ra.pobj = (double*)(c->ws + p.o_pobj);
+  ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
+  const int grid = p.row_blocks * p.n_groups;
+  hipError_t e = launch_sweep_rows(beta_class(beta), p.KB, KIND_OBJ, true, grid, s, ra);
+  if (e != hipSuccess) return NMF_ERR_HIP;
+  return hip_status(launch_finalize_objective(s, ra.pobj, grid, d_out, flags_ptr(c)));
+}
+
+nmf_status nmf_beta_grad(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K, const float* V, int64_t ldv,
+                         const float* W, int64_t ldw, const float* H, int64_t ldh, double beta, float kappa,
+                         double scale, float* dW, int64_t lddw, float* dH, int64_t lddh, double* d_objective) {
+  if (!c || !dW || !dH) return NMF_ERR_NULL;
+  nmf_status st = check_mats(F, N, K, V, ldv, W, ldw, H, ldh);
+  if (st != NMF_OK) return st;
+  if (lddw < K || lddh < N) return NMF_ERR_SHAPE;
+  if (!is_fin(beta) || !is_fin(scale) || !std::isfinite(kappa) || kappa < 0.f) return NMF_ERR_BETA;
+  {
+    const size_t sv = span_bytes(F, N, ldv), sw = span_bytes(F, K, ldw), sh = span_bytes(K, N, ldh);
+    const size_t sdw = span_bytes(F, K, lddw), sdh = span_bytes(K, N, lddh);
+    const void* in[3] = {V, W, H};
+    const size_t ns[3] = {sv, sw, sh};
+    for (int i = 0; i < 3; ++i)
+      if (overlaps(in[i], ns[i], dW, sdw) || overlaps(in[i], ns[i], dH, sdh)) return NMF_ERR_ALIAS;
+    if (overlaps(dW, sdw, dH, sdh)) return NMF_ERR_ALIAS;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const Plan p = make_plan(c, F, N, K);
+  if ((st = ensure_ws(c, s, p.total)) != NMF_OK) return st;
+  if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
+  const int bc = beta_class(beta);
+  char* ws = c->ws;
+  SweepRowsArgs ra{};
+  ra.V = V; ra.ldv = ldv; ra.W = W; ra.ldw = ldw; ra.H = H; ra.ldh = ldh;
+  ra.F = (int)F; ra.N = (int)N; ra.K = (int)K;
+  ra.bm2 = (float)(beta - 2.0); ra.kappa = kappa; ra.beta = beta;
+  ra.n_groups = p.n_groups; ra.tiles_per_group = p.tiles_n;
+  ra.pnum = (float*)(ws + p.o_pnum); ra.pobj = (double*)(ws + p.o_pobj);
+  ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
+  const int sw_grid = p.row_blocks * p.n_groups;
+  hipError_t e = launch_sweep_rows(bc, p.KB, KIND_GRAD, d_objective != nullptr, sw_grid, s, ra);
+  if (e != hipSuccess) return NMF_ERR_HIP;
+  SweepColsArgs ca{};
+  ca.V = V; ca.ldv = ldv; ca.WL = W; ca.ldwl = ldw; ca.C1 = W; ca.C2 = W; ca.ldc = ldw;
+  ca.H = H; ca.ldh = ldh; ca.F = (int)F; ca.N = (int)N; ca.K = (int)K;
+  ca.bm2 = (float)(beta - 2.0); ca.kappa = kappa;
+  ca.f_groups = p.f_groups; ca.tiles_per_group = p.tiles_f;
+  ca.pnum = (float*)(ws + p.o_pnumh);
+  e = launch_sweep_cols(bc, p.KB, KIND_GRAD, false, p.col_blocks * p.f_groups, s, ca);
+  if (e != hipSuccess) return NMF_ERR_HIP;
+  const int gw = (int)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(F * K, kBlock)));
+  if ((e = launch_grad_w(p.KB, gw, s, ra.pnum, (int)F, (int)K, p.n_groups, scale, dW, lddw)) != hipSuccess)
+    return NMF_ERR_HIP;
+  if ((e = launch_grad_h(p.KB, (int)cdiv(N, kTile), s, ca.pnum, (int)N, (int)K, p.f_groups, scale, dH, lddh)) !=
+      hipSuccess)
+    return NMF_ERR_HIP;
+  if (d_objective) return hip_status(launch_finalize_objective(s, ra.pobj, sw_grid, d_objective, flags_ptr(c)));
+  return NMF_OK;
+}
+
+nmf_status nmf_beta_validate(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K, const float* V,
+                             int64_t ldv, const float* W, int64_t ldw, const float* H, int64_t ldh, double beta,
+                             float kappa) {
+  if (!c) return NMF_ERR_NULL;
+  nmf_status st = check_mats(F, N, K, V, ldv, W, ldw, H, ldh);
+  if (st != NMF_OK) return st;
+  if (!is_fin(beta) || !std::isfinite(kappa) || kappa < 0.f) return NMF_ERR_BETA;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = ensure_ws(c, s, kHeaderBytes)) != NMF_OK) return st;
+  if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
+  const int zero_bad = (beta <= 0.0 && kappa == 0.f) ? 1 : 0;
+  return hip_status(launch_validate(s, V, ldv, W, ldw, H, ldh, (int)F, (int)N, (int)K, zero_bad, flags_ptr(c)));
+}
+
+nmf_status nmf_get_flags(nmf_ctx_t c, void* stream, uint32_t* flags, int32_t clear) {
+  if (!c || !flags) return NMF_ERR_NULL;
+  *flags = 0;
+  if (!c->ws) return NMF_OK;
+  if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(flags, c->ws, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess) return NMF_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return NMF_ERR_HIP;
+  if (clear) {
+    const uint32_t z = 0;
+    if (hipMemcpyAsync(c->ws, &z, sizeof(uint32_t), hipMemcpyHostToDevice, s) != hipSuccess) return NMF_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return NMF_ERR_HIP;
+  }
+  return NMF_OK;
+}
+
+nmf_status nmf_profile_enable(nmf_ctx_t c, uint32_t mask) {
+  if (!c) return NMF_ERR_NULL;
+  c->profile_mask = mask;
+  return NMF_OK;
+}
+
+nmf_status nmf_profile_read(nmf_ctx_t c, int32_t kernel, double* total_ms, int64_t* launches) {
+  if (!c || !total_ms || !launches) return NMF_ERR_NULL;
+  if (kernel < 0 || kernel >= NMF_KERNEL_COUNT) return NMF_ERR_ARG;
+  nmf_status st = NMF_OK;
+  for (auto& t : c->pending[kernel]) {
+    float ms = 0.f;
+    if (hipEventSynchronize(t.stop) != hipSuccess || hipEventElapsedTime(&ms, t.start, t.stop) != hipSuccess)
+      st = NMF_ERR_HIP;
+    c->prof_ms[kernel] += ms;
+    c->prof_count[kernel] += 1;
+    c->event_pool.push_back(t.start);
+    c->event_pool.push_back(t.stop);
+  }
+  c->pending[kernel].clear();
+  *total_ms = c->prof_ms[kernel];
+  *launches = c->prof_count[kernel];
+  c->prof_ms[kernel] = 0.0;
+  c->prof_count[kernel] = 0;
+  return st;
+}
+
+nmf_status nmf_set_launch(nmf_ctx_t c, int32_t target_blocks, int32_t min_tiles) {
+  if (!c) return NMF_ERR_NULL;
+  if (target_blocks < 0 || min_tiles < 0) return NMF_ERR_ARG;
+  c->target_blocks = target_blocks;
+  c->min_tiles = min_tiles > 0 ? min_tiles : 1;
+  return NMF_OK;
+}
+
+}  // extern "C"

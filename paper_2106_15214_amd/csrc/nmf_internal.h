@@ -1,0 +1,103 @@
+// Internal declarations shared by the host library and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nmf {
+
+// Classes of beta with specialised element-wise terms (the general class uses
+// exp2/log2 for Lambda^(beta-2)).
+enum BetaClass { BC_GEN = 0, BC_B2 = 1, BC_B1 = 2, BC_B0 = 3, BC_B05 = 4, BC_B15 = 5 };
+
+// What a pass over V accumulates.
+enum Kind {
+  KIND_UPDATE = 0,  // numerator (P) and denominator (Q) contractions
+  KIND_GRAD = 1,    // gradient term E = Lambda^(beta-2) (Lambda - V) only
+  KIND_OBJ = 2      // objective terms only (no contraction)
+};
+
+constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
+constexpr int kWaves = 4;
+constexpr int kTile = 32;        // tile edge handled by one wave per step
+constexpr int kRowsPerBlock = kWaves * kTile;  // 128
+
+inline int beta_class(double beta) {
+  if (beta == 2.0) return BC_B2;
+  if (beta == 1.0) return BC_B1;
+  if (beta == 0.0) return BC_B0;
+  if (beta == 0.5) return BC_B05;
+  if (beta == 1.5) return BC_B15;
+  return BC_GEN;
+}
+
+// gamma(beta), paper eq. (def_gamma)
+inline double gamma_of(double beta) {
+  if (beta < 1.0) return 1.0 / (2.0 - beta);
+  if (beta <= 2.0) return 1.0;
+  return 1.0 / (beta - 1.0);
+}
+
+struct SweepRowsArgs {
+  const float* V; int64_t ldv;
+  const float* W; int64_t ldw;     // tilde W (rows owned by each wave)
+  const float* H; int64_t ldh;     // tilde H
+  int F, N, K;
+  float bm2, kappa;                // beta - 2, smoothing constant
+  double beta;
+  int n_groups, tiles_per_group;   // grid = row_blocks * n_groups
+  float* pnum; float* pden;        // [n_groups][F][KP] partial W contractions
+  float* prs;                      // [n_groups][KP] partial row sums of H (beta = 1)
+  double* pobj;                    // [grid] objective partials (nullable)
+  int vec4;                        // V rows 16-byte aligned
+};
+
+struct SweepColsArgs {
+  const float* V; int64_t ldv;
+  const float* WL; int64_t ldwl;   // factor used to form Lambda (W~ joint, W_new alternating)
+  const float* H; int64_t ldh;     // tilde H (columns owned by each wave)
+  const float* C1; const float* C2; int64_t ldc;  // contraction operands (chi_1, chi_2)
+  int F, N, K;
+  float bm2, kappa;
+  int f_groups, tiles_per_group;   // grid = col_blocks * f_groups
+  float* pnum; float* pden;        // [f_groups][N][KP] partial H contractions
+};
+
+struct UpdateWArgs {
+  const float* W; int64_t ldw;     // tilde W
+  const float* pnum; const float* pden; const float* prs;
+  int F, K, n_groups;
+  double beta, gamma;
+  int joint, beta_one;
+  float* Wn; float* C1; float* C2; // [F][KP]
+  double* pcol;                    // [grid][2][KP] column norm^2 and sum partials
+  unsigned* counter;
+  float* norms; float* csum;       // [KP]
+  const double* pobj; int nobj; double* d_obj;
+  unsigned* flags;
+};
+
+struct UpdateHArgs {
+  float* H; int64_t ldh;
+  const float* pnum; const float* pden; const float* csum;
+  int F, N, K, f_groups;
+  double gamma;
+  int beta_one, normalize;
+  const float* norms; const float* Wn; float* W; int64_t ldw;
+  unsigned* flags;
+};
+
+// launchers (nmf_kernels.hip)
+hipError_t launch_sweep_rows(int bc, int kb, int kind, bool obj, int grid, hipStream_t s, const SweepRowsArgs& a);
+hipError_t launch_sweep_cols(int bc, int kb, int kind, bool dual, int grid, hipStream_t s, const SweepColsArgs& a);
+hipError_t launch_update_w(int kb, int grid, hipStream_t s, const UpdateWArgs& a);
+hipError_t launch_update_h(int kb, int grid, hipStream_t s, const UpdateHArgs& a);
+hipError_t launch_finalize_objective(hipStream_t s, const double* pobj, int n, double* out, unsigned* flags);
+hipError_t launch_grad_w(int kb, int grid, hipStream_t s, const float* pnum, int F, int K, int n_groups,
+                         double scale, float* dW, int64_t lddw);
+hipError_t launch_grad_h(int kb, int grid, hipStream_t s, const float* pnum, int N, int K, int f_groups,
+                         double scale, float* dH, int64_t lddh);
+hipError_t launch_validate(hipStream_t s, const float* V, int64_t ldv, const float* W, int64_t ldw,
+                           const float* H, int64_t ldh, int F, int N, int K, int zero_bad, unsigned* flags);
+
+}  // namespace nmf

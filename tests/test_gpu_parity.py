@@ -1,0 +1,260 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 CPU oracle.
+
+Every case starts both sides from the same float32 state.  Gates (relative
+Frobenius error of the new factors, relative objective error):
+  W, H: <= 1e-5 (float32 products);  objective: <= 1e-6.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+import paper_2106_15214_amd as nb
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+TOL_FACTOR = 1e-5
+TOL_OBJ = 1e-6
+BETAS = [0.0, 0.5, 1.0, 1.5, 2.0, 2.5, -0.5, 1.2]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def gpu_step(V, W, H, beta, mode, kappa=0.0, normalize=True, obj=True):
+    Vd, Wd, Hd = dev(V), dev(W), dev(H)
+    o = torch.full((1,), float("nan"), dtype=torch.float64, device=DEV) if obj else None
+    nb.step(Vd, Wd, Hd, beta, mode, kappa=kappa, normalize=normalize, objective_out=o)
+    torch.cuda.synchronize()
+    return Wd.cpu().numpy(), Hd.cpu().numpy(), (o.item() if obj else None)
+
+
+def ref_step(V, W, H, beta, mode, kappa=0.0, normalize=True):
+    f = O.jmm_iteration if mode == "joint" else O.bmm_iteration
+    return f(V.astype(np.float64), W.astype(np.float64), H.astype(np.float64), beta, kappa=kappa, norm=normalize)
+
+
+def ref_obj(V, W, H, beta, kappa=0.0):
+    return O.objective(V.astype(np.float64), W.astype(np.float64), H.astype(np.float64), beta, kappa)
+
+
+def check_step(V, W, H, beta, mode, kappa=0.0, normalize=True, tag=""):
+    print(f"[parity] {tag} F={V.shape[0]} N={V.shape[1]} K={W.shape[1]} beta={beta} mode={mode} "
+          f"kappa={kappa} norm={normalize}", flush=True)
+    Wg, Hg, dg = gpu_step(V, W, H, beta, mode, kappa, normalize)
+    Wr, Hr = ref_step(V, W, H, beta, mode, kappa, normalize)
+    d0 = ref_obj(V, W, H, beta, kappa)
+    eW, eH = rel(Wg, Wr), rel(Hg, Hr)
+    eD = abs(dg - d0) / abs(d0)
+    assert eW <= TOL_FACTOR, f"W rel err {eW:.3e}"
+    assert eH <= TOL_FACTOR, f"H rel err {eH:.3e}"
+    assert eD <= TOL_OBJ, f"objective rel err {eD:.3e} ({dg} vs {d0})"
+    assert nb.get_flags(clear=True) == 0
+    return Wg, Hg
+
+
+SHAPES = [(64, 100, 5), (200, 150, 20), (257, 300, 49), (130, 70, 64), (33, 1000, 8), (1, 40, 3), (40, 1, 3),
+          (300, 97, 100), (129, 129, 1), (96, 160, 32)]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("beta", BETAS)
+@pytest.mark.parametrize("mode", ["joint", "alternating"])
+def test_step_parity_shapes(shape, beta, mode):
+    F, N, K = shape
+    p = synth.random_positive(F, N, K, seed=F * 7 + N + K, zeros=0.1 if beta > 0 else 0.0)
+    check_step(p.V, p.W, p.H, beta, mode, tag="shape")
+
+
+@pytest.mark.parametrize("name,beta,crop", [
+    ("tiny_kl", 1.0, None),
+    ("faces_euc", 2.0, None),
+    ("spectro_is", 0.0, None),
+    ("spectro_is", 0.5, None),
+    ("counts_kl", 1.0, ((0, 200), (0, 150))),
+    ("counts_kl", 1.0, ((1000, 1700), (3000, 4100))),
+])
+@pytest.mark.parametrize("mode", ["joint", "alternating"])
+def test_workload_parity(name, beta, crop, mode):
+    p = synth.make_problem(name, beta=beta, rows=crop[0] if crop else None, cols=crop[1] if crop else None)
+    check_step(p.V, p.W, p.H, beta, mode, tag=name)
+
+
+@pytest.mark.parametrize("mode", ["joint", "alternating"])
+def test_trajectory_per_step_parity_tiny_kl(mode):
+    # 100 iterations of the tiny KL workload; at selected t the GPU state is
+    # stepped once by both sides; the objective trace is monotone.
+    p = synth.make_problem("tiny_kl")
+    V, W, H = dev(p.V), dev(p.W), dev(p.H)
+    trace = []
+    for t in range(100):
+        if t in (0, 1, 10, 50, 99):
+            check_step(p.V, W.cpu().numpy(), H.cpu().numpy(), 1.0, mode, tag=f"t={t}")
+        o = torch.zeros(1, dtype=torch.float64, device=DEV)
+        nb.step(V, W, H, 1.0, mode, objective_out=o)
+        trace.append(o.item())
+    trace = np.array(trace)
+    eps = 2e-7  # objective evaluation error of the float32 product
+    assert np.all(trace[1:] <= trace[:-1] * (1 + 2 * eps)), np.max(np.diff(trace) / trace[:-1])
+
+
+@pytest.mark.parametrize("beta", [0.0, 1.0, 2.0, 0.5])
+def test_w_step_bitwise_equal_between_modes(beta):
+    p = synth.random_positive(150, 190, 24, seed=3)
+    Wj, _, _ = gpu_step(p.V, p.W, p.H, beta, "joint")
+    Wa, _, _ = gpu_step(p.V, p.W, p.H, beta, "alternating")
+    assert np.array_equal(Wj, Wa)
+
+
+@pytest.mark.parametrize("mode", ["joint", "alternating"])
+def test_run_to_run_bitwise_determinism(mode):
+    p = synth.random_positive(300, 500, 50, seed=4)
+    a = gpu_step(p.V, p.W, p.H, 1.5, mode)
+    b = gpu_step(p.V, p.W, p.H, 1.5, mode)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+
+
+@pytest.mark.parametrize("mode", ["joint", "alternating"])
+@pytest.mark.parametrize("beta", [0.0, 1.0])
+def test_kappa_smoothing_with_zeros(mode, beta):
+    p = synth.random_positive(120, 140, 10, seed=5, zeros=0.3)
+    check_step(p.V, p.W, p.H, beta, mode, kappa=0.05, tag="kappa")
+
+
+@pytest.mark.parametrize("mode", ["joint", "alternating"])
+def test_without_normalization(mode):
+    p = synth.random_positive(100, 140, 12, seed=6)
+    check_step(p.V, p.W, p.H, 0.5, mode, normalize=False, tag="nonorm")
+
+
+def test_padded_leading_dimensions_and_unaligned_v():
+    p = synth.random_positive(90, 130, 17, seed=8)
+    big = np.zeros((90, 133), np.float32)
+    big[:, 1:131] = p.V  # V starts one float in: rows not 16-byte aligned
+    Vd = dev(big)[:, 1:131]
+    Wb = np.zeros((90, 21), np.float32)
+    Wb[:, :17] = p.W
+    Hb = np.zeros((17, 140), np.float32)
+    Hb[:, :130] = p.H
+    Wbig, Hbig = dev(Wb), dev(Hb)
+    Wd = Wbig[:, :17]
+    Hd = Hbig[:, :130]
+    o = torch.zeros(1, dtype=torch.float64, device=DEV)
+    nb.step(Vd, Wd, Hd, 1.0, "joint", objective_out=o)
+    torch.cuda.synchronize()
+    Wr, Hr = ref_step(p.V, p.W, p.H, 1.0, "joint")
+    assert rel(Wd.cpu().numpy(), Wr) <= TOL_FACTOR and rel(Hd.cpu().numpy(), Hr) <= TOL_FACTOR
+    # padding columns untouched
+    assert torch.all(Wbig[:, 17:] == 0) and torch.all(Hbig[:, 130:] == 0)
+    assert abs(o.item() - ref_obj(p.V, p.W, p.H, 1.0)) <= TOL_OBJ * ref_obj(p.V, p.W, p.H, 1.0)
+
+
+@pytest.mark.parametrize("beta", BETAS + [3.0])
+@pytest.mark.parametrize("kappa", [0.0, 0.1])
+def test_objective_call(beta, kappa):
+    p = synth.random_positive(170, 230, 19, seed=9, zeros=0.1 if (beta > 0 or kappa > 0) else 0.0)
+    out = nb.objective(dev(p.V), dev(p.W), dev(p.H), beta, kappa=kappa)
+    d0 = ref_obj(p.V, p.W, p.H, beta, kappa)
+    assert abs(out.item() - d0) <= TOL_OBJ * abs(d0)
+
+
+def _grad_tol_scale(V, W, H, beta):
+    L = W.astype(np.float64) @ H.astype(np.float64)
+    E = np.abs(L ** (beta - 2) * (L - V))
+    return np.linalg.norm(E @ np.abs(H.T)), np.linalg.norm(np.abs(W.T) @ E)
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.5, 1.0, 1.5, 2.0, 2.5])
+def test_gradient_matches_oracle(beta):
+    p = synth.random_positive(150, 260, 30, seed=10)
+    dW, dH = nb.grad(dev(p.V), dev(p.W), dev(p.H), beta, scale=1.0)
+    gW, gH = O.gradient(p.V.astype(np.float64), p.W.astype(np.float64), p.H.astype(np.float64), beta)
+    sW, sH = _grad_tol_scale(p.V, p.W, p.H, beta)
+    assert np.linalg.norm(dW.cpu().numpy() - gW) <= 1e-5 * sW
+    assert np.linalg.norm(dH.cpu().numpy() - gH) <= 1e-5 * sH
+
+
+def test_gradient_count_crop_finite_differences_and_autograd():
+    # count-data crop V[:200, :150], K = 50: GPU autograd backward vs the oracle
+    # gradient and vs central finite differences of the oracle objective
+    p = synth.make_problem("counts_kl", rows=(0, 200), cols=(0, 150))
+    V, W, H = dev(p.V), dev(p.W).requires_grad_(True), dev(p.H).requires_grad_(True)
+    D = nb.beta_divergence(V, W, H, 1.0)
+    (3.0 * D).backward()
+    V64, W64, H64 = (a.astype(np.float64) for a in (p.V, p.W, p.H))
+    gW, gH = O.gradient(V64, W64, H64, 1.0)
+    sW, sH = _grad_tol_scale(p.V, p.W, p.H, 1.0)
+    assert np.linalg.norm(W.grad.cpu().numpy() - 3.0 * gW) <= 3e-5 * sW
+    assert np.linalg.norm(H.grad.cpu().numpy() - 3.0 * gH) <= 3e-5 * sH
+    rng = np.random.default_rng(0)
+    for _ in range(10):
+        f, k = rng.integers(0, 200), rng.integers(0, 50)
+        h = 1e-6 * max(1.0, W64[f, k])
+        Wp, Wm = W64.copy(), W64.copy()
+        Wp[f, k] += h
+        Wm[f, k] -= h
+        fd = (O.objective(V64, Wp, H64, 1.0) - O.objective(V64, Wm, H64, 1.0)) / (2 * h)
+        assert abs(W.grad[f, k].item() / 3.0 - fd) <= 1e-4 * max(1.0, abs(fd))
+    assert abs(D.item() - O.objective(V64, W64, H64, 1.0)) <= TOL_OBJ * O.objective(V64, W64, H64, 1.0)
+
+
+def test_flags_nonfinite_and_domain():
+    nb.get_flags(clear=True)
+    p = synth.random_positive(64, 80, 6, seed=11)
+    Vd, Wd, Hd = dev(p.V), dev(p.W), dev(p.H)
+    nb.validate(Vd, Wd, Hd, 1.0)
+    assert nb.get_flags(clear=True) == 0
+    Vbad = p.V.copy()
+    Vbad[3, 4] = -1.0
+    nb.validate(dev(Vbad), Wd, Hd, 1.0)
+    assert nb.get_flags(clear=True) & nb.FLAG_DOMAIN
+    Vz = p.V.copy()
+    Vz[0, 0] = 0.0
+    nb.validate(dev(Vz), Wd, Hd, 0.0)
+    assert nb.get_flags(clear=True) & nb.FLAG_DOMAIN
+    nb.validate(dev(Vz), Wd, Hd, 0.0, kappa=0.1)
+    assert nb.get_flags(clear=True) == 0
+    Hz = torch.zeros_like(Hd)
+    nb.step(Vd, Wd, Hz, 1.0, "joint")
+    assert nb.get_flags(clear=True) & nb.FLAG_NONFINITE
+    assert nb.get_flags() == 0
+
+
+def test_workspace_regrowth_between_sizes():
+    for (F, N, K) in [(50, 60, 4), (700, 900, 70), (40, 30, 2), (1200, 300, 33)]:
+        p = synth.random_positive(F, N, K, seed=F + N)
+        check_step(p.V, p.W, p.H, 1.0, "joint", tag="regrow")
+
+
+def test_reserve_then_steps_do_not_allocate():
+    ctx = nb.Context(0)
+    ctx.reserve(400, 500, 40)
+    p = synth.random_positive(400, 500, 40, seed=12)
+    Vd, Wd, Hd = dev(p.V), dev(p.W), dev(p.H)
+    nb.step(Vd, Wd, Hd, 2.0, "joint", ctx=ctx)
+    torch.cuda.synchronize()
+    Wr, Hr = ref_step(p.V, p.W, p.H, 2.0, "joint")
+    assert rel(Wd.cpu().numpy(), Wr) <= TOL_FACTOR and rel(Hd.cpu().numpy(), Hr) <= TOL_FACTOR
+    # a smaller problem inside the reservation must also work while capturing
+    q = synth.random_positive(100, 333, 17, seed=13)
+    Vq, Wq, Hq = dev(q.V), dev(q.W), dev(q.H)
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        nb.step(Vq, Wq, Hq, 1.0, "joint", ctx=ctx, stream=s)
+    Wq.copy_(dev(q.W))
+    Hq.copy_(dev(q.H))
+    g.replay()
+    torch.cuda.synchronize()
+    Wr, Hr = ref_step(q.V, q.W, q.H, 1.0, "joint")
+    assert rel(Wq.cpu().numpy(), Wr) <= TOL_FACTOR and rel(Hq.cpu().numpy(), Hr) <= TOL_FACTOR
+    ctx.close()
