@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Joint MM vs alternating MU on one MI355X: iterations/s, time-to-objective,
+per-kernel roofline, and the FP64 CPU oracle timed on the host cores.
+
+A step is one outer iteration (W update, H update, normalization, objective of
+the entry iterate) of the joint method on the chosen workload; the alternating
+method is timed the same way and reported beside it.  Inputs are resident in
+device memory before timing starts.
+
+    python bench.py [--steps K] [--warmup W] [--workload faces_euc]
+
+Prints one JSON line.  Only one GPU is used; --gpus above 1 exits.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "joint-MM vs alternating-MU iterations/s and time-to-objective per β, 1 MI355X"
+PEAK_FP32_MFMA = 157.3e12   # dense FP32 matrix FLOP/s
+PEAK_HBM = 8.0e12           # bytes/s
+
+
+def _flops_bytes(F, N, K, beta, mode):
+    """Algorithmic work per launch of each kernel (one outer iteration).
+
+    sweep_w : Lambda = W~H~ (2FNK) + P H~^T (2FNK) + Q H~^T (2FNK; omitted at beta = 1,
+              where the denominator is a row sum); reads V once (4FN bytes).
+    sweep_h : the two H-step contractions (4FNK; 2FNK at beta = 1).  Re-forming
+              Lambda costs another 2FNK: algorithmic for the alternating method
+              (Lambda' = W_new H~), implementation overhead for the joint one.
+    """
+    b1 = (beta == 1.0)
+    sw = (4 if b1 else 6) * F * N * K
+    sh = (2 if b1 else 4) * F * N * K + (2 * F * N * K if mode == "alternating" else 0)
+    return {"sweep_w": (sw, 4 * F * N), "sweep_h": (sh, 4 * F * N)}
+
+
+def _run_steps(nb, V, W, H, beta, mode, n, ctx, obj=None, trace=None):
+    for t in range(n):
+        o = trace[t:t + 1] if trace is not None else obj
+        nb.step(V, W, H, beta, mode, objective_out=o, ctx=ctx)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="faces_euc")
+    ap.add_argument("--beta", type=float, default=None)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle timing sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration under a profiler)")
+    ap.add_argument("--target-blocks", type=int, default=0)
+    ap.add_argument("--min-tiles", type=int, default=0)
+    args = ap.parse_args(argv)
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not supported",
+                          "n_gpus": args.gpus}), flush=True)
+        return 2
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_2106_15214_amd as nb
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        return 2
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    p = synth.make_problem(args.workload, beta=args.beta)
+    F, N, K = p.shape
+    beta = p.beta
+    print(f"# workload {args.workload}: F={F} N={N} K={K} beta={beta}", file=sys.stderr, flush=True)
+
+    ctx = nb.Context(0)
+    ctx.set_launch(args.target_blocks, args.min_tiles)
+    ctx.reserve(F, N, K)
+    V = torch.from_numpy(p.V).to(dev)
+    W0 = torch.from_numpy(p.W).to(dev)
+    H0 = torch.from_numpy(p.H).to(dev)
+    obj = torch.zeros(1, dtype=torch.float64, device=dev)
+    res = {}
+
+    for mode in ("joint", "alternating"):
+        W, H = W0.clone(), H0.clone()
+        _run_steps(nb, V, W, H, beta, mode, args.warmup, ctx, obj=obj)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        _run_steps(nb, V, W, H, beta, mode, args.steps, ctx, obj=obj)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1) / args.steps
+        res[mode] = {"ms_per_step": ms, "iters_per_s": 1e3 / ms, "wall_s": wall}
+        print(f"# {mode}: {ms * 1e3:.2f} us/iteration ({1e3 / ms:.1f} it/s)", file=sys.stderr, flush=True)
+    if nb.get_flags(clear=True, ctx=ctx):
+        print("# warning: numeric flags raised", file=sys.stderr)
+
+    # per-kernel durations with HIP events on the launch stream (same K steps)
+    kern = {}
+    for mode in ("joint", "alternating"):
+        W, H = W0.clone(), H0.clone()
+        _run_steps(nb, V, W, H, beta, mode, 2, ctx, obj=obj)
+        torch.cuda.synchronize()
+        ctx.profile(["sweep_w", "update_w", "sweep_h", "update_h"])
+        _run_steps(nb, V, W, H, beta, mode, args.steps, ctx, obj=obj)
+        torch.cuda.synchronize()
+        ctx.profile([])
+        kern[mode] = {}
+        for k in ("sweep_w", "update_w", "sweep_h", "update_h"):
+            tot, n = ctx.profile_read(k)
+            kern[mode][k] = {"avg_us": 1e3 * tot / max(n, 1), "launches": n}
+    fb = _flops_bytes(F, N, K, beta, "joint")
+    dom = max(("sweep_w", "sweep_h"), key=lambda k: kern["joint"][k]["avg_us"])
+    flops, vbytes = fb[dom]
+    t_dom = kern["joint"][dom]["avg_us"] * 1e-6
+    intensity = flops / vbytes
+    if intensity >= PEAK_FP32_MFMA / PEAK_HBM:
+        roof = {"bound": "mfma", "achieved": flops / t_dom / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": vbytes / t_dom / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["algorithmic_flops_per_launch"] = flops
+    roof["algorithmic_bytes_per_launch"] = vbytes
+    roof["avg_launch_us"] = kern["joint"][dom]["avg_us"]
+
+    # time-to-objective: same init, objective of every iterate, T = steps
+    T = args.steps
+    traces, tper = {}, {}
+    for mode in ("joint", "alternating"):
+        W, H = W0.clone(), H0.clone()
+        tr = torch.zeros(T + 1, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _run_steps(nb, V, W, H, beta, mode, T, ctx, trace=tr)
+        e1.record()
+        nb.objective(V, W, H, beta, out=tr[T:T + 1], ctx=ctx)
+        torch.cuda.synchronize()
+        traces[mode] = tr.cpu().numpy()
+        tper[mode] = e0.elapsed_time(e1) / T
+    D0 = traces["joint"][0]
+    Dend = max(traces["joint"][-1], traces["alternating"][-1])
+    tto = {}
+    for q in (0.9, 0.99, 0.999, 1.0):
+        target = D0 - q * (D0 - Dend)
+        row = {"target": target}
+        for mode in ("joint", "alternating"):
+            hit = np.nonzero(traces[mode] <= target * (1 + 1e-12))[0]
+            it = int(hit[0]) if hit.size else None
+            row[mode] = {"iterations": it, "ms": (it * tper[mode]) if it is not None else None}
+        tto[str(q)] = row
+    stop = {}
+    for mode in ("joint", "alternating"):
+        d = traces[mode]
+        rd = (d[:-1] - d[1:]) / d[1:]
+        hit = np.nonzero(rd <= 1e-5)[0]
+        stop[mode] = int(hit[0] + 1) if hit.size else None
+    mono = {m: int(np.sum(np.diff(traces[m]) > 0)) for m in traces}
+
+    out = {
+        "metric": METRIC,
+        "value": res["joint"]["iters_per_s"],
+        "unit": "iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["joint"]["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "F": F, "N": N, "K": K, "beta": beta, "mode": "joint",
+                   "precision": "fp32", "objective_every_step": True, "normalize": True},
+        "alternating": {"value": res["alternating"]["iters_per_s"], "ms_per_step": res["alternating"]["ms_per_step"]},
+        "joint_speedup_per_iteration": res["alternating"]["ms_per_step"] / res["joint"]["ms_per_step"],
+        "time_to_objective": {"T": T, "D0": D0, "D_T": {m: float(traces[m][-1]) for m in traces},
+                              "ms_per_iteration": tper, "targets": tto,
+                              "stop_rule_1e-5_iteration": stop, "objective_increases": mono},
+        "roofline": roof,
+        "kernels_us": kern,
+    }
+
+    if args.calib_copy:
+        x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = {"read": x.numel() * 4, "write": y.numel() * 4}
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
+def cpu_baseline(p, budget_s):
+    """The FP64 oracle's joint iteration (with the objective, as on the GPU) timed
+    on the host cores for about `budget_s` seconds from the same init."""
+    import numpy as np
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:  # pragma: no cover
+        threads = len(os.sched_getaffinity(0))
+    V = p.V.astype(np.float64)
+    W = p.W.astype(np.float64)
+    H = p.H.astype(np.float64)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.objective(V, W, H, p.beta)
+        W, H = oracle.jmm_iteration(V, W, H, p.beta)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or n >= 100000:
+            break
+    return {"value": n / el, "unit": "iterations/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} joint iterations (objective + update + normalization, float64 NumPy) of the "
+                      f"{p.name} workload from the benchmark's init, {el:.1f} s"}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -42,17 +42,18 @@ struct nmf_ctx_s {
 
 namespace {
 
-// Workspace header: flags word and the update_w arrival counter (zeroed at allocation).
+// Workspace header: the sticky flags word (zeroed at allocation).
 constexpr size_t kHeaderBytes = 256;
-constexpr int kUpdateWBlocks = 128;
+constexpr int kUpdateWBlocks = 64;
 
 struct Plan {
   int KB, KP;
   int row_blocks, n_groups, tiles_n;  // sweep_rows grid = row_blocks * n_groups
   int col_blocks, f_groups, tiles_f;  // sweep_cols grid = col_blocks * f_groups
   int uw_blocks, uh_blocks;
+  int64_t ldt;                        // leading dimension of the transposed factor (K x F)
   // byte offsets inside the workspace
-  size_t o_pobj, o_pnum, o_pden, o_prs, o_wn, o_c1, o_c2, o_pcol, o_norms, o_csum, o_pnumh, o_pdenh, total;
+  size_t o_pobj, o_pnum, o_pden, o_prs, o_wn, o_c1, o_c2, o_wt, o_pcol, o_pnumh, o_pdenh, total;
 };
 
 int kblocks_for(int64_t K) {
@@ -61,26 +62,39 @@ int kblocks_for(int64_t K) {
   return 4;
 }
 
-struct Grid {
-  int row_blocks, n_groups, tiles_n;
-  int col_blocks, f_groups, tiles_f;
-};
-
-int64_t target_of(const nmf_ctx_s* c) {
-  return c->target_blocks > 0 ? c->target_blocks : 2 * (int64_t)c->num_cus;
-}
-
-// Splits `tiles` 32-wide tiles over groups so that blocks * groups ~ target.
-void split(int64_t tiles, int64_t blocks, int64_t target, int64_t min_tiles, int* groups, int* per_group) {
-  const int64_t g = std::min<int64_t>(tiles, std::max<int64_t>(1, cdiv(target, blocks)));
-  const int64_t tpg = std::max<int64_t>(min_tiles, cdiv(tiles, g));
+// Number of groups the contracted dimension (`tiles` 32-wide tiles) is split
+// into, for `blocks` workgroups along the other dimension.  Minimizes a cost in
+// tile-times: resident rounds x (tiles per group + 2 for prologue/epilogue)
+// plus the partial-sum traffic (two arrays of groups * out_len * KP floats,
+// written and read at ~12 MB per tile-time).
+int choose_groups(const nmf_ctx_s* c, int64_t tiles, int64_t blocks, int64_t out_len, int KB, int occupancy,
+                  int* per_group) {
+  const int64_t slots = (int64_t)c->num_cus * occupancy;
+  const int64_t min_tpg = std::max(1, c->min_tiles);
+  int64_t best_g = 1;
+  const int64_t gcap = std::max<int64_t>(1, cdiv(4 * 2 * (int64_t)c->num_cus, blocks));
+  if (c->target_blocks > 0) {
+    best_g = std::max<int64_t>(1, std::min<int64_t>(std::min(cdiv(tiles, min_tpg), gcap), cdiv(c->target_blocks, blocks)));
+  } else {
+    double best = 1e300;
+    const int64_t gmax = std::min<int64_t>(cdiv(tiles, min_tpg), gcap);
+    for (int64_t g = 1; g <= gmax; ++g) {
+      const int64_t tpg = cdiv(tiles, g);
+      if (g > 1 && cdiv(tiles, tpg) < g) continue;  // same split as a smaller g
+      const double rounds = (double)cdiv(blocks * g, slots);
+      const double partial = 4.0 * (double)g * out_len * 32 * KB * 4 / 12.0e6;
+      const double cost = rounds * (tpg + 2.0) + partial;
+      if (cost < best) { best = cost; best_g = g; }
+    }
+  }
+  const int64_t tpg = cdiv(tiles, best_g);
   *per_group = (int)tpg;
-  *groups = (int)cdiv(tiles, tpg);
+  return (int)cdiv(tiles, tpg);
 }
 
 // Region sizes (bytes) of the workspace; offsets are assigned in this order.
 struct Sizes {
-  size_t pobj, pnum, prs, wn, pcol, kvec, pnumh;
+  size_t pobj, pnum, prs, fk, wt, pcol, pnumh;
 };
 
 Plan layout(const Sizes& z, Plan p) {
@@ -90,63 +104,62 @@ Plan layout(const Sizes& z, Plan p) {
   p.o_pnum = take(z.pnum);
   p.o_pden = take(z.pnum);
   p.o_prs = take(z.prs);
-  p.o_wn = take(z.wn);
-  p.o_c1 = take(z.wn);
-  p.o_c2 = take(z.wn);
+  p.o_wn = take(z.fk);
+  p.o_c1 = take(z.fk);
+  p.o_c2 = take(z.fk);
+  p.o_wt = take(z.wt);
   p.o_pcol = take(z.pcol);
-  p.o_norms = take(z.kvec);
-  p.o_csum = take(z.kvec);
   p.o_pnumh = take(z.pnumh);
   p.o_pdenh = take(z.pnumh);
   p.total = o;
   return p;
 }
 
-Plan make_plan(const nmf_ctx_s* c, int64_t F, int64_t N, int64_t K) {
+// `cols_occ`: workgroups per CU of the column pass this call launches.
+Plan make_plan(const nmf_ctx_s* c, int64_t F, int64_t N, int64_t K, int cols_occ = 2) {
   Plan p{};
   p.KB = kblocks_for(K);
   p.KP = 32 * p.KB;
-  const int64_t target = target_of(c);
-  const int64_t min_tiles = std::max(1, c->min_tiles);
-  p.row_blocks = (int)cdiv(F, kRowsPerBlock);
-  split(cdiv(N, kTile), p.row_blocks, target, min_tiles, &p.n_groups, &p.tiles_n);
-  p.col_blocks = (int)cdiv(N, kRowsPerBlock);
-  split(cdiv(F, kTile), p.col_blocks, target, min_tiles, &p.f_groups, &p.tiles_f);
-  p.uw_blocks = (int)std::min<int64_t>(kUpdateWBlocks, std::max<int64_t>(1, cdiv(F, kBlock / p.KP)));
-  p.uh_blocks = (int)std::max<int64_t>(cdiv(N, kTile), 1);
+  p.row_blocks = (int)cdiv(F, kBlockRows);
+  p.n_groups = choose_groups(c, cdiv(N, kTile), p.row_blocks, F, p.KB, sweep_rows_occupancy(p.KB), &p.tiles_n);
+  p.col_blocks = (int)cdiv(N, kBlockRows);
+  p.f_groups = choose_groups(c, cdiv(F, kTile), p.col_blocks, N, p.KB, std::min(cols_occ, sweep_rows_occupancy(p.KB)),
+                             &p.tiles_f);
+  p.uw_blocks = (int)std::min<int64_t>(kUpdateWBlocks, cdiv(F, kTile));
+  p.uh_blocks = (int)cdiv(N, kTile);
+  p.ldt = cdiv(F, 4) * 4;
   Sizes z;
   z.pobj = sizeof(double) * (size_t)p.row_blocks * p.n_groups;
   z.pnum = sizeof(float) * (size_t)p.n_groups * F * p.KP;
   z.prs = sizeof(float) * (size_t)p.n_groups * p.KP;
-  z.wn = sizeof(float) * (size_t)F * p.KP;
+  z.fk = sizeof(float) * (size_t)F * p.KP;
+  z.wt = sizeof(float) * (size_t)p.KP * p.ldt;
   z.pcol = sizeof(double) * (size_t)p.uw_blocks * 2 * p.KP;
-  z.kvec = sizeof(float) * p.KP;
   z.pnumh = sizeof(float) * (size_t)p.f_groups * N * p.KP;
   return layout(z, p);
 }
 
-// Workspace size that covers every call with F <= maxF, N <= maxN, K <= maxK
-// under the current launch settings: each region at its largest over all shapes.
+// Workspace size covering every call with F <= maxF, N <= maxN, K <= maxK under
+// the current launch settings.  choose_groups keeps blocks * groups <= 4 * slots
+// + blocks, so a partial array holds at most (4 * slots + blocks) * 128 rows
+// (or columns), and never more than tiles * extent.
 size_t plan_bound(const nmf_ctx_s* c, int64_t maxF, int64_t maxN, int64_t maxK) {
   const int64_t KP = 32 * kblocks_for(maxK);
-  const int64_t target = target_of(c);
-  const int64_t ntmax = cdiv(maxN, kTile), ftmax = cdiv(maxF, kTile);
+  const int64_t slots = 2 * (int64_t)c->num_cus;
+  const int64_t cap_blocks = 4 * slots;
+  auto rows_bound = [&](int64_t extent, int64_t other) {
+    const int64_t tiles = cdiv(other, kTile);
+    const int64_t a = (cap_blocks + cdiv(extent, kBlockRows)) * kBlockRows;
+    return std::min<int64_t>(a, tiles * extent);
+  };
   Sizes z{};
-  for (int64_t rb = 1; rb <= cdiv(maxF, kRowsPerBlock); ++rb) {
-    const int64_t groups = std::min<int64_t>(ntmax, std::max<int64_t>(1, cdiv(target, rb)));
-    const int64_t F = std::min<int64_t>(maxF, rb * kRowsPerBlock);
-    z.pobj = std::max(z.pobj, sizeof(double) * (size_t)(rb * groups));
-    z.pnum = std::max(z.pnum, sizeof(float) * (size_t)(groups * F * KP));
-    z.prs = std::max(z.prs, sizeof(float) * (size_t)(groups * KP));
-  }
-  for (int64_t cb = 1; cb <= cdiv(maxN, kRowsPerBlock); ++cb) {
-    const int64_t groups = std::min<int64_t>(ftmax, std::max<int64_t>(1, cdiv(target, cb)));
-    const int64_t N = std::min<int64_t>(maxN, cb * kRowsPerBlock);
-    z.pnumh = std::max(z.pnumh, sizeof(float) * (size_t)(groups * N * KP));
-  }
-  z.wn = sizeof(float) * (size_t)(maxF * KP);
+  z.pobj = sizeof(double) * (size_t)(cap_blocks + cdiv(maxF, kBlockRows));
+  z.pnum = sizeof(float) * (size_t)(rows_bound(maxF, maxN) * KP);
+  z.prs = sizeof(float) * (size_t)((cap_blocks + 1) * KP);
+  z.fk = sizeof(float) * (size_t)(maxF * KP);
+  z.wt = sizeof(float) * (size_t)(KP * cdiv(maxF, 4) * 4);
   z.pcol = sizeof(double) * (size_t)(kUpdateWBlocks * 2 * KP);
-  z.kvec = sizeof(float) * KP;
+  z.pnumh = sizeof(float) * (size_t)(rows_bound(maxN, maxF) * KP);
   return layout(z, Plan{}).total;
 }
 
@@ -215,7 +228,6 @@ nmf_status ensure_ws(nmf_ctx_s* c, hipStream_t s, size_t bytes) {
 }
 
 unsigned* flags_ptr(nmf_ctx_s* c) { return (unsigned*)c->ws; }
-unsigned* counter_ptr(nmf_ctx_s* c) { return (unsigned*)(c->ws + 4); }
 
 hipEvent_t get_event(nmf_ctx_s* c) {
   if (!c->event_pool.empty()) {
@@ -330,19 +342,17 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   nmf_default_opts(&o);
   if (opts) o = *opts;
   hipStream_t s = (hipStream_t)stream;
-  const Plan p = make_plan(c, F, N, K);
+  const int bc = beta_class(beta);
+  const bool joint = (mode == NMF_JOINT);
+  const Plan p = make_plan(c, F, N, K, sweep_cols_occupancy(bc, kblocks_for(K), KIND_UPDATE, joint));
   if ((st = ensure_ws(c, s, p.total)) != NMF_OK) return st;
   if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
 
-  const int bc = beta_class(beta);
-  const bool joint = (mode == NMF_JOINT);
   const bool beta_one = (bc == BC_B1);
   char* ws = c->ws;
   float* Wn = (float*)(ws + p.o_wn);
   float* C1 = (float*)(ws + p.o_c1);
   float* C2 = (float*)(ws + p.o_c2);
-  float* norms = (float*)(ws + p.o_norms);
-  float* csum = (float*)(ws + p.o_csum);
 
   SweepRowsArgs ra{};
   ra.V = V; ra.ldv = ldv; ra.W = W; ra.ldw = ldw; ra.H = H; ra.ldh = ldh;
@@ -352,6 +362,7 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   ra.pnum = (float*)(ws + p.o_pnum); ra.pden = (float*)(ws + p.o_pden); ra.prs = (float*)(ws + p.o_prs);
   ra.pobj = (double*)(ws + p.o_pobj);
   ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
+  ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
   const int sw_grid = p.row_blocks * p.n_groups;
   hipError_t e = timed(c, NMF_KERNEL_SWEEP_W, s, [&] {
     return launch_sweep_rows(bc, p.KB, KIND_UPDATE, d_objective != nullptr, sw_grid, s, ra);
@@ -363,16 +374,17 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   ua.F = (int)F; ua.K = (int)K; ua.n_groups = p.n_groups;
   ua.beta = beta; ua.gamma = gamma_of(beta); ua.joint = joint; ua.beta_one = beta_one;
   ua.Wn = Wn; ua.C1 = C1; ua.C2 = C2; ua.pcol = (double*)(ws + p.o_pcol);
-  ua.counter = counter_ptr(c); ua.norms = norms; ua.csum = csum;
-  ua.pobj = ra.pobj; ua.nobj = sw_grid; ua.d_obj = d_objective; ua.flags = flags_ptr(c);
+  ua.WT = (float*)(ws + p.o_wt); ua.ldt = p.ldt;
+  ua.flags = flags_ptr(c);
   e = timed(c, NMF_KERNEL_UPDATE_W, s, [&] { return launch_update_w(p.KB, p.uw_blocks, s, ua); });
   if (e != hipSuccess) return NMF_ERR_HIP;
 
   SweepColsArgs ca{};
   ca.V = V; ca.ldv = ldv;
-  if (joint) { ca.WL = W; ca.ldwl = ldw; ca.C1 = C1; ca.C2 = C2; }
-  else { ca.WL = Wn; ca.ldwl = p.KP; ca.C1 = Wn; ca.C2 = Wn; }
-  ca.ldc = p.KP; ca.H = H; ca.ldh = ldh;
+  ca.WT = ua.WT; ca.ldwt = p.ldt;
+  if (joint) { ca.C1 = C1; ca.C2 = C2; }
+  else { ca.C1 = Wn; ca.C2 = Wn; }
+  ca.H = H; ca.ldh = ldh;
   ca.F = (int)F; ca.N = (int)N; ca.K = (int)K;
   ca.bm2 = (float)(beta - 2.0); ca.kappa = o.kappa;
   ca.f_groups = p.f_groups; ca.tiles_per_group = p.tiles_f;
@@ -382,10 +394,12 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   if (e != hipSuccess) return NMF_ERR_HIP;
 
   UpdateHArgs ha{};
-  ha.H = H; ha.ldh = ldh; ha.pnum = ca.pnum; ha.pden = ca.pden; ha.csum = csum;
+  ha.H = H; ha.ldh = ldh; ha.pnum = ca.pnum; ha.pden = ca.pden;
   ha.F = (int)F; ha.N = (int)N; ha.K = (int)K; ha.f_groups = p.f_groups;
   ha.gamma = gamma_of(beta); ha.beta_one = beta_one; ha.normalize = o.normalize;
-  ha.norms = norms; ha.Wn = Wn; ha.W = W; ha.ldw = ldw; ha.flags = flags_ptr(c);
+  ha.pcol = ua.pcol; ha.pcol_blocks = p.uw_blocks;
+  ha.pobj = ra.pobj; ha.nobj = sw_grid; ha.d_obj = d_objective;
+  ha.Wn = Wn; ha.W = W; ha.ldw = ldw; ha.flags = flags_ptr(c);
   e = timed(c, NMF_KERNEL_UPDATE_H, s, [&] { return launch_update_h(p.KB, p.uh_blocks, s, ha); });
   return hip_status(e);
 }
@@ -408,6 +422,7 @@ nmf_status nmf_beta_objective(nmf_ctx_t c, void* stream, int64_t F, int64_t N, i
   ra.n_groups = p.n_groups; ra.tiles_per_group = p.tiles_n;
   ra.pobj = (double*)(c->ws + p.o_pobj);
   ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
+  ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
   const int grid = p.row_blocks * p.n_groups;
   hipError_t e = launch_sweep_rows(beta_class(beta), p.KB, KIND_OBJ, true, grid, s, ra);
   if (e != hipSuccess) return NMF_ERR_HIP;
@@ -444,11 +459,15 @@ nmf_status nmf_beta_grad(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   ra.n_groups = p.n_groups; ra.tiles_per_group = p.tiles_n;
   ra.pnum = (float*)(ws + p.o_pnum); ra.pobj = (double*)(ws + p.o_pobj);
   ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
+  ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
   const int sw_grid = p.row_blocks * p.n_groups;
   hipError_t e = launch_sweep_rows(bc, p.KB, KIND_GRAD, d_objective != nullptr, sw_grid, s, ra);
   if (e != hipSuccess) return NMF_ERR_HIP;
+  float* WT = (float*)(ws + p.o_wt);
+  float* Wp = (float*)(ws + p.o_wn);
+  if ((e = launch_transpose(s, W, ldw, (int)F, (int)K, p.KP, WT, p.ldt, Wp)) != hipSuccess) return NMF_ERR_HIP;
   SweepColsArgs ca{};
-  ca.V = V; ca.ldv = ldv; ca.WL = W; ca.ldwl = ldw; ca.C1 = W; ca.C2 = W; ca.ldc = ldw;
+  ca.V = V; ca.ldv = ldv; ca.WT = WT; ca.ldwt = p.ldt; ca.C1 = Wp; ca.C2 = Wp;
   ca.H = H; ca.ldh = ldh; ca.F = (int)F; ca.N = (int)N; ca.K = (int)K;
   ca.bm2 = (float)(beta - 2.0); ca.kappa = kappa;
   ca.f_groups = p.f_groups; ca.tiles_per_group = p.tiles_f;

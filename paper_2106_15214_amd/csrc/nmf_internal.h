@@ -20,7 +20,15 @@ enum Kind {
 constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
 constexpr int kWaves = 4;
 constexpr int kTile = 32;        // tile edge handled by one wave per step
-constexpr int kRowsPerBlock = kWaves * kTile;  // 128
+constexpr int kBlockRows = kWaves * kTile;  // rows (or columns) owned by one workgroup
+
+// Workgroups per compute unit the sweeps are compiled for (register budget):
+// the column pass with separate chi_1 / chi_2 tiles and all K > 64 variants
+// need the whole register file of a SIMD.
+constexpr int sweep_rows_occupancy(int KB) { return KB >= 4 ? 1 : 2; }
+constexpr int sweep_cols_occupancy(int bc, int KB, int kind, bool dual) {
+  return (KB >= 4 || (dual && kind == KIND_UPDATE && bc != BC_B1)) ? 1 : 2;
+}
 
 inline int beta_class(double beta) {
   if (beta == 2.0) return BC_B2;
@@ -45,21 +53,22 @@ struct SweepRowsArgs {
   int F, N, K;
   float bm2, kappa;                // beta - 2, smoothing constant
   double beta;
-  int n_groups, tiles_per_group;   // grid = row_blocks * n_groups
+  int n_groups, tiles_per_group;   // grid = row_blocks (128 rows) * n_groups
   float* pnum; float* pden;        // [n_groups][F][KP] partial W contractions
   float* prs;                      // [n_groups][KP] partial row sums of H (beta = 1)
   double* pobj;                    // [grid] objective partials (nullable)
   int vec4;                        // V rows 16-byte aligned
+  int hvec;                        // H rows 16-byte aligned
 };
 
 struct SweepColsArgs {
   const float* V; int64_t ldv;
-  const float* WL; int64_t ldwl;   // factor used to form Lambda (W~ joint, W_new alternating)
+  const float* WT; int64_t ldwt;   // transposed factor forming Lambda (K x F): W~ joint, W_new alternating
   const float* H; int64_t ldh;     // tilde H (columns owned by each wave)
-  const float* C1; const float* C2; int64_t ldc;  // contraction operands (chi_1, chi_2)
+  const float* C1; const float* C2;  // contraction operands (chi_1, chi_2): F x KP, ld KP, zero-padded
   int F, N, K;
   float bm2, kappa;
-  int f_groups, tiles_per_group;   // grid = col_blocks * f_groups
+  int f_groups, tiles_per_group;   // grid = col_blocks (128 columns) * f_groups
   float* pnum; float* pden;        // [f_groups][N][KP] partial H contractions
 };
 
@@ -70,20 +79,20 @@ struct UpdateWArgs {
   double beta, gamma;
   int joint, beta_one;
   float* Wn; float* C1; float* C2; // [F][KP]
+  float* WT; int64_t ldt;          // [KP][ldt]: W~^T (joint) or W_new^T (alternating)
   double* pcol;                    // [grid][2][KP] column norm^2 and sum partials
-  unsigned* counter;
-  float* norms; float* csum;       // [KP]
-  const double* pobj; int nobj; double* d_obj;
   unsigned* flags;
 };
 
 struct UpdateHArgs {
   float* H; int64_t ldh;
-  const float* pnum; const float* pden; const float* csum;
+  const float* pnum; const float* pden;
   int F, N, K, f_groups;
   double gamma;
   int beta_one, normalize;
-  const float* norms; const float* Wn; float* W; int64_t ldw;
+  const double* pcol; int pcol_blocks;   // update_w's column partials
+  const double* pobj; int nobj; double* d_obj;  // objective partials of the W pass
+  const float* Wn; float* W; int64_t ldw;
   unsigned* flags;
 };
 
@@ -97,6 +106,8 @@ hipError_t launch_grad_w(int kb, int grid, hipStream_t s, const float* pnum, int
                          double scale, float* dW, int64_t lddw);
 hipError_t launch_grad_h(int kb, int grid, hipStream_t s, const float* pnum, int N, int K, int f_groups,
                          double scale, float* dH, int64_t lddh);
+hipError_t launch_transpose(hipStream_t s, const float* W, int64_t ldw, int F, int K, int KP, float* WT,
+                            int64_t ldt, float* Wp);
 hipError_t launch_validate(hipStream_t s, const float* V, int64_t ldv, const float* W, int64_t ldw,
                            const float* H, int64_t ldh, int F, int N, int K, int zero_bad, unsigned* flags);
 

@@ -53,6 +53,13 @@ __device__ __forceinline__ void beta_terms(float v, float lam, float bm2, float&
   Q = lam * e;
 }
 
+// General-beta term of eq. (beta-div) (kept out of line: three float64 pows).
+__device__ __noinline__ double d_beta_general(double v, double l, double beta) {
+  if (v > 0.0)
+    return pow(v, beta) / (beta * (beta - 1.0)) + pow(l, beta) / beta - v * pow(l, beta - 1.0) / (beta - 1.0);
+  return beta > 0.0 ? pow(l, beta) / beta : __builtin_inf();
+}
+
 // d_beta(v | l) in float64 (v, l include kappa), paper eq. (beta-div);
 // v = 0 takes the limit of the expression.
 template <int BC>
@@ -62,9 +69,7 @@ __device__ __forceinline__ double d_beta(double v, double l, double beta) {
   if (BC == BC_B0) { double r = v / l; return r - log(r) - 1.0; }
   if (BC == BC_B05) { double sy = sqrt(l); return -4.0 * sqrt(v) + 2.0 * sy + 2.0 * v / sy; }
   if (BC == BC_B15) { double sy = sqrt(l); return v * sqrt(v) / 0.75 + l * sy / 1.5 - 2.0 * v * sy; }
-  if (v > 0.0)
-    return pow(v, beta) / (beta * (beta - 1.0)) + pow(l, beta) / beta - v * pow(l, beta - 1.0) / (beta - 1.0);
-  return beta > 0.0 ? pow(l, beta) / beta : __builtin_inf();
+  return d_beta_general(v, l, beta);
 }
 
 __device__ __forceinline__ double wave_sum(double x) {
@@ -87,26 +92,32 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
 }
 
 // ---------------------------------------------------------------------------
-// sweep_rows: W-step contractions (reduction over n), optional objective
+// sweep_rows: W-step contractions (reduction over n), optional objective.
+// A workgroup's four waves own four consecutive 32-row slabs of V and walk the
+// same 32-column tiles in lockstep.  The H~ tile (KP x 32) is staged in LDS by
+// the whole workgroup, double-buffered; each wave prefetches its next V tile
+// into registers while the matrix cores work on the current one.
 // ---------------------------------------------------------------------------
-constexpr int kHsStride = 36;  // LDS row stride of the H~ tile; float4 reads conflict-free
+constexpr int kHS = 36;  // LDS row stride of [k][32] tiles: float4 and dword reads conflict-free
 
 template <int BC, int KB, int KIND, bool OBJ>
-__global__ __launch_bounds__(kBlock) void sweep_rows_kernel(SweepRowsArgs a) {
+__global__ __launch_bounds__(kBlock, sweep_rows_occupancy(KB)) void sweep_rows_kernel(SweepRowsArgs a) {
   constexpr int KP = 32 * KB;
   constexpr int K2MAX = KP / 2;
   constexpr bool CONTRACT = (KIND != KIND_OBJ);
   constexpr bool NEED_DEN = (KIND == KIND_UPDATE) && (BC != BC_B1);
   constexpr bool ROWSUM = (KIND == KIND_UPDATE) && (BC == BC_B1);
-  __shared__ __align__(16) float Hs[KP * kHsStride];
-  __shared__ double red[kWaves];
+  __shared__ __align__(16) float Hs[2][KP * kHS];
+  __shared__ double dred[kWaves];
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 31, hi = lane >> 5;
-  const int rb = blockIdx.x / a.n_groups, gj = blockIdx.x % a.n_groups;
-  const int f0 = rb * kRowsPerBlock + wave * kTile;
+  const int rb = blockIdx.x / a.n_groups, g = blockIdx.x % a.n_groups;
+  const int f0 = rb * (kWaves * kTile) + wave * kTile;
   const int frow = f0 + li;
   const bool frow_ok = frow < a.F;
+  const bool wave_on = f0 < a.F;
   const int K = a.K, N = a.N;
   const int K2 = (K + 1) >> 1;
 
@@ -123,40 +134,39 @@ __global__ __launch_bounds__(kBlock) void sweep_rows_kernel(SweepRowsArgs a) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) { accN[kb][r] = 0.f; accD[kb][r] = 0.f; }
   }
-  float rsum = 0.f;
+  float rsum[KB];
+#pragma unroll
+  for (int j = 0; j < KB; ++j) rsum[j] = 0.f;
   double objsum = 0.0;
 
-  const int nt_total = (N + kTile - 1) / kTile;
-  const int t_begin = gj * a.tiles_per_group;
-  const int t_end = min(nt_total, t_begin + a.tiles_per_group);
+  // cooperative staging of the H~ tile: thread float4 j covers row (tid + 256 j) / 8,
+  // columns 4 * ((tid + 256 j) % 8) .. + 3
+  auto load_h = [&](int n0, float4 (&r)[KB]) {
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int e4 = tid + kBlock * j;
+      const int k = e4 >> 3, n = n0 + 4 * (e4 & 7);
+      const float* src = a.H + (int64_t)k * a.ldh + n;
+      if (k < K && a.hvec && n + 3 < N) {
+        r[j] = *reinterpret_cast<const float4*>(src);
+      } else {
+        r[j].x = (k < K && n + 0 < N) ? src[0] : 0.f;
+        r[j].y = (k < K && n + 1 < N) ? src[1] : 0.f;
+        r[j].z = (k < K && n + 2 < N) ? src[2] : 0.f;
+        r[j].w = (k < K && n + 3 < N) ? src[3] : 0.f;
+      }
+    }
+  };
+  auto store_h = [&](float* buf, const float4 (&r)[KB]) {
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int e4 = tid + kBlock * j;
+      *reinterpret_cast<float4*>(&buf[(e4 >> 3) * kHS + 4 * (e4 & 7)]) = r[j];
+    }
+  };
   const float* vrow = a.V + (int64_t)frow * a.ldv;
-
-  for (int t = t_begin; t < t_end; ++t) {
-    const int n0 = t * kTile;
-    // stage H~[0:KP, n0:n0+32] (zero outside K x N)
-    for (int e = threadIdx.x; e < KP * kTile; e += kBlock) {
-      const int k = e >> 5, c = e & 31;
-      float h = 0.f;
-      if (k < K && n0 + c < N) h = a.H[(int64_t)k * a.ldh + n0 + c];
-      Hs[k * kHsStride + c] = h;
-    }
-    __syncthreads();
-    if (ROWSUM && rb == 0 && threadIdx.x < KP) {
-      float s = 0.f;
-      for (int c = 0; c < kTile; ++c) s += Hs[threadIdx.x * kHsStride + c];
-      rsum += s;
-    }
-
-    // Lambda^T tile: lam[r] = Lambda[frow][n0 + acc_row(r, hi)]
-    f32x16 lam;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) lam[r] = 0.f;
-#pragma unroll
-    for (int s = 0; s < K2MAX; ++s)
-      if (s < K2) lam = mfma32(Hs[(2 * s + hi) * kHsStride + li], wB[s], lam);
-
-    // V at the same positions: registers 4q..4q+3 are columns n0 + 8q + 4hi + 0..3
-    float v[16];
+  // V at the accumulator positions: registers 4q..4q+3 are columns n0 + 8q + 4hi + 0..3
+  auto load_v = [&](int n0, float (&v)[16]) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int nb = n0 + 8 * q + 4 * hi;
@@ -168,87 +178,145 @@ __global__ __launch_bounds__(kBlock) void sweep_rows_kernel(SweepRowsArgs a) {
         for (int j = 0; j < 4; ++j) v[4 * q + j] = (frow_ok && nb + j < N) ? vrow[nb + j] : 0.f;
       }
     }
+  };
 
-    float P[16], Q[16];
+  const int nt_total = (N + kTile - 1) / kTile;
+  const int t0 = g * a.tiles_per_group;
+  const int t1 = min(nt_total, t0 + a.tiles_per_group);
+  float4 hreg[KB];
+  float vcur[16], vnext[16];
+  if (t0 < t1) {
+    load_h(t0 * kTile, hreg);
+    if (ROWSUM)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int n = n0 + acc_row(r, hi);
-      const bool ok = frow_ok && n < N;
-      const float lk = lam[r] + a.kappa;
-      const float vk = v[r] + a.kappa;
-      if (KIND == KIND_UPDATE) {
-        beta_terms<BC>(vk, lk, a.bm2, P[r], Q[r]);
-        if (!ok) { P[r] = 0.f; Q[r] = 0.f; }
-      } else if (KIND == KIND_GRAD) {
-        P[r] = ok ? pow_bm2<BC>(lk, a.bm2) * (lam[r] - v[r]) : 0.f;
-      }
-      if (OBJ && ok) objsum += d_beta<BC>((double)vk, (double)lk, a.beta);
+      for (int j = 0; j < KB; ++j) rsum[j] += (hreg[j].x + hreg[j].y) + (hreg[j].z + hreg[j].w);
+    if (wave_on) load_v(t0 * kTile, vcur);
+    store_h(Hs[0], hreg);
+  }
+  __syncthreads();
+
+  for (int t = t0; t < t1; ++t) {
+    const float* hs = Hs[(t - t0) & 1];
+    const bool more = t + 1 < t1;
+    if (more) {
+      load_h((t + 1) * kTile, hreg);
+      if (wave_on) load_v((t + 1) * kTile, vnext);
     }
+    if (wave_on) {
+      const int n0 = t * kTile;
+      // Lambda^T tile: lam[r] = Lambda[frow][n0 + acc_row(r, hi)]; A operand H~[2s+hi][n0+li]
+      f32x16 lam;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) lam[r] = 0.f;
+#pragma unroll
+      for (int s = 0; s < K2MAX; ++s)
+        if (s < K2) lam = mfma32(hs[(2 * s + hi) * kHS + li], wB[s], lam);
 
-    if (CONTRACT) {
+      float P[16], Q[16];
 #pragma unroll
-      for (int kb = 0; kb < KB; ++kb) {
+      for (int r = 0; r < 16; ++r) {
+        const int n = n0 + acc_row(r, hi);
+        const bool ok = frow_ok && n < N;
+        const float lk = lam[r] + a.kappa;
+        const float vk = vcur[r] + a.kappa;
+        if (KIND == KIND_UPDATE) {
+          beta_terms<BC>(vk, lk, a.bm2, P[r], Q[r]);
+          if (!ok) { P[r] = 0.f; Q[r] = 0.f; }
+        } else if (KIND == KIND_GRAD) {
+          P[r] = ok ? pow_bm2<BC>(lk, a.bm2) * (lam[r] - vcur[r]) : 0.f;
+        }
+        if (OBJ && ok) objsum += d_beta<BC>((double)vk, (double)lk, a.beta);
+      }
+      if (CONTRACT) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          // B operand: H~[kb*32 + li][n0 + 8q + 4hi + j]
-          const float4 b = *reinterpret_cast<const float4*>(&Hs[(kb * 32 + li) * kHsStride + 8 * q + 4 * hi]);
-          accN[kb] = mfma32(P[4 * q + 0], b.x, accN[kb]);
-          accN[kb] = mfma32(P[4 * q + 1], b.y, accN[kb]);
-          accN[kb] = mfma32(P[4 * q + 2], b.z, accN[kb]);
-          accN[kb] = mfma32(P[4 * q + 3], b.w, accN[kb]);
-          if (NEED_DEN) {
-            accD[kb] = mfma32(Q[4 * q + 0], b.x, accD[kb]);
-            accD[kb] = mfma32(Q[4 * q + 1], b.y, accD[kb]);
-            accD[kb] = mfma32(Q[4 * q + 2], b.z, accD[kb]);
-            accD[kb] = mfma32(Q[4 * q + 3], b.w, accD[kb]);
+        for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            // B operand: H~[kb*32 + li][n0 + 8q + 4hi + j]
+            const float4 b = *reinterpret_cast<const float4*>(&hs[(kb * 32 + li) * kHS + 8 * q + 4 * hi]);
+            accN[kb] = mfma32(P[4 * q + 0], b.x, accN[kb]);
+            accN[kb] = mfma32(P[4 * q + 1], b.y, accN[kb]);
+            accN[kb] = mfma32(P[4 * q + 2], b.z, accN[kb]);
+            accN[kb] = mfma32(P[4 * q + 3], b.w, accN[kb]);
+            if (NEED_DEN) {
+              accD[kb] = mfma32(Q[4 * q + 0], b.x, accD[kb]);
+              accD[kb] = mfma32(Q[4 * q + 1], b.y, accD[kb]);
+              accD[kb] = mfma32(Q[4 * q + 2], b.z, accD[kb]);
+              accD[kb] = mfma32(Q[4 * q + 3], b.w, accD[kb]);
+            }
           }
         }
       }
     }
+    if (more) {
+      store_h(Hs[(t - t0 + 1) & 1], hreg);
+      if (ROWSUM)
+#pragma unroll
+        for (int j = 0; j < KB; ++j) rsum[j] += (hreg[j].x + hreg[j].y) + (hreg[j].z + hreg[j].w);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) vcur[i] = vnext[i];
+    }
     __syncthreads();
   }
 
-  if (CONTRACT) {
-    // accumulator (i = row offset f, j = li = column k)
+  if (CONTRACT && wave_on) {
+    // accumulator (i = row offset f, j = li = column k); each wave owns its rows
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int f = f0 + acc_row(r, hi);
         if (f < a.F) {
-          const int64_t o = ((int64_t)gj * a.F + f) * KP + kb * 32 + li;
+          const int64_t o = ((int64_t)g * a.F + f) * KP + kb * 32 + li;
           a.pnum[o] = accN[kb][r];
           if (NEED_DEN) a.pden[o] = accD[kb][r];
         }
       }
     }
   }
-  if (ROWSUM && rb == 0 && threadIdx.x < KP) a.prs[gj * KP + threadIdx.x] = rsum;
+  if (ROWSUM) {
+    // the eight threads sharing a row of the staged tile hold its column sums
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      float x = rsum[j];
+      x += __shfl_xor(x, 1, 64);
+      x += __shfl_xor(x, 2, 64);
+      x += __shfl_xor(x, 4, 64);
+      const int e4 = tid + kBlock * j;
+      if (rb == 0 && (e4 & 7) == 0) a.prs[g * KP + (e4 >> 3)] = x;
+    }
+  }
   if (OBJ) {
-    const double s = block_sum(objsum, red);
-    if (threadIdx.x == 0) a.pobj[blockIdx.x] = s;
+    const double sum = block_sum(objsum, dred);
+    if (tid == 0) a.pobj[blockIdx.x] = sum;
   }
 }
 
 // ---------------------------------------------------------------------------
-// sweep_cols: H-step contractions (reduction over f)
+// sweep_cols: H-step contractions (reduction over f).  The four waves own four
+// 32-column slabs and walk the same 32-row tiles in lockstep.  Per tile the
+// workgroup stages, double-buffered in LDS: the transposed factor forming
+// Lambda (KP x 32, from WT), chi_1 and chi_2 (32 x KP, row-major with ld KP).
 // ---------------------------------------------------------------------------
 template <int BC, int KB, int KIND, bool DUAL>
-__global__ __launch_bounds__(kBlock) void sweep_cols_kernel(SweepColsArgs a) {
+__global__ __launch_bounds__(kBlock, sweep_cols_occupancy(BC, KB, KIND, DUAL)) void sweep_cols_kernel(SweepColsArgs a) {
   constexpr int KP = 32 * KB;
-  constexpr int WS = KP + 1;  // LDS row stride: A-operand reads conflict-free
   constexpr int K2MAX = KP / 2;
+  constexpr int CS = KP + 4;  // LDS row stride of [f][KP] tiles
   constexpr bool NEED_DEN = (KIND == KIND_UPDATE) && (BC != BC_B1);
-  __shared__ float Ws[kTile * WS];
-  __shared__ float C1s[DUAL ? kTile * WS : 1];
-  __shared__ float C2s[(DUAL && NEED_DEN) ? kTile * WS : 1];
+  constexpr bool C2_TILE = DUAL && NEED_DEN;
+  __shared__ __align__(16) float Ws[2][KP * kHS];
+  __shared__ __align__(16) float C1s[2][kTile * CS];
+  __shared__ __align__(16) float C2s[C2_TILE ? 2 : 1][C2_TILE ? kTile * CS : 4];
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 31, hi = lane >> 5;
-  const int cb = blockIdx.x / a.f_groups, gi = blockIdx.x % a.f_groups;
-  const int n0w = cb * kRowsPerBlock + wave * kTile;
+  const int cb = blockIdx.x / a.f_groups, g = blockIdx.x % a.f_groups;
+  const int n0w = cb * (kWaves * kTile) + wave * kTile;
   const int ncol = n0w + li;
   const bool ncol_ok = ncol < a.N;
+  const bool wave_on = n0w < a.N;
   const int K = a.K, F = a.F;
   const int K2 = (K + 1) >> 1;
 
@@ -266,177 +334,269 @@ __global__ __launch_bounds__(kBlock) void sweep_cols_kernel(SweepColsArgs a) {
     for (int r = 0; r < 16; ++r) { accN[kb][r] = 0.f; accD[kb][r] = 0.f; }
   }
 
-  const int ft_total = (F + kTile - 1) / kTile;
-  const int t_begin = gi * a.tiles_per_group;
-  const int t_end = min(ft_total, t_begin + a.tiles_per_group);
-  const float* c1src = DUAL ? C1s : Ws;
-  const float* c2src = DUAL ? C2s : Ws;
-
-  for (int t = t_begin; t < t_end; ++t) {
-    const int f0 = t * kTile;
-    for (int e = threadIdx.x; e < kTile * KP; e += kBlock) {
-      const int i = e / KP, k = e % KP;
-      const bool ok = (f0 + i < F) && (k < K);
-      Ws[i * WS + k] = ok ? a.WL[(int64_t)(f0 + i) * a.ldwl + k] : 0.f;
-      if (DUAL) {
-        C1s[i * WS + k] = ok ? a.C1[(int64_t)(f0 + i) * a.ldc + k] : 0.f;
-        if (NEED_DEN) C2s[i * WS + k] = ok ? a.C2[(int64_t)(f0 + i) * a.ldc + k] : 0.f;
+  // staging: WT tile thread float4 j -> row k = e4 / 8, columns f0 + 4 (e4 % 8);
+  //          chi tile thread float4 j -> row i = e4 / (KP/4), columns 4 (e4 % (KP/4))
+  float4 wreg[KB], c1reg[KB], c2reg[C2_TILE ? KB : 1];
+  auto load_tiles = [&](int f0) {
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int e4 = tid + kBlock * j;
+      const int k = e4 >> 3, f = f0 + 4 * (e4 & 7);
+      const float* src = a.WT + (int64_t)k * a.ldwt + f;
+      if (f + 3 < F) {
+        wreg[j] = *reinterpret_cast<const float4*>(src);
+      } else {
+        wreg[j].x = (f + 0 < F) ? src[0] : 0.f;
+        wreg[j].y = (f + 1 < F) ? src[1] : 0.f;
+        wreg[j].z = (f + 2 < F) ? src[2] : 0.f;
+        wreg[j].w = (f + 3 < F) ? src[3] : 0.f;
       }
+      const int i = e4 / (KP / 4), c = 4 * (e4 % (KP / 4));
+      const bool ok = f0 + i < F;
+      const int64_t o = (int64_t)(f0 + i) * KP + c;
+      c1reg[j] = ok ? *reinterpret_cast<const float4*>(a.C1 + o) : make_float4(0.f, 0.f, 0.f, 0.f);
+      if (C2_TILE) c2reg[j] = ok ? *reinterpret_cast<const float4*>(a.C2 + o) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    __syncthreads();
-
-    // Lambda tile: lam[r] = Lambda[f0 + acc_row(r, hi)][ncol]
-    f32x16 lam;
+  };
+  auto store_tiles = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) lam[r] = 0.f;
-#pragma unroll
-    for (int s = 0; s < K2MAX; ++s)
-      if (s < K2) lam = mfma32(Ws[li * WS + 2 * s + hi], hB[s], lam);
-
-    float P[16], Q[16];
+    for (int j = 0; j < KB; ++j) {
+      const int e4 = tid + kBlock * j;
+      *reinterpret_cast<float4*>(&Ws[buf][(e4 >> 3) * kHS + 4 * (e4 & 7)]) = wreg[j];
+      const int i = e4 / (KP / 4), c = 4 * (e4 % (KP / 4));
+      *reinterpret_cast<float4*>(&C1s[buf][i * CS + c]) = c1reg[j];
+      if (C2_TILE) *reinterpret_cast<float4*>(&C2s[buf][i * CS + c]) = c2reg[j];
+    }
+  };
+  // V at the accumulator positions: register r is row f0 + acc_row(r, hi), column ncol
+  auto load_v = [&](int f0, float (&v)[16]) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int f = f0 + acc_row(r, hi);
-      const bool ok = ncol_ok && f < F;
-      const float vv = ok ? a.V[(int64_t)f * a.ldv + ncol] : 0.f;
-      const float lk = lam[r] + a.kappa;
-      const float vk = vv + a.kappa;
-      if (KIND == KIND_UPDATE) {
-        beta_terms<BC>(vk, lk, a.bm2, P[r], Q[r]);
-        if (!ok) { P[r] = 0.f; Q[r] = 0.f; }
-      } else {
-        P[r] = ok ? pow_bm2<BC>(lk, a.bm2) * (lam[r] - vv) : 0.f;
-      }
+      v[r] = (ncol_ok && f < F) ? a.V[(int64_t)f * a.ldv + ncol] : 0.f;
     }
+  };
 
+  const int ft_total = (F + kTile - 1) / kTile;
+  const int t0 = g * a.tiles_per_group;
+  const int t1 = min(ft_total, t0 + a.tiles_per_group);
+  float vcur[16], vnext[16];
+  if (t0 < t1) {
+    load_tiles(t0 * kTile);
+    if (wave_on) load_v(t0 * kTile, vcur);
+    store_tiles(0);
+  }
+  __syncthreads();
+
+  for (int t = t0; t < t1; ++t) {
+    const int buf = (t - t0) & 1;
+    const bool more = t + 1 < t1;
+    if (more) {
+      load_tiles((t + 1) * kTile);
+      if (wave_on) load_v((t + 1) * kTile, vnext);
+    }
+    if (wave_on) {
+      const int f0 = t * kTile;
+      const float* ws = Ws[buf];
+      const float* c1s = C1s[buf];
+      const float* c2s = C2_TILE ? C2s[buf] : C1s[buf];
+      // Lambda tile: lam[r] = Lambda[f0 + acc_row(r, hi)][ncol]; A operand W[f0+li][2s+hi]
+      f32x16 lam;
 #pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
+      for (int r = 0; r < 16; ++r) lam[r] = 0.f;
+#pragma unroll
+      for (int s = 0; s < K2MAX; ++s)
+        if (s < K2) lam = mfma32(ws[(2 * s + hi) * kHS + li], hB[s], lam);
+
+      float P[16], Q[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int row = acc_row(r, hi) * WS + kb * 32 + li;
-        accN[kb] = mfma32(P[r], c1src[row], accN[kb]);
-        if (NEED_DEN) accD[kb] = mfma32(Q[r], c2src[row], accD[kb]);
+        const int f = f0 + acc_row(r, hi);
+        const bool ok = ncol_ok && f < F;
+        const float lk = lam[r] + a.kappa;
+        const float vk = vcur[r] + a.kappa;
+        if (KIND == KIND_UPDATE) {
+          beta_terms<BC>(vk, lk, a.bm2, P[r], Q[r]);
+          if (!ok) { P[r] = 0.f; Q[r] = 0.f; }
+        } else {
+          P[r] = ok ? pow_bm2<BC>(lk, a.bm2) * (lam[r] - vcur[r]) : 0.f;
+        }
       }
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = acc_row(r, hi) * CS + kb * 32 + li;
+          accN[kb] = mfma32(P[r], c1s[row], accN[kb]);
+          if (NEED_DEN) accD[kb] = mfma32(Q[r], c2s[row], accD[kb]);
+        }
+      }
+    }
+    if (more) {
+      store_tiles(buf ^ 1);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) vcur[i] = vnext[i];
     }
     __syncthreads();
   }
 
-  // accumulator (i = column offset n, j = li = k)
+  if (wave_on) {
+    // accumulator (i = column offset n, j = li = k); each wave owns its columns
 #pragma unroll
-  for (int kb = 0; kb < KB; ++kb) {
+    for (int kb = 0; kb < KB; ++kb) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int n = n0w + acc_row(r, hi);
-      if (n < a.N) {
-        const int64_t o = ((int64_t)gi * a.N + n) * KP + kb * 32 + li;
-        a.pnum[o] = accN[kb][r];
-        if (NEED_DEN) a.pden[o] = accD[kb][r];
+      for (int r = 0; r < 16; ++r) {
+        const int n = n0w + acc_row(r, hi);
+        if (n < a.N) {
+          const int64_t o = ((int64_t)g * a.N + n) * KP + kb * 32 + li;
+          a.pnum[o] = accN[kb][r];
+          if (NEED_DEN) a.pden[o] = accD[kb][r];
+        }
       }
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// update_w: W_new = W~ (num/den)^gamma, chi terms, column norms / sums,
-// objective finalization (last workgroup)
+// update_w: W_new = W~ (num/den)^gamma, chi terms, transposed copy of the factor
+// that forms Lambda in the H pass, per-block column norm / sum partials.
+// A block handles 32-row slabs (grid-stride).
 // ---------------------------------------------------------------------------
+__device__ __noinline__ double pow_out_of_line(double x, double y) { return pow(x, y); }
+
 __device__ __forceinline__ double pow_gamma(double x, double g) {
   if (g == 1.0) return x;
   if (g == 0.5) return sqrt(x);
-  return pow(x, g);
+  return pow_out_of_line(x, g);
 }
 
 __device__ __forceinline__ void set_flag(unsigned* flags, unsigned bit) {
   __hip_atomic_fetch_or(flags, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Returns true in every thread of the last workgroup to arrive at `counter`.
-__device__ __forceinline__ bool last_block(unsigned* counter) {
-  __shared__ int is_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (prev == gridDim.x - 1);
+// chi_1(W, W~) = W~^(2-b) / W^(1-b) = W~ r^(b-1) for b <= 2, else W;
+// chi_2(W, W~) = W for b < 1, else W^b / W~^(b-1) = W~ r^b   (r = W / W~)
+__device__ __forceinline__ void chi_terms(double beta, double wt, double r, double wnew, float& c1, float& c2) {
+  double x1, x2;
+  if (beta > 2.0) x1 = wnew;
+  else if (beta == 2.0) x1 = wnew;
+  else if (beta == 1.0) x1 = wt;
+  else if (beta == 0.0) x1 = wt / r;
+  else if (beta == 0.5) x1 = wt / sqrt(r);
+  else if (beta == 1.5) x1 = wt * sqrt(r);
+  else x1 = wt * pow_out_of_line(r, beta - 1.0);
+  if (beta <= 1.0) x2 = wnew;
+  else if (beta == 2.0) x2 = wnew * r;
+  else if (beta == 1.5) x2 = wnew * sqrt(r);
+  else x2 = wt * pow_out_of_line(r, beta);
+  c1 = (float)x1;
+  c2 = (float)x2;
+}
+
+// Sums `groups` partial arrays (stride `gstride` floats) at offsets base + tid + i*kBlock
+// (i < PER, entries below `limit`), four groups per round so that many loads
+// are in flight; fixed order, float64 accumulation rounded once to float.
+template <int PER>
+__device__ __forceinline__ void sum_partials(const float* __restrict__ pn, const float* __restrict__ pd, int groups,
+                                             int64_t gstride, int64_t base, int64_t limit, float (&num)[PER],
+                                             float (&den)[PER]) {
+  double sn[PER], sd[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) { sn[i] = 0.0; sd[i] = 0.0; }
+  const int tid = threadIdx.x;
+  int g = 0;
+  for (; g + 4 <= groups; g += 4) {
+    float xn[4][PER], xd[4][PER];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int64_t e = tid + i * kBlock;
+        const int64_t o = (int64_t)(g + u) * gstride + base + e;
+        xn[u][i] = e < limit ? pn[o] : 0.f;
+        xd[u][i] = (pd && e < limit) ? pd[o] : 0.f;
+      }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int i = 0; i < PER; ++i) { sn[i] += (double)xn[u][i]; sd[i] += (double)xd[u][i]; }
   }
-  __syncthreads();
-  const bool r = is_last != 0;
-  if (r) __threadfence();
-  return r;
+  for (; g < groups; ++g) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int64_t e = tid + i * kBlock;
+      const int64_t o = (int64_t)g * gstride + base + e;
+      sn[i] += e < limit ? (double)pn[o] : 0.0;
+      sd[i] += (pd && e < limit) ? (double)pd[o] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) { num[i] = (float)sn[i]; den[i] = (float)sd[i]; }
 }
 
 template <int KB>
 __global__ __launch_bounds__(kBlock) void update_w_kernel(UpdateWArgs a) {
   constexpr int KP = 32 * KB;
-  constexpr int RPS = kBlock / KP;  // rows per step
+  constexpr int PER = kTile * KP / kBlock;  // entries per thread per slab (4 KB)
+  __shared__ float T[KP * 33];
   __shared__ double sn[kBlock], sc[kBlock];
-  __shared__ double red[kWaves];
-  const int k = threadIdx.x % KP, rs = threadIdx.x / KP;
+  const int tid = threadIdx.x;
+  const int k = tid % KP;  // the same k for all of a thread's entries (kBlock % KP == 0)
   const bool kok = k < a.K;
   double den1 = 0.0;
   if (a.beta_one && kok)
     for (int g = 0; g < a.n_groups; ++g) den1 += (double)a.prs[g * KP + k];
 
   double nrm = 0.0, cs = 0.0;
-  for (int f = blockIdx.x * RPS + rs; f < a.F; f += gridDim.x * RPS) {
-    float wn = 0.f, c1 = 0.f, c2 = 0.f;
-    if (kok) {
-      double num = 0.0, den = 0.0;
-      for (int g = 0; g < a.n_groups; ++g) {
-        const int64_t o = ((int64_t)g * a.F + f) * KP + k;
-        num += (double)a.pnum[o];
-        if (!a.beta_one) den += (double)a.pden[o];
+  const int slabs = (a.F + kTile - 1) / kTile;
+  for (int sl = blockIdx.x; sl < slabs; sl += gridDim.x) {
+    const int f0 = sl * kTile;
+    float num[PER], den[PER];
+    sum_partials<PER>(a.pnum, a.beta_one ? nullptr : a.pden, a.n_groups, (int64_t)a.F * KP,
+                      (int64_t)f0 * KP, (int64_t)(min(a.F - f0, kTile)) * KP, num, den);
+#pragma unroll 1
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * kBlock;
+      const int fl = e / KP, f = f0 + fl;
+      float wn = 0.f, c1 = 0.f, c2 = 0.f, wtf = 0.f;
+      if (f < a.F && kok) {
+        const double dd = a.beta_one ? den1 : (double)den[i];
+        const double ratio = (double)num[i] / dd;
+        if (!(dd > 0.0) || !isfinite(ratio)) set_flag(a.flags, 1u);
+        const double r = pow_gamma(ratio, a.gamma);
+        wtf = a.W[(int64_t)f * a.ldw + k];
+        const double wt = (double)wtf;
+        const double wnew = wt * r;
+        wn = (float)wnew;
+        if (a.joint) chi_terms(a.beta, wt, r, wnew, c1, c2);
+        nrm += (double)wn * (double)wn;
+        cs += (double)wn;
       }
-      if (a.beta_one) den = den1;
-      const double ratio = num / den;
-      if (!(den > 0.0) || !isfinite(ratio)) set_flag(a.flags, 1u);
-      const double r = pow_gamma(ratio, a.gamma);
-      const double wt = (double)a.W[(int64_t)f * a.ldw + k];
-      const double wnew = wt * r;
-      wn = (float)wnew;
-      if (a.joint) {
-        // chi_1(W, W~) = W~^(2-b) / W^(1-b) = W~ r^(b-1)  (b <= 2), else W
-        // chi_2(W, W~) = W (b < 1), else W^b / W~^(b-1) = W~ r^b
-        c1 = (float)(a.beta <= 2.0 ? (a.beta == 1.0 ? wt : wt * pow(r, a.beta - 1.0)) : wnew);
-        c2 = (float)(a.beta < 1.0 ? wnew : (a.beta == 1.0 ? wnew : wt * pow(r, a.beta)));
+      if (f < a.F) {
+        const int64_t o = (int64_t)f * KP + k;
+        a.Wn[o] = wn;
+        if (a.joint) { a.C1[o] = c1; a.C2[o] = c2; }
       }
-      nrm += (double)wn * (double)wn;
-      cs += (double)wn;
+      T[k * 33 + fl] = a.joint ? wtf : wn;
     }
-    const int64_t o = (int64_t)f * KP + k;
-    a.Wn[o] = wn;
-    if (a.joint) { a.C1[o] = c1; a.C2[o] = c2; }
+    __syncthreads();
+    // transposed copy (KP x ldt) of the factor that forms Lambda in the H pass
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * kBlock;
+      const int kk = e / kTile, fl = e % kTile;
+      if (f0 + fl < a.F) a.WT[(int64_t)kk * a.ldt + f0 + fl] = T[kk * 33 + fl];
+    }
+    __syncthreads();
   }
-  sn[threadIdx.x] = nrm;
-  sc[threadIdx.x] = cs;
+  sn[tid] = nrm;
+  sc[tid] = cs;
   __syncthreads();
-  if (threadIdx.x < KP) {
+  if (tid < KP) {
     double x = 0.0, y = 0.0;
-    for (int j = 0; j < RPS; ++j) { x += sn[j * KP + threadIdx.x]; y += sc[j * KP + threadIdx.x]; }
-    a.pcol[(int64_t)blockIdx.x * 2 * KP + threadIdx.x] = x;
-    a.pcol[(int64_t)blockIdx.x * 2 * KP + KP + threadIdx.x] = y;
-  }
-  if (last_block(a.counter)) {
-    const double* pc = a.pcol;
-    if (threadIdx.x < KP) {
-      double x = 0.0, y = 0.0;
-      for (int b = 0; b < (int)gridDim.x; ++b) {
-        x += pc[(int64_t)b * 2 * KP + threadIdx.x];
-        y += pc[(int64_t)b * 2 * KP + KP + threadIdx.x];
-      }
-      a.norms[threadIdx.x] = (float)sqrt(x);
-      a.csum[threadIdx.x] = (float)y;
-    }
-    if (a.d_obj) {
-      double s = 0.0;
-      for (int i = threadIdx.x; i < a.nobj; i += kBlock) s += a.pobj[i];
-      s = block_sum(s, red);
-      if (threadIdx.x == 0) {
-        *a.d_obj = s;
-        if (!isfinite(s)) set_flag(a.flags, 1u);
-      }
-    }
-    if (threadIdx.x == 0) *a.counter = 0u;
+    for (int j = 0; j < kBlock / KP; ++j) { x += sn[j * KP + tid]; y += sc[j * KP + tid]; }
+    a.pcol[(int64_t)blockIdx.x * 2 * KP + tid] = x;
+    a.pcol[(int64_t)blockIdx.x * 2 * KP + KP + tid] = y;
   }
 }
 
@@ -446,49 +606,107 @@ __global__ __launch_bounds__(kBlock) void update_w_kernel(UpdateWArgs a) {
 template <int KB>
 __global__ __launch_bounds__(kBlock) void update_h_kernel(UpdateHArgs a) {
   constexpr int KP = 32 * KB;
+  constexpr int PER = kTile * KP / kBlock;
   __shared__ double S[KP * 33];
+  __shared__ double cn[kBlock], cc[kBlock];
+  __shared__ float norm_s[KP], csum_s[KP];
+  __shared__ double red[kWaves];
+  const int tid = threadIdx.x;
+  const int k = tid % KP;
   const int n0 = blockIdx.x * kTile;
+  // column norms and sums of W_new from update_w's per-block partials (fixed order)
+  {
+    constexpr int R = kBlock / KP;
+    const int part = tid / KP;
+    double x = 0.0, y = 0.0;
+    for (int b = part; b < a.pcol_blocks; b += R) {
+      x += a.pcol[(int64_t)b * 2 * KP + k];
+      y += a.pcol[(int64_t)b * 2 * KP + KP + k];
+    }
+    cn[tid] = x;
+    cc[tid] = y;
+    __syncthreads();
+    if (tid < KP) {
+      double xs = 0.0, ys = 0.0;
+      for (int j = 0; j < R; ++j) { xs += cn[j * KP + tid]; ys += cc[j * KP + tid]; }
+      norm_s[tid] = (float)sqrt(xs);
+      csum_s[tid] = (float)ys;
+    }
+    __syncthreads();
+  }
+  if (blockIdx.x == 0 && a.d_obj) {
+    double s = 0.0;
+    for (int i = tid; i < a.nobj; i += kBlock) s += a.pobj[i];
+    s = block_sum(s, red);
+    if (tid == 0) {
+      *a.d_obj = s;
+      if (!isfinite(s)) set_flag(a.flags, 1u);
+    }
+  }
   if (n0 < a.N) {
-    for (int e = threadIdx.x; e < kTile * KP; e += kBlock) {
-      const int nl = e / KP, k = e % KP, n = n0 + nl;
+    float num[PER], den[PER];
+    sum_partials<PER>(a.pnum, a.beta_one ? nullptr : a.pden, a.f_groups, (int64_t)a.N * KP, (int64_t)n0 * KP,
+                      (int64_t)(min(a.N - n0, kTile)) * KP, num, den);
+    double nk = 1.0;
+    if (a.normalize && k < a.K) {
+      const float x = norm_s[k];
+      if (x > 0.f) nk = (double)x;
+    }
+#pragma unroll 1
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * kBlock;
+      const int nl = e / KP, n = n0 + nl;
       double s = 0.0;
       if (n < a.N && k < a.K) {
-        double num = 0.0, den = 0.0;
-        for (int g = 0; g < a.f_groups; ++g) {
-          const int64_t o = ((int64_t)g * a.N + n) * KP + k;
-          num += (double)a.pnum[o];
-          if (!a.beta_one) den += (double)a.pden[o];
-        }
-        if (a.beta_one) den = (double)a.csum[k];
-        const double ratio = num / den;
-        if (!(den > 0.0) || !isfinite(ratio)) set_flag(a.flags, 1u);
-        s = pow_gamma(ratio, a.gamma);
-        if (a.normalize) {
-          const float nk = a.norms[k];
-          if (nk > 0.f) s *= (double)nk;
-        }
+        const double dd = a.beta_one ? (double)csum_s[k] : (double)den[i];
+        const double ratio = (double)num[i] / dd;
+        if (!(dd > 0.0) || !isfinite(ratio)) set_flag(a.flags, 1u);
+        s = pow_gamma(ratio, a.gamma) * nk;
       }
       S[k * 33 + nl] = s;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < KP * kTile; e += kBlock) {
-      const int k = e / kTile, nl = e % kTile, n = n0 + nl;
-      if (k < a.K && n < a.N) {
-        float* h = a.H + (int64_t)k * a.ldh + n;
-        *h = (float)((double)*h * S[k * 33 + nl]);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * kBlock;
+      const int kk = e / kTile, nl = e % kTile, n = n0 + nl;
+      if (kk < a.K && n < a.N) {
+        float* h = a.H + (int64_t)kk * a.ldh + n;
+        *h = (float)((double)*h * S[kk * 33 + nl]);
       }
     }
   }
   // normalized W (every block takes a strided share)
   const int64_t total = (int64_t)a.F * a.K;
-  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += (int64_t)gridDim.x * kBlock) {
-    const int f = (int)(e / a.K), k = (int)(e % a.K);
-    float w = a.Wn[(int64_t)f * KP + k];
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + tid; e < total; e += (int64_t)gridDim.x * kBlock) {
+    const int f = (int)(e / a.K), kk = (int)(e % a.K);
+    float w = a.Wn[(int64_t)f * KP + kk];
     if (a.normalize) {
-      const float nk = a.norms[k];
-      if (nk > 0.f) w = (float)((double)w / (double)nk);
+      const float x = norm_s[kk];
+      if (x > 0.f) w = (float)((double)w / (double)x);
     }
-    a.W[(int64_t)f * a.ldw + k] = w;
+    a.W[(int64_t)f * a.ldw + kk] = w;
+  }
+}
+
+// Transposed copy WT[k][f] = W[f][k] (k < KP, zero-padded) and a row-major copy
+// Wp[f][k] with leading dimension KP (zero-padded): the layouts the H pass stages.
+__global__ __launch_bounds__(kBlock) void transpose_kernel(const float* W, int64_t ldw, int F, int K, int KP,
+                                                           float* WT, int64_t ldt, float* Wp) {
+  __shared__ float T[32 * 33];
+  const int f0 = blockIdx.x * 32, k0 = blockIdx.y * 32;
+  for (int e = threadIdx.x; e < 32 * 32; e += kBlock) {
+    const int fl = e / 32, kl = e % 32;
+    const int f = f0 + fl, k = k0 + kl;
+    const float w = (f < F && k < K) ? W[(int64_t)f * ldw + k] : 0.f;
+    T[kl * 33 + fl] = w;
+    if (f < F) Wp[(int64_t)f * KP + k] = w;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 32 * 32; e += kBlock) {
+    const int kl = e / 32, fl = e % 32;
+    const int f = f0 + fl, k = k0 + kl;
+    if (f < F) WT[(int64_t)k * ldt + f] = T[kl * 33 + fl];
   }
 }
 
@@ -677,6 +895,12 @@ hipError_t launch_grad_h(int kb, int grid, hipStream_t s, const float* pnum, int
     case 4: hipLaunchKernelGGL(grad_h_kernel<4>, dim3(grid), dim3(kBlock), 0, s, pnum, N, K, f_groups, scale, dH, lddh); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(hipStream_t s, const float* W, int64_t ldw, int F, int K, int KP, float* WT,
+                            int64_t ldt, float* Wp) {
+  hipLaunchKernelGGL(transpose_kernel, dim3((F + 31) / 32, KP / 32), dim3(kBlock), 0, s, W, ldw, F, K, KP, WT, ldt, Wp);
   return hipGetLastError();
 }
 
