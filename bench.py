@@ -31,16 +31,24 @@ PEAK_HBM = 8.0e12           # bytes/s
 def _flops_bytes(F, N, K, beta, mode):
     """Algorithmic work per launch of each kernel (one outer iteration).
 
-    sweep_w : Lambda = W~H~ (2FNK) + P H~^T (2FNK) + Q H~^T (2FNK; omitted at beta = 1,
-              where the denominator is a row sum); reads V once (4FN bytes).
-    sweep_h : the two H-step contractions (4FNK; 2FNK at beta = 1).  Re-forming
-              Lambda costs another 2FNK: algorithmic for the alternating method
-              (Lambda' = W_new H~), implementation overhead for the joint one.
+    sweep_w    : Lambda = W~H~ (2FNK) + P H~^T (2FNK) + Q H~^T (2FNK; omitted at
+                 beta = 1, where the denominator is a row sum); reads V once (4FN bytes).
+    sweep_h    : the two H-step contractions (4FNK; 2FNK at beta = 1).  Re-forming
+                 Lambda costs another 2FNK: algorithmic for the alternating method
+                 (Lambda' = W_new H~), implementation overhead for the joint one.
+    fused_step : the whole iteration: joint 10FNK (6FNK at beta = 1) reading V
+                 once; alternating 12FNK (8FNK) reading V twice.
     """
     b1 = (beta == 1.0)
-    sw = (4 if b1 else 6) * F * N * K
-    sh = (2 if b1 else 4) * F * N * K + (2 * F * N * K if mode == "alternating" else 0)
-    return {"sweep_w": (sw, 4 * F * N), "sweep_h": (sh, 4 * F * N)}
+    fnk = F * N * K
+    sw = (4 if b1 else 6) * fnk
+    sh = (2 if b1 else 4) * fnk + (2 * fnk if mode == "alternating" else 0)
+    vb = 4 * F * N
+    return {"sweep_w": (sw, vb), "sweep_h": (sh, vb),
+            "fused_step": (sw + sh, vb if mode == "joint" else 2 * vb)}
+
+
+KERNEL_NAMES = ("sweep_w", "update_w", "sweep_h", "update_h", "fused_step")
 
 
 def _run_steps(nb, V, W, H, beta, mode, n, ctx, obj=None, trace=None):
@@ -60,6 +68,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration under a profiler)")
+    ap.add_argument("--path", default="auto", choices=["auto", "stream", "fused"])
     ap.add_argument("--target-blocks", type=int, default=0)
     ap.add_argument("--min-tiles", type=int, default=0)
     args = ap.parse_args(argv)
@@ -87,6 +96,7 @@ def main(argv=None):
 
     ctx = nb.Context(0)
     ctx.set_launch(args.target_blocks, args.min_tiles)
+    ctx.set_path(args.path)
     ctx.reserve(F, N, K)
     V = torch.from_numpy(p.V).to(dev)
     W0 = torch.from_numpy(p.W).to(dev)
@@ -112,21 +122,25 @@ def main(argv=None):
         print("# warning: numeric flags raised", file=sys.stderr)
 
     # per-kernel durations with HIP events on the launch stream (same K steps)
-    kern = {}
+    kern, phases = {}, {}
     for mode in ("joint", "alternating"):
         W, H = W0.clone(), H0.clone()
         _run_steps(nb, V, W, H, beta, mode, 2, ctx, obj=obj)
         torch.cuda.synchronize()
-        ctx.profile(["sweep_w", "update_w", "sweep_h", "update_h"])
+        ctx.profile(KERNEL_NAMES)
         _run_steps(nb, V, W, H, beta, mode, args.steps, ctx, obj=obj)
         torch.cuda.synchronize()
-        ctx.profile([])
         kern[mode] = {}
-        for k in ("sweep_w", "update_w", "sweep_h", "update_h"):
+        for k in KERNEL_NAMES:
             tot, n = ctx.profile_read(k)
-            kern[mode][k] = {"avg_us": 1e3 * tot / max(n, 1), "launches": n}
+            if n:
+                kern[mode][k] = {"avg_us": 1e3 * tot / n, "launches": n}
+        if "fused_step" in kern[mode]:
+            phases[mode] = dict(zip(["w_pass", "barrier1", "w_update", "barrier2", "h_pass", "barrier3", "h_update"],
+                                    [round(x, 2) for x in ctx.profile_phases()]))
+        ctx.profile([])
     fb = _flops_bytes(F, N, K, beta, "joint")
-    dom = max(("sweep_w", "sweep_h"), key=lambda k: kern["joint"][k]["avg_us"])
+    dom = max((k for k in kern["joint"] if k in fb), key=lambda k: kern["joint"][k]["avg_us"])
     flops, vbytes = fb[dom]
     t_dom = kern["joint"][dom]["avg_us"] * 1e-6
     intensity = flops / vbytes
@@ -190,7 +204,8 @@ def main(argv=None):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "F": F, "N": N, "K": K, "beta": beta, "mode": "joint",
-                   "precision": "fp32", "objective_every_step": True, "normalize": True},
+                   "precision": "fp32", "objective_every_step": True, "normalize": True,
+                   "path": "fused" if "fused_step" in kern["joint"] else "stream"},
         "alternating": {"value": res["alternating"]["iters_per_s"], "ms_per_step": res["alternating"]["ms_per_step"]},
         "joint_speedup_per_iteration": res["alternating"]["ms_per_step"] / res["joint"]["ms_per_step"],
         "time_to_objective": {"T": T, "D0": D0, "D_T": {m: float(traces[m][-1]) for m in traces},
@@ -198,6 +213,7 @@ def main(argv=None):
                               "stop_rule_1e-5_iteration": stop, "objective_increases": mono},
         "roofline": roof,
         "kernels_us": kern,
+        "fused_phases_us": phases,
     }
 
     if args.calib_copy:

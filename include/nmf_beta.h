@@ -64,6 +64,8 @@ typedef enum {
 /* sticky numeric flags (nmf_get_flags) */
 #define NMF_FLAG_NONFINITE 1u /* an update ratio num/den was non-finite or den <= 0 */
 #define NMF_FLAG_DOMAIN 2u    /* nmf_beta_validate found data outside the domain */
+#define NMF_FLAG_BARRIER 4u   /* a single-launch step gave up waiting at a grid barrier
+                                 (results of that call are invalid) */
 
 typedef struct {
   int32_t precision;   /* nmf_precision; default NMF_FP32 */
@@ -157,9 +159,28 @@ nmf_status nmf_get_flags(nmf_ctx_t ctx, void* stream, uint32_t* flags, int32_t c
 #define NMF_KERNEL_SWEEP_H 2   /* pass over V accumulating the H-step contractions */
 #define NMF_KERNEL_UPDATE_H 3  /* reduction of H partials, H update, normalization */
 #define NMF_KERNEL_FUSED_KL 4  /* single pass for the joint update at beta = 1 */
+#define NMF_KERNEL_FUSED_STEP 5 /* whole outer iteration in one cooperative launch */
 #define NMF_KERNEL_COUNT 8
 nmf_status nmf_profile_enable(nmf_ctx_t ctx, uint32_t kernel_mask);
+/* With NMF_KERNEL_FUSED_STEP selected, the single-launch step also records the
+ * device clock at its phase boundaries; this returns (synchronizing `stream`)
+ * the n <= 7 intervals of the most recent launch in microseconds: W pass, grid
+ * barrier, W update, barrier, H pass, barrier, H update. */
+nmf_status nmf_profile_phases(nmf_ctx_t ctx, void* stream, double* us, int32_t n);
 nmf_status nmf_profile_read(nmf_ctx_t ctx, int32_t kernel, double* total_ms, int64_t* launches);
+
+/* Execution path of nmf_beta_step.  STREAM: four launches per outer iteration
+ * (W pass, W update, H pass, H update).  FUSED: one cooperative launch running
+ * the same four phases separated by grid barriers; in joint mode its H pass
+ * contracts the element-wise terms P, Q stored by the W pass instead of forming
+ * Lambda again; available for F*N <= 2^24 and K <= 64 outside stream capture,
+ * else NMF_ERR_UNSUPPORTED.  AUTO (default) currently selects STREAM, the
+ * faster of the two on MI355X at every size measured.  Results agree to
+ * rounding between the paths. */
+#define NMF_PATH_AUTO 0
+#define NMF_PATH_STREAM 1
+#define NMF_PATH_FUSED 2
+nmf_status nmf_set_path(nmf_ctx_t ctx, int32_t path);
 
 /* Launch geometry override for tuning: target number of workgroups per sweep
  * (0 = default, twice the number of compute units) and minimum number of 32-wide

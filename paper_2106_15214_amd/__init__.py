@@ -32,7 +32,9 @@ __all__ = [
 ALTERNATING, JOINT = 0, 1
 FP32, BF16, FP16 = 0, 1, 2
 FLAG_NONFINITE, FLAG_DOMAIN = 1, 2
-KERNELS = {"sweep_w": 0, "update_w": 1, "sweep_h": 2, "update_h": 3, "fused_kl": 4}
+KERNELS = {"sweep_w": 0, "update_w": 1, "sweep_h": 2, "update_h": 3, "fused_kl": 4, "fused_step": 5}
+PATHS = {"auto": 0, "stream": 1, "fused": 2}
+FLAG_BARRIER = 4
 MODES = {"alternating": ALTERNATING, "bmm": ALTERNATING, "joint": JOINT, "jmm": JOINT}
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16}
 
@@ -94,9 +96,12 @@ def lib() -> ctypes.CDLL:
         L.nmf_profile_enable.argtypes = [_vp, _u32]
         L.nmf_profile_read.argtypes = [_vp, _i32, ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]
         L.nmf_set_launch.argtypes = [_vp, _i32, _i32]
+        L.nmf_set_path.argtypes = [_vp, _i32]
+        L.nmf_profile_phases.argtypes = [_vp, _vp, ctypes.POINTER(_dbl), _i32]
         for name in ("nmf_create", "nmf_destroy", "nmf_reserve", "nmf_check_step_args", "nmf_beta_step",
                      "nmf_beta_objective", "nmf_beta_grad", "nmf_beta_validate", "nmf_get_flags",
-                     "nmf_profile_enable", "nmf_profile_read", "nmf_set_launch"):
+                     "nmf_profile_enable", "nmf_profile_read", "nmf_set_launch", "nmf_set_path",
+                     "nmf_profile_phases"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -144,11 +149,22 @@ class Context:
     def set_launch(self, target_blocks: int = 0, min_tiles: int = 0):
         _check(lib().nmf_set_launch(self.handle, target_blocks, min_tiles), "nmf_set_launch")
 
+    def set_path(self, path="auto"):
+        """Execution path of step(): "auto", "stream" (four launches) or "fused" (one)."""
+        _check(lib().nmf_set_path(self.handle, PATHS[path] if isinstance(path, str) else int(path)), "nmf_set_path")
+
     def profile(self, kernels) -> None:
         mask = 0
         for k in kernels:
             mask |= 1 << (KERNELS[k] if isinstance(k, str) else int(k))
         _check(lib().nmf_profile_enable(self.handle, mask), "nmf_profile_enable")
+
+    def profile_phases(self, stream=None):
+        """Phase durations (us) of the last single-launch step: W pass, barrier,
+        W update, barrier, H pass, barrier, H update."""
+        arr = (_dbl * 7)()
+        _check(lib().nmf_profile_phases(self.handle, _stream(stream), arr, 7), "nmf_profile_phases")
+        return list(arr)
 
     def profile_read(self, kernel) -> Tuple[float, int]:
         ms, n = _dbl(), _i64()

@@ -31,8 +31,10 @@ struct nmf_ctx_s {
   int num_cus = 256;
   char* ws = nullptr;  // workspace base
   size_t ws_bytes = 0;
-  int target_blocks = 0;  // 0: 2 x CUs
+  int target_blocks = 0;  // 0: cost model
   int min_tiles = 1;
+  int path = NMF_PATH_AUTO;
+  int fused_grid[2][6][2][2] = {};  // cached cooperative capacity per instantiation (+1)
   uint32_t profile_mask = 0;
   std::vector<TimedLaunch> pending[NMF_KERNEL_COUNT];
   std::vector<hipEvent_t> event_pool;
@@ -42,9 +44,12 @@ struct nmf_ctx_s {
 
 namespace {
 
-// Workspace header: the sticky flags word (zeroed at allocation).
+// Workspace header (zeroed at allocation): the sticky flags word at byte 0,
+// the fused kernel's grid-barrier words (arrivals, generation) at bytes 8, 12,
+// and its eight phase stamps (uint64) at bytes 64..127.
 constexpr size_t kHeaderBytes = 256;
-constexpr int kUpdateWBlocks = 64;
+constexpr int kUpdateWBlocks = 256;
+constexpr int kUnitRowsMin = 1;
 
 struct Plan {
   int KB, KP;
@@ -52,8 +57,11 @@ struct Plan {
   int col_blocks, f_groups, tiles_f;  // sweep_cols grid = col_blocks * f_groups
   int uw_blocks, uh_blocks;
   int64_t ldt;                        // leading dimension of the transposed factor (K x F)
+  bool fused;                         // one cooperative launch (grid = fused_grid)
+  int fused_grid;
   // byte offsets inside the workspace
-  size_t o_pobj, o_pnum, o_pden, o_prs, o_wn, o_c1, o_c2, o_wt, o_pcol, o_pnumh, o_pdenh, total;
+  size_t o_pobj, o_pnum, o_pden, o_prs, o_wn, o_c1, o_c2, o_wt, o_pcol, o_pnumh, o_pdenh, o_colsum, o_pst,
+      o_qst, total;
 };
 
 int kblocks_for(int64_t K) {
@@ -67,12 +75,11 @@ int kblocks_for(int64_t K) {
 // tile-times: resident rounds x (tiles per group + 2 for prologue/epilogue)
 // plus the partial-sum traffic (two arrays of groups * out_len * KP floats,
 // written and read at ~12 MB per tile-time).
-int choose_groups(const nmf_ctx_s* c, int64_t tiles, int64_t blocks, int64_t out_len, int KB, int occupancy,
+int choose_groups(const nmf_ctx_s* c, int64_t tiles, int64_t blocks, int64_t out_len, int KB, int64_t slots,
                   int* per_group) {
-  const int64_t slots = (int64_t)c->num_cus * occupancy;
   const int64_t min_tpg = std::max(1, c->min_tiles);
   int64_t best_g = 1;
-  const int64_t gcap = std::max<int64_t>(1, cdiv(4 * 2 * (int64_t)c->num_cus, blocks));
+  const int64_t gcap = std::max<int64_t>(1, cdiv(4 * std::max<int64_t>(slots, 2 * (int64_t)c->num_cus), blocks));
   if (c->target_blocks > 0) {
     best_g = std::max<int64_t>(1, std::min<int64_t>(std::min(cdiv(tiles, min_tpg), gcap), cdiv(c->target_blocks, blocks)));
   } else {
@@ -94,7 +101,7 @@ int choose_groups(const nmf_ctx_s* c, int64_t tiles, int64_t blocks, int64_t out
 
 // Region sizes (bytes) of the workspace; offsets are assigned in this order.
 struct Sizes {
-  size_t pobj, pnum, prs, fk, wt, pcol, pnumh;
+  size_t pobj, pnum, prs, fk, wt, pcol, pnumh, pq;
 };
 
 Plan layout(const Sizes& z, Plan p) {
@@ -111,31 +118,50 @@ Plan layout(const Sizes& z, Plan p) {
   p.o_pcol = take(z.pcol);
   p.o_pnumh = take(z.pnumh);
   p.o_pdenh = take(z.pnumh);
+  p.o_colsum = take(sizeof(float) * 2 * 128);
+  p.o_pst = take(z.pq);
+  p.o_qst = take(z.pq);
   p.total = o;
   return p;
 }
 
-// `cols_occ`: workgroups per CU of the column pass this call launches.
-Plan make_plan(const nmf_ctx_s* c, int64_t F, int64_t N, int64_t K, int cols_occ = 2) {
+// Largest problem (F N entries) run as one fused launch: its P and Q tiles
+// (8 bytes per entry) stay well inside the 256 MB last-level cache.
+constexpr int64_t kFusedMaxEntries = int64_t(1) << 24;
+
+int fused_capacity(nmf_ctx_s* c, int bc, int kb, bool joint, bool obj) {
+  int& slot = c->fused_grid[kb - 1][bc][joint][obj];
+  if (slot == 0) slot = 1 + fused_max_blocks(bc, kb, joint, obj, c->num_cus);
+  return slot - 1;
+}
+
+// `cols_occ`: workgroups per CU of the streaming column pass.  `fused_grid` > 0
+// plans the single-launch path with that many workgroups.
+Plan make_plan(const nmf_ctx_s* c, int64_t F, int64_t N, int64_t K, int cols_occ = 2, int fused_grid = 0) {
   Plan p{};
   p.KB = kblocks_for(K);
   p.KP = 32 * p.KB;
+  p.fused = fused_grid > 0;
+  p.fused_grid = fused_grid;
+  const int64_t rows_slots = p.fused ? fused_grid : (int64_t)c->num_cus * sweep_rows_occupancy(p.KB);
+  const int64_t cols_slots =
+      p.fused ? fused_grid : (int64_t)c->num_cus * std::min(cols_occ, sweep_rows_occupancy(p.KB));
   p.row_blocks = (int)cdiv(F, kBlockRows);
-  p.n_groups = choose_groups(c, cdiv(N, kTile), p.row_blocks, F, p.KB, sweep_rows_occupancy(p.KB), &p.tiles_n);
+  p.n_groups = choose_groups(c, cdiv(N, kTile), p.row_blocks, F, p.KB, rows_slots, &p.tiles_n);
   p.col_blocks = (int)cdiv(N, kBlockRows);
-  p.f_groups = choose_groups(c, cdiv(F, kTile), p.col_blocks, N, p.KB, std::min(cols_occ, sweep_rows_occupancy(p.KB)),
-                             &p.tiles_f);
-  p.uw_blocks = (int)std::min<int64_t>(kUpdateWBlocks, cdiv(F, kTile));
+  p.f_groups = choose_groups(c, cdiv(F, kTile), p.col_blocks, N, p.KB, cols_slots, &p.tiles_f);
+  p.uw_blocks = p.fused ? fused_grid : (int)std::min<int64_t>(kUpdateWBlocks, cdiv(F, kUnitRowsMin));
   p.uh_blocks = (int)cdiv(N, kTile);
   p.ldt = cdiv(F, 4) * 4;
   Sizes z;
-  z.pobj = sizeof(double) * (size_t)p.row_blocks * p.n_groups;
+  z.pobj = sizeof(double) * (size_t)std::max<int64_t>((int64_t)p.row_blocks * p.n_groups, fused_grid);
   z.pnum = sizeof(float) * (size_t)p.n_groups * F * p.KP;
   z.prs = sizeof(float) * (size_t)p.n_groups * p.KP;
   z.fk = sizeof(float) * (size_t)F * p.KP;
   z.wt = sizeof(float) * (size_t)p.KP * p.ldt;
   z.pcol = sizeof(double) * (size_t)p.uw_blocks * 2 * p.KP;
   z.pnumh = sizeof(float) * (size_t)p.f_groups * N * p.KP;
+  z.pq = p.fused ? sizeof(float) * (size_t)cdiv(F, kTile) * cdiv(N, kTile) * kTile * kTile : 0;
   return layout(z, p);
 }
 
@@ -153,13 +179,15 @@ size_t plan_bound(const nmf_ctx_s* c, int64_t maxF, int64_t maxN, int64_t maxK) 
     return std::min<int64_t>(a, tiles * extent);
   };
   Sizes z{};
-  z.pobj = sizeof(double) * (size_t)(cap_blocks + cdiv(maxF, kBlockRows));
+  z.pobj = sizeof(double) * (size_t)(cap_blocks + cdiv(maxF, kBlockRows) + 4 * c->num_cus);
   z.pnum = sizeof(float) * (size_t)(rows_bound(maxF, maxN) * KP);
   z.prs = sizeof(float) * (size_t)((cap_blocks + 1) * KP);
   z.fk = sizeof(float) * (size_t)(maxF * KP);
   z.wt = sizeof(float) * (size_t)(KP * cdiv(maxF, 4) * 4);
   z.pcol = sizeof(double) * (size_t)(kUpdateWBlocks * 2 * KP);
   z.pnumh = sizeof(float) * (size_t)(rows_bound(maxN, maxF) * KP);
+  const int64_t ft = cdiv(maxF, kTile), nt = cdiv(maxN, kTile);
+  if (ft * nt * kTile * kTile <= 2 * kFusedMaxEntries) z.pq = sizeof(float) * (size_t)(ft * nt * kTile * kTile);
   return layout(z, Plan{}).total;
 }
 
@@ -344,9 +372,19 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   hipStream_t s = (hipStream_t)stream;
   const int bc = beta_class(beta);
   const bool joint = (mode == NMF_JOINT);
-  const Plan p = make_plan(c, F, N, K, sweep_cols_occupancy(bc, kblocks_for(K), KIND_UPDATE, joint));
-  if ((st = ensure_ws(c, s, p.total)) != NMF_OK) return st;
+  const bool want_obj = d_objective != nullptr;
   if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
+  // path: one cooperative launch for problems whose P, Q tiles stay cache
+  // resident (not under stream capture), else four streaming launches
+  int fused_grid = 0;
+  if (c->path == NMF_PATH_FUSED && kblocks_for(K) <= 2 && F * N <= kFusedMaxEntries) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return NMF_ERR_HIP;
+    if (cs == hipStreamCaptureStatusNone) fused_grid = fused_capacity(c, bc, kblocks_for(K), joint, want_obj);
+  }
+  if (c->path == NMF_PATH_FUSED && fused_grid <= 0) return NMF_ERR_UNSUPPORTED;
+  const Plan p = make_plan(c, F, N, K, sweep_cols_occupancy(bc, kblocks_for(K), KIND_UPDATE, joint), fused_grid);
+  if ((st = ensure_ws(c, s, p.total)) != NMF_OK) return st;
 
   const bool beta_one = (bc == BC_B1);
   char* ws = c->ws;
@@ -364,10 +402,6 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
   ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
   const int sw_grid = p.row_blocks * p.n_groups;
-  hipError_t e = timed(c, NMF_KERNEL_SWEEP_W, s, [&] {
-    return launch_sweep_rows(bc, p.KB, KIND_UPDATE, d_objective != nullptr, sw_grid, s, ra);
-  });
-  if (e != hipSuccess) return NMF_ERR_HIP;
 
   UpdateWArgs ua{};
   ua.W = W; ua.ldw = ldw; ua.pnum = ra.pnum; ua.pden = ra.pden; ua.prs = ra.prs;
@@ -376,8 +410,6 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   ua.Wn = Wn; ua.C1 = C1; ua.C2 = C2; ua.pcol = (double*)(ws + p.o_pcol);
   ua.WT = (float*)(ws + p.o_wt); ua.ldt = p.ldt;
   ua.flags = flags_ptr(c);
-  e = timed(c, NMF_KERNEL_UPDATE_W, s, [&] { return launch_update_w(p.KB, p.uw_blocks, s, ua); });
-  if (e != hipSuccess) return NMF_ERR_HIP;
 
   SweepColsArgs ca{};
   ca.V = V; ca.ldv = ldv;
@@ -390,8 +422,6 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   ca.f_groups = p.f_groups; ca.tiles_per_group = p.tiles_f;
   ca.pnum = (float*)(ws + p.o_pnumh); ca.pden = (float*)(ws + p.o_pdenh);
   const int sh_grid = p.col_blocks * p.f_groups;
-  e = timed(c, NMF_KERNEL_SWEEP_H, s, [&] { return launch_sweep_cols(bc, p.KB, KIND_UPDATE, joint, sh_grid, s, ca); });
-  if (e != hipSuccess) return NMF_ERR_HIP;
 
   UpdateHArgs ha{};
   ha.H = H; ha.ldh = ldh; ha.pnum = ca.pnum; ha.pden = ca.pden;
@@ -400,6 +430,36 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   ha.pcol = ua.pcol; ha.pcol_blocks = p.uw_blocks;
   ha.pobj = ra.pobj; ha.nobj = sw_grid; ha.d_obj = d_objective;
   ha.Wn = Wn; ha.W = W; ha.ldw = ldw; ha.flags = flags_ptr(c);
+
+  if (p.fused) {
+    // joint: the H pass contracts the P, Q tiles stored by the W pass
+    ra.NT = (int)cdiv(N, kTile);
+    ra.Pst = (float*)(ws + p.o_pst);
+    ra.Qst = (float*)(ws + p.o_qst);
+    ca.NT = ra.NT; ca.Pst = ra.Pst; ca.Qst = ra.Qst;
+    ha.nobj = p.fused_grid;
+    FusedArgs fa{};
+    fa.r = ra; fa.uw = ua; fa.c = ca; fa.uh = ha;
+    fa.n_items_w = sw_grid;
+    fa.n_items_h = sh_grid;
+    fa.slabs = (int)cdiv(F, kTile);
+    fa.ntiles = (int)cdiv(N, kTile);
+    fa.bar = (unsigned*)(ws + 8);
+    fa.colsum = (float*)(ws + p.o_colsum);
+    fa.spin_limit = 1u << 22;
+    fa.stamps = ((c->profile_mask >> NMF_KERNEL_FUSED_STEP) & 1u) ? (unsigned long long*)(ws + 64) : nullptr;
+    return hip_status(timed(c, NMF_KERNEL_FUSED_STEP, s, [&] {
+      return launch_fused(bc, p.KB, joint, want_obj, p.fused_grid, s, fa);
+    }));
+  }
+  hipError_t e = timed(c, NMF_KERNEL_SWEEP_W, s, [&] {
+    return launch_sweep_rows(bc, p.KB, KIND_UPDATE, want_obj, sw_grid, s, ra);
+  });
+  if (e != hipSuccess) return NMF_ERR_HIP;
+  e = timed(c, NMF_KERNEL_UPDATE_W, s, [&] { return launch_update_w(p.KB, p.uw_blocks, s, ua); });
+  if (e != hipSuccess) return NMF_ERR_HIP;
+  e = timed(c, NMF_KERNEL_SWEEP_H, s, [&] { return launch_sweep_cols(bc, p.KB, KIND_UPDATE, joint, sh_grid, s, ca); });
+  if (e != hipSuccess) return NMF_ERR_HIP;
   e = timed(c, NMF_KERNEL_UPDATE_H, s, [&] { return launch_update_h(p.KB, p.uh_blocks, s, ha); });
   return hip_status(e);
 }
@@ -539,6 +599,25 @@ nmf_status nmf_profile_read(nmf_ctx_t c, int32_t kernel, double* total_ms, int64
   c->prof_ms[kernel] = 0.0;
   c->prof_count[kernel] = 0;
   return st;
+}
+
+nmf_status nmf_profile_phases(nmf_ctx_t c, void* stream, double* us, int32_t n) {
+  if (!c || !us) return NMF_ERR_NULL;
+  if (n < 1 || n > 7) return NMF_ERR_ARG;
+  if (!c->ws) return NMF_ERR_ARG;
+  unsigned long long t[8];
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(t, c->ws + 64, sizeof(t), hipMemcpyDeviceToHost, s) != hipSuccess) return NMF_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return NMF_ERR_HIP;
+  for (int i = 0; i < n; ++i) us[i] = (double)(t[i + 1] - t[i]) * 0.01;  // 100 MHz clock
+  return NMF_OK;
+}
+
+nmf_status nmf_set_path(nmf_ctx_t c, int32_t path) {
+  if (!c) return NMF_ERR_NULL;
+  if (path != NMF_PATH_AUTO && path != NMF_PATH_STREAM && path != NMF_PATH_FUSED) return NMF_ERR_ARG;
+  c->path = path;
+  return NMF_OK;
 }
 
 nmf_status nmf_set_launch(nmf_ctx_t c, int32_t target_blocks, int32_t min_tiles) {

@@ -1,0 +1,833 @@
+// Device-side building blocks of the beta-NMF kernels (gfx950, wave64).
+//
+// Data layout: V (F x N), W (F x K), H (K x N), float32 row-major.  Lambda = W H
+// is formed tile by tile on the matrix cores (v_mfma_f32_32x32x2_f32) and is
+// never written to memory.
+//
+// v_mfma_f32_32x32x2_f32 operand layout (lane l, li = l % 32, hi = l / 32):
+//   A[i][kk] : lane holds A[li][hi];  B[kk][j] : lane holds B[hi][li];
+//   C[i][j]  : lane holds C[acc_row(r, hi)][li] in accumulator register r.
+// An accumulator is therefore directly the A operand of a product whose
+// contraction runs over the accumulator's row index, 2 rows per instruction.
+//
+// Two orientations of a pass over V, each a "work item" processed by one
+// workgroup of four waves:
+//  * rows item: the waves own four 32-row slabs and walk 32-column tiles in
+//    lockstep; Lambda^T is formed (lane -> f, register -> n), so P H^T and Q H^T
+//    (the W-step contractions, reduced over n) accumulate in registers.
+//  * cols item: the waves own four 32-column slabs and walk 32-row tiles;
+//    Lambda is formed (lane -> n, register -> f), so chi_1^T P and chi_2^T Q (the
+//    H-step contractions, reduced over f) accumulate in registers.
+// Operand tiles are staged in LDS by the whole workgroup, double-buffered; each
+// wave prefetches its next V tile into registers while the matrix cores work.
+// An item writes one partial per output entry; update code sums the partials
+// in a fixed order, so every result is deterministic.
+#pragma once
+
+#include "nmf_internal.h"
+
+namespace nmf {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// Row offset held in accumulator register r by lane half `hi`: 8(r/4) + 4hi + r%4.
+__device__ __forceinline__ int acc_row(int r, int hi) { return 8 * (r >> 2) + 4 * hi + (r & 3); }
+
+// Lambda^(beta-2) for a smoothed Lambda (> 0).
+template <int BC>
+__device__ __forceinline__ float pow_bm2(float lam, float bm2) {
+  if (BC == BC_B2) return 1.f;
+  if (BC == BC_B1) return __builtin_amdgcn_rcpf(lam);
+  if (BC == BC_B0) { float r = __builtin_amdgcn_rcpf(lam); return r * r; }
+  if (BC == BC_B05) { float s = __builtin_amdgcn_rsqf(lam); return s * s * s; }
+  if (BC == BC_B15) return __builtin_amdgcn_rsqf(lam);
+  return __builtin_amdgcn_exp2f(bm2 * __builtin_amdgcn_logf(lam));
+}
+
+// P = v lam^(beta-2), Q = lam^(beta-1) (v and lam include kappa), the two
+// element-wise terms of eqs. (alt_update) / (jnt_update).
+template <int BC>
+__device__ __forceinline__ void beta_terms(float v, float lam, float bm2, float& P, float& Q) {
+  if (BC == BC_B2) { P = v; Q = lam; return; }
+  if (BC == BC_B1) { P = v * __builtin_amdgcn_rcpf(lam); Q = 1.f; return; }
+  if (BC == BC_B0) { float r = __builtin_amdgcn_rcpf(lam); Q = r; P = v * r * r; return; }
+  if (BC == BC_B05) { float s = __builtin_amdgcn_rsqf(lam); Q = s; P = v * (s * s * s); return; }
+  if (BC == BC_B15) { float s = __builtin_amdgcn_rsqf(lam); P = v * s; Q = lam * s; return; }
+  float e = __builtin_amdgcn_exp2f(bm2 * __builtin_amdgcn_logf(lam));
+  P = v * e;
+  Q = lam * e;
+}
+
+// General-beta term of eq. (beta-div) (out of line: three float64 pows).
+__device__ __noinline__ inline double d_beta_general(double v, double l, double beta) {
+  if (v > 0.0)
+    return pow(v, beta) / (beta * (beta - 1.0)) + pow(l, beta) / beta - v * pow(l, beta - 1.0) / (beta - 1.0);
+  return beta > 0.0 ? pow(l, beta) / beta : __builtin_inf();
+}
+
+// d_beta(v | l) in float64 (v, l include kappa), eq. (beta-div); v = 0 takes
+// the limit of the expression.
+template <int BC>
+__device__ __forceinline__ double d_beta(double v, double l, double beta) {
+  if (BC == BC_B2) { double t = v - l; return 0.5 * t * t; }
+  if (BC == BC_B1) return v > 0.0 ? v * log(v / l) - v + l : l;
+  if (BC == BC_B0) { double r = v / l; return r - log(r) - 1.0; }
+  if (BC == BC_B05) { double sy = sqrt(l); return -4.0 * sqrt(v) + 2.0 * sy + 2.0 * v / sy; }
+  if (BC == BC_B15) { double sy = sqrt(l); return v * sqrt(v) / 0.75 + l * sy / 1.5 - 2.0 * v * sy; }
+  return d_beta_general(v, l, beta);
+}
+
+// p[idx] when ok, else 0.  The load is issued unconditionally (from p[0] when
+// !ok, so p must be the start of a non-empty array): a conditional load would
+// be compiled as a branch that waits for it, serializing consecutive loads.
+__device__ __forceinline__ float ldz(const float* __restrict__ p, int64_t idx, bool ok) {
+  const float x = p[ok ? idx : 0];
+  return ok ? x : 0.f;
+}
+// p[idx] when ok, else p[0] (a finite in-bounds value the caller masks or
+// multiplies by zero later).  Only the address is selected: a select on the
+// loaded value would make the compiler wait for the load right there.
+__device__ __forceinline__ float ldc(const float* __restrict__ p, int64_t idx, bool ok) { return p[ok ? idx : 0]; }
+__device__ __forceinline__ float4 ldc4(const float* __restrict__ p, int64_t idx, bool ok) {
+  return *reinterpret_cast<const float4*>(p + (ok ? idx : 0));
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// Block-wide deterministic sum of one double per thread; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double x, double* red) {
+  x = wave_sum(x);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = x;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kWaves; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ void set_flag(unsigned* flags, unsigned bit) {
+  __hip_atomic_fetch_or(flags, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __noinline__ inline double pow_out_of_line(double x, double y) { return pow(x, y); }
+
+__device__ __forceinline__ double pow_gamma(double x, double g) {
+  if (g == 1.0) return x;
+  if (g == 0.5) return sqrt(x);
+  return pow_out_of_line(x, g);
+}
+
+// chi_1(W, W~) = W~^(2-b) / W^(1-b) = W~ r^(b-1) for b <= 2, else W;
+// chi_2(W, W~) = W for b < 1, else W^b / W~^(b-1) = W~ r^b   (r = W / W~).
+__device__ __forceinline__ void chi_terms(double beta, double wt, double r, double wnew, float& c1, float& c2) {
+  double x1, x2;
+  if (beta >= 2.0) x1 = wnew;
+  else if (beta == 1.0) x1 = wt;
+  else if (beta == 0.0) x1 = wt / r;
+  else if (beta == 0.5) x1 = wt / sqrt(r);
+  else if (beta == 1.5) x1 = wt * sqrt(r);
+  else x1 = wt * pow_out_of_line(r, beta - 1.0);
+  if (beta <= 1.0) x2 = wnew;
+  else if (beta == 2.0) x2 = wnew * r;
+  else if (beta == 1.5) x2 = wnew * sqrt(r);
+  else x2 = wt * pow_out_of_line(r, beta);
+  c1 = (float)x1;
+  c2 = (float)x2;
+}
+
+// Sums `groups` partial arrays (stride `gstride` floats) at offsets base + tid +
+// i*kBlock (i < PER), several groups per round so that many loads are in
+// flight; fixed order, float64 accumulation.  Entries at or beyond `limit`
+// hold meaningless sums the caller does not use.
+template <int PER>
+__device__ __forceinline__ void sum_partials(const float* __restrict__ pn, const float* __restrict__ pd, int groups,
+                                             int64_t gstride, int64_t base, int64_t limit, double (&num)[PER],
+                                             double (&den)[PER]) {
+  constexpr int U = PER >= 4 ? 4 : 16 / PER;  // groups per round
+#pragma unroll
+  for (int i = 0; i < PER; ++i) { num[i] = 0.0; den[i] = 0.0; }
+  const int tid = threadIdx.x;
+  bool ok[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) ok[i] = tid + i * kBlock < limit;
+  int g = 0;
+  for (; g + U <= groups; g += U) {
+    float xn[U][PER], xd[U][PER];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int64_t o = (int64_t)(g + u) * gstride + base + tid + i * kBlock;
+        xn[u][i] = ldc(pn, o, ok[i]);
+        xd[u][i] = pd ? ldc(pd, o, ok[i]) : 0.f;
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int i = 0; i < PER; ++i) { num[i] += (double)xn[u][i]; den[i] += (double)xd[u][i]; }
+  }
+  for (; g < groups; ++g) {
+    float xn[PER], xd[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int64_t o = (int64_t)g * gstride + base + tid + i * kBlock;
+      xn[i] = ldc(pn, o, ok[i]);
+      xd[i] = pd ? ldc(pd, o, ok[i]) : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) { num[i] += (double)xn[i]; den[i] += (double)xd[i]; }
+  }
+}
+
+constexpr int kHS = 36;  // LDS row stride of [k][32] tiles: float4 and dword reads conflict-free
+
+// LDS bytes a rows item needs (two H~ tiles).
+template <int KB>
+constexpr int rows_item_lds() { return 2 * 32 * KB * kHS * 4; }
+
+// ---------------------------------------------------------------------------
+// rows item: W-step contractions (reduction over n) for 128 rows of V over the
+// column tiles of one group.  Optional objective terms (added to objsum), and
+// optionally P and Q stored tile by tile ([tile][n][f], tile = ti * NT + tj) for
+// a later H pass that reuses them (joint MM: V~ and its element-wise terms are
+// formed once per outer iteration).
+// ---------------------------------------------------------------------------
+template <int BC, int KB, int KIND, bool OBJ, bool STORE_PQ>
+__device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, float* lds, double& objsum) {
+  constexpr int KP = 32 * KB;
+  constexpr int K2MAX = KP / 2;
+  constexpr bool CONTRACT = (KIND != KIND_OBJ);
+  constexpr bool NEED_DEN = (KIND == KIND_UPDATE) && (BC != BC_B1);
+  constexpr bool ROWSUM = (KIND == KIND_UPDATE) && (BC == BC_B1);
+  float* const Hs0 = lds;
+  float* const Hs1 = lds + KP * kHS;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, hi = lane >> 5;
+  const int rb = item / a.n_groups, g = item % a.n_groups;
+  const int f0 = rb * kBlockRows + wave * kTile;
+  const int frow = f0 + li;
+  const bool frow_ok = frow < a.F;
+  const bool wave_on = f0 < a.F;
+  const int K = a.K, N = a.N;
+  const int K2 = (K + 1) >> 1;
+
+  // B operand of Lambda^T = H~^T W~^T: lane holds W~[frow][2s + hi]
+  // (all loads issued before any is masked, so they are in flight together)
+  float wB[K2MAX];
+#pragma unroll
+  for (int s = 0; s < K2MAX; ++s) wB[s] = ldc(a.W, (int64_t)frow * a.ldw + 2 * s + hi, frow_ok && 2 * s + hi < K);
+#pragma unroll
+  for (int s = 0; s < K2MAX; ++s) wB[s] = (frow_ok && 2 * s + hi < K) ? wB[s] : 0.f;
+  f32x16 accN[KB], accD[KB];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) { accN[kb][r] = 0.f; accD[kb][r] = 0.f; }
+  }
+  float rsum[KB];
+#pragma unroll
+  for (int j = 0; j < KB; ++j) rsum[j] = 0.f;
+
+  // staging of the H~ tile: thread float4 j covers row (tid + 256 j) / 8,
+  // columns 4 ((tid + 256 j) % 8) .. + 3
+  // Out-of-range entries (k >= K or n >= N) hold finite values from inside H~:
+  // they meet zero weights (wB, or P = Q = 0) and only feed unused outputs.
+  auto load_h = [&](int n0, float4 (&r)[KB]) {
+    const bool full = a.hvec && n0 + kTile <= N;  // whole tile in range: 16-byte loads
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int e4 = tid + kBlock * j;
+      const int k = e4 >> 3, n = n0 + 4 * (e4 & 7);
+      const int64_t o = (int64_t)k * a.ldh + n;
+      if (full) {
+        r[j] = ldc4(a.H, o, k < K);
+      } else {
+        r[j].x = ldc(a.H, o + 0, k < K && n + 0 < N);
+        r[j].y = ldc(a.H, o + 1, k < K && n + 1 < N);
+        r[j].z = ldc(a.H, o + 2, k < K && n + 2 < N);
+        r[j].w = ldc(a.H, o + 3, k < K && n + 3 < N);
+      }
+    }
+  };
+  // exact zeros outside K x N for the beta = 1 row sums
+  auto masked_sum = [&](int n0, const float4& x, int j) {
+    const int e4 = tid + kBlock * j;
+    const int k = e4 >> 3, n = n0 + 4 * (e4 & 7);
+    if (k >= K) return 0.f;
+    return (n + 0 < N ? x.x : 0.f) + (n + 1 < N ? x.y : 0.f) + (n + 2 < N ? x.z : 0.f) + (n + 3 < N ? x.w : 0.f);
+  };
+  auto store_h = [&](float* buf, const float4 (&r)[KB]) {
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int e4 = tid + kBlock * j;
+      *reinterpret_cast<float4*>(&buf[(e4 >> 3) * kHS + 4 * (e4 & 7)]) = r[j];
+    }
+  };
+  const int64_t vrow = (int64_t)frow * a.ldv;
+  // V at the accumulator positions: registers 4q..4q+3 are columns n0 + 8q + 4hi + 0..3
+  // (out-of-range entries are finite stand-ins; P and Q are zeroed there)
+  auto load_v = [&](int n0, float (&v)[16]) {
+    const bool full = a.vec4 && n0 + kTile <= N;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int nb = n0 + 8 * q + 4 * hi;
+      if (full) {
+        const float4 x = ldc4(a.V, vrow + nb, frow_ok);
+        v[4 * q + 0] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[4 * q + j] = ldc(a.V, vrow + nb + j, frow_ok && nb + j < N);
+      }
+    }
+  };
+
+  const int nt_total = (N + kTile - 1) / kTile;
+  const int t0 = g * a.tiles_per_group;
+  const int t1 = min(nt_total, t0 + a.tiles_per_group);
+  float4 hreg[KB];
+  float vcur[16], vnext[16];
+  __syncthreads();  // LDS may still be read by the previous item
+  if (t0 < t1) {
+    load_h(t0 * kTile, hreg);
+    if (ROWSUM)
+#pragma unroll
+      for (int j = 0; j < KB; ++j) rsum[j] += masked_sum(t0 * kTile, hreg[j], j);
+    if (wave_on) load_v(t0 * kTile, vcur);
+    store_h(Hs0, hreg);
+  }
+  __syncthreads();
+
+  for (int t = t0; t < t1; ++t) {
+    const float* hs = ((t - t0) & 1) ? Hs1 : Hs0;
+    const bool more = t + 1 < t1;
+    if (more) {
+      load_h((t + 1) * kTile, hreg);
+      if (wave_on) load_v((t + 1) * kTile, vnext);
+    }
+    if (wave_on) {
+      const int n0 = t * kTile;
+      // Lambda^T tile: lam[r] = Lambda[frow][n0 + acc_row(r, hi)]; A operand H~[2s+hi][n0+li]
+      f32x16 lam;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) lam[r] = 0.f;
+      {
+        // operands read one block of 4 steps ahead; blocks past K2 skipped
+        float av[4], an[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) av[j] = hs[(2 * j + hi) * kHS + li];
+#pragma unroll
+        for (int b = 0; b < K2MAX / 4; ++b) {
+          if (b + 1 < K2MAX / 4)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) an[j] = hs[(2 * (4 * b + 4 + j) + hi) * kHS + li];
+          if (4 * b < K2)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) lam = mfma32(av[j], wB[4 * b + j], lam);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) av[j] = an[j];
+        }
+      }
+
+      float P[16], Q[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int n = n0 + acc_row(r, hi);
+        const bool ok = frow_ok && n < N;
+        const float lk = lam[r] + a.kappa;
+        const float vk = vcur[r] + a.kappa;
+        if (KIND == KIND_UPDATE) {
+          beta_terms<BC>(vk, lk, a.bm2, P[r], Q[r]);
+          if (!ok) { P[r] = 0.f; Q[r] = 0.f; }
+        } else if (KIND == KIND_GRAD) {
+          P[r] = ok ? pow_bm2<BC>(lk, a.bm2) * (lam[r] - vcur[r]) : 0.f;
+        }
+        if (OBJ && ok) objsum += d_beta<BC>((double)vk, (double)lk, a.beta);
+      }
+      if (STORE_PQ) {
+        // tile (slab of this wave, column tile t) as [n][f]: coalesced 32-float rows
+        const int64_t tb = ((int64_t)(f0 >> 5) * a.NT + t) * (kTile * kTile);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int64_t o = tb + acc_row(r, hi) * kTile + li;
+          a.Pst[o] = P[r];
+          if (BC != BC_B1) a.Qst[o] = Q[r];
+        }
+      }
+      if (CONTRACT) {
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            // B operand: H~[kb*32 + li][n0 + 8q + 4hi + j]
+            const float4 b = *reinterpret_cast<const float4*>(&hs[(kb * 32 + li) * kHS + 8 * q + 4 * hi]);
+            accN[kb] = mfma32(P[4 * q + 0], b.x, accN[kb]);
+            accN[kb] = mfma32(P[4 * q + 1], b.y, accN[kb]);
+            accN[kb] = mfma32(P[4 * q + 2], b.z, accN[kb]);
+            accN[kb] = mfma32(P[4 * q + 3], b.w, accN[kb]);
+            if (NEED_DEN) {
+              accD[kb] = mfma32(Q[4 * q + 0], b.x, accD[kb]);
+              accD[kb] = mfma32(Q[4 * q + 1], b.y, accD[kb]);
+              accD[kb] = mfma32(Q[4 * q + 2], b.z, accD[kb]);
+              accD[kb] = mfma32(Q[4 * q + 3], b.w, accD[kb]);
+            }
+          }
+        }
+      }
+    }
+    if (more) {
+      store_h(((t - t0 + 1) & 1) ? Hs1 : Hs0, hreg);
+      if (ROWSUM)
+#pragma unroll
+        for (int j = 0; j < KB; ++j) rsum[j] += masked_sum((t + 1) * kTile, hreg[j], j);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) vcur[i] = vnext[i];
+    }
+    __syncthreads();
+  }
+
+  if (CONTRACT && wave_on) {
+    // accumulator (i = row offset f, j = li = column k); each wave owns its rows
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int f = f0 + acc_row(r, hi);
+        if (f < a.F) {
+          const int64_t o = ((int64_t)g * a.F + f) * KP + kb * 32 + li;
+          a.pnum[o] = accN[kb][r];
+          if (NEED_DEN) a.pden[o] = accD[kb][r];
+        }
+      }
+    }
+  }
+  if (ROWSUM) {
+    // the eight threads sharing a row of the staged tile hold its column sums
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      float x = rsum[j];
+      x += __shfl_xor(x, 1, 64);
+      x += __shfl_xor(x, 2, 64);
+      x += __shfl_xor(x, 4, 64);
+      const int e4 = tid + kBlock * j;
+      if (rb == 0 && (e4 & 7) == 0) a.prs[g * KP + (e4 >> 3)] = x;
+    }
+  }
+}
+
+// LDS bytes a cols item needs.
+template <int KB, bool C2_TILE>
+constexpr int cols_item_lds() {
+  return (2 * 32 * KB * kHS + 2 * kTile * (32 * KB + 4) * (C2_TILE ? 2 : 1)) * 4;
+}
+
+// ---------------------------------------------------------------------------
+// cols item: H-step contractions (reduction over f) for 128 columns over the
+// row tiles of one group.  Per tile the workgroup stages (LDS, double
+// buffered) the transposed factor forming Lambda (KP x 32 from WT, unless
+// LOAD_PQ) and chi_1, chi_2 (32 x KP, row-major with ld KP).  With LOAD_PQ the
+// element-wise terms P, Q come from the tiles a rows item stored (no Lambda
+// re-formation, no V pass).
+// ---------------------------------------------------------------------------
+template <int BC, int KB, int KIND, bool DUAL, bool LOAD_PQ>
+__device__ __forceinline__ void cols_item(const SweepColsArgs& a, int item, float* lds) {
+  constexpr int KP = 32 * KB;
+  constexpr int K2MAX = KP / 2;
+  constexpr int CS = KP + 4;  // LDS row stride of [f][KP] tiles
+  constexpr bool NEED_DEN = (KIND == KIND_UPDATE) && (BC != BC_B1);
+  constexpr bool C2_TILE = DUAL && NEED_DEN;
+  float* const Ws0 = lds;
+  float* const Ws1 = lds + KP * kHS;
+  float* const C1s0 = lds + 2 * KP * kHS;
+  float* const C1s1 = C1s0 + kTile * CS;
+  float* const C2s0 = C1s1 + kTile * CS;
+  float* const C2s1 = C2s0 + kTile * CS;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, hi = lane >> 5;
+  const int cb = item / a.f_groups, g = item % a.f_groups;
+  const int n0w = cb * kBlockRows + wave * kTile;
+  const int ncol = n0w + li;
+  const bool ncol_ok = ncol < a.N;
+  const bool wave_on = n0w < a.N;
+  const int K = a.K, F = a.F;
+  const int K2 = (K + 1) >> 1;
+
+  // B operand of Lambda = W H~: lane holds H~[2s + hi][ncol]
+  float hB[LOAD_PQ ? 1 : K2MAX];
+  if (!LOAD_PQ) {
+#pragma unroll
+    for (int s = 0; s < K2MAX; ++s) hB[s] = ldc(a.H, (int64_t)(2 * s + hi) * a.ldh + ncol, ncol_ok && 2 * s + hi < K);
+#pragma unroll
+    for (int s = 0; s < K2MAX; ++s) hB[s] = (ncol_ok && 2 * s + hi < K) ? hB[s] : 0.f;
+  }
+  f32x16 accN[KB], accD[KB];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) { accN[kb][r] = 0.f; accD[kb][r] = 0.f; }
+  }
+
+  // staging: WT tile float4 j -> row k = e4 / 8, columns f0 + 4 (e4 % 8);
+  //          chi tile float4 j -> row i = e4 / (KP/4), columns 4 (e4 % (KP/4))
+  float4 wreg[LOAD_PQ ? 1 : KB], c1reg[KB], c2reg[C2_TILE ? KB : 1];
+  auto load_tiles = [&](int f0) {
+    const bool full = f0 + kTile <= F;
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int e4 = tid + kBlock * j;
+      if (!LOAD_PQ) {
+        const int k = e4 >> 3, f = f0 + 4 * (e4 & 7);
+        const int64_t o = (int64_t)k * a.ldwt + f;
+        if (full) {
+          wreg[j] = ldc4(a.WT, o, true);
+        } else {
+          wreg[j].x = ldc(a.WT, o + 0, f + 0 < F);
+          wreg[j].y = ldc(a.WT, o + 1, f + 1 < F);
+          wreg[j].z = ldc(a.WT, o + 2, f + 2 < F);
+          wreg[j].w = ldc(a.WT, o + 3, f + 3 < F);
+        }
+      }
+      const int i = e4 / (KP / 4), c = 4 * (e4 % (KP / 4));
+      const bool ok = f0 + i < F;
+      const int64_t o = (int64_t)(f0 + i) * KP + c;
+      c1reg[j] = ldc4(a.C1, o, ok);  // rows f >= F meet P = Q = 0
+      if (C2_TILE) c2reg[j] = ldc4(a.C2, o, ok);
+    }
+  };
+  auto store_tiles = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int e4 = tid + kBlock * j;
+      if (!LOAD_PQ) *reinterpret_cast<float4*>(&(buf ? Ws1 : Ws0)[(e4 >> 3) * kHS + 4 * (e4 & 7)]) = wreg[j];
+      const int i = e4 / (KP / 4), c = 4 * (e4 % (KP / 4));
+      *reinterpret_cast<float4*>(&(buf ? C1s1 : C1s0)[i * CS + c]) = c1reg[j];
+      if (C2_TILE) *reinterpret_cast<float4*>(&(buf ? C2s1 : C2s0)[i * CS + c]) = c2reg[j];
+    }
+  };
+  // per-wave tile data at the accumulator positions (register r: row
+  // f0 + acc_row(r, hi), column ncol): V, or the stored P and Q
+  auto load_v = [&](int f0, float (&v)[16], float (&w)[16]) {
+    if (LOAD_PQ) {
+      const int64_t tb = ((int64_t)(f0 >> 5) * a.NT + (n0w >> 5)) * (kTile * kTile) + li * kTile;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 x = *reinterpret_cast<const float4*>(a.Pst + tb + 8 * q + 4 * hi);
+        v[4 * q + 0] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+        if (NEED_DEN) {
+          const float4 y = *reinterpret_cast<const float4*>(a.Qst + tb + 8 * q + 4 * hi);
+          w[4 * q + 0] = y.x; w[4 * q + 1] = y.y; w[4 * q + 2] = y.z; w[4 * q + 3] = y.w;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int f = f0 + acc_row(r, hi);
+        v[r] = ldc(a.V, (int64_t)f * a.ldv + ncol, ncol_ok && f < F);
+      }
+    }
+  };
+
+  const int ft_total = (F + kTile - 1) / kTile;
+  const int t0 = g * a.tiles_per_group;
+  const int t1 = min(ft_total, t0 + a.tiles_per_group);
+  float vcur[16], vnext[16], wcur[16], wnext[16];  // w*: stored Q (LOAD_PQ only)
+  __syncthreads();  // LDS may still be read by the previous item
+  if (t0 < t1) {
+    load_tiles(t0 * kTile);
+    if (wave_on) load_v(t0 * kTile, vcur, wcur);
+    store_tiles(0);
+  }
+  __syncthreads();
+
+  for (int t = t0; t < t1; ++t) {
+    const int buf = (t - t0) & 1;
+    const bool more = t + 1 < t1;
+    if (more) {
+      load_tiles((t + 1) * kTile);
+      if (wave_on) load_v((t + 1) * kTile, vnext, wnext);
+    }
+    if (wave_on) {
+      const int f0 = t * kTile;
+      const float* c1s = buf ? C1s1 : C1s0;
+      const float* c2s = C2_TILE ? (buf ? C2s1 : C2s0) : c1s;
+      float P[16], Q[16];
+      if (LOAD_PQ) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) { P[r] = vcur[r]; Q[r] = NEED_DEN ? wcur[r] : 0.f; }
+      } else {
+        const float* ws = buf ? Ws1 : Ws0;
+        // Lambda tile: lam[r] = Lambda[f0 + acc_row(r, hi)][ncol]; A operand W[f0+li][2s+hi]
+        f32x16 lam;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) lam[r] = 0.f;
+        {
+          float av[4], an[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) av[j] = ws[(2 * j + hi) * kHS + li];
+#pragma unroll
+          for (int b = 0; b < K2MAX / 4; ++b) {
+            if (b + 1 < K2MAX / 4)
+#pragma unroll
+              for (int j = 0; j < 4; ++j) an[j] = ws[(2 * (4 * b + 4 + j) + hi) * kHS + li];
+            if (4 * b < K2)
+#pragma unroll
+              for (int j = 0; j < 4; ++j) lam = mfma32(av[j], hB[4 * b + j], lam);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) av[j] = an[j];
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int f = f0 + acc_row(r, hi);
+          const bool ok = ncol_ok && f < F;
+          const float lk = lam[r] + a.kappa;
+          const float vk = vcur[r] + a.kappa;
+          if (KIND == KIND_UPDATE) {
+            beta_terms<BC>(vk, lk, a.bm2, P[r], Q[r]);
+            if (!ok) { P[r] = 0.f; Q[r] = 0.f; }
+          } else {
+            P[r] = ok ? pow_bm2<BC>(lk, a.bm2) * (lam[r] - vcur[r]) : 0.f;
+          }
+        }
+      }
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = acc_row(r, hi) * CS + kb * 32 + li;
+          accN[kb] = mfma32(P[r], c1s[row], accN[kb]);
+          if (NEED_DEN) accD[kb] = mfma32(Q[r], c2s[row], accD[kb]);
+        }
+      }
+    }
+    if (more) {
+      store_tiles(buf ^ 1);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) vcur[i] = vnext[i];
+      if (LOAD_PQ)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) wcur[i] = wnext[i];
+    }
+    __syncthreads();
+  }
+
+  if (wave_on) {
+    // accumulator (i = column offset n, j = li = k); each wave owns its columns
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int n = n0w + acc_row(r, hi);
+        if (n < a.N) {
+          const int64_t o = ((int64_t)g * a.N + n) * KP + kb * 32 + li;
+          a.pnum[o] = accN[kb][r];
+          if (NEED_DEN) a.pden[o] = accD[kb][r];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// W update for one unit of kUnitRows(KB) rows: W_new = W~ (num/den)^gamma with
+// the partials summed in a fixed order (four thread slices take every fourth
+// group, combined slice 0..3 through LDS), the chi terms (joint), the
+// transposed copy of the factor that forms Lambda in a later H pass (when
+// `write_wt`), and running column sums of W_new^2 and W_new in (nrm, cs) for
+// the normalization (threads of slice 0 only).
+// ---------------------------------------------------------------------------
+constexpr int kSlices = 4;
+template <int KB>
+constexpr int unit_rows() { return kBlock / (32 * KB * kSlices) > 0 ? kBlock / (32 * KB * kSlices) : 1; }
+template <int KB>
+constexpr int unit_slices() { return kBlock / (32 * KB * unit_rows<KB>()); }
+template <int KB>
+constexpr int update_w_lds_floats() { return 2 * kBlock; }
+
+template <int KB>
+__device__ __forceinline__ void update_w_unit(const UpdateWArgs& a, int unit, bool write_wt, float* lds,
+                                              double den1, double& nrm, double& cs) {
+  constexpr int KP = 32 * KB;
+  constexpr int RU = unit_rows<KB>();
+  constexpr int GS = unit_slices<KB>();
+  constexpr int U = 8;  // groups per round
+  const int tid = threadIdx.x;
+  const int k = tid % KP, r = (tid / KP) % RU, gs = tid / (KP * RU);
+  const int f = unit * RU + r;
+  const bool fok = f < a.F;
+  const int64_t gstride = (int64_t)a.F * KP;
+  const int64_t base = (int64_t)f * KP + k;
+  float sn = 0.f, sd = 0.f;
+  double dn = 0.0, dd = 0.0;
+  int g = gs;
+  for (; g + (U - 1) * GS < a.n_groups; g += U * GS) {
+    float xn[U], xd[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      xn[u] = ldc(a.pnum, (int64_t)(g + u * GS) * gstride + base, fok);
+      xd[u] = a.beta_one ? 0.f : ldc(a.pden, (int64_t)(g + u * GS) * gstride + base, fok);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) { dn += (double)xn[u]; dd += (double)xd[u]; }
+  }
+  for (; g < a.n_groups; g += GS) {
+    dn += (double)ldc(a.pnum, (int64_t)g * gstride + base, fok);
+    if (!a.beta_one) dd += (double)ldc(a.pden, (int64_t)g * gstride + base, fok);
+  }
+  (void)sn; (void)sd;
+  double* red = reinterpret_cast<double*>(lds);  // [2][GS][RU*KP]
+  const float wtf = ldz(a.W, (int64_t)f * a.ldw + k, fok && k < a.K);
+  __syncthreads();  // red may still be read by the previous unit
+  red[tid] = dn;
+  red[kBlock + tid] = dd;
+  __syncthreads();
+  if (gs == 0) {
+    double num = 0.0, den = 0.0;
+#pragma unroll
+    for (int j = 0; j < GS; ++j) {
+      num += red[j * KP * RU + tid];
+      den += red[kBlock + j * KP * RU + tid];
+    }
+    float wn = 0.f, c1 = 0.f, c2 = 0.f;
+    if (fok && k < a.K) {
+      const double dsum = a.beta_one ? den1 : den;
+      const double ratio = num / dsum;
+      if (!(dsum > 0.0) || !isfinite(ratio)) set_flag(a.flags, 1u);
+      const double rr = pow_gamma(ratio, a.gamma);
+      const double wt = (double)wtf;
+      const double wnew = wt * rr;
+      wn = (float)wnew;
+      if (a.joint) chi_terms(a.beta, wt, rr, wnew, c1, c2);
+      nrm += (double)wn * (double)wn;
+      cs += (double)wn;
+    }
+    if (fok) {
+      const int64_t o = (int64_t)f * KP + k;
+      a.Wn[o] = wn;
+      if (a.joint) { a.C1[o] = c1; a.C2[o] = c2; }
+      if (write_wt) a.WT[(int64_t)k * a.ldt + f] = a.joint ? wtf : wn;
+    }
+  }
+}
+
+// Column norms / sums of W_new from per-block partials pcol[b][2][KP] (b <
+// nblocks), summed in a fixed order into norm_s / csum_s (LDS, KP each).
+template <int KB>
+__device__ __forceinline__ void reduce_columns(const double* pcol, int nblocks, double* scratch, float* norm_s,
+                                               float* csum_s) {
+  constexpr int KP = 32 * KB;
+  constexpr int R = kBlock / KP;
+  constexpr int U = 8;
+  const int tid = threadIdx.x;
+  const int k = tid % KP, part = tid / KP;
+  double x = 0.0, y = 0.0;
+  int b = part;
+  for (; b + (U - 1) * R < nblocks; b += U * R) {
+    double xs[U], ys[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      xs[u] = pcol[(int64_t)(b + u * R) * 2 * KP + k];
+      ys[u] = pcol[(int64_t)(b + u * R) * 2 * KP + KP + k];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) { x += xs[u]; y += ys[u]; }
+  }
+  for (; b < nblocks; b += R) {
+    x += pcol[(int64_t)b * 2 * KP + k];
+    y += pcol[(int64_t)b * 2 * KP + KP + k];
+  }
+  __syncthreads();
+  scratch[tid] = x;
+  scratch[kBlock + tid] = y;
+  __syncthreads();
+  if (tid < KP) {
+    double xs = 0.0, ys = 0.0;
+    for (int j = 0; j < R; ++j) { xs += scratch[j * KP + tid]; ys += scratch[kBlock + j * KP + tid]; }
+    norm_s[tid] = (float)sqrt(xs);
+    csum_s[tid] = (float)ys;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// H update for one 32-column tile: H_new = H~ (num/den)^gamma (times the column
+// norm of W_new when normalizing), with den = column sums of W_new at beta = 1.
+// ---------------------------------------------------------------------------
+template <int KB>
+__device__ __forceinline__ void update_h_tile(const UpdateHArgs& a, int ntile, const float* norm_s,
+                                              const float* csum_s, double* S /* [KP][33] */) {
+  constexpr int KP = 32 * KB;
+  constexpr int PER = kTile * KP / kBlock;
+  const int tid = threadIdx.x;
+  const int k = tid % KP;
+  const int n0 = ntile * kTile;
+  double num[PER], den[PER];
+  sum_partials<PER>(a.pnum, a.beta_one ? nullptr : a.pden, a.f_groups, (int64_t)a.N * KP, (int64_t)n0 * KP,
+                    (int64_t)(min(a.N - n0, kTile)) * KP, num, den);
+  // H~ entries this thread rewrites (kk = e / 32, n = n0 + e % 32), loaded up front
+  float hv[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + i * kBlock;
+    const int kk = e / kTile, n = n0 + e % kTile;
+    hv[i] = ldc(a.H, (int64_t)kk * a.ldh + n, kk < a.K && n < a.N);
+  }
+  double nk = 1.0;
+  if (a.normalize && k < a.K) {
+    const float x = norm_s[k];
+    if (x > 0.f) nk = (double)x;
+  }
+  __syncthreads();  // S may still be read by the previous tile
+#pragma unroll 1
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + i * kBlock;
+    const int nl = e / KP, n = n0 + nl;
+    double s = 0.0;
+    if (n < a.N && k < a.K) {
+      const double dd = a.beta_one ? (double)csum_s[k] : den[i];
+      const double ratio = num[i] / dd;
+      if (!(dd > 0.0) || !isfinite(ratio)) set_flag(a.flags, 1u);
+      s = pow_gamma(ratio, a.gamma) * nk;
+    }
+    S[k * 33 + nl] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + i * kBlock;
+    const int kk = e / kTile, nl = e % kTile, n = n0 + nl;
+    if (kk < a.K && n < a.N) a.H[(int64_t)kk * a.ldh + n] = (float)((double)hv[i] * S[kk * 33 + nl]);
+  }
+}
+
+// W <- W_new / norm (or W_new), entries e0, e0 + stride, ...
+template <int KB>
+__device__ __forceinline__ void write_w(const UpdateHArgs& a, const float* norm_s, int64_t e0, int64_t stride) {
+  constexpr int KP = 32 * KB;
+  const int64_t total = (int64_t)a.F * a.K;
+  for (int64_t e = e0; e < total; e += stride) {
+    const int f = (int)(e / a.K), kk = (int)(e % a.K);
+    float w = a.Wn[(int64_t)f * KP + kk];
+    if (a.normalize) {
+      const float x = norm_s[kk];
+      if (x > 0.f) w = (float)((double)w / (double)x);
+    }
+    a.W[(int64_t)f * a.ldw + kk] = w;
+  }
+}
+
+}  // namespace nmf

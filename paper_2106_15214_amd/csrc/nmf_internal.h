@@ -59,6 +59,7 @@ struct SweepRowsArgs {
   double* pobj;                    // [grid] objective partials (nullable)
   int vec4;                        // V rows 16-byte aligned
   int hvec;                        // H rows 16-byte aligned
+  float* Pst; float* Qst; int NT;  // P, Q tiles [row tile * NT + column tile][32 n][32 f] (fused joint pass)
 };
 
 struct SweepColsArgs {
@@ -70,6 +71,7 @@ struct SweepColsArgs {
   float bm2, kappa;
   int f_groups, tiles_per_group;   // grid = col_blocks (128 columns) * f_groups
   float* pnum; float* pden;        // [f_groups][N][KP] partial H contractions
+  const float* Pst; const float* Qst; int NT;  // stored P, Q tiles (fused joint pass)
 };
 
 struct UpdateWArgs {
@@ -108,6 +110,23 @@ hipError_t launch_grad_h(int kb, int grid, hipStream_t s, const float* pnum, int
                          double scale, float* dH, int64_t lddh);
 hipError_t launch_transpose(hipStream_t s, const float* W, int64_t ldw, int F, int K, int KP, float* WT,
                             int64_t ldt, float* Wp);
+// Fused single-launch outer iteration (cooperative; grid barriers between the
+// W pass, W update, H pass and H update).  Returns hipErrorNotSupported when
+// the instantiation does not exist.
+struct FusedArgs {
+  SweepRowsArgs r;
+  UpdateWArgs uw;
+  SweepColsArgs c;
+  UpdateHArgs uh;
+  int n_items_w, n_items_h, slabs, ntiles;
+  unsigned* bar;        // [2]: arrival count, generation
+  float* colsum;        // [2][KP]: column norms and sums of W_new
+  unsigned spin_limit;  // barrier polls before giving up (sets NMF_FLAG_BARRIER)
+  unsigned long long* stamps;  // nullable: [8] wall-clock stamps of workgroup 0 at phase boundaries
+};
+int fused_max_blocks(int bc, int kb, bool joint, bool obj, int num_cus);
+hipError_t launch_fused(int bc, int kb, bool joint, bool obj, int grid, hipStream_t s, const FusedArgs& a);
+
 hipError_t launch_validate(hipStream_t s, const float* V, int64_t ldv, const float* W, int64_t ldw,
                            const float* H, int64_t ldh, int F, int N, int K, int zero_bad, unsigned* flags);
 

@@ -26,15 +26,29 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
 
 
+_CTX = {}
+
+
+def ctx_for(path):
+    """One library context per execution path ("auto", "stream", "fused")."""
+    if path not in _CTX:
+        c = nb.Context(0)
+        c.set_path(path)
+        _CTX[path] = c
+    return _CTX[path]
+
+
 def rel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
 
 
-def gpu_step(V, W, H, beta, mode, kappa=0.0, normalize=True, obj=True):
+def gpu_step(V, W, H, beta, mode, kappa=0.0, normalize=True, obj=True, path="auto"):
     Vd, Wd, Hd = dev(V), dev(W), dev(H)
     o = torch.full((1,), float("nan"), dtype=torch.float64, device=DEV) if obj else None
-    nb.step(Vd, Wd, Hd, beta, mode, kappa=kappa, normalize=normalize, objective_out=o)
+    ctx = ctx_for(path)
+    nb.step(Vd, Wd, Hd, beta, mode, kappa=kappa, normalize=normalize, objective_out=o, ctx=ctx)
     torch.cuda.synchronize()
+    assert nb.get_flags(clear=True, ctx=ctx) == 0
     return Wd.cpu().numpy(), Hd.cpu().numpy(), (o.item() if obj else None)
 
 
@@ -47,10 +61,10 @@ def ref_obj(V, W, H, beta, kappa=0.0):
     return O.objective(V.astype(np.float64), W.astype(np.float64), H.astype(np.float64), beta, kappa)
 
 
-def check_step(V, W, H, beta, mode, kappa=0.0, normalize=True, tag=""):
+def check_step(V, W, H, beta, mode, kappa=0.0, normalize=True, tag="", path="auto"):
     print(f"[parity] {tag} F={V.shape[0]} N={V.shape[1]} K={W.shape[1]} beta={beta} mode={mode} "
-          f"kappa={kappa} norm={normalize}", flush=True)
-    Wg, Hg, dg = gpu_step(V, W, H, beta, mode, kappa, normalize)
+          f"kappa={kappa} norm={normalize} path={path}", flush=True)
+    Wg, Hg, dg = gpu_step(V, W, H, beta, mode, kappa, normalize, path=path)
     Wr, Hr = ref_step(V, W, H, beta, mode, kappa, normalize)
     d0 = ref_obj(V, W, H, beta, kappa)
     eW, eH = rel(Wg, Wr), rel(Hg, Hr)
@@ -58,7 +72,6 @@ def check_step(V, W, H, beta, mode, kappa=0.0, normalize=True, tag=""):
     assert eW <= TOL_FACTOR, f"W rel err {eW:.3e}"
     assert eH <= TOL_FACTOR, f"H rel err {eH:.3e}"
     assert eD <= TOL_OBJ, f"objective rel err {eD:.3e} ({dg} vs {d0})"
-    assert nb.get_flags(clear=True) == 0
     return Wg, Hg
 
 
@@ -69,10 +82,13 @@ SHAPES = [(64, 100, 5), (200, 150, 20), (257, 300, 49), (130, 70, 64), (33, 1000
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
 @pytest.mark.parametrize("beta", BETAS)
 @pytest.mark.parametrize("mode", ["joint", "alternating"])
-def test_step_parity_shapes(shape, beta, mode):
+@pytest.mark.parametrize("path", ["stream", "fused"])
+def test_step_parity_shapes(shape, beta, mode, path):
     F, N, K = shape
+    if path == "fused" and K > 64:
+        pytest.skip("the single-launch path covers K <= 64")
     p = synth.random_positive(F, N, K, seed=F * 7 + N + K, zeros=0.1 if beta > 0 else 0.0)
-    check_step(p.V, p.W, p.H, beta, mode, tag="shape")
+    check_step(p.V, p.W, p.H, beta, mode, tag="shape", path=path)
 
 
 @pytest.mark.parametrize("name,beta,crop", [
@@ -84,9 +100,10 @@ def test_step_parity_shapes(shape, beta, mode):
     ("counts_kl", 1.0, ((1000, 1700), (3000, 4100))),
 ])
 @pytest.mark.parametrize("mode", ["joint", "alternating"])
-def test_workload_parity(name, beta, crop, mode):
+@pytest.mark.parametrize("path", ["stream", "fused"])
+def test_workload_parity(name, beta, crop, mode, path):
     p = synth.make_problem(name, beta=beta, rows=crop[0] if crop else None, cols=crop[1] if crop else None)
-    check_step(p.V, p.W, p.H, beta, mode, tag=name)
+    check_step(p.V, p.W, p.H, beta, mode, tag=name, path=path)
 
 
 @pytest.mark.parametrize("mode", ["joint", "alternating"])
@@ -108,32 +125,53 @@ def test_trajectory_per_step_parity_tiny_kl(mode):
 
 
 @pytest.mark.parametrize("beta", [0.0, 1.0, 2.0, 0.5])
-def test_w_step_bitwise_equal_between_modes(beta):
+@pytest.mark.parametrize("path", ["stream", "fused"])
+def test_w_step_bitwise_equal_between_modes(beta, path):
     p = synth.random_positive(150, 190, 24, seed=3)
-    Wj, _, _ = gpu_step(p.V, p.W, p.H, beta, "joint")
-    Wa, _, _ = gpu_step(p.V, p.W, p.H, beta, "alternating")
+    Wj, _, _ = gpu_step(p.V, p.W, p.H, beta, "joint", path=path)
+    Wa, _, _ = gpu_step(p.V, p.W, p.H, beta, "alternating", path=path)
     assert np.array_equal(Wj, Wa)
 
 
 @pytest.mark.parametrize("mode", ["joint", "alternating"])
-def test_run_to_run_bitwise_determinism(mode):
+@pytest.mark.parametrize("path", ["stream", "fused"])
+def test_run_to_run_bitwise_determinism(mode, path):
     p = synth.random_positive(300, 500, 50, seed=4)
-    a = gpu_step(p.V, p.W, p.H, 1.5, mode)
-    b = gpu_step(p.V, p.W, p.H, 1.5, mode)
+    a = gpu_step(p.V, p.W, p.H, 1.5, mode, path=path)
+    b = gpu_step(p.V, p.W, p.H, 1.5, mode, path=path)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+
+
+@pytest.mark.parametrize("beta", [0.0, 1.0, 2.0])
+@pytest.mark.parametrize("mode", ["joint", "alternating"])
+def test_paths_agree(beta, mode):
+    # the single launch and the four launches compute the same update (to rounding)
+    p = synth.random_positive(230, 410, 33, seed=21)
+    a = gpu_step(p.V, p.W, p.H, beta, mode, path="stream")
+    b = gpu_step(p.V, p.W, p.H, beta, mode, path="fused")
+    assert rel(b[0], a[0].astype(np.float64)) <= 2e-6 and rel(b[1], a[1].astype(np.float64)) <= 2e-6
+    assert abs(a[2] - b[2]) <= 1e-12 * abs(a[2])
+
+
+def test_fused_path_refuses_large_k():
+    p = synth.random_positive(40, 50, 100, seed=22)
+    with pytest.raises(nb.NmfError):
+        gpu_step(p.V, p.W, p.H, 1.0, "joint", path="fused")
 
 
 @pytest.mark.parametrize("mode", ["joint", "alternating"])
 @pytest.mark.parametrize("beta", [0.0, 1.0])
-def test_kappa_smoothing_with_zeros(mode, beta):
+@pytest.mark.parametrize("path", ["stream", "fused"])
+def test_kappa_smoothing_with_zeros(mode, beta, path):
     p = synth.random_positive(120, 140, 10, seed=5, zeros=0.3)
-    check_step(p.V, p.W, p.H, beta, mode, kappa=0.05, tag="kappa")
+    check_step(p.V, p.W, p.H, beta, mode, kappa=0.05, tag="kappa", path=path)
 
 
 @pytest.mark.parametrize("mode", ["joint", "alternating"])
-def test_without_normalization(mode):
+@pytest.mark.parametrize("path", ["stream", "fused"])
+def test_without_normalization(mode, path):
     p = synth.random_positive(100, 140, 12, seed=6)
-    check_step(p.V, p.W, p.H, 0.5, mode, normalize=False, tag="nonorm")
+    check_step(p.V, p.W, p.H, 0.5, mode, normalize=False, tag="nonorm", path=path)
 
 
 def test_padded_leading_dimensions_and_unaligned_v():
@@ -223,10 +261,12 @@ def test_flags_nonfinite_and_domain():
     assert nb.get_flags(clear=True) & nb.FLAG_DOMAIN
     nb.validate(dev(Vz), Wd, Hd, 0.0, kappa=0.1)
     assert nb.get_flags(clear=True) == 0
-    Hz = torch.zeros_like(Hd)
-    nb.step(Vd, Wd, Hz, 1.0, "joint")
-    assert nb.get_flags(clear=True) & nb.FLAG_NONFINITE
-    assert nb.get_flags() == 0
+    for path in ("stream", "fused"):
+        ctx = ctx_for(path)
+        Hz = torch.zeros_like(Hd)
+        nb.step(Vd, Wd.clone(), Hz, 1.0, "joint", ctx=ctx)
+        assert nb.get_flags(clear=True, ctx=ctx) & nb.FLAG_NONFINITE
+        assert nb.get_flags(ctx=ctx) == 0
 
 
 def test_workspace_regrowth_between_sizes():
