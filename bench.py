@@ -24,7 +24,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "joint-MM vs alternating-MU iterations/s and time-to-objective per β, 1 MI355X"
-PEAK_FP32_MFMA = 157.3e12   # dense FP32 matrix FLOP/s
+PEAK_MFMA = {"fp32": 157.3e12, "bf16": 2.5e15, "fp16": 2.5e15}  # dense matrix FLOP/s
 PEAK_HBM = 8.0e12           # bytes/s
 
 
@@ -51,10 +51,10 @@ def _flops_bytes(F, N, K, beta, mode):
 KERNEL_NAMES = ("sweep_w", "update_w", "sweep_h", "update_h", "fused_step")
 
 
-def _run_steps(nb, V, W, H, beta, mode, n, ctx, obj=None, trace=None):
+def _run_steps(nb, V, W, H, beta, mode, n, ctx, obj=None, trace=None, precision="fp32"):
     for t in range(n):
         o = trace[t:t + 1] if trace is not None else obj
-        nb.step(V, W, H, beta, mode, objective_out=o, ctx=ctx)
+        nb.step(V, W, H, beta, mode, precision=precision, objective_out=o, ctx=ctx)
 
 
 def main(argv=None):
@@ -71,6 +71,8 @@ def main(argv=None):
     ap.add_argument("--path", default="auto", choices=["auto", "stream", "fused"])
     ap.add_argument("--target-blocks", type=int, default=0)
     ap.add_argument("--min-tiles", type=int, default=0)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"],
+                    help="operand type of the matrix products (element-wise terms stay float32)")
     args = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -106,12 +108,12 @@ def main(argv=None):
 
     for mode in ("joint", "alternating"):
         W, H = W0.clone(), H0.clone()
-        _run_steps(nb, V, W, H, beta, mode, args.warmup, ctx, obj=obj)
+        _run_steps(nb, V, W, H, beta, mode, args.warmup, ctx, obj=obj, precision=args.precision)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         e0.record()
-        _run_steps(nb, V, W, H, beta, mode, args.steps, ctx, obj=obj)
+        _run_steps(nb, V, W, H, beta, mode, args.steps, ctx, obj=obj, precision=args.precision)
         e1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -125,10 +127,10 @@ def main(argv=None):
     kern, phases = {}, {}
     for mode in ("joint", "alternating"):
         W, H = W0.clone(), H0.clone()
-        _run_steps(nb, V, W, H, beta, mode, 2, ctx, obj=obj)
+        _run_steps(nb, V, W, H, beta, mode, 2, ctx, obj=obj, precision=args.precision)
         torch.cuda.synchronize()
         ctx.profile(KERNEL_NAMES)
-        _run_steps(nb, V, W, H, beta, mode, args.steps, ctx, obj=obj)
+        _run_steps(nb, V, W, H, beta, mode, args.steps, ctx, obj=obj, precision=args.precision)
         torch.cuda.synchronize()
         kern[mode] = {}
         for k in KERNEL_NAMES:
@@ -144,8 +146,9 @@ def main(argv=None):
     flops, vbytes = fb[dom]
     t_dom = kern["joint"][dom]["avg_us"] * 1e-6
     intensity = flops / vbytes
-    if intensity >= PEAK_FP32_MFMA / PEAK_HBM:
-        roof = {"bound": "mfma", "achieved": flops / t_dom / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
+    peak_mfma = PEAK_MFMA[args.precision]
+    if intensity >= peak_mfma / PEAK_HBM:
+        roof = {"bound": "mfma", "achieved": flops / t_dom / 1e12, "peak": peak_mfma / 1e12,
                 "unit": "TFLOP/s"}
     else:
         roof = {"bound": "hbm", "achieved": vbytes / t_dom / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
@@ -165,7 +168,7 @@ def main(argv=None):
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        _run_steps(nb, V, W, H, beta, mode, T, ctx, trace=tr)
+        _run_steps(nb, V, W, H, beta, mode, T, ctx, trace=tr, precision=args.precision)
         e1.record()
         nb.objective(V, W, H, beta, out=tr[T:T + 1], ctx=ctx)
         torch.cuda.synchronize()
@@ -201,10 +204,10 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp16": "f16"}[args.precision],
         "data": "synthetic",
         "config": {"workload": args.workload, "F": F, "N": N, "K": K, "beta": beta, "mode": "joint",
-                   "precision": "fp32", "objective_every_step": True, "normalize": True,
+                   "precision": args.precision, "objective_every_step": True, "normalize": True,
                    "path": "fused" if "fused_step" in kern["joint"] else "stream"},
         "alternating": {"value": res["alternating"]["iters_per_s"], "ms_per_step": res["alternating"]["ms_per_step"]},
         "joint_speedup_per_iteration": res["alternating"]["ms_per_step"] / res["joint"]["ms_per_step"],

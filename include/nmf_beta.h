@@ -57,8 +57,13 @@ typedef enum {
 
 typedef enum {
   NMF_FP32 = 0, /* every product in float32 (matrix cores, fp32 accumulate) */
-  NMF_BF16 = 1, /* the three products with bfloat16 operands, fp32 accumulate */
-  NMF_FP16 = 2  /* the three products with float16 operands, fp32 accumulate */
+  NMF_BF16 = 1, /* products on bfloat16 matrix cores, fp32 accumulate: the W- and
+                   H-step contractions with single bfloat16 operands; Lambda = WH
+                   as hi*hi + lo*hi + hi*lo of split operands (about 2^-16
+                   relative), so the float32 element-wise terms and the float64
+                   objective see an almost float32 Lambda.  K <= 64. */
+  NMF_FP16 = 2  /* the same with float16 operands (operands must stay within
+                   float16 range).  K <= 64. */
 } nmf_precision;
 
 /* sticky numeric flags (nmf_get_flags) */
@@ -66,6 +71,9 @@ typedef enum {
 #define NMF_FLAG_DOMAIN 2u    /* nmf_beta_validate found data outside the domain */
 #define NMF_FLAG_BARRIER 4u   /* a single-launch step gave up waiting at a grid barrier
                                  (results of that call are invalid) */
+#define NMF_FLAG_RANGE 8u     /* NMF_FP16 mode: an operand of a float16 product was
+                                 outside the float16 range or not finite (the step's
+                                 result is then not meaningful) */
 
 typedef struct {
   int32_t precision;   /* nmf_precision; default NMF_FP32 */

@@ -24,7 +24,7 @@ from typing import Optional, Tuple
 __all__ = [
     "NmfError", "lib", "library_path", "Context", "default_context",
     "ALTERNATING", "JOINT", "FP32", "BF16", "FP16",
-    "FLAG_NONFINITE", "FLAG_DOMAIN", "KERNELS",
+    "FLAG_NONFINITE", "FLAG_DOMAIN", "FLAG_BARRIER", "FLAG_RANGE", "KERNELS",
     "step", "objective", "grad", "validate", "get_flags", "check_step_args",
     "BetaDivergence", "beta_divergence",
 ]
@@ -35,6 +35,7 @@ FLAG_NONFINITE, FLAG_DOMAIN = 1, 2
 KERNELS = {"sweep_w": 0, "update_w": 1, "sweep_h": 2, "update_h": 3, "fused_kl": 4, "fused_step": 5}
 PATHS = {"auto": 0, "stream": 1, "fused": 2}
 FLAG_BARRIER = 4
+FLAG_RANGE = 8  # float16 mode: an operand outside the float16 range
 MODES = {"alternating": ALTERNATING, "bmm": ALTERNATING, "joint": JOINT, "jmm": JOINT}
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16}
 

@@ -60,7 +60,7 @@ struct Plan {
   bool fused;                         // one cooperative launch (grid = fused_grid)
   int fused_grid;
   // byte offsets inside the workspace
-  size_t o_pobj, o_pnum, o_pden, o_prs, o_wn, o_c1, o_c2, o_wt, o_pcol, o_pnumh, o_pdenh, o_colsum, o_pst,
+  size_t o_pobj, o_pnum, o_pden, o_prs, o_wn, o_c1, o_c2, o_c0, o_wt, o_pcol, o_pnumh, o_pdenh, o_colsum, o_pst,
       o_qst, total;
 };
 
@@ -114,6 +114,7 @@ Plan layout(const Sizes& z, Plan p) {
   p.o_wn = take(z.fk);
   p.o_c1 = take(z.fk);
   p.o_c2 = take(z.fk);
+  p.o_c0 = take(z.fk);
   p.o_wt = take(z.wt);
   p.o_pcol = take(z.pcol);
   p.o_pnumh = take(z.pnumh);
@@ -218,7 +219,6 @@ nmf_status check_mats(int64_t F, int64_t N, int64_t K, const float* V, int64_t l
 nmf_status check_opts(const nmf_step_opts* o) {
   if (!o) return NMF_OK;
   if (o->precision != NMF_FP32 && o->precision != NMF_BF16 && o->precision != NMF_FP16) return NMF_ERR_UNSUPPORTED;
-  if (o->precision != NMF_FP32) return NMF_ERR_UNSUPPORTED;
   if (!is_fin(o->kappa) || o->kappa < 0.f) return NMF_ERR_BETA;
   if (o->inner_iters != 1) return NMF_ERR_UNSUPPORTED;
   if (o->normalize != 0 && o->normalize != 1) return NMF_ERR_ARG;
@@ -357,7 +357,10 @@ nmf_status nmf_check_step_args(int64_t F, int64_t N, int64_t K, const float* V, 
   if (st != NMF_OK) return st;
   if (!is_fin(beta)) return NMF_ERR_BETA;
   if (mode != NMF_ALTERNATING && mode != NMF_JOINT) return NMF_ERR_ARG;
-  return check_opts(opts);
+  st = check_opts(opts);
+  if (st != NMF_OK) return st;
+  if (opts && opts->precision != NMF_FP32 && K > 64) return NMF_ERR_UNSUPPORTED;
+  return NMF_OK;
 }
 
 nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K, const float* V, int64_t ldv,
@@ -373,11 +376,12 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   const int bc = beta_class(beta);
   const bool joint = (mode == NMF_JOINT);
   const bool want_obj = d_objective != nullptr;
+  const int prec = opts ? opts->precision : NMF_FP32;
   if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
   // path: one cooperative launch for problems whose P, Q tiles stay cache
   // resident (not under stream capture), else four streaming launches
   int fused_grid = 0;
-  if (c->path == NMF_PATH_FUSED && kblocks_for(K) <= 2 && F * N <= kFusedMaxEntries) {
+  if (c->path == NMF_PATH_FUSED && prec == NMF_FP32 && kblocks_for(K) <= 2 && F * N <= kFusedMaxEntries) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess) return NMF_ERR_HIP;
     if (cs == hipStreamCaptureStatusNone) fused_grid = fused_capacity(c, bc, kblocks_for(K), joint, want_obj);
@@ -401,6 +405,7 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   ra.pobj = (double*)(ws + p.o_pobj);
   ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
   ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
+  ra.flags = flags_ptr(c);
   const int sw_grid = p.row_blocks * p.n_groups;
 
   UpdateWArgs ua{};
@@ -409,11 +414,14 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   ua.beta = beta; ua.gamma = gamma_of(beta); ua.joint = joint; ua.beta_one = beta_one;
   ua.Wn = Wn; ua.C1 = C1; ua.C2 = C2; ua.pcol = (double*)(ws + p.o_pcol);
   ua.WT = (float*)(ws + p.o_wt); ua.ldt = p.ldt;
+  ua.C0 = (prec != NMF_FP32 && joint) ? (float*)(ws + p.o_c0) : nullptr;
   ua.flags = flags_ptr(c);
 
   SweepColsArgs ca{};
   ca.V = V; ca.ldv = ldv;
   ca.WT = ua.WT; ca.ldwt = p.ldt;
+  ca.C0 = ua.C0;
+  ca.flags = flags_ptr(c);
   if (joint) { ca.C1 = C1; ca.C2 = C2; }
   else { ca.C1 = Wn; ca.C2 = Wn; }
   ca.H = H; ca.ldh = ldh;
@@ -453,12 +461,16 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
     }));
   }
   hipError_t e = timed(c, NMF_KERNEL_SWEEP_W, s, [&] {
-    return launch_sweep_rows(bc, p.KB, KIND_UPDATE, want_obj, sw_grid, s, ra);
+    return prec == NMF_FP32 ? launch_sweep_rows(bc, p.KB, KIND_UPDATE, want_obj, sw_grid, s, ra)
+                            : launch_sweep_rows_lp(prec, bc, p.KB, want_obj, sw_grid, s, ra);
   });
   if (e != hipSuccess) return NMF_ERR_HIP;
   e = timed(c, NMF_KERNEL_UPDATE_W, s, [&] { return launch_update_w(p.KB, p.uw_blocks, s, ua); });
   if (e != hipSuccess) return NMF_ERR_HIP;
-  e = timed(c, NMF_KERNEL_SWEEP_H, s, [&] { return launch_sweep_cols(bc, p.KB, KIND_UPDATE, joint, sh_grid, s, ca); });
+  e = timed(c, NMF_KERNEL_SWEEP_H, s, [&] {
+    return prec == NMF_FP32 ? launch_sweep_cols(bc, p.KB, KIND_UPDATE, joint, sh_grid, s, ca)
+                            : launch_sweep_cols_lp(prec, bc, p.KB, joint, sh_grid, s, ca);
+  });
   if (e != hipSuccess) return NMF_ERR_HIP;
   e = timed(c, NMF_KERNEL_UPDATE_H, s, [&] { return launch_update_h(p.KB, p.uh_blocks, s, ha); });
   return hip_status(e);

@@ -427,6 +427,463 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
   }
 }
 
+// ---------------------------------------------------------------------------
+// Low-precision products (bfloat16 or float16 operands, float32 accumulation)
+// with v_mfma_f32_32x32x16_{bf16,f16}: lane (li, hi) supplies A[li][8hi..8hi+7]
+// and B[8hi..8hi+7][li]; the accumulator layout is the float32 one, so eight
+// consecutive accumulator registers (rows acc_row(8s + e, hi)) form the A
+// operand of a product contracting over those rows.
+// Lambda is formed as hi*hi + lo*hi + hi*lo of split operands (x = hi + lo,
+// both rounded to nearest even), accurate to about 2^-16 relative, so P, Q and
+// the objective are computed from an almost float32 Lambda; the W- and H-step
+// contractions take single low-precision operands.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+template <class T> struct LowP;
+template <> struct LowP<__bf16> {
+  typedef bf16x8 v8;
+  static __device__ __forceinline__ f32x16 mfma(v8 a, v8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct LowP<_Float16> {
+  typedef f16x8 v8;
+  static __device__ __forceinline__ f32x16 mfma(v8 a, v8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+// float16 operands must stay within the float16 range: ok is cleared when a
+// value about to be converted is larger than the largest finite float16 (or not
+// finite).  bfloat16 has the float32 range and needs no check.
+template <class T>
+__device__ __forceinline__ void range_check(const float (&x)[8], bool& ok) {
+  if constexpr (__is_same(T, _Float16)) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) ok = ok && (__builtin_fabsf(x[e]) <= 65504.f);
+  }
+}
+
+template <class T>
+__device__ __forceinline__ typename LowP<T>::v8 to_low(const float (&x)[8]) {
+  typename LowP<T>::v8 r;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) r[e] = (T)x[e];
+  return r;
+}
+template <class T>
+__device__ __forceinline__ void split_low(const float (&x)[8], typename LowP<T>::v8& h, typename LowP<T>::v8& l) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const T t = (T)x[e];
+    h[e] = t;
+    l[e] = (T)(x[e] - (float)t);
+  }
+}
+
+// rows item with low-precision products (update kind).  The H~ tile is staged
+// in LDS in float32 as in rows_item; operands are converted when read.
+template <int BC, int KB, bool OBJ, class T>
+__device__ __forceinline__ void rows_item_lp(const SweepRowsArgs& a, int item, float* lds, double& objsum) {
+  typedef typename LowP<T>::v8 v8;
+  constexpr int KP = 32 * KB;
+  constexpr int KS = KP / 16;  // 16-deep steps of Lambda
+  constexpr bool NEED_DEN = (BC != BC_B1);
+  constexpr bool ROWSUM = (BC == BC_B1);
+  float* const Hs0 = lds;
+  float* const Hs1 = lds + KP * kHS;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, hi = lane >> 5;
+  const int rb = item / a.n_groups, g = item % a.n_groups;
+  const int f0 = rb * kBlockRows + wave * kTile;
+  const int frow = f0 + li;
+  const bool frow_ok = frow < a.F;
+  const bool wave_on = f0 < a.F;
+  const int K = a.K, N = a.N;
+
+  bool rok = true;
+  // B operand of Lambda^T: lane holds W~[frow][16s + 8hi + e], split in two
+  v8 wBh[KS], wBl[KS];
+  {
+    float w[KS][8];
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = 16 * s + 8 * hi + e;
+        w[s][e] = ldc(a.W, (int64_t)frow * a.ldw + k, frow_ok && k < K);
+      }
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) w[s][e] = (frow_ok && 16 * s + 8 * hi + e < K) ? w[s][e] : 0.f;
+      range_check<T>(w[s], rok);
+      split_low<T>(w[s], wBh[s], wBl[s]);
+    }
+  }
+  f32x16 accN[KB], accD[KB];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) { accN[kb][r] = 0.f; accD[kb][r] = 0.f; }
+  }
+  float rsum[KB];
+#pragma unroll
+  for (int j = 0; j < KB; ++j) rsum[j] = 0.f;
+
+  auto load_h = [&](int n0, float4 (&r)[KB]) {
+    const bool full = a.hvec && n0 + kTile <= N;
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int e4 = tid + kBlock * j;
+      const int k = e4 >> 3, n = n0 + 4 * (e4 & 7);
+      const int64_t o = (int64_t)k * a.ldh + n;
+      if (full) {
+        r[j] = ldc4(a.H, o, k < K);
+      } else {
+        r[j].x = ldc(a.H, o + 0, k < K && n + 0 < N);
+        r[j].y = ldc(a.H, o + 1, k < K && n + 1 < N);
+        r[j].z = ldc(a.H, o + 2, k < K && n + 2 < N);
+        r[j].w = ldc(a.H, o + 3, k < K && n + 3 < N);
+      }
+    }
+  };
+  // rows k >= K must be exact zeros here: Lambda's split products do not
+  // multiply them by a zero weight in every term
+  auto store_h = [&](float* buf, int n0, const float4 (&r)[KB]) {
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int e4 = tid + kBlock * j;
+      const int k = e4 >> 3, n = n0 + 4 * (e4 & 7);
+      float4 x = r[j];
+      if (k >= K) x = make_float4(0.f, 0.f, 0.f, 0.f);
+      x.x = n + 0 < N ? x.x : 0.f;
+      x.y = n + 1 < N ? x.y : 0.f;
+      x.z = n + 2 < N ? x.z : 0.f;
+      x.w = n + 3 < N ? x.w : 0.f;
+      if (ROWSUM) rsum[j] += (x.x + x.y) + (x.z + x.w);
+      *reinterpret_cast<float4*>(&buf[k * kHS + 4 * (e4 & 7)]) = x;
+    }
+  };
+  const int64_t vrow = (int64_t)frow * a.ldv;
+  auto load_v = [&](int n0, float (&v)[16]) {
+    const bool full = a.vec4 && n0 + kTile <= N;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int nb = n0 + 8 * q + 4 * hi;
+      if (full) {
+        const float4 x = ldc4(a.V, vrow + nb, frow_ok);
+        v[4 * q + 0] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[4 * q + j] = ldc(a.V, vrow + nb + j, frow_ok && nb + j < N);
+      }
+    }
+  };
+
+  const int nt_total = (N + kTile - 1) / kTile;
+  const int t0 = g * a.tiles_per_group;
+  const int t1 = min(nt_total, t0 + a.tiles_per_group);
+  float4 hreg[KB];
+  float vcur[16], vnext[16];
+  __syncthreads();
+  if (t0 < t1) {
+    load_h(t0 * kTile, hreg);
+    if (wave_on) load_v(t0 * kTile, vcur);
+    store_h(Hs0, t0 * kTile, hreg);
+  }
+  __syncthreads();
+
+  for (int t = t0; t < t1; ++t) {
+    const float* hs = ((t - t0) & 1) ? Hs1 : Hs0;
+    const bool more = t + 1 < t1;
+    if (more) {
+      load_h((t + 1) * kTile, hreg);
+      if (wave_on) load_v((t + 1) * kTile, vnext);
+    }
+    if (wave_on) {
+      const int n0 = t * kTile;
+      f32x16 lam;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) lam[r] = 0.f;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        // A operand H~^T[n0+li][16s + 8hi + e] = H~[16s + 8hi + e][n0 + li]
+        float x[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = hs[(16 * s + 8 * hi + e) * kHS + li];
+        v8 ah, al;
+        split_low<T>(x, ah, al);
+        lam = LowP<T>::mfma(ah, wBh[s], lam);
+        lam = LowP<T>::mfma(al, wBh[s], lam);
+        lam = LowP<T>::mfma(ah, wBl[s], lam);
+      }
+      float P[16], Q[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int n = n0 + acc_row(r, hi);
+        const bool ok = frow_ok && n < N;
+        const float lk = lam[r] + a.kappa;
+        const float vk = vcur[r] + a.kappa;
+        beta_terms<BC>(vk, lk, a.bm2, P[r], Q[r]);
+        if (!ok) { P[r] = 0.f; Q[r] = 0.f; }
+        if (OBJ && ok) objsum += d_beta<BC>((double)vk, (double)lk, a.beta);
+      }
+#pragma unroll
+      for (int st = 0; st < 2; ++st) {
+        float pa[8], qa[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) { pa[e] = P[8 * st + e]; qa[e] = Q[8 * st + e]; }
+        range_check<T>(pa, rok);
+        if (NEED_DEN) range_check<T>(qa, rok);
+        const v8 pv = to_low<T>(pa);
+        const v8 qv = to_low<T>(qa);
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+          // B operand H~[kb*32 + li][n0 + acc_row(8 st + e, hi)]: columns 16 st + 4hi + {0..3, 8..11}
+          const float* row = &hs[(kb * 32 + li) * kHS + 16 * st + 4 * hi];
+          const float4 b0 = *reinterpret_cast<const float4*>(row);
+          const float4 b1 = *reinterpret_cast<const float4*>(row + 8);
+          const float bx[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+          range_check<T>(bx, rok);
+          const v8 bv = to_low<T>(bx);
+          accN[kb] = LowP<T>::mfma(pv, bv, accN[kb]);
+          if (NEED_DEN) accD[kb] = LowP<T>::mfma(qv, bv, accD[kb]);
+        }
+      }
+    }
+    if (more) {
+      store_h(((t - t0 + 1) & 1) ? Hs1 : Hs0, (t + 1) * kTile, hreg);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) vcur[i] = vnext[i];
+    }
+    __syncthreads();
+  }
+
+  if (wave_on) {
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int f = f0 + acc_row(r, hi);
+        if (f < a.F) {
+          const int64_t o = ((int64_t)g * a.F + f) * KP + kb * 32 + li;
+          a.pnum[o] = accN[kb][r];
+          if (NEED_DEN) a.pden[o] = accD[kb][r];
+        }
+      }
+    }
+  }
+  if (!rok) set_flag(a.flags, 8u);  // operand outside the float16 range
+  if (ROWSUM) {
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      float x = rsum[j];
+      x += __shfl_xor(x, 1, 64);
+      x += __shfl_xor(x, 2, 64);
+      x += __shfl_xor(x, 4, 64);
+      const int e4 = tid + kBlock * j;
+      if (rb == 0 && (e4 & 7) == 0) a.prs[g * KP + (e4 >> 3)] = x;
+    }
+  }
+}
+
+// LDS bytes of a low-precision cols item: the Lambda-forming factor tile and
+// chi_1 (and chi_2), row-major [32][KP + 4], double-buffered.
+template <int KB, bool C2_TILE>
+constexpr int cols_item_lp_lds() {
+  return 2 * kTile * (32 * KB + 4) * (C2_TILE ? 3 : 2) * 4;
+}
+
+// cols item with low-precision products (update kind).  The factor forming
+// Lambda is read row-major (C0, ld KP): W~ (joint) or W_new (alternating, then
+// C0 == C1 and its tile is staged once).
+template <int BC, int KB, bool DUAL, class T>
+__device__ __forceinline__ void cols_item_lp(const SweepColsArgs& a, int item, float* lds) {
+  typedef typename LowP<T>::v8 v8;
+  constexpr int KP = 32 * KB;
+  constexpr int KS = KP / 16;
+  constexpr int CS = KP + 4;
+  constexpr bool NEED_DEN = (BC != BC_B1);
+  constexpr bool C2_TILE = DUAL && NEED_DEN;
+  constexpr int NT_ = C2_TILE ? 3 : 2;  // staged tiles per buffer (C0, C1[, C2]); C0 unused when !DUAL
+  float* const base0 = lds;
+  float* const base1 = lds + NT_ * kTile * CS;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, hi = lane >> 5;
+  const int cb = item / a.f_groups, g = item % a.f_groups;
+  const int n0w = cb * kBlockRows + wave * kTile;
+  const int ncol = n0w + li;
+  const bool ncol_ok = ncol < a.N;
+  const bool wave_on = n0w < a.N;
+  const int K = a.K, F = a.F;
+
+  bool rok = true;
+  // B operand of Lambda = W H~: lane holds H~[16s + 8hi + e][ncol], split
+  v8 hBh[KS], hBl[KS];
+  {
+    float h[KS][8];
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = 16 * s + 8 * hi + e;
+        h[s][e] = ldc(a.H, (int64_t)k * a.ldh + ncol, ncol_ok && k < K);
+      }
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) h[s][e] = (ncol_ok && 16 * s + 8 * hi + e < K) ? h[s][e] : 0.f;
+      range_check<T>(h[s], rok);
+      split_low<T>(h[s], hBh[s], hBl[s]);
+    }
+  }
+  f32x16 accN[KB], accD[KB];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) { accN[kb][r] = 0.f; accD[kb][r] = 0.f; }
+  }
+
+  // staged tiles: [0] factor forming Lambda (C0; == C1 when !DUAL), [1] chi_1, [2] chi_2
+  float4 treg[NT_][KB];
+  const float* src[3] = {DUAL ? a.C0 : a.C1, a.C1, a.C2};
+  auto load_tiles = [&](int f0) {
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int e4 = tid + kBlock * j;
+      const int i = e4 / (KP / 4), c = 4 * (e4 % (KP / 4));
+      const bool ok = f0 + i < F;
+      const int64_t o = (int64_t)(f0 + i) * KP + c;
+#pragma unroll
+      for (int m = (DUAL ? 0 : 1); m < NT_; ++m) treg[m][j] = ldc4(src[m], o, ok);
+    }
+  };
+  // rows f >= F staged as zeros (the Lambda split products need exact zeros)
+  auto store_tiles = [&](float* base, int f0) {
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int e4 = tid + kBlock * j;
+      const int i = e4 / (KP / 4), c = 4 * (e4 % (KP / 4));
+      const bool ok = f0 + i < F;
+#pragma unroll
+      for (int m = (DUAL ? 0 : 1); m < NT_; ++m)
+        *reinterpret_cast<float4*>(&base[m * kTile * CS + i * CS + c]) = ok ? treg[m][j] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto load_v = [&](int f0, float (&v)[16]) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int f = f0 + acc_row(r, hi);
+      v[r] = ldc(a.V, (int64_t)f * a.ldv + ncol, ncol_ok && f < F);
+    }
+  };
+
+  const int ft_total = (F + kTile - 1) / kTile;
+  const int t0 = g * a.tiles_per_group;
+  const int t1 = min(ft_total, t0 + a.tiles_per_group);
+  float vcur[16], vnext[16];
+  __syncthreads();
+  if (t0 < t1) {
+    load_tiles(t0 * kTile);
+    if (wave_on) load_v(t0 * kTile, vcur);
+    store_tiles(base0, t0 * kTile);
+  }
+  __syncthreads();
+
+  for (int t = t0; t < t1; ++t) {
+    const float* base = ((t - t0) & 1) ? base1 : base0;
+    const bool more = t + 1 < t1;
+    if (more) {
+      load_tiles((t + 1) * kTile);
+      if (wave_on) load_v((t + 1) * kTile, vnext);
+    }
+    if (wave_on) {
+      const int f0 = t * kTile;
+      const float* w0 = base + (DUAL ? 0 : 1) * kTile * CS;
+      const float* c1s = base + kTile * CS;
+      const float* c2s = C2_TILE ? base + 2 * kTile * CS : c1s;
+      f32x16 lam;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) lam[r] = 0.f;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        // A operand W[f0 + li][16s + 8hi + e]
+        const float* row = &w0[li * CS + 16 * s + 8 * hi];
+        const float4 x0 = *reinterpret_cast<const float4*>(row);
+        const float4 x1 = *reinterpret_cast<const float4*>(row + 4);
+        const float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+        if (DUAL) range_check<T>(x, rok);
+        v8 ah, al;
+        split_low<T>(x, ah, al);
+        lam = LowP<T>::mfma(ah, hBh[s], lam);
+        lam = LowP<T>::mfma(al, hBh[s], lam);
+        lam = LowP<T>::mfma(ah, hBl[s], lam);
+      }
+      float P[16], Q[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int f = f0 + acc_row(r, hi);
+        const bool ok = ncol_ok && f < F;
+        beta_terms<BC>(vcur[r] + a.kappa, lam[r] + a.kappa, a.bm2, P[r], Q[r]);
+        if (!ok) { P[r] = 0.f; Q[r] = 0.f; }
+      }
+#pragma unroll
+      for (int st = 0; st < 2; ++st) {
+        float pa[8], qa[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) { pa[e] = P[8 * st + e]; qa[e] = Q[8 * st + e]; }
+        range_check<T>(pa, rok);
+        if (NEED_DEN) range_check<T>(qa, rok);
+        const v8 pv = to_low<T>(pa);
+        const v8 qv = to_low<T>(qa);
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+          float b1[8], b2[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int row = acc_row(8 * st + e, hi) * CS + kb * 32 + li;
+            b1[e] = c1s[row];
+            b2[e] = c2s[row];
+          }
+          range_check<T>(b1, rok);
+          if (NEED_DEN) range_check<T>(b2, rok);
+          accN[kb] = LowP<T>::mfma(pv, to_low<T>(b1), accN[kb]);
+          if (NEED_DEN) accD[kb] = LowP<T>::mfma(qv, to_low<T>(b2), accD[kb]);
+        }
+      }
+    }
+    if (more) {
+      store_tiles(((t - t0 + 1) & 1) ? base1 : base0, (t + 1) * kTile);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) vcur[i] = vnext[i];
+    }
+    __syncthreads();
+  }
+
+  if (wave_on) {
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int n = n0w + acc_row(r, hi);
+        if (n < a.N) {
+          const int64_t o = ((int64_t)g * a.N + n) * KP + kb * 32 + li;
+          a.pnum[o] = accN[kb][r];
+          if (NEED_DEN) a.pden[o] = accD[kb][r];
+        }
+      }
+    }
+  }
+  if (!rok) set_flag(a.flags, 8u);  // operand outside the float16 range
+}
+
 // LDS bytes a cols item needs.
 template <int KB, bool C2_TILE>
 constexpr int cols_item_lds() {
@@ -719,6 +1176,7 @@ __device__ __forceinline__ void update_w_unit(const UpdateWArgs& a, int unit, bo
       const int64_t o = (int64_t)f * KP + k;
       a.Wn[o] = wn;
       if (a.joint) { a.C1[o] = c1; a.C2[o] = c2; }
+      if (a.C0) a.C0[o] = wtf;
       if (write_wt) a.WT[(int64_t)k * a.ldt + f] = a.joint ? wtf : wn;
     }
   }

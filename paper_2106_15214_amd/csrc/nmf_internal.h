@@ -59,6 +59,7 @@ struct SweepRowsArgs {
   double* pobj;                    // [grid] objective partials (nullable)
   int vec4;                        // V rows 16-byte aligned
   int hvec;                        // H rows 16-byte aligned
+  unsigned* flags;                 // status word (float16 range check)
   float* Pst; float* Qst; int NT;  // P, Q tiles [row tile * NT + column tile][32 n][32 f] (fused joint pass)
 };
 
@@ -67,11 +68,13 @@ struct SweepColsArgs {
   const float* WT; int64_t ldwt;   // transposed factor forming Lambda (K x F): W~ joint, W_new alternating
   const float* H; int64_t ldh;     // tilde H (columns owned by each wave)
   const float* C1; const float* C2;  // contraction operands (chi_1, chi_2): F x KP, ld KP, zero-padded
+  const float* C0;                   // row-major factor forming Lambda (low-precision joint pass): F x KP
   int F, N, K;
   float bm2, kappa;
   int f_groups, tiles_per_group;   // grid = col_blocks (128 columns) * f_groups
   float* pnum; float* pden;        // [f_groups][N][KP] partial H contractions
   const float* Pst; const float* Qst; int NT;  // stored P, Q tiles (fused joint pass)
+  unsigned* flags;                 // status word (float16 range check)
 };
 
 struct UpdateWArgs {
@@ -82,6 +85,7 @@ struct UpdateWArgs {
   int joint, beta_one;
   float* Wn; float* C1; float* C2; // [F][KP]
   float* WT; int64_t ldt;          // [KP][ldt]: W~^T (joint) or W_new^T (alternating)
+  float* C0;                       // nullable: W~ row-major, ld KP (joint, low-precision products)
   double* pcol;                    // [grid][2][KP] column norm^2 and sum partials
   unsigned* flags;
 };
@@ -101,6 +105,9 @@ struct UpdateHArgs {
 // launchers (nmf_kernels.hip)
 hipError_t launch_sweep_rows(int bc, int kb, int kind, bool obj, int grid, hipStream_t s, const SweepRowsArgs& a);
 hipError_t launch_sweep_cols(int bc, int kb, int kind, bool dual, int grid, hipStream_t s, const SweepColsArgs& a);
+// low-precision products (prec 1 = bfloat16, 2 = float16; update kind, K <= 64)
+hipError_t launch_sweep_rows_lp(int prec, int bc, int kb, bool obj, int grid, hipStream_t s, const SweepRowsArgs& a);
+hipError_t launch_sweep_cols_lp(int prec, int bc, int kb, bool dual, int grid, hipStream_t s, const SweepColsArgs& a);
 hipError_t launch_update_w(int kb, int grid, hipStream_t s, const UpdateWArgs& a);
 hipError_t launch_update_h(int kb, int grid, hipStream_t s, const UpdateHArgs& a);
 hipError_t launch_finalize_objective(hipStream_t s, const double* pobj, int n, double* out, unsigned* flags);
