@@ -48,14 +48,16 @@ namespace {
 // the fused kernel's grid-barrier words (arrivals, generation) at bytes 8, 12,
 // and its eight phase stamps (uint64) at bytes 64..127.
 constexpr size_t kHeaderBytes = 256;
-constexpr int kUpdateWBlocks = 256;
-constexpr int kUnitRowsMin = 1;
+constexpr int kFusedMaxPerCU = 8;      // bound on co-resident fused workgroups per CU (workspace sizing)
+constexpr int kUpdateWBlocks = 4096;  // W-update workgroups at most (one unit of rows each, or more)
+constexpr int kColChunkRows = 512;  // rows of W_new per column-partial workgroup of the H pass
 
 struct Plan {
   int KB, KP;
   int row_blocks, n_groups, tiles_n;  // sweep_rows grid = row_blocks * n_groups
   int col_blocks, f_groups, tiles_f;  // sweep_cols grid = col_blocks * f_groups
   int uw_blocks, uh_blocks;
+  int col_parts, col_chunk;           // column partials of W_new formed in the H pass
   int64_t ldt;                        // leading dimension of the transposed factor (K x F)
   bool fused;                         // one cooperative launch (grid = fused_grid)
   int fused_grid;
@@ -132,7 +134,7 @@ constexpr int64_t kFusedMaxEntries = int64_t(1) << 24;
 
 int fused_capacity(nmf_ctx_s* c, int bc, int kb, bool joint, bool obj) {
   int& slot = c->fused_grid[kb - 1][bc][joint][obj];
-  if (slot == 0) slot = 1 + fused_max_blocks(bc, kb, joint, obj, c->num_cus);
+  if (slot == 0) slot = 1 + std::min(fused_max_blocks(bc, kb, joint, obj, c->num_cus), kFusedMaxPerCU * c->num_cus);
   return slot - 1;
 }
 
@@ -151,8 +153,13 @@ Plan make_plan(const nmf_ctx_s* c, int64_t F, int64_t N, int64_t K, int cols_occ
   p.n_groups = choose_groups(c, cdiv(N, kTile), p.row_blocks, F, p.KB, rows_slots, &p.tiles_n);
   p.col_blocks = (int)cdiv(N, kBlockRows);
   p.f_groups = choose_groups(c, cdiv(F, kTile), p.col_blocks, N, p.KB, cols_slots, &p.tiles_f);
-  p.uw_blocks = p.fused ? fused_grid : (int)std::min<int64_t>(kUpdateWBlocks, cdiv(F, kUnitRowsMin));
-  p.uh_blocks = (int)cdiv(N, kTile);
+  p.uw_blocks = p.fused ? fused_grid : (int)std::min<int64_t>(kUpdateWBlocks, cdiv(F, update_w_unit_rows(p.KB)));
+  {
+    const int64_t rows = (int64_t)p.tiles_f * kTile;
+    p.col_parts = (int)std::min<int64_t>(p.col_blocks, cdiv(rows, kColChunkRows));
+    p.col_chunk = (int)cdiv(rows, p.col_parts);
+  }
+  p.uh_blocks = p.fused ? (int)cdiv(N, kTile) : (int)cdiv(N, kBlock / p.KP);
   p.ldt = cdiv(F, 4) * 4;
   Sizes z;
   z.pobj = sizeof(double) * (size_t)std::max<int64_t>((int64_t)p.row_blocks * p.n_groups, fused_grid);
@@ -160,7 +167,7 @@ Plan make_plan(const nmf_ctx_s* c, int64_t F, int64_t N, int64_t K, int cols_occ
   z.prs = sizeof(float) * (size_t)p.n_groups * p.KP;
   z.fk = sizeof(float) * (size_t)F * p.KP;
   z.wt = sizeof(float) * (size_t)p.KP * p.ldt;
-  z.pcol = sizeof(double) * (size_t)p.uw_blocks * 2 * p.KP;
+  z.pcol = sizeof(double) * (size_t)(p.fused ? p.uw_blocks : (int64_t)p.f_groups * p.col_parts) * 2 * p.KP;
   z.pnumh = sizeof(float) * (size_t)p.f_groups * N * p.KP;
   z.pq = p.fused ? sizeof(float) * (size_t)cdiv(F, kTile) * cdiv(N, kTile) * kTile * kTile : 0;
   return layout(z, p);
@@ -185,7 +192,9 @@ size_t plan_bound(const nmf_ctx_s* c, int64_t maxF, int64_t maxN, int64_t maxK) 
   z.prs = sizeof(float) * (size_t)((cap_blocks + 1) * KP);
   z.fk = sizeof(float) * (size_t)(maxF * KP);
   z.wt = sizeof(float) * (size_t)(KP * cdiv(maxF, 4) * 4);
-  z.pcol = sizeof(double) * (size_t)(kUpdateWBlocks * 2 * KP);
+  // fused: one row per workgroup; streaming: f_groups * col_parts <= 2 * row tiles + 1
+  const int64_t pcol_rows = std::max<int64_t>(kFusedMaxPerCU * (int64_t)c->num_cus, 2 * cdiv(maxF, kTile) + 1);
+  z.pcol = sizeof(double) * (size_t)(pcol_rows * 2 * KP);
   z.pnumh = sizeof(float) * (size_t)(rows_bound(maxN, maxF) * KP);
   const int64_t ft = cdiv(maxF, kTile), nt = cdiv(maxN, kTile);
   if (ft * nt * kTile * kTile <= 2 * kFusedMaxEntries) z.pq = sizeof(float) * (size_t)(ft * nt * kTile * kTile);
@@ -435,7 +444,8 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   ha.H = H; ha.ldh = ldh; ha.pnum = ca.pnum; ha.pden = ca.pden;
   ha.F = (int)F; ha.N = (int)N; ha.K = (int)K; ha.f_groups = p.f_groups;
   ha.gamma = gamma_of(beta); ha.beta_one = beta_one; ha.normalize = o.normalize;
-  ha.pcol = ua.pcol; ha.pcol_blocks = p.uw_blocks;
+  ha.pcol = ua.pcol; ha.pcol_blocks = p.fused ? p.uw_blocks : p.f_groups * p.col_parts;
+  if (!p.fused) { ca.Wn = Wn; ca.pcol = ua.pcol; ca.col_parts = p.col_parts; ca.col_chunk = p.col_chunk; }
   ha.pobj = ra.pobj; ha.nobj = sw_grid; ha.d_obj = d_objective;
   ha.Wn = Wn; ha.W = W; ha.ldw = ldw; ha.flags = flags_ptr(c);
 

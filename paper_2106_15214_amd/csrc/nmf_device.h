@@ -884,6 +884,59 @@ __device__ __forceinline__ void cols_item_lp(const SweepColsArgs& a, int item, f
   if (!rok) set_flag(a.flags, 8u);  // operand outside the float16 range
 }
 
+// Column sums of W_new^2 and W_new over rows [f0, f1) of the row-major W_new
+// (ld KP), in float64 and a fixed order -> out[0..KP) and out[KP..2KP).  Done
+// by a few workgroups of the H pass, so the H update reads a handful of partial
+// rows instead of one per W-update workgroup.
+template <int KB>
+__device__ __forceinline__ void column_partials(const float* Wn, int f0, int f1, double* out, double* scratch) {
+  constexpr int KP = 32 * KB;
+  constexpr int R = kBlock / KP;
+  constexpr int U = 4;
+  const int tid = threadIdx.x;
+  const int k = tid % KP, part = tid / KP;
+  double x = 0.0, y = 0.0;
+  int f = f0 + part;
+  for (; f + (U - 1) * R < f1; f += U * R) {
+    float w[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) w[u] = Wn[(int64_t)(f + u * R) * KP + k];
+#pragma unroll
+    for (int u = 0; u < U; ++u) { x += (double)w[u] * (double)w[u]; y += (double)w[u]; }
+  }
+  for (; f < f1; f += R) {
+    const double w = (double)Wn[(int64_t)f * KP + k];
+    x += w * w;
+    y += w;
+  }
+  __syncthreads();
+  scratch[tid] = x;
+  scratch[kBlock + tid] = y;
+  __syncthreads();
+  if (tid < KP) {
+    double xs = 0.0, ys = 0.0;
+    for (int j = 0; j < R; ++j) { xs += scratch[j * KP + tid]; ys += scratch[kBlock + j * KP + tid]; }
+    out[tid] = xs;
+    out[KP + tid] = ys;
+  }
+  __syncthreads();
+}
+
+// H-pass prologue: the workgroups of the first col_parts column blocks write
+// the column partials of their share of the rows (see SweepColsArgs).
+template <int KB>
+__device__ __forceinline__ void cols_prologue(const SweepColsArgs& a, int item, float* lds) {
+  if (!a.pcol) return;
+  const int cb = item / a.f_groups, g = item % a.f_groups;
+  if (cb >= a.col_parts) return;
+  const int gf0 = g * a.tiles_per_group * kTile;
+  const int gf1 = min(a.F, gf0 + a.tiles_per_group * kTile);
+  const int f0 = min(gf1, gf0 + cb * a.col_chunk);
+  const int f1 = min(gf1, f0 + a.col_chunk);
+  column_partials<KB>(a.Wn, f0, f1, a.pcol + (int64_t)(g * a.col_parts + cb) * 2 * 32 * KB,
+                      reinterpret_cast<double*>(lds));
+}
+
 // LDS bytes a cols item needs.
 template <int KB, bool C2_TILE>
 constexpr int cols_item_lds() {
@@ -1270,6 +1323,50 @@ __device__ __forceinline__ void update_h_tile(const UpdateHArgs& a, int ntile, c
     const int kk = e / kTile, nl = e % kTile, n = n0 + nl;
     if (kk < a.K && n < a.N) a.H[(int64_t)kk * a.ldh + n] = (float)((double)hv[i] * S[kk * 33 + nl]);
   }
+}
+
+// H update for a few columns (streaming kernel): thread (k, c) of the block
+// owns entry H[k][n0 + c], n0 = unit * (kBlock / KP), and sums its f_groups
+// partials in one round of independent loads (eight groups per round), so the
+// kernel's latency is one partial read plus one H read-modify-write.
+template <int KB>
+__device__ __forceinline__ void update_h_cols(const UpdateHArgs& a, int unit, const float* norm_s,
+                                              const float* csum_s) {
+  constexpr int KP = 32 * KB;
+  constexpr int UC = kBlock / KP;  // columns per unit
+  constexpr int U = 8;
+  const int tid = threadIdx.x;
+  const int k = tid % KP, n = unit * UC + tid / KP;
+  const bool ok = n < a.N && k < a.K;
+  const int64_t gstride = (int64_t)a.N * KP;
+  const int64_t base = (int64_t)n * KP + k;
+  const float hv = ldc(a.H, (int64_t)k * a.ldh + n, ok);
+  double num = 0.0, den = 0.0;
+  for (int g = 0; g < a.f_groups; g += U) {
+    float xn[U], xd[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool gu = ok && g + u < a.f_groups;
+      xn[u] = ldc(a.pnum, (int64_t)(g + u) * gstride + base, gu);
+      xd[u] = a.beta_one ? 0.f : ldc(a.pden, (int64_t)(g + u) * gstride + base, gu);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool gu = g + u < a.f_groups;
+      num += gu ? (double)xn[u] : 0.0;
+      den += gu ? (double)xd[u] : 0.0;
+    }
+  }
+  if (!ok) return;
+  const double dd = a.beta_one ? (double)csum_s[k] : den;
+  const double ratio = num / dd;
+  if (!(dd > 0.0) || !isfinite(ratio)) set_flag(a.flags, 1u);
+  double nk = 1.0;
+  if (a.normalize) {
+    const float x = norm_s[k];
+    if (x > 0.f) nk = (double)x;
+  }
+  a.H[(int64_t)k * a.ldh + n] = (float)((double)hv * (pow_gamma(ratio, a.gamma) * nk));
 }
 
 // W <- W_new / norm (or W_new), entries e0, e0 + stride, ...

@@ -26,6 +26,8 @@ constexpr int kBlockRows = kWaves * kTile;  // rows (or columns) owned by one wo
 // the column pass with separate chi_1 / chi_2 tiles and all K > 64 variants
 // need the whole register file of a SIMD.
 constexpr int sweep_rows_occupancy(int KB) { return KB >= 4 ? 1 : 2; }
+// Rows of W per W-update unit (four thread slices per row of KP threads).
+constexpr int update_w_unit_rows(int KB) { return kBlock / (32 * KB * 4) > 0 ? kBlock / (32 * KB * 4) : 1; }
 constexpr int sweep_cols_occupancy(int bc, int KB, int kind, bool dual) {
   return (KB >= 4 || (dual && kind == KIND_UPDATE && bc != BC_B1)) ? 1 : 2;
 }
@@ -75,6 +77,10 @@ struct SweepColsArgs {
   float* pnum; float* pden;        // [f_groups][N][KP] partial H contractions
   const float* Pst; const float* Qst; int NT;  // stored P, Q tiles (fused joint pass)
   unsigned* flags;                 // status word (float16 range check)
+  // column sums of W_new^2 and W_new (normalization), nullable: workgroups of
+  // the first `col_parts` column blocks each cover `col_chunk` rows of their
+  // row group and write pcol[g * col_parts + cb][2][KP]
+  const float* Wn; double* pcol; int col_parts, col_chunk;
 };
 
 struct UpdateWArgs {
@@ -96,7 +102,7 @@ struct UpdateHArgs {
   int F, N, K, f_groups;
   double gamma;
   int beta_one, normalize;
-  const double* pcol; int pcol_blocks;   // update_w's column partials
+  const double* pcol; int pcol_blocks;   // column partials of W_new (pcol_blocks rows)
   const double* pobj; int nobj; double* d_obj;  // objective partials of the W pass
   const float* Wn; float* W; int64_t ldw;
   unsigned* flags;

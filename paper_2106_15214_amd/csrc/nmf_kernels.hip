@@ -23,25 +23,9 @@ __global__ __launch_bounds__(kBlock, sweep_cols_occupancy(BC, KB, KIND, DUAL)) v
     SweepColsArgs a) {
   constexpr bool C2_TILE = DUAL && (KIND == KIND_UPDATE) && (BC != BC_B1);
   __shared__ __align__(16) float lds[cols_item_lds<KB, C2_TILE>() / 4];
+  static_assert(cols_item_lds<KB, C2_TILE>() >= 2 * kBlock * 8, "column partial scratch");
+  if (KIND == KIND_UPDATE) cols_prologue<KB>(a, blockIdx.x, lds);
   cols_item<BC, KB, KIND, DUAL, false>(a, blockIdx.x, lds);
-}
-
-// Per-block column sums of W_new^2 and W_new (threads sharing k combined in a
-// fixed order) -> pcol[block][2][KP].
-template <int KB>
-__device__ __forceinline__ void store_column_partials(double nrm, double cs, double* sn, double* pcol) {
-  constexpr int KP = 32 * KB;
-  const int tid = threadIdx.x;
-  __syncthreads();
-  sn[tid] = nrm;
-  sn[kBlock + tid] = cs;
-  __syncthreads();
-  if (tid < KP) {
-    double x = 0.0, y = 0.0;
-    for (int j = 0; j < kBlock / KP; ++j) { x += sn[j * KP + tid]; y += sn[kBlock + j * KP + tid]; }
-    pcol[(int64_t)blockIdx.x * 2 * KP + tid] = x;
-    pcol[(int64_t)blockIdx.x * 2 * KP + KP + tid] = y;
-  }
 }
 
 // Sum over groups of the beta = 1 row-sum partials of H~ (the W-step denominator).
@@ -58,21 +42,17 @@ __device__ __forceinline__ double row_sum_den(const UpdateWArgs& a) {
 template <int KB>
 __global__ __launch_bounds__(kBlock) void update_w_kernel(UpdateWArgs a) {
   __shared__ double lds[2 * kBlock];
-  __shared__ double sn[2 * kBlock];
   const double den1 = row_sum_den<KB>(a);
-  double nrm = 0.0, cs = 0.0;
+  double nrm = 0.0, cs = 0.0;  // unused here: the H pass forms the column sums
   const int units = (a.F + unit_rows<KB>() - 1) / unit_rows<KB>();
   for (int u = blockIdx.x; u < units; u += gridDim.x)
     update_w_unit<KB>(a, u, true, reinterpret_cast<float*>(lds), den1, nrm, cs);
-  store_column_partials<KB>(nrm, cs, sn, a.pcol);
 }
 
 template <int KB>
 __global__ __launch_bounds__(kBlock) void update_h_kernel(UpdateHArgs a) {
-  constexpr int KP = 32 * KB;
-  __shared__ double S[KP * 33];
   __shared__ double scratch[2 * kBlock];
-  __shared__ float norm_s[KP], csum_s[KP];
+  __shared__ float norm_s[32 * KB], csum_s[32 * KB];
   __shared__ double red[kWaves];
   reduce_columns<KB>(a.pcol, a.pcol_blocks, scratch, norm_s, csum_s);
   if (blockIdx.x == 0 && a.d_obj) {
@@ -84,8 +64,8 @@ __global__ __launch_bounds__(kBlock) void update_h_kernel(UpdateHArgs a) {
       if (!isfinite(s)) set_flag(a.flags, 1u);
     }
   }
-  if ((int)blockIdx.x * kTile < a.N) update_h_tile<KB>(a, blockIdx.x, norm_s, csum_s, S);
   write_w<KB>(a, norm_s, (int64_t)blockIdx.x * kBlock + threadIdx.x, (int64_t)gridDim.x * kBlock);
+  update_h_cols<KB>(a, blockIdx.x, norm_s, csum_s);
 }
 
 // Transposed copy WT[k][f] = W[f][k] (k < KP, zero-padded) and a row-major copy

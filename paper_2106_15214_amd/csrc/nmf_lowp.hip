@@ -19,6 +19,8 @@ __global__ __launch_bounds__(kBlock, 2) void sweep_rows_lp_kernel(SweepRowsArgs 
 template <int BC, int KB, bool DUAL, class T>
 __global__ __launch_bounds__(kBlock, 2) void sweep_cols_lp_kernel(SweepColsArgs a) {
   __shared__ __align__(16) float lds[cols_item_lp_lds<KB, DUAL && (BC != BC_B1)>() / 4];
+  static_assert(cols_item_lp_lds<KB, DUAL && (BC != BC_B1)>() >= 2 * kBlock * 8, "column partial scratch");
+  cols_prologue<KB>(a, blockIdx.x, lds);
   cols_item_lp<BC, KB, DUAL, T>(a, blockIdx.x, lds);
 }
 
