@@ -76,7 +76,7 @@ int kblocks_for(int64_t K) {
 // into, for `blocks` workgroups along the other dimension.  Minimizes a cost in
 // tile-times: resident rounds x (tiles per group + 2 for prologue/epilogue)
 // plus the partial-sum traffic (two arrays of groups * out_len * KP floats,
-// written and read at ~12 MB per tile-time).
+// written and read at ~24 MB per tile-time).
 int choose_groups(const nmf_ctx_s* c, int64_t tiles, int64_t blocks, int64_t out_len, int KB, int64_t slots,
                   int* per_group) {
   const int64_t min_tpg = std::max(1, c->min_tiles);
@@ -91,7 +91,7 @@ int choose_groups(const nmf_ctx_s* c, int64_t tiles, int64_t blocks, int64_t out
       const int64_t tpg = cdiv(tiles, g);
       if (g > 1 && cdiv(tiles, tpg) < g) continue;  // same split as a smaller g
       const double rounds = (double)cdiv(blocks * g, slots);
-      const double partial = 4.0 * (double)g * out_len * 32 * KB * 4 / 12.0e6;
+      const double partial = 4.0 * (double)g * out_len * 32 * KB * 4 / 24.0e6;
       const double cost = rounds * (tpg + 2.0) + partial;
       if (cost < best) { best = cost; best_g = g; }
     }
@@ -293,6 +293,71 @@ hipError_t timed(nmf_ctx_s* c, int kernel, hipStream_t s, Fn&& launch) {
   return e;
 }
 
+// Kernel arguments of one outer iteration of a problem whose workspace regions
+// (offsets of `p`) start at `ws`.
+struct StepArgs {
+  SweepRowsArgs ra;
+  UpdateWArgs ua;
+  SweepColsArgs ca;
+  UpdateHArgs ha;
+  int sw_grid, sh_grid;
+};
+
+StepArgs make_step_args(const Plan& p, char* ws, unsigned* flags, int64_t F, int64_t N, int64_t K, const float* V,
+                        int64_t ldv, float* W, int64_t ldw, float* H, int64_t ldh, double beta, bool joint, int prec,
+                        const nmf_step_opts& o, double* d_objective) {
+  const int bc = beta_class(beta);
+  const bool beta_one = (bc == BC_B1);
+  float* Wn = (float*)(ws + p.o_wn);
+  float* C1 = (float*)(ws + p.o_c1);
+  float* C2 = (float*)(ws + p.o_c2);
+  StepArgs sa{};
+  SweepRowsArgs& ra = sa.ra;
+  ra.V = V; ra.ldv = ldv; ra.W = W; ra.ldw = ldw; ra.H = H; ra.ldh = ldh;
+  ra.F = (int)F; ra.N = (int)N; ra.K = (int)K;
+  ra.bm2 = (float)(beta - 2.0); ra.kappa = o.kappa; ra.beta = beta;
+  ra.n_groups = p.n_groups; ra.tiles_per_group = p.tiles_n;
+  ra.pnum = (float*)(ws + p.o_pnum); ra.pden = (float*)(ws + p.o_pden); ra.prs = (float*)(ws + p.o_prs);
+  ra.pobj = (double*)(ws + p.o_pobj);
+  ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
+  ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
+  ra.flags = flags;
+  sa.sw_grid = p.row_blocks * p.n_groups;
+
+  UpdateWArgs& ua = sa.ua;
+  ua.W = W; ua.ldw = ldw; ua.pnum = ra.pnum; ua.pden = ra.pden; ua.prs = ra.prs;
+  ua.F = (int)F; ua.K = (int)K; ua.n_groups = p.n_groups;
+  ua.beta = beta; ua.gamma = gamma_of(beta); ua.joint = joint; ua.beta_one = beta_one;
+  ua.Wn = Wn; ua.C1 = C1; ua.C2 = C2; ua.pcol = (double*)(ws + p.o_pcol);
+  ua.WT = (float*)(ws + p.o_wt); ua.ldt = p.ldt;
+  ua.C0 = (prec != NMF_FP32 && joint) ? (float*)(ws + p.o_c0) : nullptr;
+  ua.flags = flags;
+
+  SweepColsArgs& ca = sa.ca;
+  ca.V = V; ca.ldv = ldv;
+  ca.WT = ua.WT; ca.ldwt = p.ldt;
+  ca.C0 = ua.C0;
+  ca.flags = flags;
+  if (joint) { ca.C1 = C1; ca.C2 = C2; }
+  else { ca.C1 = Wn; ca.C2 = Wn; }
+  ca.H = H; ca.ldh = ldh;
+  ca.F = (int)F; ca.N = (int)N; ca.K = (int)K;
+  ca.bm2 = (float)(beta - 2.0); ca.kappa = o.kappa;
+  ca.f_groups = p.f_groups; ca.tiles_per_group = p.tiles_f;
+  ca.pnum = (float*)(ws + p.o_pnumh); ca.pden = (float*)(ws + p.o_pdenh);
+  sa.sh_grid = p.col_blocks * p.f_groups;
+
+  UpdateHArgs& ha = sa.ha;
+  ha.H = H; ha.ldh = ldh; ha.pnum = ca.pnum; ha.pden = ca.pden;
+  ha.F = (int)F; ha.N = (int)N; ha.K = (int)K; ha.f_groups = p.f_groups;
+  ha.gamma = gamma_of(beta); ha.beta_one = beta_one; ha.normalize = o.normalize;
+  ha.pcol = ua.pcol; ha.pcol_blocks = p.fused ? p.uw_blocks : p.f_groups * p.col_parts;
+  if (!p.fused) { ca.Wn = Wn; ca.pcol = ua.pcol; ca.col_parts = p.col_parts; ca.col_chunk = p.col_chunk; }
+  ha.pobj = ra.pobj; ha.nobj = sa.sw_grid; ha.d_obj = d_objective;
+  ha.Wn = Wn; ha.W = W; ha.ldw = ldw; ha.flags = flags;
+  return sa;
+}
+
 }  // namespace
 
 extern "C" {
@@ -399,55 +464,14 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   const Plan p = make_plan(c, F, N, K, sweep_cols_occupancy(bc, kblocks_for(K), KIND_UPDATE, joint), fused_grid);
   if ((st = ensure_ws(c, s, p.total)) != NMF_OK) return st;
 
-  const bool beta_one = (bc == BC_B1);
+  StepArgs sa = make_step_args(p, c->ws, flags_ptr(c), F, N, K, V, ldv, W, ldw, H, ldh, beta, joint, prec, o,
+                                d_objective);
+  SweepRowsArgs& ra = sa.ra;
+  UpdateWArgs& ua = sa.ua;
+  SweepColsArgs& ca = sa.ca;
+  UpdateHArgs& ha = sa.ha;
+  const int sw_grid = sa.sw_grid, sh_grid = sa.sh_grid;
   char* ws = c->ws;
-  float* Wn = (float*)(ws + p.o_wn);
-  float* C1 = (float*)(ws + p.o_c1);
-  float* C2 = (float*)(ws + p.o_c2);
-
-  SweepRowsArgs ra{};
-  ra.V = V; ra.ldv = ldv; ra.W = W; ra.ldw = ldw; ra.H = H; ra.ldh = ldh;
-  ra.F = (int)F; ra.N = (int)N; ra.K = (int)K;
-  ra.bm2 = (float)(beta - 2.0); ra.kappa = o.kappa; ra.beta = beta;
-  ra.n_groups = p.n_groups; ra.tiles_per_group = p.tiles_n;
-  ra.pnum = (float*)(ws + p.o_pnum); ra.pden = (float*)(ws + p.o_pden); ra.prs = (float*)(ws + p.o_prs);
-  ra.pobj = (double*)(ws + p.o_pobj);
-  ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
-  ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
-  ra.flags = flags_ptr(c);
-  const int sw_grid = p.row_blocks * p.n_groups;
-
-  UpdateWArgs ua{};
-  ua.W = W; ua.ldw = ldw; ua.pnum = ra.pnum; ua.pden = ra.pden; ua.prs = ra.prs;
-  ua.F = (int)F; ua.K = (int)K; ua.n_groups = p.n_groups;
-  ua.beta = beta; ua.gamma = gamma_of(beta); ua.joint = joint; ua.beta_one = beta_one;
-  ua.Wn = Wn; ua.C1 = C1; ua.C2 = C2; ua.pcol = (double*)(ws + p.o_pcol);
-  ua.WT = (float*)(ws + p.o_wt); ua.ldt = p.ldt;
-  ua.C0 = (prec != NMF_FP32 && joint) ? (float*)(ws + p.o_c0) : nullptr;
-  ua.flags = flags_ptr(c);
-
-  SweepColsArgs ca{};
-  ca.V = V; ca.ldv = ldv;
-  ca.WT = ua.WT; ca.ldwt = p.ldt;
-  ca.C0 = ua.C0;
-  ca.flags = flags_ptr(c);
-  if (joint) { ca.C1 = C1; ca.C2 = C2; }
-  else { ca.C1 = Wn; ca.C2 = Wn; }
-  ca.H = H; ca.ldh = ldh;
-  ca.F = (int)F; ca.N = (int)N; ca.K = (int)K;
-  ca.bm2 = (float)(beta - 2.0); ca.kappa = o.kappa;
-  ca.f_groups = p.f_groups; ca.tiles_per_group = p.tiles_f;
-  ca.pnum = (float*)(ws + p.o_pnumh); ca.pden = (float*)(ws + p.o_pdenh);
-  const int sh_grid = p.col_blocks * p.f_groups;
-
-  UpdateHArgs ha{};
-  ha.H = H; ha.ldh = ldh; ha.pnum = ca.pnum; ha.pden = ca.pden;
-  ha.F = (int)F; ha.N = (int)N; ha.K = (int)K; ha.f_groups = p.f_groups;
-  ha.gamma = gamma_of(beta); ha.beta_one = beta_one; ha.normalize = o.normalize;
-  ha.pcol = ua.pcol; ha.pcol_blocks = p.fused ? p.uw_blocks : p.f_groups * p.col_parts;
-  if (!p.fused) { ca.Wn = Wn; ca.pcol = ua.pcol; ca.col_parts = p.col_parts; ca.col_chunk = p.col_chunk; }
-  ha.pobj = ra.pobj; ha.nobj = sw_grid; ha.d_obj = d_objective;
-  ha.Wn = Wn; ha.W = W; ha.ldw = ldw; ha.flags = flags_ptr(c);
 
   if (p.fused) {
     // joint: the H pass contracts the P, Q tiles stored by the W pass

@@ -1327,7 +1327,7 @@ __device__ __forceinline__ void update_h_tile(const UpdateHArgs& a, int ntile, c
 
 // H update for a few columns (streaming kernel): thread (k, c) of the block
 // owns entry H[k][n0 + c], n0 = unit * (kBlock / KP), and sums its f_groups
-// partials in one round of independent loads (eight groups per round), so the
+// partials in rounds of independent loads (eight groups per round), so the
 // kernel's latency is one partial read plus one H read-modify-write.
 template <int KB>
 __device__ __forceinline__ void update_h_cols(const UpdateHArgs& a, int unit, const float* norm_s,
