@@ -51,6 +51,42 @@ def _flops_bytes(F, N, K, beta, mode):
 KERNEL_NAMES = ("sweep_w", "update_w", "sweep_h", "update_h", "fused_step")
 
 
+def source_digest() -> str:
+    """SHA-256 over the library sources and the public header: identifies the
+    kernels a committed counter summary was taken on."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2106_15214_amd", "csrc", "*")))
+    files += sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, precision: str, kernel: str):
+    """Calibrated HBM bytes per launch of `kernel` in the joint step, from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of this workload, or None
+    when there is none or the kernels changed since it was taken."""
+    name = f"kernels_{workload}" + ("" if precision == "fp32" else f"_precision_{precision}") + ".txt"
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    digest, value = None, None
+    with open(path) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) == 2 and parts[0] == "source_sha256":
+                digest = parts[1]
+            elif len(parts) == 3 and parts[0] == "traffic_joint" and parts[1] == kernel:
+                value = float(parts[2])
+    if digest != source_digest():
+        return None
+    return value
+
+
 def _run_steps(nb, V, W, H, beta, mode, n, ctx, obj=None, trace=None, precision="fp32"):
     for t in range(n):
         o = trace[t:t + 1] if trace is not None else obj
@@ -71,6 +107,8 @@ def main(argv=None):
     ap.add_argument("--path", default="auto", choices=["auto", "stream", "fused"])
     ap.add_argument("--target-blocks", type=int, default=0)
     ap.add_argument("--min-tiles", type=int, default=0)
+    ap.add_argument("--problems", type=int, default=512, help="batched workload: number of problems")
+    ap.add_argument("--tune", default=None, help="batched workload: autotune, caching results in this JSON file")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"],
                     help="operand type of the matrix products (element-wise terms stay float32)")
     args = ap.parse_args(argv)
@@ -91,6 +129,8 @@ def main(argv=None):
         return 2
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "batched":
+        return main_batched(args, nb, synth, torch, np, dev)
     p = synth.make_problem(args.workload, beta=args.beta)
     F, N, K = p.shape
     beta = p.beta
@@ -153,7 +193,7 @@ def main(argv=None):
     else:
         roof = {"bound": "hbm", "achieved": vbytes / t_dom / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(args.workload, args.precision, dom)
     roof["kernel"] = dom
     roof["algorithmic_flops_per_launch"] = flops
     roof["algorithmic_bytes_per_launch"] = vbytes
@@ -232,6 +272,122 @@ def main(argv=None):
     print(json.dumps(out), flush=True)
     ctx.close()
     return 0
+
+
+def main_batched(args, nb, synth, torch, np, dev):
+    """Many uneven problems (each with its own beta and rank) updated by one
+    persistent launch per outer iteration.  A step is one outer iteration of
+    every problem; `value` is steps per second."""
+    specs = synth.batched_specs(args.problems)
+    t0 = time.perf_counter()
+    probs, host = [], []
+    for sp in specs:
+        q = synth.make_batched_problem(sp)
+        host.append(q)
+        probs.append((torch.from_numpy(q.V).to(dev), torch.from_numpy(q.W).to(dev), torch.from_numpy(q.H).to(dev),
+                      q.beta))
+    fnk = sum(q.V.shape[0] * q.V.shape[1] * q.W.shape[1] for q in host)
+    fn = sum(q.V.shape[0] * q.V.shape[1] for q in host)
+    # algorithmic work of the joint step: 10 FNK (6 FNK at beta = 1), V read in both passes
+    flops = sum((6 if q.beta == 1.0 else 10) * q.V.shape[0] * q.V.shape[1] * q.W.shape[1] for q in host)
+    vbytes = 8 * fn
+    print(f"# batched: {len(probs)} problems, sum FN = {fn:.3e}, sum FNK = {fnk:.3e} "
+          f"(generated in {time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    ctx = nb.Context(0)
+    cfg = {"tiles_per_item": 0, "workers": 0}
+    tuned_ms = None
+    if args.tune:
+        cfg, tuned_ms = nb.batch_tune(probs, "joint", precision=args.precision, iters=3, cache=args.tune, ctx=ctx)
+        print(f"# tuned: {cfg} ({tuned_ms:.3f} ms/step)", file=sys.stderr, flush=True)
+    res = {}
+    W0 = [(W.clone(), H.clone()) for _, W, H, _ in probs]
+    for mode in ("joint", "alternating"):
+        for (_, W, H, _), (Ws, Hs) in zip(probs, W0):
+            W.copy_(Ws)
+            H.copy_(Hs)
+        b = nb.Batch(probs, mode, precision=args.precision, ctx=ctx, **cfg)
+        obj = torch.zeros(len(probs), dtype=torch.float64, device=dev)
+        for _ in range(args.warmup):
+            b.step(objectives=obj)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            b.step(objectives=obj)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        fl = b.flags(clear=True)
+        res[mode] = {"ms_per_step": ms, "steps_per_s": 1e3 / ms, "flags": fl, **b.info()}
+        print(f"# {mode}: {ms:.3f} ms/step, flags {fl}, {b.info()}", file=sys.stderr, flush=True)
+        b.close()
+    t = res["joint"]["ms_per_step"] * 1e-3
+    peak_mfma = PEAK_MFMA[args.precision]
+    if flops / vbytes >= peak_mfma / PEAK_HBM:
+        roof = {"bound": "mfma", "achieved": flops / t / 1e12, "peak": peak_mfma / 1e12, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": vbytes / t / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = measured_traffic("batched", args.precision, "batched_step")
+    roof["kernel"] = "batched_step"
+    roof["algorithmic_flops_per_launch"] = flops
+    roof["algorithmic_bytes_per_launch"] = vbytes
+    roof["avg_launch_us"] = res["joint"]["ms_per_step"] * 1e3
+    out = {
+        "metric": METRIC,
+        "value": res["joint"]["steps_per_s"],
+        "unit": "iterations/s (all problems per iteration)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res["joint"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp16": "f16"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "batched", "problems": len(probs), "sum_FN": fn, "sum_FNK": fnk, "mode": "joint",
+                   "precision": args.precision, "objective_every_step": True, "launches_per_step": 1, **cfg},
+        "problem_iterations_per_s": len(probs) * res["joint"]["steps_per_s"],
+        "alternating": {"value": res["alternating"]["steps_per_s"], "ms_per_step": res["alternating"]["ms_per_step"]},
+        "tuned_ms": tuned_ms,
+        "roofline": roof,
+        "batch": res,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batched(host, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
+def cpu_baseline_batched(host, budget_s):
+    """The FP64 oracle's joint iteration over the problems in order for about
+    `budget_s` seconds, scaled to one iteration of the whole batch by the share
+    of sum(FNK) covered."""
+    import numpy as np
+    import oracle
+    total = sum(q.V.shape[0] * q.V.shape[1] * q.W.shape[1] for q in host)
+    done, n = 0, 0
+    t0 = time.perf_counter()
+    for q in host:
+        V, W, H = q.V.astype(np.float64), q.W.astype(np.float64), q.H.astype(np.float64)
+        oracle.objective(V, W, H, q.beta)
+        oracle.jmm_iteration(V, W, H, q.beta)
+        done += q.V.shape[0] * q.V.shape[1] * q.W.shape[1]
+        n += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    share = done / total
+    return {"value": share / el, "unit": "iterations/s (all problems per iteration)", "cores": _blas_threads(),
+            "kind": "oracle",
+            "sample": f"{n} of {len(host)} problems, one joint iteration each (objective + update, float64 NumPy), "
+                      f"{share * 100:.1f}% of sum FNK in {el:.1f} s, scaled to the whole batch"}
+
+
+def _blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:  # pragma: no cover
+        return len(os.sched_getaffinity(0))
 
 
 def cpu_baseline(p, budget_s):

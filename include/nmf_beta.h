@@ -195,6 +195,67 @@ nmf_status nmf_set_path(nmf_ctx_t ctx, int32_t path);
  * tiles each workgroup walks (0 = default 1).  Applies to later calls. */
 nmf_status nmf_set_launch(nmf_ctx_t ctx, int32_t target_blocks, int32_t min_tiles);
 
+/* ---------------------------------------------------------------------------
+ * Many problems in one launch.
+ *
+ * A batch holds P independent problems of uneven sizes, each with its own beta
+ * (and K <= 64), and runs one outer iteration of every problem -- the same
+ * computation as nmf_beta_step in the batch's mode -- in ONE persistent kernel
+ * launch.  Work items of all problems (W pass, W update, H pass, H update) are
+ * taken from a queue listed phase by phase; a per-problem completion counter
+ * lets an item start once its problem's previous phase has finished.
+ *
+ * The batch owns its own device memory (descriptors, queue, workspace, status
+ * word), allocated by nmf_batch_create; nmf_batch_step allocates nothing and
+ * may be captured into a HIP graph.  The problems' V, W, H stay caller-owned;
+ * their pointers are fixed at creation.  W and H of different problems must not
+ * overlap each other or any V (NMF_ERR_ALIAS); V may be shared.
+ * ------------------------------------------------------------------------- */
+typedef struct nmf_batch_s* nmf_batch_t;
+
+typedef struct {
+  int64_t F, N, K;          /* sizes; 1 <= K <= 64 */
+  const float* V; int64_t ldv;
+  float* W; int64_t ldw;
+  float* H; int64_t ldh;
+  double beta;
+} nmf_problem;
+
+typedef struct {
+  int32_t tiles_per_item;   /* 32-wide tiles each pass item walks (0: default 8) */
+  int32_t workers;          /* persistent workgroups (0: as many as fit on the GPU) */
+} nmf_batch_config;
+
+/* Validates every problem (as nmf_beta_step would; opts->precision FP32 or BF16,
+ * inner_iters 1), plans the work items, allocates and uploads the batch.  `cfg`
+ * may be NULL (defaults).  Synchronous.  *out is NULL on error. */
+nmf_status nmf_batch_create(nmf_ctx_t ctx, const nmf_problem* problems, int32_t count, int32_t mode,
+                            const nmf_step_opts* opts, const nmf_batch_config* cfg, nmf_batch_t* out);
+
+/* One outer iteration of every problem in one launch on `stream`.
+ * d_objectives (device double[count], may be NULL) receives each problem's
+ * objective at its entry iterate. */
+nmf_status nmf_batch_step(nmf_batch_t batch, void* stream, double* d_objectives);
+
+/* Sticky flags of the batch (as nmf_get_flags); NMF_FLAG_BARRIER means a work
+ * item gave up waiting for its problem's previous phase. */
+nmf_status nmf_batch_get_flags(nmf_batch_t batch, void* stream, uint32_t* flags, int32_t clear);
+
+/* Number of work items per launch and persistent workgroups of the batch. */
+nmf_status nmf_batch_info(nmf_batch_t batch, int64_t* work_items, int32_t* workers, int64_t* device_bytes);
+
+/* Frees the batch (synchronizes the device first). */
+nmf_status nmf_batch_destroy(nmf_batch_t batch);
+
+/* Autotuner: times `iters` batch steps (after one warm-up step) for each
+ * candidate tiles_per_item in {2, 4, 8, 16, 32} on the given problems and
+ * returns the fastest configuration and its time per step in milliseconds.
+ * The problems' W and H are saved before and restored after every candidate, so
+ * they are unchanged on return.  Synchronous. */
+nmf_status nmf_batch_tune(nmf_ctx_t ctx, const nmf_problem* problems, int32_t count, int32_t mode,
+                          const nmf_step_opts* opts, void* stream, int32_t iters, nmf_batch_config* best,
+                          double* best_ms);
+
 #ifdef __cplusplus
 }
 #endif

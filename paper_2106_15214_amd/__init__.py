@@ -25,7 +25,7 @@ __all__ = [
     "NmfError", "lib", "library_path", "Context", "default_context",
     "ALTERNATING", "JOINT", "FP32", "BF16", "FP16",
     "FLAG_NONFINITE", "FLAG_DOMAIN", "FLAG_BARRIER", "FLAG_RANGE", "KERNELS",
-    "step", "objective", "grad", "validate", "get_flags", "check_step_args",
+    "step", "objective", "grad", "validate", "get_flags", "check_step_args", "Batch", "batch_tune",
     "BetaDivergence", "beta_divergence",
 ]
 
@@ -55,6 +55,18 @@ class NmfError(RuntimeError):
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("kappa", ctypes.c_float),
                 ("inner_iters", ctypes.c_int32), ("normalize", ctypes.c_int32)]
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("F", ctypes.c_int64), ("N", ctypes.c_int64), ("K", ctypes.c_int64),
+                ("V", ctypes.c_void_p), ("ldv", ctypes.c_int64),
+                ("W", ctypes.c_void_p), ("ldw", ctypes.c_int64),
+                ("H", ctypes.c_void_p), ("ldh", ctypes.c_int64),
+                ("beta", ctypes.c_double)]
+
+
+class _BatchConfig(ctypes.Structure):
+    _fields_ = [("tiles_per_item", ctypes.c_int32), ("workers", ctypes.c_int32)]
 
 
 _lib = None
@@ -99,10 +111,19 @@ def lib() -> ctypes.CDLL:
         L.nmf_set_launch.argtypes = [_vp, _i32, _i32]
         L.nmf_set_path.argtypes = [_vp, _i32]
         L.nmf_profile_phases.argtypes = [_vp, _vp, ctypes.POINTER(_dbl), _i32]
+        PP, PC = ctypes.POINTER(_Problem), ctypes.POINTER(_BatchConfig)
+        L.nmf_batch_create.argtypes = [_vp, PP, _i32, _i32, ctypes.POINTER(_Opts), PC, ctypes.POINTER(_vp)]
+        L.nmf_batch_step.argtypes = [_vp, _vp, _vp]
+        L.nmf_batch_get_flags.argtypes = [_vp, _vp, ctypes.POINTER(_u32), _i32]
+        L.nmf_batch_info.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_i64)]
+        L.nmf_batch_destroy.argtypes = [_vp]
+        L.nmf_batch_tune.argtypes = [_vp, PP, _i32, _i32, ctypes.POINTER(_Opts), _vp, _i32, PC,
+                                     ctypes.POINTER(_dbl)]
         for name in ("nmf_create", "nmf_destroy", "nmf_reserve", "nmf_check_step_args", "nmf_beta_step",
                      "nmf_beta_objective", "nmf_beta_grad", "nmf_beta_validate", "nmf_get_flags",
                      "nmf_profile_enable", "nmf_profile_read", "nmf_set_launch", "nmf_set_path",
-                     "nmf_profile_phases"):
+                     "nmf_profile_phases", "nmf_batch_create", "nmf_batch_step", "nmf_batch_get_flags",
+                     "nmf_batch_info", "nmf_batch_destroy", "nmf_batch_tune"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -342,3 +363,119 @@ BetaDivergence = _LazyAutograd()
 def beta_divergence(V, W, H, beta: float, kappa: float = 0.0):
     """Differentiable D_beta(V + kappa | WH + kappa) (float64 0-d tensor)."""
     return BetaDivergence.apply(V, W, H, beta, kappa)
+
+
+# ---------------------------------------------------------------------------
+# many problems in one launch
+# ---------------------------------------------------------------------------
+def _problems(problems):
+    """[(V, W, H, beta), ...] of device tensors -> ctypes array (tensors kept alive by the caller)."""
+    arr = (_Problem * len(problems))()
+    for i, (V, W, H, beta) in enumerate(problems):
+        v, ldv = _mat(V, "V")
+        w, ldw = _mat(W, "W", True)
+        h, ldh = _mat(H, "H", True)
+        F, N = V.shape
+        K = W.shape[1]
+        if W.shape[0] != F or H.shape != (K, N):
+            raise ValueError(f"problem {i}: shapes V {tuple(V.shape)}, W {tuple(W.shape)}, H {tuple(H.shape)}")
+        arr[i] = _Problem(F, N, K, v, ldv, w, ldw, h, ldh, float(beta))
+    return arr
+
+
+class Batch:
+    """Many problems updated by one persistent launch per outer iteration
+    (nmf_batch_create / nmf_batch_step).  ``problems`` is a list of
+    (V, W, H, beta) device tensors; W and H are updated in place by step()."""
+
+    def __init__(self, problems, mode="joint", *, precision="fp32", kappa: float = 0.0, normalize: bool = True,
+                 tiles_per_item: int = 0, workers: int = 0, ctx: Optional[Context] = None):
+        self._tensors = list(problems)  # keep the caller's tensors alive
+        self.count = len(problems)
+        arr = _problems(problems)
+        o = _opts(precision, kappa, 1, normalize)
+        cfg = _BatchConfig(int(tiles_per_item), int(workers))
+        h = _vp()
+        _check(lib().nmf_batch_create(_ctx(ctx), arr, self.count, MODES[mode], ctypes.byref(o), ctypes.byref(cfg),
+                                      ctypes.byref(h)), "nmf_batch_create")
+        self.handle = h
+
+    def step(self, objectives=None, stream=None):
+        """One outer iteration of every problem; ``objectives``: optional float64
+        device tensor of ``count`` entries receiving the entry objectives."""
+        optr = None
+        if objectives is not None:
+            import torch
+            if objectives.dtype != torch.float64 or not objectives.is_cuda or objectives.numel() < self.count:
+                raise ValueError("objectives must be a float64 device tensor with one entry per problem")
+            optr = objectives.data_ptr()
+        _check(lib().nmf_batch_step(self.handle, _stream(stream), optr), "nmf_batch_step")
+
+    def flags(self, clear: bool = False, stream=None) -> int:
+        f = _u32()
+        _check(lib().nmf_batch_get_flags(self.handle, _stream(stream), ctypes.byref(f), 1 if clear else 0),
+               "nmf_batch_get_flags")
+        return int(f.value)
+
+    def info(self):
+        n, w, b = _i64(), _i32(), _i64()
+        _check(lib().nmf_batch_info(self.handle, ctypes.byref(n), ctypes.byref(w), ctypes.byref(b)), "nmf_batch_info")
+        return {"work_items": n.value, "workers": w.value, "device_bytes": b.value}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().nmf_batch_destroy(self.handle)
+            self.handle = _vp()
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _batch_signature(problems, mode, precision) -> str:
+    """Tuning-cache key: device architecture, mode, precision and a histogram of
+    problem shape buckets (log2 of F, N; K in steps of 16; beta)."""
+    import hashlib
+    import math
+    import torch
+    arch = getattr(torch.cuda.get_device_properties(0), "gcnArchName", "gpu").split(":")[0]
+    hist = {}
+    for V, W, H, beta in problems:
+        F, N = V.shape
+        key = (int(math.log2(F)), int(math.log2(N)), (W.shape[1] - 1) // 16, float(beta))
+        hist[key] = hist.get(key, 0) + 1
+    digest = hashlib.sha1(repr(sorted(hist.items())).encode()).hexdigest()[:16]
+    return f"{arch}/{mode}/{precision}/{len(problems)}/{digest}"
+
+
+def batch_tune(problems, mode="joint", *, precision="fp32", kappa: float = 0.0, normalize: bool = True,
+               iters: int = 3, cache: Optional[str] = None, stream=None, ctx: Optional[Context] = None):
+    """Autotunes the batch configuration (nmf_batch_tune) and returns
+    (config dict, ms per step).  With ``cache`` (a JSON file) a configuration
+    measured before for the same device, mode, precision and shape histogram is
+    returned without measuring; new results are added to the file."""
+    import json
+    key = _batch_signature(problems, mode, precision)
+    table = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            table = json.load(f)
+        if key in table:
+            e = table[key]
+            return {"tiles_per_item": e["tiles_per_item"], "workers": e["workers"]}, e["ms"]
+    arr = _problems(problems)
+    o = _opts(precision, kappa, 1, normalize)
+    cfg = _BatchConfig()
+    ms = _dbl()
+    _check(lib().nmf_batch_tune(_ctx(ctx), arr, len(problems), MODES[mode], ctypes.byref(o), _stream(stream),
+                                int(iters), ctypes.byref(cfg), ctypes.byref(ms)), "nmf_batch_tune")
+    best = {"tiles_per_item": cfg.tiles_per_item, "workers": cfg.workers}
+    if cache:
+        table[key] = dict(best, ms=ms.value)
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return best, ms.value

@@ -42,6 +42,18 @@ struct nmf_ctx_s {
   int64_t prof_count[NMF_KERNEL_COUNT] = {};
 };
 
+struct nmf_batch_s {
+  int device = 0;
+  int count = 0;
+  int mode = NMF_JOINT;
+  int prec = NMF_FP32;
+  int grid = 0;
+  int64_t total = 0;
+  char* mem = nullptr;  // header | counters | descriptors | queue | problem workspaces
+  size_t bytes = 0;
+  BatchArgs args{};
+};
+
 namespace {
 
 // Workspace header (zeroed at allocation): the sticky flags word at byte 0,
@@ -140,6 +152,27 @@ int fused_capacity(nmf_ctx_s* c, int bc, int kb, bool joint, bool obj) {
 
 // `cols_occ`: workgroups per CU of the streaming column pass.  `fused_grid` > 0
 // plans the single-launch path with that many workgroups.
+// Column-partial split, transposed leading dimension and workspace offsets of
+// a plan whose splits are set.
+Plan finish_plan(Plan p, int64_t F, int64_t N) {
+  {
+    const int64_t rows = (int64_t)p.tiles_f * kTile;
+    p.col_parts = (int)std::min<int64_t>(p.col_blocks, cdiv(rows, kColChunkRows));
+    p.col_chunk = (int)cdiv(rows, p.col_parts);
+  }
+  p.ldt = cdiv(F, 4) * 4;
+  Sizes z;
+  z.pobj = sizeof(double) * (size_t)std::max<int64_t>((int64_t)p.row_blocks * p.n_groups, p.fused_grid);
+  z.pnum = sizeof(float) * (size_t)p.n_groups * F * p.KP;
+  z.prs = sizeof(float) * (size_t)p.n_groups * p.KP;
+  z.fk = sizeof(float) * (size_t)F * p.KP;
+  z.wt = sizeof(float) * (size_t)p.KP * p.ldt;
+  z.pcol = sizeof(double) * (size_t)(p.fused ? p.uw_blocks : (int64_t)p.f_groups * p.col_parts) * 2 * p.KP;
+  z.pnumh = sizeof(float) * (size_t)p.f_groups * N * p.KP;
+  z.pq = p.fused ? sizeof(float) * (size_t)cdiv(F, kTile) * cdiv(N, kTile) * kTile * kTile : 0;
+  return layout(z, p);
+}
+
 Plan make_plan(const nmf_ctx_s* c, int64_t F, int64_t N, int64_t K, int cols_occ = 2, int fused_grid = 0) {
   Plan p{};
   p.KB = kblocks_for(K);
@@ -154,23 +187,29 @@ Plan make_plan(const nmf_ctx_s* c, int64_t F, int64_t N, int64_t K, int cols_occ
   p.col_blocks = (int)cdiv(N, kBlockRows);
   p.f_groups = choose_groups(c, cdiv(F, kTile), p.col_blocks, N, p.KB, cols_slots, &p.tiles_f);
   p.uw_blocks = p.fused ? fused_grid : (int)std::min<int64_t>(kUpdateWBlocks, cdiv(F, update_w_unit_rows(p.KB)));
-  {
-    const int64_t rows = (int64_t)p.tiles_f * kTile;
-    p.col_parts = (int)std::min<int64_t>(p.col_blocks, cdiv(rows, kColChunkRows));
-    p.col_chunk = (int)cdiv(rows, p.col_parts);
-  }
   p.uh_blocks = p.fused ? (int)cdiv(N, kTile) : (int)cdiv(N, kBlock / p.KP);
-  p.ldt = cdiv(F, 4) * 4;
-  Sizes z;
-  z.pobj = sizeof(double) * (size_t)std::max<int64_t>((int64_t)p.row_blocks * p.n_groups, fused_grid);
-  z.pnum = sizeof(float) * (size_t)p.n_groups * F * p.KP;
-  z.prs = sizeof(float) * (size_t)p.n_groups * p.KP;
-  z.fk = sizeof(float) * (size_t)F * p.KP;
-  z.wt = sizeof(float) * (size_t)p.KP * p.ldt;
-  z.pcol = sizeof(double) * (size_t)(p.fused ? p.uw_blocks : (int64_t)p.f_groups * p.col_parts) * 2 * p.KP;
-  z.pnumh = sizeof(float) * (size_t)p.f_groups * N * p.KP;
-  z.pq = p.fused ? sizeof(float) * (size_t)cdiv(F, kTile) * cdiv(N, kTile) * kTile * kTile : 0;
-  return layout(z, p);
+  return finish_plan(p, F, N);
+}
+
+// Splits of a problem inside a batch: every row (column) group covers about
+// `tiles` column (row) tiles; one W-update unit of rows and one H-update unit
+// of columns per work item.
+Plan make_batch_plan(int64_t F, int64_t N, int64_t K, int tiles) {
+  Plan p{};
+  p.KB = kblocks_for(K);
+  p.KP = 32 * p.KB;
+  const int64_t tn = cdiv(N, kTile), tf = cdiv(F, kTile);
+  p.row_blocks = (int)cdiv(F, kBlockRows);
+  p.n_groups = (int)cdiv(tn, tiles);
+  p.tiles_n = (int)cdiv(tn, p.n_groups);
+  p.n_groups = (int)cdiv(tn, p.tiles_n);
+  p.col_blocks = (int)cdiv(N, kBlockRows);
+  p.f_groups = (int)cdiv(tf, tiles);
+  p.tiles_f = (int)cdiv(tf, p.f_groups);
+  p.f_groups = (int)cdiv(tf, p.tiles_f);
+  p.uw_blocks = (int)cdiv(F, update_w_unit_rows(p.KB));
+  p.uh_blocks = (int)cdiv(N, kBlock / p.KP);
+  return finish_plan(p, F, N);
 }
 
 // Workspace size covering every call with F <= maxF, N <= maxN, K <= maxK under
@@ -357,6 +396,37 @@ StepArgs make_step_args(const Plan& p, char* ws, unsigned* flags, int64_t F, int
   ha.Wn = Wn; ha.W = W; ha.ldw = ldw; ha.flags = flags;
   return sa;
 }
+
+// Byte ranges [lo, hi) of caller memory written (W, H) or read (V) by a batch.
+struct Span {
+  uintptr_t lo, hi;
+  int prob;
+};
+
+nmf_status check_batch_alias(const nmf_problem* pr, int count) {
+  std::vector<Span> wr, rd;
+  for (int i = 0; i < count; ++i) {
+    const nmf_problem& q = pr[i];
+    wr.push_back({(uintptr_t)q.W, (uintptr_t)q.W + span_bytes(q.F, q.K, q.ldw), i});
+    wr.push_back({(uintptr_t)q.H, (uintptr_t)q.H + span_bytes(q.K, q.N, q.ldh), i});
+    rd.push_back({(uintptr_t)q.V, (uintptr_t)q.V + span_bytes(q.F, q.N, q.ldv), i});
+  }
+  std::sort(wr.begin(), wr.end(), [](const Span& a, const Span& b) { return a.lo < b.lo; });
+  for (size_t i = 1; i < wr.size(); ++i)
+    if (wr[i].lo < wr[i - 1].hi) return NMF_ERR_ALIAS;
+  for (const Span& v : rd) {
+    // first writable span ending after v.lo
+    auto it = std::upper_bound(wr.begin(), wr.end(), v.lo, [](uintptr_t x, const Span& b) { return x < b.lo; });
+    if (it != wr.begin() && std::prev(it)->hi > v.lo) return NMF_ERR_ALIAS;
+    if (it != wr.end() && it->lo < v.hi) return NMF_ERR_ALIAS;
+  }
+  return NMF_OK;
+}
+
+constexpr int kBatchTilesDefault = 8;
+constexpr int kBatchUpdateRows = 32;   // rows of W per W-update work item
+constexpr int kBatchUpdateCols = 64;   // columns of H per H-update work item
+constexpr unsigned kBatchSpinLimit = 1u << 22;
 
 }  // namespace
 
@@ -672,6 +742,242 @@ nmf_status nmf_set_launch(nmf_ctx_t c, int32_t target_blocks, int32_t min_tiles)
   c->target_blocks = target_blocks;
   c->min_tiles = min_tiles > 0 ? min_tiles : 1;
   return NMF_OK;
+}
+
+nmf_status nmf_batch_create(nmf_ctx_t c, const nmf_problem* pr, int32_t count, int32_t mode,
+                            const nmf_step_opts* opts, const nmf_batch_config* cfg, nmf_batch_t* out) {
+  if (!out) return NMF_ERR_NULL;
+  *out = nullptr;
+  if (!c || !pr) return NMF_ERR_NULL;
+  if (count < 1) return NMF_ERR_ARG;
+  if (mode != NMF_ALTERNATING && mode != NMF_JOINT) return NMF_ERR_ARG;
+  nmf_status st = check_opts(opts);
+  if (st != NMF_OK) return st;
+  nmf_step_opts o;
+  nmf_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.precision != NMF_FP32 && o.precision != NMF_BF16) return NMF_ERR_UNSUPPORTED;
+  const int tiles = cfg && cfg->tiles_per_item > 0 ? cfg->tiles_per_item : kBatchTilesDefault;
+  if (cfg && cfg->workers < 0) return NMF_ERR_ARG;
+  for (int i = 0; i < count; ++i) {
+    const nmf_problem& q = pr[i];
+    st = nmf_check_step_args(q.F, q.N, q.K, q.V, q.ldv, q.W, q.ldw, q.H, q.ldh, q.beta, mode, &o);
+    if (st != NMF_OK) return st;
+    if (q.K > 64) return NMF_ERR_UNSUPPORTED;
+  }
+  if ((st = check_batch_alias(pr, count)) != NMF_OK) return st;
+  if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
+  const bool joint = mode == NMF_JOINT;
+  const int max_grid = batched_max_blocks(o.precision, joint, c->num_cus);
+  if (max_grid <= 0) return NMF_ERR_HIP;
+  const int grid = cfg && cfg->workers > 0 ? std::min(cfg->workers, max_grid) : max_grid;
+
+  // plans and memory layout
+  std::vector<Plan> plans(count);
+  std::vector<size_t> base(count);
+  size_t off = kHeaderBytes;
+  const size_t o_done = off;
+  off = align_up(off + sizeof(unsigned) * 4 * (size_t)count);
+  const size_t o_desc = off;
+  off = align_up(off + sizeof(BatchProblem) * (size_t)count);
+  int64_t total = 0;
+  for (int i = 0; i < count; ++i) {
+    plans[i] = make_batch_plan(pr[i].F, pr[i].N, pr[i].K, tiles);
+    const Plan& p = plans[i];
+    total += (int64_t)p.row_blocks * p.n_groups + cdiv(p.uw_blocks, std::max(1, kBatchUpdateRows / update_w_unit_rows(p.KB))) +
+             (int64_t)p.col_blocks * p.f_groups + cdiv(p.uh_blocks, std::max(1, kBatchUpdateCols / (kBlock / p.KP)));
+  }
+  if (total >= (int64_t)1 << 31) return NMF_ERR_UNSUPPORTED;
+  const size_t o_list = off;
+  off = align_up(off + sizeof(int2) * (size_t)total);
+  for (int i = 0; i < count; ++i) {
+    base[i] = off;
+    off = align_up(off + plans[i].total);
+  }
+  nmf_batch_s* b = new (std::nothrow) nmf_batch_s();
+  if (!b) return NMF_ERR_HIP;
+  b->device = c->device;
+  b->count = count;
+  b->mode = mode;
+  b->prec = o.precision;
+  b->grid = grid;
+  b->total = total;
+  b->bytes = off;
+  if (hipMalloc(&b->mem, off) != hipSuccess) {
+    delete b;
+    return NMF_ERR_HIP;
+  }
+  char* mem = b->mem;
+  unsigned* flags = (unsigned*)mem;
+
+  // descriptors
+  std::vector<BatchProblem> desc(count);
+  for (int i = 0; i < count; ++i) {
+    const nmf_problem& q = pr[i];
+    const Plan& p = plans[i];
+    StepArgs sa = make_step_args(p, mem + base[i], flags, q.F, q.N, q.K, q.V, q.ldv, q.W, q.ldw, q.H, q.ldh,
+                                 q.beta, joint, o.precision, o, nullptr);
+    BatchProblem& d = desc[i];
+    d.ra = sa.ra;
+    d.ua = sa.ua;
+    d.ca = sa.ca;
+    d.ha = sa.ha;
+    d.bc = beta_class(q.beta);
+    d.kb = p.KB;
+    for (int ph = 0; ph < 4; ++ph) d.per_item[ph] = 1;
+    d.units[PH_WPASS] = p.row_blocks * p.n_groups;
+    d.units[PH_WUPDATE] = p.uw_blocks;
+    d.units[PH_HPASS] = p.col_blocks * p.f_groups;
+    d.units[PH_HUPDATE] = p.uh_blocks;
+    d.per_item[PH_WUPDATE] = std::max(1, kBatchUpdateRows / update_w_unit_rows(p.KB));
+    d.per_item[PH_HUPDATE] = std::max(1, kBatchUpdateCols / (kBlock / p.KP));
+    for (int ph = 0; ph < 4; ++ph) d.items[ph] = (int)cdiv(d.units[ph], d.per_item[ph]);
+  }
+  // queue: phase-major; within a phase the larger problems first
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int bb) {
+    return pr[a].F * pr[a].N * pr[a].K > pr[bb].F * pr[bb].N * pr[bb].K;
+  });
+  std::vector<int2> list;
+  list.reserve((size_t)total);
+  for (int ph = 0; ph < 4; ++ph)
+    for (int i : order)
+      for (int it = 0; it < desc[i].items[ph]; ++it) list.push_back(make_int2(i, (ph << 24) | it));
+
+  hipError_t e = hipMemset(mem, 0, o_desc);
+  if (e == hipSuccess) e = hipMemcpy(mem + o_desc, desc.data(), sizeof(BatchProblem) * count, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(mem + o_list, list.data(), sizeof(int2) * list.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(b->mem);
+    delete b;
+    return NMF_ERR_HIP;
+  }
+  BatchArgs& a = b->args;
+  a.probs = (const BatchProblem*)(mem + o_desc);
+  a.list = (const int2*)(mem + o_list);
+  a.total = (int)total;
+  a.next = (unsigned*)(mem + 8);
+  a.exited = (unsigned*)(mem + 12);
+  a.done = (unsigned*)(mem + o_done);
+  a.nprob = count;
+  a.d_obj = nullptr;
+  a.flags = flags;
+  a.spin_limit = kBatchSpinLimit;
+  *out = b;
+  return NMF_OK;
+}
+
+nmf_status nmf_batch_step(nmf_batch_t b, void* stream, double* d_objectives) {
+  if (!b) return NMF_ERR_NULL;
+  if (hipSetDevice(b->device) != hipSuccess) return NMF_ERR_HIP;
+  BatchArgs a = b->args;
+  a.d_obj = d_objectives;
+  return hip_status(launch_batched(b->prec, b->mode == NMF_JOINT, b->grid, (hipStream_t)stream, a));
+}
+
+nmf_status nmf_batch_get_flags(nmf_batch_t b, void* stream, uint32_t* flags, int32_t clear) {
+  if (!b || !flags) return NMF_ERR_NULL;
+  *flags = 0;
+  if (hipSetDevice(b->device) != hipSuccess) return NMF_ERR_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(flags, b->mem, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess) return NMF_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return NMF_ERR_HIP;
+  if (clear) {
+    const uint32_t z = 0;
+    if (hipMemcpyAsync(b->mem, &z, sizeof(uint32_t), hipMemcpyHostToDevice, s) != hipSuccess) return NMF_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return NMF_ERR_HIP;
+  }
+  return NMF_OK;
+}
+
+nmf_status nmf_batch_info(nmf_batch_t b, int64_t* work_items, int32_t* workers, int64_t* device_bytes) {
+  if (!b) return NMF_ERR_NULL;
+  if (work_items) *work_items = b->total;
+  if (workers) *workers = b->grid;
+  if (device_bytes) *device_bytes = (int64_t)b->bytes;
+  return NMF_OK;
+}
+
+nmf_status nmf_batch_destroy(nmf_batch_t b) {
+  if (!b) return NMF_ERR_NULL;
+  (void)hipSetDevice(b->device);
+  (void)hipDeviceSynchronize();
+  if (b->mem) (void)hipFree(b->mem);
+  delete b;
+  return NMF_OK;
+}
+
+nmf_status nmf_batch_tune(nmf_ctx_t c, const nmf_problem* pr, int32_t count, int32_t mode,
+                          const nmf_step_opts* opts, void* stream, int32_t iters, nmf_batch_config* best,
+                          double* best_ms) {
+  if (!c || !pr || !best) return NMF_ERR_NULL;
+  if (iters < 1) return NMF_ERR_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  // save W and H of every problem (packed) to restore them after each candidate
+  size_t words = 0;
+  for (int i = 0; i < count; ++i) words += (size_t)(pr[i].F * pr[i].K + pr[i].K * pr[i].N);
+  float* save = nullptr;
+  if (hipMalloc(&save, sizeof(float) * std::max<size_t>(words, 1)) != hipSuccess) return NMF_ERR_HIP;
+  auto copy_all = [&](bool to_save) -> hipError_t {
+    size_t w = 0;
+    for (int i = 0; i < count; ++i) {
+      const nmf_problem& q = pr[i];
+      float* sw = save + w;
+      float* sh = sw + q.F * q.K;
+      w += (size_t)(q.F * q.K + q.K * q.N);
+      hipError_t e;
+      if (to_save) {
+        e = hipMemcpy2DAsync(sw, q.K * 4, q.W, q.ldw * 4, q.K * 4, q.F, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpy2DAsync(sh, q.N * 4, q.H, q.ldh * 4, q.N * 4, q.K, hipMemcpyDeviceToDevice, s);
+      } else {
+        e = hipMemcpy2DAsync(q.W, q.ldw * 4, sw, q.K * 4, q.K * 4, q.F, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpy2DAsync(q.H, q.ldh * 4, sh, q.N * 4, q.N * 4, q.K, hipMemcpyDeviceToDevice, s);
+      }
+      if (e != hipSuccess) return e;
+    }
+    return hipStreamSynchronize(s);
+  };
+  nmf_status result = NMF_OK;
+  double best_t = 1e300;
+  nmf_batch_config best_cfg{kBatchTilesDefault, 0};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess || copy_all(true) != hipSuccess) {
+    result = NMF_ERR_HIP;
+  }
+  static const int kCandidates[] = {2, 4, 8, 16, 32};
+  for (int ci = 0; result == NMF_OK && ci < (int)(sizeof(kCandidates) / sizeof(int)); ++ci) {
+    nmf_batch_config cfg{kCandidates[ci], 0};
+    nmf_batch_t b = nullptr;
+    nmf_status st = nmf_batch_create(c, pr, count, mode, opts, &cfg, &b);
+    if (st != NMF_OK) { result = st; break; }
+    float ms = 0.f;
+    hipError_t e = launch_batched(b->prec, b->mode == NMF_JOINT, b->grid, s, b->args);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int t = 0; e == hipSuccess && t < iters; ++t) e = launch_batched(b->prec, b->mode == NMF_JOINT, b->grid, s, b->args);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    uint32_t fl = 0;
+    if (e == hipSuccess && nmf_batch_get_flags(b, stream, &fl, 1) != NMF_OK) e = hipErrorUnknown;
+    (void)nmf_batch_destroy(b);
+    if (e == hipSuccess) e = copy_all(false);
+    if (e != hipSuccess) { result = NMF_ERR_HIP; break; }
+    const double t = (double)ms / iters;
+    if (fl == 0 && t < best_t) {
+      best_t = t;
+      best_cfg = cfg;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(save);
+  if (result == NMF_OK) {
+    *best = best_cfg;
+    if (best_ms) *best_ms = best_t;
+  }
+  return result;
 }
 
 }  // extern "C"

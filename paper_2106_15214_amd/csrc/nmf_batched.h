@@ -1,0 +1,179 @@
+// Many beta-NMF problems of uneven sizes, each with its own beta and rank, in
+// one persistent launch.  Workgroups take work items from a queue listed
+// phase-major over all problems:
+//   W-pass items  (rows items: Lambda~ tiles, P, Q, W-step partials, objective)
+//   W-update units (partials reduced, W_new, chi terms)
+//   H-pass items  (cols items: H-step partials, column sums of W_new)
+//   H-update units (H_new, normalization, W write-back, objective total)
+// A per-problem counter of finished items per phase replaces grid barriers: an
+// item of phase q waits until its problem's phase q - 1 is complete.  Every
+// item it can wait for was taken from the queue before it by a running
+// workgroup, so the wait ends without co-residency of the grid.
+#pragma once
+
+#include "nmf_device.h"
+
+namespace nmf {
+
+// Largest LDS footprint of any item: the float32 joint H pass at KB = 2.
+constexpr int kBatchLdsBytes = cols_item_lds<2, true>();
+static_assert(cols_item_lp_lds<2, true>() <= kBatchLdsBytes, "batched LDS");
+static_assert(rows_item_lds<2>() <= kBatchLdsBytes, "batched LDS");
+static_assert(2 * kBlock * 8 <= kBatchLdsBytes, "batched LDS");
+
+// Descriptors never change during the launch: reading them through the
+// constant address space lets the compiler keep their fields in scalar
+// registers.
+typedef const __attribute__((address_space(4))) BatchProblem* ConstProblemPtr;
+
+// Copies a descriptor field group out of constant memory (dword by dword).
+template <class T>
+__device__ __forceinline__ T load_const(const __attribute__((address_space(4))) T* p) {
+  static_assert(sizeof(T) % 4 == 0, "dword copy");
+  T r;
+  const __attribute__((address_space(4))) uint32_t* s = (const __attribute__((address_space(4))) uint32_t*)p;
+  uint32_t* d = reinterpret_cast<uint32_t*>(&r);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = s[i];
+  return r;
+}
+
+template <int BC, int KB, int PREC, bool JOINT, bool OBJ>
+__device__ __forceinline__ void batch_item(ConstProblemPtr P, int prob, int phase, int item, const BatchArgs& b,
+                                           float* lds, double* red, float* norm_s, float* csum_s) {
+  if (phase == PH_WPASS) {
+    const SweepRowsArgs ra = load_const(&P->ra);
+    double objsum = 0.0;
+    if constexpr (PREC == 0) rows_item<BC, KB, KIND_UPDATE, OBJ, false>(ra, item, lds, objsum);
+    else if constexpr (PREC == 1) rows_item_lp<BC, KB, OBJ, __bf16>(ra, item, lds, objsum);
+    else rows_item_lp<BC, KB, OBJ, _Float16>(ra, item, lds, objsum);
+    if (OBJ) {
+      const double sum = block_sum(objsum, red);
+      if (threadIdx.x == 0) ra.pobj[item] = sum;
+    }
+  } else if (phase == PH_WUPDATE) {
+    const UpdateWArgs ua = load_const(&P->ua);
+    const double den1 = row_sum_den<KB>(ua);
+    double nrm = 0.0, cs = 0.0;
+    const int per = P->per_item[PH_WUPDATE];
+    const int u1 = min(P->units[PH_WUPDATE], (item + 1) * per);
+    for (int u = item * per; u < u1; ++u) update_w_unit<KB>(ua, u, true, lds, den1, nrm, cs);
+  } else if (phase == PH_HPASS) {
+    const SweepColsArgs ca = load_const(&P->ca);
+    cols_prologue<KB>(ca, item, lds);
+    if constexpr (PREC == 0) cols_item<BC, KB, KIND_UPDATE, JOINT, false>(ca, item, lds);
+    else if constexpr (PREC == 1) cols_item_lp<BC, KB, JOINT, __bf16>(ca, item, lds);
+    else cols_item_lp<BC, KB, JOINT, _Float16>(ca, item, lds);
+  } else {
+    const UpdateHArgs ha = load_const(&P->ha);
+    reduce_columns<KB>(ha.pcol, ha.pcol_blocks, reinterpret_cast<double*>(lds), norm_s, csum_s);
+    if (OBJ && item == 0 && b.d_obj) {
+      double s = 0.0;
+      for (int i = threadIdx.x; i < ha.nobj; i += kBlock) s += ha.pobj[i];
+      s = block_sum(s, red);
+      if (threadIdx.x == 0) {
+        b.d_obj[prob] = s;
+        if (!isfinite(s)) set_flag(b.flags, 1u);
+      }
+    }
+    const int items = P->items[PH_HUPDATE];
+    write_w<KB>(ha, norm_s, (int64_t)item * kBlock + threadIdx.x, (int64_t)items * kBlock);
+    const int per = P->per_item[PH_HUPDATE];
+    const int u1 = min(P->units[PH_HUPDATE], (item + 1) * per);
+    for (int u = item * per; u < u1; ++u) update_h_cols<KB>(ha, u, norm_s, csum_s);
+  }
+}
+
+template <int KB, int PREC, bool JOINT, bool OBJ>
+__device__ __forceinline__ void batch_item_bc(int bc, ConstProblemPtr P, int prob, int phase, int item,
+                                              const BatchArgs& b, float* lds, double* red, float* norm_s,
+                                              float* csum_s) {
+  switch (bc) {
+    case BC_GEN: batch_item<BC_GEN, KB, PREC, JOINT, OBJ>(P, prob, phase, item, b, lds, red, norm_s, csum_s); break;
+    case BC_B2: batch_item<BC_B2, KB, PREC, JOINT, OBJ>(P, prob, phase, item, b, lds, red, norm_s, csum_s); break;
+    case BC_B1: batch_item<BC_B1, KB, PREC, JOINT, OBJ>(P, prob, phase, item, b, lds, red, norm_s, csum_s); break;
+    case BC_B0: batch_item<BC_B0, KB, PREC, JOINT, OBJ>(P, prob, phase, item, b, lds, red, norm_s, csum_s); break;
+    case BC_B05: batch_item<BC_B05, KB, PREC, JOINT, OBJ>(P, prob, phase, item, b, lds, red, norm_s, csum_s); break;
+    default: batch_item<BC_B15, KB, PREC, JOINT, OBJ>(P, prob, phase, item, b, lds, red, norm_s, csum_s); break;
+  }
+}
+
+template <int PREC, bool JOINT, bool OBJ>
+__global__ __launch_bounds__(kBlock, 1) void batched_step_kernel(BatchArgs b) {
+  __shared__ __align__(16) float lds[kBatchLdsBytes / 4];
+  __shared__ double red[kWaves];
+  __shared__ float norm_s[64], csum_s[64];
+  __shared__ int2 entry;
+  __shared__ int last;
+  const int tid = threadIdx.x;
+  const ConstProblemPtr probs = (ConstProblemPtr)b.probs;
+
+  for (;;) {
+    __syncthreads();  // every thread has read the previous entry
+    if (tid == 0) {
+      const unsigned idx = atomicAdd(b.next, 1u);
+      entry = idx < (unsigned)b.total ? b.list[idx] : make_int2(-1, 0);
+    }
+    __syncthreads();
+    const int prob = __builtin_amdgcn_readfirstlane(entry.x);
+    const int code = __builtin_amdgcn_readfirstlane(entry.y);
+    if (prob < 0) break;
+    const int phase = code >> 24, item = code & 0xffffff;
+    ConstProblemPtr P = probs + prob;
+
+    // wait until the previous phase of this problem is complete (bounded)
+    if (phase > 0) {
+      if (tid == 0) {
+        const unsigned need = (unsigned)P->items[phase - 1];
+        unsigned* cnt = b.done + 4 * prob + phase - 1;
+        unsigned polls = 0;
+        // polled with read-modify-write atomics, which are performed where the
+        // producers' increments are, never served from a cached copy
+        while (__hip_atomic_fetch_add(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          if (++polls > b.spin_limit) {
+            set_flag(b.flags, 4u);  // gave up waiting: this launch's results are invalid
+            break;
+          }
+          // once any wait has given up, later waits do not spin again
+          if ((polls & 1023u) == 0u &&
+              (__hip_atomic_fetch_or(b.flags, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 4u))
+            break;
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the finished items' writes are visible
+    }
+
+    const int kb = P->kb, bc = P->bc;
+    if (kb == 1) batch_item_bc<1, PREC, JOINT, OBJ>(bc, P, prob, phase, item, b, lds, red, norm_s, csum_s);
+    else batch_item_bc<2, PREC, JOINT, OBJ>(bc, P, prob, phase, item, b, lds, red, norm_s, csum_s);
+
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this item's writes before its count
+    __syncthreads();
+    if (tid == 0) atomicAdd(b.done + 4 * prob + phase, 1u);
+  }
+
+  // the last workgroup out resets the queue and the counters for the next launch
+  if (tid == 0) {
+    __threadfence();
+    last = atomicAdd(b.exited, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    // atomic exchanges: the counters are only ever accessed atomically
+    for (int i = tid; i < 4 * b.nprob; i += kBlock)
+      (void)__hip_atomic_exchange(b.done + i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) {
+      (void)__hip_atomic_exchange(b.next, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      (void)__hip_atomic_exchange(b.exited, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// per-precision entry points (one translation unit each, to keep builds parallel)
+const void* batched_kernel_f32(bool joint);
+const void* batched_kernel_bf16(bool joint);
+
+}  // namespace nmf

@@ -1235,6 +1235,17 @@ __device__ __forceinline__ void update_w_unit(const UpdateWArgs& a, int unit, bo
   }
 }
 
+// Sum over groups of the beta = 1 row-sum partials of H~ (the W-step denominator).
+template <int KB>
+__device__ __forceinline__ double row_sum_den(const UpdateWArgs& a) {
+  constexpr int KP = 32 * KB;
+  const int k = threadIdx.x % KP;
+  double d = 0.0;
+  if (a.beta_one && k < a.K)
+    for (int g = 0; g < a.n_groups; ++g) d += (double)a.prs[g * KP + k];
+  return d;
+}
+
 // Column norms / sums of W_new from per-block partials pcol[b][2][KP] (b <
 // nblocks), summed in a fixed order into norm_s / csum_s (LDS, KP each).
 template <int KB>

@@ -140,6 +140,40 @@ struct FusedArgs {
 int fused_max_blocks(int bc, int kb, bool joint, bool obj, int num_cus);
 hipError_t launch_fused(int bc, int kb, bool joint, bool obj, int grid, hipStream_t s, const FusedArgs& a);
 
+// Many problems in one persistent launch.  Each problem's outer iteration is
+// split into four phases of independent work items (W-pass items, W-update
+// units, H-pass items, H-update units); phase q of a problem may start once
+// every item of its phase q - 1 has finished.  The items of all problems are
+// listed phase-major, so an item only ever waits for items listed before it:
+// those were taken by running workgroups, which makes the wait finite without
+// co-residency or a cooperative launch.
+enum { PH_WPASS = 0, PH_WUPDATE = 1, PH_HPASS = 2, PH_HUPDATE = 3 };
+struct BatchProblem {
+  SweepRowsArgs ra;
+  UpdateWArgs ua;
+  SweepColsArgs ca;
+  UpdateHArgs ha;
+  int bc, kb;
+  int items[4];  // work items per phase
+  int units[4];  // update units per phase (W rows / H columns groups); an item covers `per_item` of them
+  int per_item[4];
+};
+struct BatchArgs {
+  const BatchProblem* probs;
+  const int2* list;     // [total]: (problem, phase << 24 | item), phase-major
+  int total;
+  unsigned* next;       // queue position (zero at launch; reset by the last workgroup)
+  unsigned* exited;     // workgroups that left the queue loop
+  unsigned* done;       // [problems][4] finished items per phase (reset at exit)
+  int nprob;
+  double* d_obj;        // nullable: [problems] objective of the entry iterate
+  unsigned* flags;      // sticky status word
+  unsigned spin_limit;  // dependency polls before giving up (sets NMF_FLAG_BARRIER)
+};
+// prec 0 = float32, 1 = bfloat16 products
+hipError_t launch_batched(int prec, bool joint, int grid, hipStream_t s, const BatchArgs& a);
+int batched_max_blocks(int prec, bool joint, int num_cus);
+
 hipError_t launch_validate(hipStream_t s, const float* V, int64_t ldv, const float* W, int64_t ldw,
                            const float* H, int64_t ldh, int F, int N, int K, int zero_bad, unsigned* flags);
 

@@ -28,17 +28,6 @@ __global__ __launch_bounds__(kBlock, sweep_cols_occupancy(BC, KB, KIND, DUAL)) v
   cols_item<BC, KB, KIND, DUAL, false>(a, blockIdx.x, lds);
 }
 
-// Sum over groups of the beta = 1 row-sum partials of H~ (the W-step denominator).
-template <int KB>
-__device__ __forceinline__ double row_sum_den(const UpdateWArgs& a) {
-  constexpr int KP = 32 * KB;
-  const int k = threadIdx.x % KP;
-  double d = 0.0;
-  if (a.beta_one && k < a.K)
-    for (int g = 0; g < a.n_groups; ++g) d += (double)a.prs[g * KP + k];
-  return d;
-}
-
 template <int KB>
 __global__ __launch_bounds__(kBlock) void update_w_kernel(UpdateWArgs a) {
   __shared__ double lds[2 * kBlock];

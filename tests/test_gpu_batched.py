@@ -1,0 +1,208 @@
+"""GPU parity of the batched persistent step (many uneven problems, each with
+its own beta and rank, one launch per outer iteration) against the FP64 oracle
+and against the single-problem step.
+
+Gates as for the single-problem path: W, H relative Frobenius error <= 1e-5
+(float32) or 3e-3 (bfloat16), objective <= 1e-6 (float32 Lambda); against the
+single-problem step (same arithmetic, other split of the reductions) <= 2e-6.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+import paper_2106_15214_amd as nb
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+_CTX = {}
+
+
+def ctx():
+    if "c" not in _CTX:
+        _CTX["c"] = nb.Context(0)
+        _CTX["c"].set_path("stream")
+    return _CTX["c"]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+# uneven shapes, ranks on both sides of 32, every beta class
+SPECS = [(64, 100, 5, 1.0), (200, 150, 20, 0.0), (257, 300, 49, 0.5), (130, 70, 64, 2.0), (33, 1000, 8, 1.5),
+         (1, 40, 3, 1.2), (40, 1, 3, 2.5), (129, 129, 1, -0.5), (96, 160, 32, 1.0), (300, 97, 33, 0.0),
+         (500, 260, 17, 2.0), (77, 611, 60, 0.5)]
+
+
+# problems with K < min(F, N): several steps stay away from an exact fit, after
+# which the update ratio is the undefined 0/0 (flagged by every path)
+WELL_POSED = [s for s in SPECS if s[2] < min(s[0], s[1])]
+
+
+def make_set(specs, seed0=100):
+    out = []
+    for i, (F, N, K, beta) in enumerate(specs):
+        p = synth.random_positive(F, N, K, seed=seed0 + i, zeros=0.1 if beta > 0 else 0.0)
+        out.append((p.V, p.W, p.H, beta))
+    return out
+
+
+def to_dev(probs):
+    return [(dev(V), dev(W), dev(H), b) for V, W, H, b in probs]
+
+
+def oracle_step(V, W, H, beta, mode):
+    f = O.jmm_iteration if mode == "joint" else O.bmm_iteration
+    return f(V.astype(np.float64), W.astype(np.float64), H.astype(np.float64), beta)
+
+
+@pytest.mark.parametrize("mode", ["joint", "alternating"])
+@pytest.mark.parametrize("tiles", [0, 1, 3])
+def test_batched_step_matches_oracle(mode, tiles):
+    probs = make_set(SPECS)
+    d = to_dev(probs)
+    print(f"[batched] mode={mode} tiles={tiles} problems={len(d)}", flush=True)
+    b = nb.Batch(d, mode, tiles_per_item=tiles, ctx=ctx())
+    obj = torch.full((len(d),), float("nan"), dtype=torch.float64, device=DEV)
+    b.step(objectives=obj)
+    torch.cuda.synchronize()
+    assert b.flags(clear=True) == 0
+    o = obj.cpu().numpy()
+    for i, ((V, W, H, beta), (_, Wd, Hd, _)) in enumerate(zip(probs, d)):
+        Wr, Hr = oracle_step(V, W, H, beta, mode)
+        d0 = O.objective(V.astype(np.float64), W.astype(np.float64), H.astype(np.float64), beta)
+        eW, eH = rel(Wd.cpu().numpy(), Wr), rel(Hd.cpu().numpy(), Hr)
+        assert eW <= 1e-5 and eH <= 1e-5, (i, V.shape, W.shape[1], beta, eW, eH)
+        assert abs(o[i] - d0) <= 1e-6 * abs(d0), (i, o[i], d0)
+    b.close()
+
+
+@pytest.mark.parametrize("mode", ["joint", "alternating"])
+def test_batched_several_steps_match_single_problem_steps(mode):
+    probs = make_set(WELL_POSED, seed0=300)
+    d = to_dev(probs)
+    ref = to_dev(probs)
+    b = nb.Batch(d, mode, ctx=ctx())
+    obj = torch.zeros(len(d), dtype=torch.float64, device=DEV)
+    o1 = torch.zeros(1, dtype=torch.float64, device=DEV)
+    for t in range(6):
+        b.step(objectives=obj)
+        ob = obj.cpu().numpy()
+        for i, (V, W, H, beta) in enumerate(ref):
+            nb.step(V, W, H, beta, mode, objective_out=o1, ctx=ctx())
+            assert abs(ob[i] - o1.item()) <= 2e-6 * abs(o1.item()) + 1e-10, (t, i)
+    torch.cuda.synchronize()
+    assert b.flags() == 0 and nb.get_flags(clear=True, ctx=ctx()) == 0
+    for i, ((_, Wb, Hb, _), (_, Wr, Hr, _)) in enumerate(zip(d, ref)):
+        assert rel(Wb.cpu().numpy(), Wr.cpu().numpy().astype(np.float64)) <= 1e-5, i
+        assert rel(Hb.cpu().numpy(), Hr.cpu().numpy().astype(np.float64)) <= 1e-5, i
+    b.close()
+
+
+@pytest.mark.parametrize("mode", ["joint", "alternating"])
+def test_batched_bf16_matches_oracle(mode):
+    specs = [s for s in SPECS]
+    probs = make_set(specs, seed0=500)
+    d = to_dev(probs)
+    b = nb.Batch(d, mode, precision="bf16", ctx=ctx())
+    b.step()
+    torch.cuda.synchronize()
+    assert b.flags(clear=True) == 0
+    for i, ((V, W, H, beta), (_, Wd, Hd, _)) in enumerate(zip(probs, d)):
+        Wr, Hr = oracle_step(V, W, H, beta, mode)
+        eW, eH = rel(Wd.cpu().numpy(), Wr), rel(Hd.cpu().numpy(), Hr)
+        assert eW <= 3e-3 and eH <= 3e-3, (i, eW, eH)
+    b.close()
+
+
+def test_batched_graph_capture_replays_match_eager():
+    probs = make_set(WELL_POSED, seed0=700)
+    eager = to_dev(probs)
+    graph = to_dev(probs)
+    be = nb.Batch(eager, "joint", ctx=ctx())
+    bg = nb.Batch(graph, "joint", ctx=ctx())
+    oe = torch.zeros(len(probs), dtype=torch.float64, device=DEV)
+    og = torch.zeros(len(probs), dtype=torch.float64, device=DEV)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bg.step(objectives=og)
+    torch.cuda.synchronize()
+    # capture does not run the kernel: both batches are still at the start
+    for rep in range(4):
+        be.step(objectives=oe)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(oe, og), rep
+        for (_, We, He, _), (_, Wg, Hg, _) in zip(eager, graph):
+            assert torch.equal(We, Wg) and torch.equal(He, Hg), rep
+    assert be.flags() == 0 and bg.flags() == 0
+    be.close()
+    bg.close()
+
+
+def test_batched_workload_sample_matches_single_steps():
+    # 48 problems of the batched workload's draw (F, N scaled by 1/4)
+    specs = synth.batched_specs(48)
+    probs = []
+    for sp in specs:
+        p = synth.make_batched_problem(sp, scale=0.25)
+        probs.append((p.V, p.W, p.H, p.beta))
+    d = to_dev(probs)
+    ref = to_dev(probs)
+    b = nb.Batch(d, "joint", ctx=ctx())
+    print(f"[batched] workload sample: {b.info()}", flush=True)
+    obj = torch.zeros(len(d), dtype=torch.float64, device=DEV)
+    b.step(objectives=obj)
+    o1 = torch.zeros(1, dtype=torch.float64, device=DEV)
+    ob = obj.cpu().numpy()
+    for i, (V, W, H, beta) in enumerate(ref):
+        nb.step(V, W, H, beta, "joint", objective_out=o1, ctx=ctx())
+        assert abs(ob[i] - o1.item()) <= 2e-6 * abs(o1.item()) + 1e-10, i
+    torch.cuda.synchronize()
+    for i, ((_, Wb, Hb, _), (_, Wr, Hr, _)) in enumerate(zip(d, ref)):
+        assert rel(Wb.cpu().numpy(), Wr.cpu().numpy().astype(np.float64)) <= 2e-6, i
+        assert rel(Hb.cpu().numpy(), Hr.cpu().numpy().astype(np.float64)) <= 2e-6, i
+    assert b.flags() == 0
+    b.close()
+
+
+def test_batched_rejects_aliasing_and_large_k():
+    a, b = to_dev(make_set([(64, 100, 5, 1.0), (64, 100, 5, 0.5)], seed0=900))
+    # the second problem updates the first one's W
+    with pytest.raises(nb.NmfError):
+        nb.Batch([a, (b[0], a[1], b[2], b[3])], "joint", ctx=ctx())
+    # a problem's W inside another problem's V
+    with pytest.raises(nb.NmfError):
+        nb.Batch([a, (b[0], a[0][:, :5], b[2], b[3])], "joint", ctx=ctx())
+    # V shared between problems is allowed (read-only)
+    c = (a[0], a[1].clone(), a[2].clone(), 2.0)
+    nb.Batch([a, c], "joint", ctx=ctx()).close()
+    p = synth.random_positive(40, 50, 65, seed=3)
+    with pytest.raises(nb.NmfError):
+        nb.Batch([(dev(p.V), dev(p.W), dev(p.H), 1.0)], "joint", ctx=ctx())
+
+
+def test_batch_tune_restores_state_and_caches(tmp_path):
+    probs = to_dev(make_set(WELL_POSED, seed0=1100))
+    before = [(W.clone(), H.clone()) for _, W, H, _ in probs]
+    cache = str(tmp_path / "tune.json")
+    cfg, ms = nb.batch_tune(probs, "joint", iters=2, cache=cache, ctx=ctx())
+    assert cfg["tiles_per_item"] in (2, 4, 8, 16, 32) and ms > 0
+    for (W0, H0), (_, W, H, _) in zip(before, probs):
+        assert torch.equal(W0, W) and torch.equal(H0, H)
+    cfg2, ms2 = nb.batch_tune(probs, "joint", iters=2, cache=cache, ctx=ctx())
+    assert cfg2 == cfg and ms2 == ms
+    b = nb.Batch(probs, "joint", ctx=ctx(), **cfg)
+    b.step()
+    torch.cuda.synchronize()
+    assert b.flags() == 0
+    b.close()
