@@ -109,6 +109,7 @@ def main(argv=None):
     ap.add_argument("--min-tiles", type=int, default=0)
     ap.add_argument("--problems", type=int, default=512, help="batched workload: number of problems")
     ap.add_argument("--tune", default=None, help="batched workload: autotune, caching results in this JSON file")
+    ap.add_argument("--tiles", type=int, default=0, help="batched workload: tiles per pass item (0: library default)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"],
                     help="operand type of the matrix products (element-wise terms stay float32)")
     args = ap.parse_args(argv)
@@ -260,18 +261,24 @@ def main(argv=None):
     }
 
     if args.calib_copy:
-        x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
-        y = torch.empty_like(x)
-        for _ in range(3):
-            y.copy_(x)
-        torch.cuda.synchronize()
-        out["calib_copy_bytes"] = {"read": x.numel() * 4, "write": y.numel() * 4}
+        out["calib_copy_bytes"] = calib_copy(torch, dev)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     ctx.close()
     return 0
+
+
+def calib_copy(torch, dev):
+    """A plain 256 MiB device-to-device copy (three times): the known-size
+    reference that scales FETCH_SIZE / WRITE_SIZE counter readings."""
+    x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    return {"read": x.numel() * 4, "write": y.numel() * 4}
 
 
 def main_batched(args, nb, synth, torch, np, dev):
@@ -294,7 +301,7 @@ def main_batched(args, nb, synth, torch, np, dev):
     print(f"# batched: {len(probs)} problems, sum FN = {fn:.3e}, sum FNK = {fnk:.3e} "
           f"(generated in {time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
     ctx = nb.Context(0)
-    cfg = {"tiles_per_item": 0, "workers": 0}
+    cfg = {"tiles_per_item": args.tiles, "workers": 0}
     tuned_ms = None
     if args.tune:
         cfg, tuned_ms = nb.batch_tune(probs, "joint", precision=args.precision, iters=3, cache=args.tune, ctx=ctx)
@@ -350,6 +357,8 @@ def main_batched(args, nb, synth, torch, np, dev):
         "roofline": roof,
         "batch": res,
     }
+    if args.calib_copy:
+        out["calib_copy_bytes"] = calib_copy(torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batched(host, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -248,7 +248,7 @@ nmf_status nmf_batch_info(nmf_batch_t batch, int64_t* work_items, int32_t* worke
 nmf_status nmf_batch_destroy(nmf_batch_t batch);
 
 /* Autotuner: times `iters` batch steps (after one warm-up step) for each
- * candidate tiles_per_item in {2, 4, 8, 16, 32} on the given problems and
+ * candidate tiles_per_item in {4, 8, 16, 32, 64, 128} on the given problems and
  * returns the fastest configuration and its time per step in milliseconds.
  * The problems' W and H are saved before and restored after every candidate, so
  * they are unchanged on return.  Synchronous. */

@@ -426,6 +426,10 @@ nmf_status check_batch_alias(const nmf_problem* pr, int count) {
 constexpr int kBatchTilesDefault = 8;
 constexpr int kBatchUpdateRows = 32;   // rows of W per W-update work item
 constexpr int kBatchUpdateCols = 64;   // columns of H per H-update work item
+// the batched W update uses one thread slice per row: kBlock / KP rows per unit
+inline int batch_unit_rows(int KB) { return kBlock / (32 * KB); }
+inline int batch_w_units(int KB) { return std::max(1, kBatchUpdateRows / batch_unit_rows(KB)); }
+inline int batch_h_units(int KB) { return std::max(1, kBatchUpdateCols / (kBlock / (32 * KB))); }
 constexpr unsigned kBatchSpinLimit = 1u << 22;
 
 }  // namespace
@@ -784,8 +788,8 @@ nmf_status nmf_batch_create(nmf_ctx_t c, const nmf_problem* pr, int32_t count, i
   for (int i = 0; i < count; ++i) {
     plans[i] = make_batch_plan(pr[i].F, pr[i].N, pr[i].K, tiles);
     const Plan& p = plans[i];
-    total += (int64_t)p.row_blocks * p.n_groups + cdiv(p.uw_blocks, std::max(1, kBatchUpdateRows / update_w_unit_rows(p.KB))) +
-             (int64_t)p.col_blocks * p.f_groups + cdiv(p.uh_blocks, std::max(1, kBatchUpdateCols / (kBlock / p.KP)));
+    total += (int64_t)p.row_blocks * p.n_groups + cdiv(cdiv(pr[i].F, batch_unit_rows(p.KB)), batch_w_units(p.KB)) +
+             (int64_t)p.col_blocks * p.f_groups + cdiv(p.uh_blocks, batch_h_units(p.KB));
   }
   if (total >= (int64_t)1 << 31) return NMF_ERR_UNSUPPORTED;
   const size_t o_list = off;
@@ -826,11 +830,11 @@ nmf_status nmf_batch_create(nmf_ctx_t c, const nmf_problem* pr, int32_t count, i
     d.kb = p.KB;
     for (int ph = 0; ph < 4; ++ph) d.per_item[ph] = 1;
     d.units[PH_WPASS] = p.row_blocks * p.n_groups;
-    d.units[PH_WUPDATE] = p.uw_blocks;
+    d.units[PH_WUPDATE] = (int)cdiv(q.F, batch_unit_rows(p.KB));
     d.units[PH_HPASS] = p.col_blocks * p.f_groups;
     d.units[PH_HUPDATE] = p.uh_blocks;
-    d.per_item[PH_WUPDATE] = std::max(1, kBatchUpdateRows / update_w_unit_rows(p.KB));
-    d.per_item[PH_HUPDATE] = std::max(1, kBatchUpdateCols / (kBlock / p.KP));
+    d.per_item[PH_WUPDATE] = batch_w_units(p.KB);
+    d.per_item[PH_HUPDATE] = batch_h_units(p.KB);
     for (int ph = 0; ph < 4; ++ph) d.items[ph] = (int)cdiv(d.units[ph], d.per_item[ph]);
   }
   // queue: phase-major; within a phase the larger problems first
@@ -946,7 +950,7 @@ nmf_status nmf_batch_tune(nmf_ctx_t c, const nmf_problem* pr, int32_t count, int
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess || copy_all(true) != hipSuccess) {
     result = NMF_ERR_HIP;
   }
-  static const int kCandidates[] = {2, 4, 8, 16, 32};
+  static const int kCandidates[] = {4, 8, 16, 32, 64, 128};
   for (int ci = 0; result == NMF_OK && ci < (int)(sizeof(kCandidates) / sizeof(int)); ++ci) {
     nmf_batch_config cfg{kCandidates[ci], 0};
     nmf_batch_t b = nullptr;

@@ -57,7 +57,7 @@ __device__ __forceinline__ void batch_item(ConstProblemPtr P, int prob, int phas
     double nrm = 0.0, cs = 0.0;
     const int per = P->per_item[PH_WUPDATE];
     const int u1 = min(P->units[PH_WUPDATE], (item + 1) * per);
-    for (int u = item * per; u < u1; ++u) update_w_unit<KB>(ua, u, true, lds, den1, nrm, cs);
+    for (int u = item * per; u < u1; ++u) update_w_unit<KB, 1>(ua, u, true, lds, den1, nrm, cs);
   } else if (phase == PH_HPASS) {
     const SweepColsArgs ca = load_const(&P->ca);
     cols_prologue<KB>(ca, item, lds);
@@ -80,7 +80,7 @@ __device__ __forceinline__ void batch_item(ConstProblemPtr P, int prob, int phas
     write_w<KB>(ha, norm_s, (int64_t)item * kBlock + threadIdx.x, (int64_t)items * kBlock);
     const int per = P->per_item[PH_HUPDATE];
     const int u1 = min(P->units[PH_HUPDATE], (item + 1) * per);
-    for (int u = item * per; u < u1; ++u) update_h_cols<KB>(ha, u, norm_s, csum_s);
+    update_h_cols_multi<KB, 8>(ha, item * per, u1, norm_s, csum_s);
   }
 }
 

@@ -1161,19 +1161,21 @@ __device__ __forceinline__ void cols_item(const SweepColsArgs& a, int item, floa
 // the normalization (threads of slice 0 only).
 // ---------------------------------------------------------------------------
 constexpr int kSlices = 4;
-template <int KB>
-constexpr int unit_rows() { return kBlock / (32 * KB * kSlices) > 0 ? kBlock / (32 * KB * kSlices) : 1; }
-template <int KB>
-constexpr int unit_slices() { return kBlock / (32 * KB * unit_rows<KB>()); }
+template <int KB, int SL = kSlices>
+constexpr int unit_rows() { return kBlock / (32 * KB * SL) > 0 ? kBlock / (32 * KB * SL) : 1; }
+template <int KB, int SL = kSlices>
+constexpr int unit_slices() { return kBlock / (32 * KB * unit_rows<KB, SL>()); }
 template <int KB>
 constexpr int update_w_lds_floats() { return 2 * kBlock; }
 
-template <int KB>
+// SL: thread slices sharing a row's group sums (more slices: fewer rows per unit,
+// shorter per-thread sums for many groups).
+template <int KB, int SL = kSlices>
 __device__ __forceinline__ void update_w_unit(const UpdateWArgs& a, int unit, bool write_wt, float* lds,
                                               double den1, double& nrm, double& cs) {
   constexpr int KP = 32 * KB;
-  constexpr int RU = unit_rows<KB>();
-  constexpr int GS = unit_slices<KB>();
+  constexpr int RU = unit_rows<KB, SL>();
+  constexpr int GS = unit_slices<KB, SL>();
   constexpr int U = 8;  // groups per round
   const int tid = threadIdx.x;
   const int k = tid % KP, r = (tid / KP) % RU, gs = tid / (KP * RU);
@@ -1194,9 +1196,18 @@ __device__ __forceinline__ void update_w_unit(const UpdateWArgs& a, int unit, bo
 #pragma unroll
     for (int u = 0; u < U; ++u) { dn += (double)xn[u]; dd += (double)xd[u]; }
   }
-  for (; g < a.n_groups; g += GS) {
-    dn += (double)ldc(a.pnum, (int64_t)g * gstride + base, fok);
-    if (!a.beta_one) dd += (double)ldc(a.pden, (int64_t)g * gstride + base, fok);
+  if (g < a.n_groups) {  // the remaining groups in one round of predicated loads
+    float xn[U], xd[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool gu = fok && g + u * GS < a.n_groups;
+      xn[u] = ldc(a.pnum, (int64_t)(g + u * GS) * gstride + base, gu);
+      xd[u] = a.beta_one ? 0.f : ldc(a.pden, (int64_t)(g + u * GS) * gstride + base, gu);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (g + u * GS < a.n_groups) { dn += (double)xn[u]; dd += (double)xd[u]; }
+    }
   }
   (void)sn; (void)sd;
   double* red = reinterpret_cast<double*>(lds);  // [2][GS][RU*KP]
@@ -1378,6 +1389,56 @@ __device__ __forceinline__ void update_h_cols(const UpdateHArgs& a, int unit, co
     if (x > 0.f) nk = (double)x;
   }
   a.H[(int64_t)k * a.ldh + n] = (float)((double)hv * (pow_gamma(ratio, a.gamma) * nk));
+}
+
+// Units [u0, u1) of update_h_cols, M at a time with all their loads in flight
+// together (few row groups: each unit alone is one short load round trip).
+template <int KB, int M>
+__device__ __forceinline__ void update_h_cols_multi(const UpdateHArgs& a, int u0, int u1, const float* norm_s,
+                                                    const float* csum_s) {
+  constexpr int KP = 32 * KB;
+  constexpr int UC = kBlock / KP;
+  const int tid = threadIdx.x;
+  const int k = tid % KP;
+  const int64_t gstride = (int64_t)a.N * KP;
+  double nk = 1.0;
+  if (a.normalize && k < a.K) {
+    const float x = norm_s[k];
+    if (x > 0.f) nk = (double)x;
+  }
+  for (int ub = u0; ub < u1; ub += M) {
+    int n[M];
+    bool ok[M];
+    float hv[M];
+    double num[M], den[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      n[m] = (ub + m) * UC + tid / KP;
+      ok[m] = ub + m < u1 && n[m] < a.N && k < a.K;
+      hv[m] = ldc(a.H, (int64_t)k * a.ldh + n[m], ok[m]);
+      num[m] = 0.0;
+      den[m] = 0.0;
+    }
+    for (int g = 0; g < a.f_groups; ++g) {
+      float xn[M], xd[M];
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const int64_t o = (int64_t)g * gstride + (int64_t)n[m] * KP + k;
+        xn[m] = ldc(a.pnum, o, ok[m]);
+        xd[m] = a.beta_one ? 0.f : ldc(a.pden, o, ok[m]);
+      }
+#pragma unroll
+      for (int m = 0; m < M; ++m) { num[m] += (double)xn[m]; den[m] += (double)xd[m]; }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      if (!ok[m]) continue;
+      const double dd = a.beta_one ? (double)csum_s[k] : den[m];
+      const double ratio = num[m] / dd;
+      if (!(dd > 0.0) || !isfinite(ratio)) set_flag(a.flags, 1u);
+      a.H[(int64_t)k * a.ldh + n[m]] = (float)((double)hv[m] * (pow_gamma(ratio, a.gamma) * nk));
+    }
+  }
 }
 
 // W <- W_new / norm (or W_new), entries e0, e0 + stride, ...
