@@ -149,9 +149,13 @@ __global__ __launch_bounds__(kBlock, 1) void batched_step_kernel(BatchArgs b) {
     if (kb == 1) batch_item_bc<1, PREC, JOINT, OBJ>(bc, P, prob, phase, item, b, lds, red, norm_s, csum_s);
     else batch_item_bc<2, PREC, JOINT, OBJ>(bc, P, prob, phase, item, b, lds, red, norm_s, csum_s);
 
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this item's writes before its count
-    __syncthreads();
-    if (tid == 0) atomicAdd(b.done + 4 * prob + phase, 1u);
+    // nothing in the launch waits for the H update (its writes are read by the
+    // next launch), so only the first three phases publish their items
+    if (phase != PH_HUPDATE) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this item's writes before its count
+      __syncthreads();
+      if (tid == 0) atomicAdd(b.done + 4 * prob + phase, 1u);
+    }
   }
 
   // the last workgroup out resets the queue and the counters for the next launch

@@ -1183,6 +1183,7 @@ __device__ __forceinline__ void update_w_unit(const UpdateWArgs& a, int unit, bo
   const bool fok = f < a.F;
   const int64_t gstride = (int64_t)a.F * KP;
   const int64_t base = (int64_t)f * KP + k;
+  const float wtf = ldz(a.W, (int64_t)f * a.ldw + k, fok && k < a.K);  // issued with the partial loads
   float sn = 0.f, sd = 0.f;
   double dn = 0.0, dd = 0.0;
   int g = gs;
@@ -1211,7 +1212,6 @@ __device__ __forceinline__ void update_w_unit(const UpdateWArgs& a, int unit, bo
   }
   (void)sn; (void)sd;
   double* red = reinterpret_cast<double*>(lds);  // [2][GS][RU*KP]
-  const float wtf = ldz(a.W, (int64_t)f * a.ldw + k, fok && k < a.K);
   __syncthreads();  // red may still be read by the previous unit
   red[tid] = dn;
   red[kBlock + tid] = dd;

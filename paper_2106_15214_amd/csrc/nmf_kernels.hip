@@ -38,23 +38,86 @@ __global__ __launch_bounds__(kBlock) void update_w_kernel(UpdateWArgs a) {
     update_w_unit<KB>(a, u, true, reinterpret_cast<float*>(lds), den1, nrm, cs);
 }
 
+// H update of kBlock / KP columns per workgroup (thread (k, c) owns H[k][n]).
+// Every independent load -- the H~ entry, the first round of H partials, the
+// first W_new entry of the write-back -- is issued before the column-sum
+// reduction, so the kernel's latency is about one memory round trip plus the
+// reduction.
 template <int KB>
 __global__ __launch_bounds__(kBlock) void update_h_kernel(UpdateHArgs a) {
+  constexpr int KP = 32 * KB;
+  constexpr int UC = kBlock / KP;
+  constexpr int U = 8;
   __shared__ double scratch[2 * kBlock];
-  __shared__ float norm_s[32 * KB], csum_s[32 * KB];
+  __shared__ float norm_s[KP], csum_s[KP];
   __shared__ double red[kWaves];
+  const int tid = threadIdx.x;
+  const int k = tid % KP, n = blockIdx.x * UC + tid / KP;
+  const bool ok = n < a.N && k < a.K;
+  const int64_t gstride = (int64_t)a.N * KP;
+  const int64_t base = (int64_t)n * KP + k;
+  const float hv = ldc(a.H, (int64_t)k * a.ldh + n, ok);
+  float xn[U], xd[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const bool gu = ok && u < a.f_groups;
+    xn[u] = ldc(a.pnum, (int64_t)u * gstride + base, gu);
+    xd[u] = a.beta_one ? 0.f : ldc(a.pden, (int64_t)u * gstride + base, gu);
+  }
+  const int64_t total_w = (int64_t)a.F * a.K;
+  const int64_t e0 = (int64_t)blockIdx.x * kBlock + tid, estride = (int64_t)gridDim.x * kBlock;
+  const int f0 = (int)(e0 / (a.K > 0 ? a.K : 1)), kk0 = (int)(e0 % (a.K > 0 ? a.K : 1));
+  const float w0 = ldc(a.Wn, (int64_t)f0 * KP + kk0, e0 < total_w);
+
   reduce_columns<KB>(a.pcol, a.pcol_blocks, scratch, norm_s, csum_s);
   if (blockIdx.x == 0 && a.d_obj) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < a.nobj; i += kBlock) s += a.pobj[i];
+    for (int i = tid; i < a.nobj; i += kBlock) s += a.pobj[i];
     s = block_sum(s, red);
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       *a.d_obj = s;
       if (!isfinite(s)) set_flag(a.flags, 1u);
     }
   }
-  write_w<KB>(a, norm_s, (int64_t)blockIdx.x * kBlock + threadIdx.x, (int64_t)gridDim.x * kBlock);
-  update_h_cols<KB>(a, blockIdx.x, norm_s, csum_s);
+  // W <- W_new / norm: the first entry from the prefetched value, the rest (when
+  // the grid is smaller than F * K) by write_w
+  if (e0 < total_w) {
+    float w = w0;
+    if (a.normalize) {
+      const float x = norm_s[kk0];
+      if (x > 0.f) w = (float)((double)w / (double)x);
+    }
+    a.W[(int64_t)f0 * a.ldw + kk0] = w;
+  }
+  if (e0 + estride < total_w) write_w<KB>(a, norm_s, e0 + estride, estride);
+
+  double num = 0.0, den = 0.0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (u < a.f_groups) { num += (double)xn[u]; den += (double)xd[u]; }
+  }
+  for (int g = U; g < a.f_groups; g += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool gu = ok && g + u < a.f_groups;
+      xn[u] = ldc(a.pnum, (int64_t)(g + u) * gstride + base, gu);
+      xd[u] = a.beta_one ? 0.f : ldc(a.pden, (int64_t)(g + u) * gstride + base, gu);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (g + u < a.f_groups) { num += (double)xn[u]; den += (double)xd[u]; }
+    }
+  }
+  if (!ok) return;
+  const double dd = a.beta_one ? (double)csum_s[k] : den;
+  const double ratio = num / dd;
+  if (!(dd > 0.0) || !isfinite(ratio)) set_flag(a.flags, 1u);
+  double nk = 1.0;
+  if (a.normalize) {
+    const float x = norm_s[k];
+    if (x > 0.f) nk = (double)x;
+  }
+  a.H[(int64_t)k * a.ldh + n] = (float)((double)hv * (pow_gamma(ratio, a.gamma) * nk));
 }
 
 // Transposed copy WT[k][f] = W[f][k] (k < KP, zero-padded) and a row-major copy
