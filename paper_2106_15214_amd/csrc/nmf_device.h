@@ -25,6 +25,7 @@
 #pragma once
 
 #include "nmf_internal.h"
+#include "nmf_math.h"
 
 namespace nmf {
 
@@ -74,8 +75,15 @@ __device__ __noinline__ inline double d_beta_general(double v, double l, double 
 template <int BC>
 __device__ __forceinline__ double d_beta(double v, double l, double beta) {
   if (BC == BC_B2) { double t = v - l; return 0.5 * t * t; }
-  if (BC == BC_B1) return v > 0.0 ? v * log(v / l) - v + l : l;
-  if (BC == BC_B0) { double r = v / l; return r - log(r) - 1.0; }
+  if (BC == BC_B1) {  // v log(v / l) - v + l, and the limit l at v = 0
+    const double t = v * log64(div64(v, l)) - v + l;
+    return v > 0.0 ? t : l;
+  }
+  if (BC == BC_B0) {  // r - log r - 1 with r = v / l, and +inf at v = 0
+    const double r = div64(v, l);
+    const double t = r - log64(r) - 1.0;
+    return v > 0.0 ? t : __builtin_inf();
+  }
   if (BC == BC_B05) { double sy = sqrt(l); return -4.0 * sqrt(v) + 2.0 * sy + 2.0 * v / sy; }
   if (BC == BC_B15) { double sy = sqrt(l); return v * sqrt(v) / 0.75 + l * sy / 1.5 - 2.0 * v * sy; }
   return d_beta_general(v, l, beta);
@@ -354,7 +362,10 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
         } else if (KIND == KIND_GRAD) {
           P[r] = ok ? pow_bm2<BC>(lk, a.bm2) * (lam[r] - vcur[r]) : 0.f;
         }
-        if (OBJ && ok) objsum += d_beta<BC>((double)vk, (double)lk, a.beta);
+        if (OBJ) {
+          const double d = d_beta<BC>((double)vk, (double)lk, a.beta);
+          objsum += ok ? d : 0.0;
+        }
       }
       if (STORE_PQ) {
         // tile (slab of this wave, column tile t) as [n][f]: coalesced 32-float rows
@@ -631,7 +642,10 @@ __device__ __forceinline__ void rows_item_lp(const SweepRowsArgs& a, int item, f
         const float vk = vcur[r] + a.kappa;
         beta_terms<BC>(vk, lk, a.bm2, P[r], Q[r]);
         if (!ok) { P[r] = 0.f; Q[r] = 0.f; }
-        if (OBJ && ok) objsum += d_beta<BC>((double)vk, (double)lk, a.beta);
+        if (OBJ) {
+          const double d = d_beta<BC>((double)vk, (double)lk, a.beta);
+          objsum += ok ? d : 0.0;
+        }
       }
 #pragma unroll
       for (int st = 0; st < 2; ++st) {
