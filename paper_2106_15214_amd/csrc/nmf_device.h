@@ -201,8 +201,67 @@ __device__ __forceinline__ void sum_partials(const float* __restrict__ pn, const
 constexpr int kHS = 36;  // LDS row stride of [k][32] tiles: float4 and dword reads conflict-free
 
 // LDS bytes a rows item needs (two H~ tiles).
+// ---------------------------------------------------------------------------
+// KL objective terms with many zero data entries.  d_1(0 | l) = l needs no
+// logarithm; the entries with v > 0 are queued per wavefront in LDS (ballot +
+// prefix count) and their float64 terms evaluated 64 at a time, so the
+// logarithms cost one round per 64 nonzero entries instead of one per register.
+// ---------------------------------------------------------------------------
+constexpr int kKlQueue = 128;  // entries per wavefront (< 64 carried + 64 added)
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double kl_term(double v, double l) { return v * log64(div64(v, l)) - v + l; }
+
+struct KlQueue {
+  float* qv;  // [kKlQueue] data values
+  float* ql;  // [kKlQueue] Lambda values
+  int qn;     // queued entries (uniform over the wavefront)
+
+  __device__ __forceinline__ void push(bool ok, float v, float l, double& sum) {
+    const int lane = threadIdx.x & 63;
+    const bool nz = ok && v > 0.f;
+    sum += (ok && !nz) ? (double)l : 0.0;
+    const unsigned long long m = __ballot(nz);
+    const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    if (nz) {
+      const int pos = qn + __popcll(m & below);
+      qv[pos] = v;
+      ql[pos] = l;
+    }
+    qn += __popcll(m);
+    if (qn >= 64) {
+      wave_lds_sync();
+      sum += kl_term((double)qv[lane], (double)ql[lane]);
+      const int rest = qn - 64;
+      float rv = 0.f, rl = 0.f;
+      if (lane < rest) {
+        rv = qv[64 + lane];
+        rl = ql[64 + lane];
+      }
+      wave_lds_sync();
+      if (lane < rest) {
+        qv[lane] = rv;
+        ql[lane] = rl;
+      }
+      qn = rest;
+    }
+  }
+  __device__ __forceinline__ void drain(double& sum) {
+    const int lane = threadIdx.x & 63;
+    wave_lds_sync();
+    if (lane < qn) sum += kl_term((double)qv[lane], (double)ql[lane]);
+    qn = 0;
+    wave_lds_sync();
+  }
+};
+
 template <int KB>
-constexpr int rows_item_lds() { return 2 * 32 * KB * kHS * 4; }
+constexpr int rows_item_lds() { return 2 * 32 * KB * kHS * 4 + kWaves * 2 * kKlQueue * 4; }
 
 // ---------------------------------------------------------------------------
 // rows item: W-step contractions (reduction over n) for 128 rows of V over the
@@ -231,6 +290,7 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
   const bool wave_on = f0 < a.F;
   const int K = a.K, N = a.N;
   const int K2 = (K + 1) >> 1;
+  KlQueue klq{lds + 2 * KP * kHS + wave * 2 * kKlQueue, lds + 2 * KP * kHS + wave * 2 * kKlQueue + kKlQueue, 0};
 
   // B operand of Lambda^T = H~^T W~^T: lane holds W~[frow][2s + hi]
   // (all loads issued before any is masked, so they are in flight together)
@@ -363,8 +423,12 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
           P[r] = ok ? pow_bm2<BC>(lk, a.bm2) * (lam[r] - vcur[r]) : 0.f;
         }
         if (OBJ) {
-          const double d = d_beta<BC>((double)vk, (double)lk, a.beta);
-          objsum += ok ? d : 0.0;
+          if constexpr (BC == BC_B1) {
+            klq.push(ok, vk, lk, objsum);
+          } else {
+            const double d = d_beta<BC>((double)vk, (double)lk, a.beta);
+            objsum += ok ? d : 0.0;
+          }
         }
       }
       if (STORE_PQ) {
@@ -409,6 +473,7 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
     __syncthreads();
   }
 
+  if (OBJ && BC == BC_B1 && wave_on) klq.drain(objsum);
   if (CONTRACT && wave_on) {
     // accumulator (i = row offset f, j = li = column k); each wave owns its rows
 #pragma unroll
