@@ -84,8 +84,16 @@ __device__ __forceinline__ double d_beta(double v, double l, double beta) {
     const double t = r - log64(r) - 1.0;
     return v > 0.0 ? t : __builtin_inf();
   }
-  if (BC == BC_B05) { double sy = sqrt(l); return -4.0 * sqrt(v) + 2.0 * sy + 2.0 * v / sy; }
-  if (BC == BC_B15) { double sy = sqrt(l); return v * sqrt(v) / 0.75 + l * sy / 1.5 - 2.0 * v * sy; }
+  // beta = 1/2 and 3/2 in the factored forms (s = sqrt v, t = sqrt l):
+  //   d_{1/2} = 2 (s - t)^2 / t,   d_{3/2} = (2/3) (s - t)^2 (2 s + t),
+  // algebraically equal to eq. (beta-div) and free of its cancellation at v ~ l
+  if (BC == BC_B05 || BC == BC_B15) {
+    const double rl = rsqrt64(l), t = l > 0.0 ? sqrt64(l, rl) : 0.0;
+    const double s = v > 0.0 ? sqrt64(v, rsqrt64(v)) : 0.0;
+    const double dst = (s - t) * (s - t);
+    if (BC == BC_B05) return 2.0 * dst * rl;
+    return (2.0 / 3.0) * dst * (2.0 * s + t);
+  }
   return d_beta_general(v, l, beta);
 }
 

@@ -34,6 +34,30 @@ NMF_HD inline float rcp_seed(float x) {
 #endif
 }
 
+NMF_HD inline float rsq_seed(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rsqf(x);
+#else
+  return 1.0f / sqrtf(x);
+#endif
+}
+
+// 1 / sqrt(x) for x a positive normal float64 within the float32 range:
+// float32 seed, two Newton steps y <- y (3 - x y^2) / 2.
+NMF_HD inline double rsqrt64(double x) {
+  double y = (double)rsq_seed((float)x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+
+// sqrt(x) = x / sqrt(x) with one residual correction; `r` is rsqrt64(x).
+NMF_HD inline double sqrt64(double x, double r) {
+  const double s = x * r;
+  return fma(fma(-s, s, x), 0.5 * r, s);
+}
+
 // 1 / x for x a positive normal float64 within the float32 range.
 NMF_HD inline double rcp64(double x) {
   double y = (double)rcp_seed((float)x);   // about 2^-23 relative

@@ -1,4 +1,4 @@
-"""Host build of the float64 reciprocal / quotient / logarithm used for the
+"""Host build of the float64 reciprocal / quotient / logarithm / square root used for the
 objective terms (csrc/nmf_math.h), checked against the C library on random
 arguments spanning the float64 range that quotients of float32 values reach.
 On the GPU the same code starts from the hardware float32 reciprocal instead of
@@ -28,7 +28,7 @@ static double ulps(double got, double ref) {
 int main() {
   std::mt19937_64 rng(12345);
   std::uniform_real_distribution<double> ex(-160.0, 160.0), unit(-1.0, 1.0);
-  double worst_log = 0, worst_div = 0, worst_rcp = 0;
+  double worst_log = 0, worst_div = 0, worst_rcp = 0, worst_sqrt = 0, worst_rsq = 0;
   for (int i = 0; i < 2000000; ++i) {
     double x;
     if (i % 4 == 0) x = 1.0 + unit(rng) * std::ldexp(1.0, -(int)(i % 53));  // near 1
@@ -38,9 +38,12 @@ int main() {
     if (std::fabs(std::log2(x)) < 120) {
       worst_rcp = std::fmax(worst_rcp, ulps(nmf::rcp64(x), 1.0 / x));
       worst_div = std::fmax(worst_div, ulps(nmf::div64(a, x), a / x));
+      const double r = nmf::rsqrt64(x);
+      worst_rsq = std::fmax(worst_rsq, ulps(r, 1.0 / std::sqrt(x)));
+      worst_sqrt = std::fmax(worst_sqrt, ulps(nmf::sqrt64(x, r), std::sqrt(x)));
     }
   }
-  std::printf("%.3f %.3f %.3f\n", worst_log, worst_div, worst_rcp);
+  std::printf("%.3f %.3f %.3f %.3f %.3f\n", worst_log, worst_div, worst_rcp, worst_sqrt, worst_rsq);
   return 0;
 }
 """
@@ -56,8 +59,10 @@ def test_fast_log_div_rcp_match_libm(tmp_path):
     subprocess.run([cxx, "-O2", "-std=c++17", "-ffp-contract=off", "-I" + CSRC, str(src), "-o", str(exe)],
                    check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
-    worst_log, worst_div, worst_rcp = map(float, out)
+    worst_log, worst_div, worst_rcp, worst_sqrt, worst_rsq = map(float, out)
     # a few units in the last place: far below what the 1e-6 objective gate needs
     assert worst_log <= 4.0, worst_log
     assert worst_div <= 1.0, worst_div
     assert worst_rcp <= 1.0, worst_rcp
+    assert worst_sqrt <= 1.0, worst_sqrt
+    assert worst_rsq <= 4.0, worst_rsq
