@@ -166,7 +166,6 @@ nmf_status nmf_get_flags(nmf_ctx_t ctx, void* stream, uint32_t* flags, int32_t c
 #define NMF_KERNEL_UPDATE_W 1  /* reduction of W partials, W update, chi terms */
 #define NMF_KERNEL_SWEEP_H 2   /* pass over V accumulating the H-step contractions */
 #define NMF_KERNEL_UPDATE_H 3  /* reduction of H partials, H update, normalization */
-#define NMF_KERNEL_FUSED_KL 4  /* single pass for the joint update at beta = 1 */
 #define NMF_KERNEL_FUSED_STEP 5 /* whole outer iteration in one cooperative launch */
 #define NMF_KERNEL_COUNT 8
 nmf_status nmf_profile_enable(nmf_ctx_t ctx, uint32_t kernel_mask);

@@ -32,7 +32,7 @@ __all__ = [
 ALTERNATING, JOINT = 0, 1
 FP32, BF16, FP16 = 0, 1, 2
 FLAG_NONFINITE, FLAG_DOMAIN = 1, 2
-KERNELS = {"sweep_w": 0, "update_w": 1, "sweep_h": 2, "update_h": 3, "fused_kl": 4, "fused_step": 5}
+KERNELS = {"sweep_w": 0, "update_w": 1, "sweep_h": 2, "update_h": 3, "fused_step": 5}
 PATHS = {"auto": 0, "stream": 1, "fused": 2}
 FLAG_BARRIER = 4
 FLAG_RANGE = 8  # float16 mode: an operand outside the float16 range

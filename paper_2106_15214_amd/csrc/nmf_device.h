@@ -1434,52 +1434,9 @@ __device__ __forceinline__ void update_h_tile(const UpdateHArgs& a, int ntile, c
   }
 }
 
-// H update for a few columns (streaming kernel): thread (k, c) of the block
-// owns entry H[k][n0 + c], n0 = unit * (kBlock / KP), and sums its f_groups
-// partials in rounds of independent loads (eight groups per round), so the
-// kernel's latency is one partial read plus one H read-modify-write.
-template <int KB>
-__device__ __forceinline__ void update_h_cols(const UpdateHArgs& a, int unit, const float* norm_s,
-                                              const float* csum_s) {
-  constexpr int KP = 32 * KB;
-  constexpr int UC = kBlock / KP;  // columns per unit
-  constexpr int U = 8;
-  const int tid = threadIdx.x;
-  const int k = tid % KP, n = unit * UC + tid / KP;
-  const bool ok = n < a.N && k < a.K;
-  const int64_t gstride = (int64_t)a.N * KP;
-  const int64_t base = (int64_t)n * KP + k;
-  const float hv = ldc(a.H, (int64_t)k * a.ldh + n, ok);
-  double num = 0.0, den = 0.0;
-  for (int g = 0; g < a.f_groups; g += U) {
-    float xn[U], xd[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const bool gu = ok && g + u < a.f_groups;
-      xn[u] = ldc(a.pnum, (int64_t)(g + u) * gstride + base, gu);
-      xd[u] = a.beta_one ? 0.f : ldc(a.pden, (int64_t)(g + u) * gstride + base, gu);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const bool gu = g + u < a.f_groups;
-      num += gu ? (double)xn[u] : 0.0;
-      den += gu ? (double)xd[u] : 0.0;
-    }
-  }
-  if (!ok) return;
-  const double dd = a.beta_one ? (double)csum_s[k] : den;
-  const double ratio = num / dd;
-  if (!(dd > 0.0) || !isfinite(ratio)) set_flag(a.flags, 1u);
-  double nk = 1.0;
-  if (a.normalize) {
-    const float x = norm_s[k];
-    if (x > 0.f) nk = (double)x;
-  }
-  a.H[(int64_t)k * a.ldh + n] = (float)((double)hv * (pow_gamma(ratio, a.gamma) * nk));
-}
-
-// Units [u0, u1) of update_h_cols, M at a time with all their loads in flight
-// together (few row groups: each unit alone is one short load round trip).
+// H update of column units [u0, u1) (unit u: columns u * kBlock / KP + c, one
+// thread per (k, c)), M units at a time with all their loads in flight together
+// (with few row groups each unit alone is one short load round trip).
 template <int KB, int M>
 __device__ __forceinline__ void update_h_cols_multi(const UpdateHArgs& a, int u0, int u1, const float* norm_s,
                                                     const float* csum_s) {
