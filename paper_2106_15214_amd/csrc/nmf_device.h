@@ -1248,21 +1248,22 @@ __device__ __forceinline__ void cols_item(const SweepColsArgs& a, int item, floa
 // the normalization (threads of slice 0 only).
 // ---------------------------------------------------------------------------
 constexpr int kSlices = 4;
-template <int KB, int SL = kSlices>
-constexpr int unit_rows() { return kBlock / (32 * KB * SL) > 0 ? kBlock / (32 * KB * SL) : 1; }
-template <int KB, int SL = kSlices>
-constexpr int unit_slices() { return kBlock / (32 * KB * unit_rows<KB, SL>()); }
+template <int KB, int SL = kSlices, int BT = kBlock>
+constexpr int unit_rows() { return BT / (32 * KB * SL) > 0 ? BT / (32 * KB * SL) : 1; }
+template <int KB, int SL = kSlices, int BT = kBlock>
+constexpr int unit_slices() { return BT / (32 * KB * unit_rows<KB, SL, BT>()); }
 template <int KB>
 constexpr int update_w_lds_floats() { return 2 * kBlock; }
 
 // SL: thread slices sharing a row's group sums (more slices: fewer rows per unit,
-// shorter per-thread sums for many groups).
-template <int KB, int SL = kSlices>
+// shorter per-thread sums for many groups); BT: threads of the workgroup.  `lds`
+// holds 2 * BT doubles.
+template <int KB, int SL = kSlices, int BT = kBlock>
 __device__ __forceinline__ void update_w_unit(const UpdateWArgs& a, int unit, bool write_wt, float* lds,
                                               double den1, double& nrm, double& cs) {
   constexpr int KP = 32 * KB;
-  constexpr int RU = unit_rows<KB, SL>();
-  constexpr int GS = unit_slices<KB, SL>();
+  constexpr int RU = unit_rows<KB, SL, BT>();
+  constexpr int GS = unit_slices<KB, SL, BT>();
   constexpr int U = 8;  // groups per round
   const int tid = threadIdx.x;
   const int k = tid % KP, r = (tid / KP) % RU, gs = tid / (KP * RU);
@@ -1301,14 +1302,14 @@ __device__ __forceinline__ void update_w_unit(const UpdateWArgs& a, int unit, bo
   double* red = reinterpret_cast<double*>(lds);  // [2][GS][RU*KP]
   __syncthreads();  // red may still be read by the previous unit
   red[tid] = dn;
-  red[kBlock + tid] = dd;
+  red[BT + tid] = dd;
   __syncthreads();
   if (gs == 0) {
     double num = 0.0, den = 0.0;
 #pragma unroll
     for (int j = 0; j < GS; ++j) {
       num += red[j * KP * RU + tid];
-      den += red[kBlock + j * KP * RU + tid];
+      den += red[BT + j * KP * RU + tid];
     }
     float wn = 0.f, c1 = 0.f, c2 = 0.f;
     if (fok && k < a.K) {

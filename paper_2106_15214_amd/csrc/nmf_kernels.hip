@@ -28,14 +28,22 @@ __global__ __launch_bounds__(kBlock, sweep_cols_occupancy(BC, KB, KIND, DUAL)) v
   cols_item<BC, KB, KIND, DUAL, false>(a, blockIdx.x, lds);
 }
 
-template <int KB>
-__global__ __launch_bounds__(kBlock) void update_w_kernel(UpdateWArgs a) {
-  __shared__ double lds[2 * kBlock];
+// W update.  Narrow: 256 threads, four thread slices per row.  Wide: 1024
+// threads with the same rows per unit and four times as many slices, so that
+// each thread sums a quarter of the groups -- for problems split into many
+// groups, where the partial reads would otherwise take several rounds.
+constexpr int kUpdateWThreadsWide = 1024;
+
+template <int KB, int BT, int SL>
+__global__ __launch_bounds__(BT) void update_w_kernel(UpdateWArgs a) {
+  constexpr int RU = unit_rows<KB, SL, BT>();
+  static_assert(RU == unit_rows<KB>(), "rows per unit must match the host plan");
+  __shared__ double lds[2 * BT];
   const double den1 = row_sum_den<KB>(a);
   double nrm = 0.0, cs = 0.0;  // unused here: the H pass forms the column sums
-  const int units = (a.F + unit_rows<KB>() - 1) / unit_rows<KB>();
+  const int units = (a.F + RU - 1) / RU;
   for (int u = blockIdx.x; u < units; u += gridDim.x)
-    update_w_unit<KB>(a, u, true, reinterpret_cast<float*>(lds), den1, nrm, cs);
+    update_w_unit<KB, SL, BT>(a, u, true, reinterpret_cast<float*>(lds), den1, nrm, cs);
 }
 
 // H update of kBlock / KP columns per workgroup (thread (k, c) owns H[k][n]).
@@ -47,7 +55,7 @@ template <int KB>
 __global__ __launch_bounds__(kBlock) void update_h_kernel(UpdateHArgs a) {
   constexpr int KP = 32 * KB;
   constexpr int UC = kBlock / KP;
-  constexpr int U = 8;
+  constexpr int U = 16;
   __shared__ double scratch[2 * kBlock];
   __shared__ float norm_s[KP], csum_s[KP];
   __shared__ double red[kWaves];
@@ -283,10 +291,20 @@ hipError_t launch_sweep_cols(int bc, int kb, int kind, bool dual, int grid, hipS
 }
 
 hipError_t launch_update_w(int kb, int grid, hipStream_t s, const UpdateWArgs& a) {
+  const bool wide = a.n_groups > 4 * kSlices;
   switch (kb) {
-    case 1: hipLaunchKernelGGL(update_w_kernel<1>, dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(update_w_kernel<2>, dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 4: hipLaunchKernelGGL(update_w_kernel<4>, dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 1:
+      if (wide) hipLaunchKernelGGL((update_w_kernel<1, kUpdateWThreadsWide, 4 * kSlices>), dim3(grid), dim3(kUpdateWThreadsWide), 0, s, a);
+      else hipLaunchKernelGGL((update_w_kernel<1, kBlock, kSlices>), dim3(grid), dim3(kBlock), 0, s, a);
+      break;
+    case 2:
+      if (wide) hipLaunchKernelGGL((update_w_kernel<2, kUpdateWThreadsWide, 4 * kSlices>), dim3(grid), dim3(kUpdateWThreadsWide), 0, s, a);
+      else hipLaunchKernelGGL((update_w_kernel<2, kBlock, kSlices>), dim3(grid), dim3(kBlock), 0, s, a);
+      break;
+    case 4:
+      if (wide) hipLaunchKernelGGL((update_w_kernel<4, kUpdateWThreadsWide, 4 * kSlices>), dim3(grid), dim3(kUpdateWThreadsWide), 0, s, a);
+      else hipLaunchKernelGGL((update_w_kernel<4, kBlock, kSlices>), dim3(grid), dim3(kBlock), 0, s, a);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
