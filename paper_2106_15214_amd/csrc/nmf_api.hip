@@ -72,6 +72,7 @@ struct Plan {
   int col_parts, col_chunk;           // column partials of W_new formed in the H pass
   int64_t ldt;                        // leading dimension of the transposed factor (K x F)
   bool fused;                         // one cooperative launch (grid = fused_grid)
+  bool pq;                            // joint streaming path keeps P, Q between the passes
   int fused_grid;
   // byte offsets inside the workspace
   size_t o_pobj, o_pnum, o_pden, o_prs, o_wn, o_c1, o_c2, o_c0, o_wt, o_pcol, o_pnumh, o_pdenh, o_colsum, o_pst,
@@ -143,6 +144,10 @@ Plan layout(const Sizes& z, Plan p) {
 // Largest problem (F N entries) run as one fused launch: its P and Q tiles
 // (8 bytes per entry) stay well inside the 256 MB last-level cache.
 constexpr int64_t kFusedMaxEntries = int64_t(1) << 24;
+// Largest problem (F N entries) whose joint streaming step keeps P and Q in the
+// workspace between the passes (two float arrays of F N entries): the H pass
+// then contracts them instead of forming Lambda~ and its powers a second time.
+constexpr int64_t kPQMaxEntries = int64_t(1) << 28;
 
 int fused_capacity(nmf_ctx_s* c, int bc, int kb, bool joint, bool obj) {
   int& slot = c->fused_grid[kb - 1][bc][joint][obj];
@@ -169,12 +174,14 @@ Plan finish_plan(Plan p, int64_t F, int64_t N) {
   z.wt = sizeof(float) * (size_t)p.KP * p.ldt;
   z.pcol = sizeof(double) * (size_t)(p.fused ? p.uw_blocks : (int64_t)p.f_groups * p.col_parts) * 2 * p.KP;
   z.pnumh = sizeof(float) * (size_t)p.f_groups * N * p.KP;
-  z.pq = p.fused ? sizeof(float) * (size_t)cdiv(F, kTile) * cdiv(N, kTile) * kTile * kTile : 0;
+  z.pq = (p.fused || p.pq) ? sizeof(float) * (size_t)cdiv(F, kTile) * cdiv(N, kTile) * kTile * kTile : 0;
   return layout(z, p);
 }
 
-Plan make_plan(const nmf_ctx_s* c, int64_t F, int64_t N, int64_t K, int cols_occ = 2, int fused_grid = 0) {
+Plan make_plan(const nmf_ctx_s* c, int64_t F, int64_t N, int64_t K, int cols_occ = 2, int fused_grid = 0,
+               bool pq = false) {
   Plan p{};
+  p.pq = pq && fused_grid == 0;
   p.KB = kblocks_for(K);
   p.KP = 32 * p.KB;
   p.fused = fused_grid > 0;
@@ -236,7 +243,10 @@ size_t plan_bound(const nmf_ctx_s* c, int64_t maxF, int64_t maxN, int64_t maxK) 
   z.pcol = sizeof(double) * (size_t)(pcol_rows * 2 * KP);
   z.pnumh = sizeof(float) * (size_t)(rows_bound(maxN, maxF) * KP);
   const int64_t ft = cdiv(maxF, kTile), nt = cdiv(maxN, kTile);
-  if (ft * nt * kTile * kTile <= 2 * kFusedMaxEntries) z.pq = sizeof(float) * (size_t)(ft * nt * kTile * kTile);
+  // P, Q tiles: every problem within the bounds that keeps them has F N <= kPQMaxEntries
+  // (or the smaller single-launch limit), padded to whole 32 x 32 tiles
+  const int64_t pq_cap = kPQMaxEntries + kTile * (maxF + maxN) + kTile * kTile;
+  z.pq = sizeof(float) * (size_t)std::min<int64_t>(ft * nt * kTile * kTile, pq_cap);
   return layout(z, Plan{}).total;
 }
 
@@ -535,7 +545,9 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
     if (cs == hipStreamCaptureStatusNone) fused_grid = fused_capacity(c, bc, kblocks_for(K), joint, want_obj);
   }
   if (c->path == NMF_PATH_FUSED && fused_grid <= 0) return NMF_ERR_UNSUPPORTED;
-  const Plan p = make_plan(c, F, N, K, sweep_cols_occupancy(bc, kblocks_for(K), KIND_UPDATE, joint), fused_grid);
+  const bool use_pq = joint && prec == NMF_FP32 && fused_grid == 0 && F * N <= kPQMaxEntries;
+  const Plan p =
+      make_plan(c, F, N, K, sweep_cols_occupancy(bc, kblocks_for(K), KIND_UPDATE, joint), fused_grid, use_pq);
   if ((st = ensure_ws(c, s, p.total)) != NMF_OK) return st;
 
   StepArgs sa = make_step_args(p, c->ws, flags_ptr(c), F, N, K, V, ldv, W, ldw, H, ldh, beta, joint, prec, o,
@@ -568,15 +580,21 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
       return launch_fused(bc, p.KB, joint, want_obj, p.fused_grid, s, fa);
     }));
   }
+  if (p.pq) {
+    ra.NT = (int)cdiv(N, kTile);
+    ra.Pst = (float*)(ws + p.o_pst);
+    ra.Qst = (float*)(ws + p.o_qst);
+    ca.NT = ra.NT; ca.Pst = ra.Pst; ca.Qst = ra.Qst;
+  }
   hipError_t e = timed(c, NMF_KERNEL_SWEEP_W, s, [&] {
-    return prec == NMF_FP32 ? launch_sweep_rows(bc, p.KB, KIND_UPDATE, want_obj, sw_grid, s, ra)
+    return prec == NMF_FP32 ? launch_sweep_rows(bc, p.KB, KIND_UPDATE, want_obj, p.pq, sw_grid, s, ra)
                             : launch_sweep_rows_lp(prec, bc, p.KB, want_obj, sw_grid, s, ra);
   });
   if (e != hipSuccess) return NMF_ERR_HIP;
   e = timed(c, NMF_KERNEL_UPDATE_W, s, [&] { return launch_update_w(p.KB, p.uw_blocks, s, ua); });
   if (e != hipSuccess) return NMF_ERR_HIP;
   e = timed(c, NMF_KERNEL_SWEEP_H, s, [&] {
-    return prec == NMF_FP32 ? launch_sweep_cols(bc, p.KB, KIND_UPDATE, joint, sh_grid, s, ca)
+    return prec == NMF_FP32 ? launch_sweep_cols(bc, p.KB, KIND_UPDATE, joint, p.pq, sh_grid, s, ca)
                             : launch_sweep_cols_lp(prec, bc, p.KB, joint, sh_grid, s, ca);
   });
   if (e != hipSuccess) return NMF_ERR_HIP;
@@ -604,7 +622,7 @@ nmf_status nmf_beta_objective(nmf_ctx_t c, void* stream, int64_t F, int64_t N, i
   ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
   ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
   const int grid = p.row_blocks * p.n_groups;
-  hipError_t e = launch_sweep_rows(beta_class(beta), p.KB, KIND_OBJ, true, grid, s, ra);
+  hipError_t e = launch_sweep_rows(beta_class(beta), p.KB, KIND_OBJ, true, false, grid, s, ra);
   if (e != hipSuccess) return NMF_ERR_HIP;
   return hip_status(launch_finalize_objective(s, ra.pobj, grid, d_out, flags_ptr(c)));
 }
@@ -641,7 +659,7 @@ nmf_status nmf_beta_grad(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
   ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
   const int sw_grid = p.row_blocks * p.n_groups;
-  hipError_t e = launch_sweep_rows(bc, p.KB, KIND_GRAD, d_objective != nullptr, sw_grid, s, ra);
+  hipError_t e = launch_sweep_rows(bc, p.KB, KIND_GRAD, d_objective != nullptr, false, sw_grid, s, ra);
   if (e != hipSuccess) return NMF_ERR_HIP;
   float* WT = (float*)(ws + p.o_wt);
   float* Wp = (float*)(ws + p.o_wn);
@@ -652,7 +670,7 @@ nmf_status nmf_beta_grad(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   ca.bm2 = (float)(beta - 2.0); ca.kappa = kappa;
   ca.f_groups = p.f_groups; ca.tiles_per_group = p.tiles_f;
   ca.pnum = (float*)(ws + p.o_pnumh);
-  e = launch_sweep_cols(bc, p.KB, KIND_GRAD, false, p.col_blocks * p.f_groups, s, ca);
+  e = launch_sweep_cols(bc, p.KB, KIND_GRAD, false, false, p.col_blocks * p.f_groups, s, ca);
   if (e != hipSuccess) return NMF_ERR_HIP;
   const int gw = (int)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(F * K, kBlock)));
   if ((e = launch_grad_w(p.KB, gw, s, ra.pnum, (int)F, (int)K, p.n_groups, scale, dW, lddw)) != hipSuccess)

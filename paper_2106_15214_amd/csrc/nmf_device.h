@@ -445,7 +445,7 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int64_t o = tb + acc_row(r, hi) * kTile + li;
-          a.Pst[o] = P[r];
+          if (BC != BC_B2) a.Pst[o] = P[r];  // beta = 2: P is V itself, read again from V
           if (BC != BC_B1) a.Qst[o] = Q[r];
         }
       }
@@ -1122,11 +1122,20 @@ __device__ __forceinline__ void cols_item(const SweepColsArgs& a, int item, floa
       const int64_t tb = ((int64_t)(f0 >> 5) * a.NT + (n0w >> 5)) * (kTile * kTile) + li * kTile;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const float4 x = *reinterpret_cast<const float4*>(a.Pst + tb + 8 * q + 4 * hi);
-        v[4 * q + 0] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+        if (BC != BC_B2) {
+          const float4 x = *reinterpret_cast<const float4*>(a.Pst + tb + 8 * q + 4 * hi);
+          v[4 * q + 0] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+        }
         if (NEED_DEN) {
           const float4 y = *reinterpret_cast<const float4*>(a.Qst + tb + 8 * q + 4 * hi);
           w[4 * q + 0] = y.x; w[4 * q + 1] = y.y; w[4 * q + 2] = y.z; w[4 * q + 3] = y.w;
+        }
+      }
+      if (BC == BC_B2) {  // P = V + kappa: read V (masked where it is consumed)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int f = f0 + acc_row(r, hi);
+          v[r] = ldc(a.V, (int64_t)f * a.ldv + ncol, ncol_ok && f < F);
         }
       }
     } else {
@@ -1164,7 +1173,15 @@ __device__ __forceinline__ void cols_item(const SweepColsArgs& a, int item, floa
       float P[16], Q[16];
       if (LOAD_PQ) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) { P[r] = vcur[r]; Q[r] = NEED_DEN ? wcur[r] : 0.f; }
+        for (int r = 0; r < 16; ++r) {
+          if (BC == BC_B2) {
+            const bool ok = ncol_ok && f0 + acc_row(r, hi) < F;
+            P[r] = ok ? vcur[r] + a.kappa : 0.f;
+          } else {
+            P[r] = vcur[r];
+          }
+          Q[r] = NEED_DEN ? wcur[r] : 0.f;
+        }
       } else {
         const float* ws = buf ? Ws1 : Ws0;
         // Lambda tile: lam[r] = Lambda[f0 + acc_row(r, hi)][ncol]; A operand W[f0+li][2s+hi]

@@ -109,8 +109,11 @@ struct UpdateHArgs {
 };
 
 // launchers (nmf_kernels.hip)
-hipError_t launch_sweep_rows(int bc, int kb, int kind, bool obj, int grid, hipStream_t s, const SweepRowsArgs& a);
-hipError_t launch_sweep_cols(int bc, int kb, int kind, bool dual, int grid, hipStream_t s, const SweepColsArgs& a);
+// pq: the joint W pass keeps P, Q (Pst, Qst) and the joint H pass contracts them
+hipError_t launch_sweep_rows(int bc, int kb, int kind, bool obj, bool pq, int grid, hipStream_t s,
+                             const SweepRowsArgs& a);
+hipError_t launch_sweep_cols(int bc, int kb, int kind, bool dual, bool pq, int grid, hipStream_t s,
+                             const SweepColsArgs& a);
 // low-precision products (prec 1 = bfloat16, 2 = float16; update kind, K <= 64)
 hipError_t launch_sweep_rows_lp(int prec, int bc, int kb, bool obj, int grid, hipStream_t s, const SweepRowsArgs& a);
 hipError_t launch_sweep_cols_lp(int prec, int bc, int kb, bool dual, int grid, hipStream_t s, const SweepColsArgs& a);

@@ -1,32 +1,11 @@
-// Streaming HIP kernels for beta-NMF multiplicative updates on gfx950: one
-// pass over V per launch (rows or columns orientation), plus the update
-// kernels that reduce the partial contractions and apply the multiplicative
-// updates.  The device building blocks live in nmf_device.h.
+// Update kernels of the streaming path (reduction of the partial contractions,
+// multiplicative updates, normalization), transposition, gradient write-out,
+// objective finalization and the domain scan.  The passes over V are in
+// nmf_sweep_rows.hip and nmf_sweep_cols.hip; the device building blocks live in
+// nmf_device.h.
 #include "nmf_device.h"
 
 namespace nmf {
-
-template <int BC, int KB, int KIND, bool OBJ>
-__global__ __launch_bounds__(kBlock, sweep_rows_occupancy(KB)) void sweep_rows_kernel(SweepRowsArgs a) {
-  __shared__ __align__(16) float lds[rows_item_lds<KB>() / 4];
-  __shared__ double dred[kWaves];
-  double objsum = 0.0;
-  rows_item<BC, KB, KIND, OBJ, false>(a, blockIdx.x, lds, objsum);
-  if (OBJ) {
-    const double sum = block_sum(objsum, dred);
-    if (threadIdx.x == 0) a.pobj[blockIdx.x] = sum;
-  }
-}
-
-template <int BC, int KB, int KIND, bool DUAL>
-__global__ __launch_bounds__(kBlock, sweep_cols_occupancy(BC, KB, KIND, DUAL)) void sweep_cols_kernel(
-    SweepColsArgs a) {
-  constexpr bool C2_TILE = DUAL && (KIND == KIND_UPDATE) && (BC != BC_B1);
-  __shared__ __align__(16) float lds[cols_item_lds<KB, C2_TILE>() / 4];
-  static_assert(cols_item_lds<KB, C2_TILE>() >= 2 * kBlock * 8, "column partial scratch");
-  if (KIND == KIND_UPDATE) cols_prologue<KB>(a, blockIdx.x, lds);
-  cols_item<BC, KB, KIND, DUAL, false>(a, blockIdx.x, lds);
-}
 
 // W update.  Narrow: 256 threads, four thread slices per row.  Wide: 1024
 // threads with the same rows per unit and four times as many slices, so that
@@ -221,75 +200,6 @@ __global__ __launch_bounds__(kBlock) void validate_kernel(const float* V, int64_
 // ---------------------------------------------------------------------------
 // launchers: map runtime (beta class, K block count, kind) to instantiations
 // ---------------------------------------------------------------------------
-template <int BC, int KB>
-static hipError_t rows_kb(int kind, bool obj, int grid, hipStream_t s, const SweepRowsArgs& a) {
-  if (kind == KIND_UPDATE) {
-    if (obj) hipLaunchKernelGGL((sweep_rows_kernel<BC, KB, KIND_UPDATE, true>), dim3(grid), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((sweep_rows_kernel<BC, KB, KIND_UPDATE, false>), dim3(grid), dim3(kBlock), 0, s, a);
-  } else if (kind == KIND_GRAD) {
-    if (obj) hipLaunchKernelGGL((sweep_rows_kernel<BC, KB, KIND_GRAD, true>), dim3(grid), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((sweep_rows_kernel<BC, KB, KIND_GRAD, false>), dim3(grid), dim3(kBlock), 0, s, a);
-  } else {
-    hipLaunchKernelGGL((sweep_rows_kernel<BC, KB, KIND_OBJ, true>), dim3(grid), dim3(kBlock), 0, s, a);
-  }
-  return hipGetLastError();
-}
-
-template <int BC>
-static hipError_t rows_bc(int kb, int kind, bool obj, int grid, hipStream_t s, const SweepRowsArgs& a) {
-  switch (kb) {
-    case 1: return rows_kb<BC, 1>(kind, obj, grid, s, a);
-    case 2: return rows_kb<BC, 2>(kind, obj, grid, s, a);
-    case 4: return rows_kb<BC, 4>(kind, obj, grid, s, a);
-  }
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_sweep_rows(int bc, int kb, int kind, bool obj, int grid, hipStream_t s, const SweepRowsArgs& a) {
-  switch (bc) {
-    case BC_GEN: return rows_bc<BC_GEN>(kb, kind, obj, grid, s, a);
-    case BC_B2: return rows_bc<BC_B2>(kb, kind, obj, grid, s, a);
-    case BC_B1: return rows_bc<BC_B1>(kb, kind, obj, grid, s, a);
-    case BC_B0: return rows_bc<BC_B0>(kb, kind, obj, grid, s, a);
-    case BC_B05: return rows_bc<BC_B05>(kb, kind, obj, grid, s, a);
-    case BC_B15: return rows_bc<BC_B15>(kb, kind, obj, grid, s, a);
-  }
-  return hipErrorInvalidValue;
-}
-
-template <int BC, int KB>
-static hipError_t cols_kb(int kind, bool dual, int grid, hipStream_t s, const SweepColsArgs& a) {
-  if (kind == KIND_UPDATE) {
-    if (dual) hipLaunchKernelGGL((sweep_cols_kernel<BC, KB, KIND_UPDATE, true>), dim3(grid), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((sweep_cols_kernel<BC, KB, KIND_UPDATE, false>), dim3(grid), dim3(kBlock), 0, s, a);
-  } else {
-    hipLaunchKernelGGL((sweep_cols_kernel<BC, KB, KIND_GRAD, false>), dim3(grid), dim3(kBlock), 0, s, a);
-  }
-  return hipGetLastError();
-}
-
-template <int BC>
-static hipError_t cols_bc(int kb, int kind, bool dual, int grid, hipStream_t s, const SweepColsArgs& a) {
-  switch (kb) {
-    case 1: return cols_kb<BC, 1>(kind, dual, grid, s, a);
-    case 2: return cols_kb<BC, 2>(kind, dual, grid, s, a);
-    case 4: return cols_kb<BC, 4>(kind, dual, grid, s, a);
-  }
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_sweep_cols(int bc, int kb, int kind, bool dual, int grid, hipStream_t s, const SweepColsArgs& a) {
-  switch (bc) {
-    case BC_GEN: return cols_bc<BC_GEN>(kb, kind, dual, grid, s, a);
-    case BC_B2: return cols_bc<BC_B2>(kb, kind, dual, grid, s, a);
-    case BC_B1: return cols_bc<BC_B1>(kb, kind, dual, grid, s, a);
-    case BC_B0: return cols_bc<BC_B0>(kb, kind, dual, grid, s, a);
-    case BC_B05: return cols_bc<BC_B05>(kb, kind, dual, grid, s, a);
-    case BC_B15: return cols_bc<BC_B15>(kb, kind, dual, grid, s, a);
-  }
-  return hipErrorInvalidValue;
-}
-
 hipError_t launch_update_w(int kb, int grid, hipStream_t s, const UpdateWArgs& a) {
   const bool wide = a.n_groups > 4 * kSlices;
   switch (kb) {
