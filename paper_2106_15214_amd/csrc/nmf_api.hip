@@ -201,8 +201,9 @@ Plan make_plan(const nmf_ctx_s* c, int64_t F, int64_t N, int64_t K, int cols_occ
 // Splits of a problem inside a batch: every row (column) group covers about
 // `tiles` column (row) tiles; one W-update unit of rows and one H-update unit
 // of columns per work item.
-Plan make_batch_plan(int64_t F, int64_t N, int64_t K, int tiles) {
+Plan make_batch_plan(int64_t F, int64_t N, int64_t K, int tiles, bool pq) {
   Plan p{};
+  p.pq = pq;
   p.KB = kblocks_for(K);
   p.KP = 32 * p.KB;
   const int64_t tn = cdiv(N, kTile), tf = cdiv(F, kTile);
@@ -804,7 +805,7 @@ nmf_status nmf_batch_create(nmf_ctx_t c, const nmf_problem* pr, int32_t count, i
   off = align_up(off + sizeof(BatchProblem) * (size_t)count);
   int64_t total = 0;
   for (int i = 0; i < count; ++i) {
-    plans[i] = make_batch_plan(pr[i].F, pr[i].N, pr[i].K, tiles);
+    plans[i] = make_batch_plan(pr[i].F, pr[i].N, pr[i].K, tiles, joint && o.precision == NMF_FP32);
     const Plan& p = plans[i];
     total += (int64_t)p.row_blocks * p.n_groups + cdiv(cdiv(pr[i].F, batch_unit_rows(p.KB)), batch_w_units(p.KB)) +
              (int64_t)p.col_blocks * p.f_groups + cdiv(p.uh_blocks, batch_h_units(p.KB));
@@ -839,6 +840,12 @@ nmf_status nmf_batch_create(nmf_ctx_t c, const nmf_problem* pr, int32_t count, i
     const Plan& p = plans[i];
     StepArgs sa = make_step_args(p, mem + base[i], flags, q.F, q.N, q.K, q.V, q.ldv, q.W, q.ldw, q.H, q.ldh,
                                  q.beta, joint, o.precision, o, nullptr);
+    if (p.pq) {  // joint: the H pass contracts the kept P, Q tiles
+      sa.ra.NT = (int)cdiv(q.N, kTile);
+      sa.ra.Pst = (float*)(mem + base[i] + p.o_pst);
+      sa.ra.Qst = (float*)(mem + base[i] + p.o_qst);
+      sa.ca.NT = sa.ra.NT; sa.ca.Pst = sa.ra.Pst; sa.ca.Qst = sa.ra.Qst;
+    }
     BatchProblem& d = desc[i];
     d.ra = sa.ra;
     d.ua = sa.ua;

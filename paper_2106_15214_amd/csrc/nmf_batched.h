@@ -1,9 +1,11 @@
 // Many beta-NMF problems of uneven sizes, each with its own beta and rank, in
 // one persistent launch.  Workgroups take work items from a queue listed
 // phase-major over all problems:
-//   W-pass items  (rows items: Lambda~ tiles, P, Q, W-step partials, objective)
+//   W-pass items  (rows items: Lambda~ tiles, P, Q, W-step partials, objective;
+//                  in joint mode with float32 products P and Q are kept)
 //   W-update units (partials reduced, W_new, chi terms)
-//   H-pass items  (cols items: H-step partials, column sums of W_new)
+//   H-pass items  (cols items: H-step partials from the kept P, Q in joint mode,
+//                  column sums of W_new)
 //   H-update units (H_new, normalization, W write-back, objective total)
 // A per-problem counter of finished items per phase replaces grid barriers: an
 // item of phase q waits until its problem's phase q - 1 is complete.  Every
@@ -44,7 +46,7 @@ __device__ __forceinline__ void batch_item(ConstProblemPtr P, int prob, int phas
   if (phase == PH_WPASS) {
     const SweepRowsArgs ra = load_const(&P->ra);
     double objsum = 0.0;
-    if constexpr (PREC == 0) rows_item<BC, KB, KIND_UPDATE, OBJ, false>(ra, item, lds, objsum);
+    if constexpr (PREC == 0) rows_item<BC, KB, KIND_UPDATE, OBJ, JOINT>(ra, item, lds, objsum);
     else if constexpr (PREC == 1) rows_item_lp<BC, KB, OBJ, __bf16>(ra, item, lds, objsum);
     else rows_item_lp<BC, KB, OBJ, _Float16>(ra, item, lds, objsum);
     if (OBJ) {
@@ -61,7 +63,7 @@ __device__ __forceinline__ void batch_item(ConstProblemPtr P, int prob, int phas
   } else if (phase == PH_HPASS) {
     const SweepColsArgs ca = load_const(&P->ca);
     cols_prologue<KB>(ca, item, lds);
-    if constexpr (PREC == 0) cols_item<BC, KB, KIND_UPDATE, JOINT, false>(ca, item, lds);
+    if constexpr (PREC == 0) cols_item<BC, KB, KIND_UPDATE, JOINT, JOINT>(ca, item, lds);
     else if constexpr (PREC == 1) cols_item_lp<BC, KB, JOINT, __bf16>(ca, item, lds);
     else cols_item_lp<BC, KB, JOINT, _Float16>(ca, item, lds);
   } else {
