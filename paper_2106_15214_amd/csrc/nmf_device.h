@@ -230,7 +230,9 @@ struct KlQueue {
   float* ql;  // [kKlQueue] Lambda values
   int qn;     // queued entries (uniform over the wavefront)
 
-  __device__ __forceinline__ void push(bool ok, float v, float l, double& sum) {
+  // queues (ok, v > 0) entries, adds the zero entries' terms to sum; returns the
+  // number of entries with v > 0 in the wavefront
+  __device__ __forceinline__ int push(bool ok, float v, float l, double& sum) {
     const int lane = threadIdx.x & 63;
     const bool nz = ok && v > 0.f;
     sum += (ok && !nz) ? (double)l : 0.0;
@@ -241,7 +243,8 @@ struct KlQueue {
       qv[pos] = v;
       ql[pos] = l;
     }
-    qn += __popcll(m);
+    const int cnt = __popcll(m);
+    qn += cnt;
     if (qn >= 64) {
       wave_lds_sync();
       sum += kl_term((double)qv[lane], (double)ql[lane]);
@@ -258,6 +261,7 @@ struct KlQueue {
       }
       qn = rest;
     }
+    return cnt;
   }
   __device__ __forceinline__ void drain(double& sum) {
     const int lane = threadIdx.x & 63;
@@ -299,6 +303,7 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
   const int K = a.K, N = a.N;
   const int K2 = (K + 1) >> 1;
   KlQueue klq{lds + 2 * KP * kHS + wave * 2 * kKlQueue, lds + 2 * KP * kHS + wave * 2 * kKlQueue + kKlQueue, 0};
+  bool klq_dense = true;
 
   // B operand of Lambda^T = H~^T W~^T: lane holds W~[frow][2s + hi]
   // (all loads issued before any is masked, so they are in flight together)
@@ -430,14 +435,32 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
         } else if (KIND == KIND_GRAD) {
           P[r] = ok ? pow_bm2<BC>(lk, a.bm2) * (lam[r] - vcur[r]) : 0.f;
         }
-        if (OBJ) {
-          if constexpr (BC == BC_B1) {
-            klq.push(ok, vk, lk, objsum);
-          } else {
-            const double d = d_beta<BC>((double)vk, (double)lk, a.beta);
+        if (OBJ && BC != BC_B1) {
+          const double d = d_beta<BC>((double)vk, (double)lk, a.beta);
+          objsum += ok ? d : 0.0;
+        }
+      }
+      if (OBJ && BC == BC_B1) {
+        // KL: after a mostly-zero tile the next one goes through the queue,
+        // after a dense tile (and for the first tile of an item) term by term
+        int nnz = 0;
+        if (klq_dense) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const bool ok = frow_ok && n0 + acc_row(r, hi) < N;
+            const float vk = vcur[r] + a.kappa;
+            nnz += __popcll(__ballot(ok && vk > 0.f));
+            const double d = d_beta<BC>((double)vk, (double)(lam[r] + a.kappa), a.beta);
             objsum += ok ? d : 0.0;
           }
+        } else {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const bool ok = frow_ok && n0 + acc_row(r, hi) < N;
+            nnz += klq.push(ok, vcur[r] + a.kappa, lam[r] + a.kappa, objsum);
+          }
         }
+        klq_dense = nnz >= kTile * kTile / 2;
       }
       if (STORE_PQ) {
         // tile (slab of this wave, column tile t) as [n][f]: coalesced 32-float rows
@@ -1360,6 +1383,26 @@ __device__ __forceinline__ double row_sum_den(const UpdateWArgs& a) {
   if (a.beta_one && k < a.K)
     for (int g = 0; g < a.n_groups; ++g) d += (double)a.prs[g * KP + k];
   return d;
+}
+
+// The same with all BT threads of the workgroup: thread (k, j) sums groups
+// j, j + BT / KP, ... and the slices are combined through `scratch` (BT doubles)
+// in a fixed order, so every thread returns the total for its k.
+template <int KB, int BT>
+__device__ __forceinline__ double row_sum_den_wide(const UpdateWArgs& a, double* scratch) {
+  constexpr int KP = 32 * KB;
+  constexpr int SLICES = BT / KP;
+  const int k = threadIdx.x % KP, j = threadIdx.x / KP;
+  double d = 0.0;
+  if (a.beta_one && k < a.K)
+    for (int g = j; g < a.n_groups; g += SLICES) d += (double)a.prs[g * KP + k];
+  __syncthreads();
+  scratch[threadIdx.x] = d;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < SLICES; ++i) t += scratch[i * KP + k];
+  __syncthreads();
+  return t;
 }
 
 // Column norms / sums of W_new from per-block partials pcol[b][2][KP] (b <

@@ -18,7 +18,7 @@ __global__ __launch_bounds__(BT) void update_w_kernel(UpdateWArgs a) {
   constexpr int RU = unit_rows<KB, SL, BT>();
   static_assert(RU == unit_rows<KB>(), "rows per unit must match the host plan");
   __shared__ double lds[2 * BT];
-  const double den1 = row_sum_den<KB>(a);
+  const double den1 = a.beta_one ? row_sum_den_wide<KB, BT>(a, lds) : 0.0;
   double nrm = 0.0, cs = 0.0;  // unused here: the H pass forms the column sums
   const int units = (a.F + RU - 1) / RU;
   for (int u = blockIdx.x; u < units; u += gridDim.x)
