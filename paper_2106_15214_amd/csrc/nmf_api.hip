@@ -380,7 +380,7 @@ StepArgs make_step_args(const Plan& p, char* ws, unsigned* flags, int64_t F, int
   ua.beta = beta; ua.gamma = gamma_of(beta); ua.joint = joint; ua.beta_one = beta_one;
   ua.Wn = Wn; ua.C1 = C1; ua.C2 = C2; ua.pcol = (double*)(ws + p.o_pcol);
   ua.WT = (float*)(ws + p.o_wt); ua.ldt = p.ldt;
-  ua.C0 = (prec != NMF_FP32 && joint) ? (float*)(ws + p.o_c0) : nullptr;
+  ua.C0 = (prec != NMF_FP32 && joint && !p.pq) ? (float*)(ws + p.o_c0) : nullptr;
   ua.flags = flags;
 
   SweepColsArgs& ca = sa.ca;
@@ -546,7 +546,7 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
     if (cs == hipStreamCaptureStatusNone) fused_grid = fused_capacity(c, bc, kblocks_for(K), joint, want_obj);
   }
   if (c->path == NMF_PATH_FUSED && fused_grid <= 0) return NMF_ERR_UNSUPPORTED;
-  const bool use_pq = joint && prec == NMF_FP32 && fused_grid == 0 && F * N <= kPQMaxEntries;
+  const bool use_pq = joint && fused_grid == 0 && F * N <= kPQMaxEntries;
   const Plan p =
       make_plan(c, F, N, K, sweep_cols_occupancy(bc, kblocks_for(K), KIND_UPDATE, joint), fused_grid, use_pq);
   if ((st = ensure_ws(c, s, p.total)) != NMF_OK) return st;
@@ -589,14 +589,14 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   }
   hipError_t e = timed(c, NMF_KERNEL_SWEEP_W, s, [&] {
     return prec == NMF_FP32 ? launch_sweep_rows(bc, p.KB, KIND_UPDATE, want_obj, p.pq, sw_grid, s, ra)
-                            : launch_sweep_rows_lp(prec, bc, p.KB, want_obj, sw_grid, s, ra);
+                            : launch_sweep_rows_lp(prec, bc, p.KB, want_obj, p.pq, sw_grid, s, ra);
   });
   if (e != hipSuccess) return NMF_ERR_HIP;
   e = timed(c, NMF_KERNEL_UPDATE_W, s, [&] { return launch_update_w(p.KB, p.uw_blocks, s, ua); });
   if (e != hipSuccess) return NMF_ERR_HIP;
   e = timed(c, NMF_KERNEL_SWEEP_H, s, [&] {
     return prec == NMF_FP32 ? launch_sweep_cols(bc, p.KB, KIND_UPDATE, joint, p.pq, sh_grid, s, ca)
-                            : launch_sweep_cols_lp(prec, bc, p.KB, joint, sh_grid, s, ca);
+                            : launch_sweep_cols_lp(prec, bc, p.KB, joint, p.pq, sh_grid, s, ca);
   });
   if (e != hipSuccess) return NMF_ERR_HIP;
   e = timed(c, NMF_KERNEL_UPDATE_H, s, [&] { return launch_update_h(p.KB, p.uh_blocks, s, ha); });

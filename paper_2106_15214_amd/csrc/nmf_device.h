@@ -592,7 +592,7 @@ __device__ __forceinline__ void split_low(const float (&x)[8], typename LowP<T>:
 
 // rows item with low-precision products (update kind).  The H~ tile is staged
 // in LDS in float32 as in rows_item; operands are converted when read.
-template <int BC, int KB, bool OBJ, class T>
+template <int BC, int KB, bool OBJ, class T, bool STORE_PQ = false>
 __device__ __forceinline__ void rows_item_lp(const SweepRowsArgs& a, int item, float* lds, double& objsum) {
   typedef typename LowP<T>::v8 v8;
   constexpr int KP = 32 * KB;
@@ -741,6 +741,18 @@ __device__ __forceinline__ void rows_item_lp(const SweepRowsArgs& a, int item, f
         if (OBJ) {
           const double d = d_beta<BC>((double)vk, (double)lk, a.beta);
           objsum += ok ? d : 0.0;
+        }
+      }
+      if (STORE_PQ) {
+        // P, Q in the product type, tile-major [n][f] as the float32 path keeps them
+        T* const Pl = reinterpret_cast<T*>(a.Pst);
+        T* const Ql = reinterpret_cast<T*>(a.Qst);
+        const int64_t tb = ((int64_t)(f0 >> 5) * a.NT + t) * (kTile * kTile);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int64_t o = tb + acc_row(r, hi) * kTile + li;
+          if (BC != BC_B2) Pl[o] = (T)P[r];
+          if (NEED_DEN) Ql[o] = (T)Q[r];
         }
       }
 #pragma unroll
@@ -1045,6 +1057,167 @@ __device__ __forceinline__ void cols_prologue(const SweepColsArgs& a, int item, 
   const int f1 = min(gf1, f0 + a.col_chunk);
   column_partials<KB>(a.Wn, f0, f1, a.pcol + (int64_t)(g * a.col_parts + cb) * 2 * 32 * KB,
                       reinterpret_cast<double*>(lds));
+}
+
+// cols item of the joint H pass with low-precision products contracting the
+// P, Q tiles the W pass kept in the product type (no Lambda~, no powers): lane
+// (li, hi) reads, for column n0w + li, the eight rows acc_row(8 st + e, hi) of
+// step st as two 4-entry runs.  At beta = 2, P = V + kappa is read from V.
+template <int BC, int KB, class T>
+__device__ __forceinline__ void cols_item_lp_pq(const SweepColsArgs& a, int item, float* lds) {
+  typedef typename LowP<T>::v8 v8;
+  constexpr int KP = 32 * KB;
+  constexpr int CS = KP + 4;
+  constexpr bool NEED_DEN = (BC != BC_B1);
+  constexpr int NT_ = NEED_DEN ? 2 : 1;  // staged tiles per buffer: chi_1[, chi_2]
+  float* const base0 = lds;
+  float* const base1 = lds + NT_ * kTile * CS;
+  typedef T t4 __attribute__((ext_vector_type(4)));
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, hi = lane >> 5;
+  const int cb = item / a.f_groups, g = item % a.f_groups;
+  const int n0w = cb * kBlockRows + wave * kTile;
+  const int ncol = n0w + li;
+  const bool ncol_ok = ncol < a.N;
+  const bool wave_on = n0w < a.N;
+  const int F = a.F;
+  bool rok = true;
+
+  f32x16 accN[KB], accD[KB];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) { accN[kb][r] = 0.f; accD[kb][r] = 0.f; }
+  }
+  float4 treg[NT_][KB];
+  const float* src[2] = {a.C1, a.C2};
+  auto load_tiles = [&](int f0) {
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int e4 = tid + kBlock * j;
+      const int i = e4 / (KP / 4), c = 4 * (e4 % (KP / 4));
+      const bool ok = f0 + i < F;
+      const int64_t o = (int64_t)(f0 + i) * KP + c;
+#pragma unroll
+      for (int m = 0; m < NT_; ++m) treg[m][j] = ldc4(src[m], o, ok);
+    }
+  };
+  auto store_tiles = [&](float* base) {
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int e4 = tid + kBlock * j;
+      const int i = e4 / (KP / 4), c = 4 * (e4 % (KP / 4));
+#pragma unroll
+      for (int m = 0; m < NT_; ++m) *reinterpret_cast<float4*>(&base[m * kTile * CS + i * CS + c]) = treg[m][j];
+    }
+  };
+  // kept tiles: 4-entry runs of P, Q in the product type, or V at beta = 2 for P
+  struct Kept {
+    t4 p[4], q[4];
+    float v[16];
+  };
+  auto load_kept = [&](int f0, Kept& x) {
+    const int64_t tb = ((int64_t)(f0 >> 5) * a.NT + (n0w >> 5)) * (kTile * kTile) + li * kTile;
+    const T* Pl = reinterpret_cast<const T*>(a.Pst);
+    const T* Ql = reinterpret_cast<const T*>(a.Qst);
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int64_t o = tb + 16 * st + 8 * h + 4 * hi;
+        if (BC != BC_B2) x.p[2 * st + h] = *reinterpret_cast<const t4*>(Pl + o);
+        if (NEED_DEN) x.q[2 * st + h] = *reinterpret_cast<const t4*>(Ql + o);
+      }
+    }
+    if (BC == BC_B2) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int f = f0 + acc_row(r, hi);
+        x.v[r] = ldc(a.V, (int64_t)f * a.ldv + ncol, ncol_ok && f < F);
+      }
+    }
+  };
+
+  const int ft_total = (F + kTile - 1) / kTile;
+  const int t0 = g * a.tiles_per_group;
+  const int t1 = min(ft_total, t0 + a.tiles_per_group);
+  Kept cur, nxt;
+  __syncthreads();
+  if (t0 < t1) {
+    load_tiles(t0 * kTile);
+    if (wave_on) load_kept(t0 * kTile, cur);
+    store_tiles(base0);
+  }
+  __syncthreads();
+
+  for (int t = t0; t < t1; ++t) {
+    const float* base = ((t - t0) & 1) ? base1 : base0;
+    const bool more = t + 1 < t1;
+    if (more) {
+      load_tiles((t + 1) * kTile);
+      if (wave_on) load_kept((t + 1) * kTile, nxt);
+    }
+    if (wave_on) {
+      const int f0 = t * kTile;
+      const float* c1s = base;
+      const float* c2s = NEED_DEN ? base + kTile * CS : base;
+#pragma unroll
+      for (int st = 0; st < 2; ++st) {
+        v8 pv, qv;
+        if (BC == BC_B2) {
+          float pa[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int r = 8 * st + e;
+            const bool ok = ncol_ok && f0 + acc_row(r, hi) < F;
+            pa[e] = ok ? cur.v[r] + a.kappa : 0.f;
+          }
+          range_check<T>(pa, rok);
+          pv = to_low<T>(pa);
+        } else {
+          pv = __builtin_shufflevector(cur.p[2 * st], cur.p[2 * st + 1], 0, 1, 2, 3, 4, 5, 6, 7);
+        }
+        if (NEED_DEN) qv = __builtin_shufflevector(cur.q[2 * st], cur.q[2 * st + 1], 0, 1, 2, 3, 4, 5, 6, 7);
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+          float b1[8], b2[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int row = acc_row(8 * st + e, hi) * CS + kb * 32 + li;
+            b1[e] = c1s[row];
+            b2[e] = c2s[row];
+          }
+          range_check<T>(b1, rok);
+          if (NEED_DEN) range_check<T>(b2, rok);
+          accN[kb] = LowP<T>::mfma(pv, to_low<T>(b1), accN[kb]);
+          if (NEED_DEN) accD[kb] = LowP<T>::mfma(qv, to_low<T>(b2), accD[kb]);
+        }
+      }
+    }
+    if (more) {
+      store_tiles(((t - t0 + 1) & 1) ? base1 : base0);
+      cur = nxt;
+    }
+    __syncthreads();
+  }
+
+  if (wave_on) {
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int n = n0w + acc_row(r, hi);
+        if (n < a.N) {
+          const int64_t o = ((int64_t)g * a.N + n) * KP + kb * 32 + li;
+          a.pnum[o] = accN[kb][r];
+          if (NEED_DEN) a.pden[o] = accD[kb][r];
+        }
+      }
+    }
+  }
+  if (!rok) set_flag(a.flags, 8u);  // operand outside the float16 range
 }
 
 // LDS bytes a cols item needs.

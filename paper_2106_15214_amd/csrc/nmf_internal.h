@@ -115,8 +115,10 @@ hipError_t launch_sweep_rows(int bc, int kb, int kind, bool obj, bool pq, int gr
 hipError_t launch_sweep_cols(int bc, int kb, int kind, bool dual, bool pq, int grid, hipStream_t s,
                              const SweepColsArgs& a);
 // low-precision products (prec 1 = bfloat16, 2 = float16; update kind, K <= 64)
-hipError_t launch_sweep_rows_lp(int prec, int bc, int kb, bool obj, int grid, hipStream_t s, const SweepRowsArgs& a);
-hipError_t launch_sweep_cols_lp(int prec, int bc, int kb, bool dual, int grid, hipStream_t s, const SweepColsArgs& a);
+hipError_t launch_sweep_rows_lp(int prec, int bc, int kb, bool obj, bool pq, int grid, hipStream_t s,
+                                const SweepRowsArgs& a);
+hipError_t launch_sweep_cols_lp(int prec, int bc, int kb, bool dual, bool pq, int grid, hipStream_t s,
+                                const SweepColsArgs& a);
 hipError_t launch_update_w(int kb, int grid, hipStream_t s, const UpdateWArgs& a);
 hipError_t launch_update_h(int kb, int grid, hipStream_t s, const UpdateHArgs& a);
 hipError_t launch_finalize_objective(hipStream_t s, const double* pobj, int n, double* out, unsigned* flags);
