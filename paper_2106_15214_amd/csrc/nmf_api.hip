@@ -805,7 +805,7 @@ nmf_status nmf_batch_create(nmf_ctx_t c, const nmf_problem* pr, int32_t count, i
   off = align_up(off + sizeof(BatchProblem) * (size_t)count);
   int64_t total = 0;
   for (int i = 0; i < count; ++i) {
-    plans[i] = make_batch_plan(pr[i].F, pr[i].N, pr[i].K, tiles, joint && o.precision == NMF_FP32);
+    plans[i] = make_batch_plan(pr[i].F, pr[i].N, pr[i].K, tiles, joint);
     const Plan& p = plans[i];
     total += (int64_t)p.row_blocks * p.n_groups + cdiv(cdiv(pr[i].F, batch_unit_rows(p.KB)), batch_w_units(p.KB)) +
              (int64_t)p.col_blocks * p.f_groups + cdiv(p.uh_blocks, batch_h_units(p.KB));

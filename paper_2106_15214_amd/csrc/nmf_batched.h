@@ -2,7 +2,7 @@
 // one persistent launch.  Workgroups take work items from a queue listed
 // phase-major over all problems:
 //   W-pass items  (rows items: Lambda~ tiles, P, Q, W-step partials, objective;
-//                  in joint mode with float32 products P and Q are kept)
+//                  in joint mode P and Q are kept for the H pass)
 //   W-update units (partials reduced, W_new, chi terms)
 //   H-pass items  (cols items: H-step partials from the kept P, Q in joint mode,
 //                  column sums of W_new)
@@ -47,8 +47,8 @@ __device__ __forceinline__ void batch_item(ConstProblemPtr P, int prob, int phas
     const SweepRowsArgs ra = load_const(&P->ra);
     double objsum = 0.0;
     if constexpr (PREC == 0) rows_item<BC, KB, KIND_UPDATE, OBJ, JOINT>(ra, item, lds, objsum);
-    else if constexpr (PREC == 1) rows_item_lp<BC, KB, OBJ, __bf16>(ra, item, lds, objsum);
-    else rows_item_lp<BC, KB, OBJ, _Float16>(ra, item, lds, objsum);
+    else if constexpr (PREC == 1) rows_item_lp<BC, KB, OBJ, __bf16, JOINT>(ra, item, lds, objsum);
+    else rows_item_lp<BC, KB, OBJ, _Float16, JOINT>(ra, item, lds, objsum);
     if (OBJ) {
       const double sum = block_sum(objsum, red);
       if (threadIdx.x == 0) ra.pobj[item] = sum;
@@ -64,8 +64,13 @@ __device__ __forceinline__ void batch_item(ConstProblemPtr P, int prob, int phas
     const SweepColsArgs ca = load_const(&P->ca);
     cols_prologue<KB>(ca, item, lds);
     if constexpr (PREC == 0) cols_item<BC, KB, KIND_UPDATE, JOINT, JOINT>(ca, item, lds);
-    else if constexpr (PREC == 1) cols_item_lp<BC, KB, JOINT, __bf16>(ca, item, lds);
-    else cols_item_lp<BC, KB, JOINT, _Float16>(ca, item, lds);
+    else if constexpr (PREC == 1) {
+      if constexpr (JOINT) cols_item_lp_pq<BC, KB, __bf16>(ca, item, lds);
+      else cols_item_lp<BC, KB, false, __bf16>(ca, item, lds);
+    } else {
+      if constexpr (JOINT) cols_item_lp_pq<BC, KB, _Float16>(ca, item, lds);
+      else cols_item_lp<BC, KB, false, _Float16>(ca, item, lds);
+    }
   } else {
     const UpdateHArgs ha = load_const(&P->ha);
     reduce_columns<KB>(ha.pcol, ha.pcol_blocks, reinterpret_cast<double*>(lds), norm_s, csum_s);
