@@ -83,23 +83,28 @@ def source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, precision: str, kernel: str):
+def measured_traffic(workload: str, precision: str, kernel: str, beta=None):
     """Calibrated HBM bytes per launch of `kernel` in the joint step, from the
     committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of this workload, or None
-    when there is none or the kernels changed since it was taken."""
+    when there is none, it was taken at another beta (another kernel
+    instantiation), or the kernels changed since it was taken."""
     name = f"kernels_{workload}" + ("" if precision == "fp32" else f"_precision_{precision}") + ".txt"
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
-    digest, value = None, None
+    digest, value, pbeta = None, None, None
     with open(path) as f:
         for line in f:
             parts = line.split()
             if len(parts) == 2 and parts[0] == "source_sha256":
                 digest = parts[1]
+            elif len(parts) == 2 and parts[0] == "beta":
+                pbeta = float(parts[1])
             elif len(parts) == 3 and parts[0] == "traffic_joint" and parts[1] == kernel:
                 value = float(parts[2])
     if digest != source_digest():
+        return None
+    if beta is not None and pbeta != float(beta):
         return None
     return value
 
@@ -211,7 +216,7 @@ def main(argv=None):
     else:
         roof = {"bound": "hbm", "achieved": vbytes / t_dom / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(args.workload, args.precision, dom)
+    roof["traffic"] = measured_traffic(args.workload, args.precision, dom, beta)
     roof["kernel"] = dom
     roof["algorithmic_flops_per_launch"] = flops
     roof["algorithmic_bytes_per_launch"] = vbytes
