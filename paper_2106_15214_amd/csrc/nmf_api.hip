@@ -148,6 +148,10 @@ constexpr int64_t kFusedMaxEntries = int64_t(1) << 24;
 // workspace between the passes (two float arrays of F N entries): the H pass
 // then contracts them instead of forming Lambda~ and its powers a second time.
 constexpr int64_t kPQMaxEntries = int64_t(1) << 28;
+// V (bytes) above which the W pass loads it with the nontemporal hint: a V this
+// large does not stay in the 256 MB last-level cache between passes anyway.
+constexpr int64_t kStreamVBytes = int64_t(128) << 20;
+inline int stream_v(int64_t F, int64_t N) { return F * N * (int64_t)sizeof(float) > kStreamVBytes; }
 
 int fused_capacity(nmf_ctx_s* c, int bc, int kb, bool joint, bool obj) {
   int& slot = c->fused_grid[kb - 1][bc][joint][obj];
@@ -371,6 +375,7 @@ StepArgs make_step_args(const Plan& p, char* ws, unsigned* flags, int64_t F, int
   ra.pobj = (double*)(ws + p.o_pobj);
   ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
   ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
+  ra.vstream = stream_v(F, N);
   ra.flags = flags;
   sa.sw_grid = p.row_blocks * p.n_groups;
 
@@ -622,6 +627,7 @@ nmf_status nmf_beta_objective(nmf_ctx_t c, void* stream, int64_t F, int64_t N, i
   ra.pobj = (double*)(c->ws + p.o_pobj);
   ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
   ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
+  ra.vstream = stream_v(F, N);
   const int grid = p.row_blocks * p.n_groups;
   hipError_t e = launch_sweep_rows(beta_class(beta), p.KB, KIND_OBJ, true, false, grid, s, ra);
   if (e != hipSuccess) return NMF_ERR_HIP;
@@ -659,6 +665,7 @@ nmf_status nmf_beta_grad(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   ra.pnum = (float*)(ws + p.o_pnum); ra.pobj = (double*)(ws + p.o_pobj);
   ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
   ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
+  ra.vstream = stream_v(F, N);
   const int sw_grid = p.row_blocks * p.n_groups;
   hipError_t e = launch_sweep_rows(bc, p.KB, KIND_GRAD, d_objective != nullptr, false, sw_grid, s, ra);
   if (e != hipSuccess) return NMF_ERR_HIP;
@@ -833,7 +840,8 @@ nmf_status nmf_batch_create(nmf_ctx_t c, const nmf_problem* pr, int32_t count, i
   char* mem = b->mem;
   unsigned* flags = (unsigned*)mem;
 
-  // descriptors
+  // descriptors (V is loaded with the nontemporal hint by the size rule of each
+  // problem: the hint measured no gain on a batch of cache-sized problems)
   std::vector<BatchProblem> desc(count);
   for (int i = 0; i < count; ++i) {
     const nmf_problem& q = pr[i];
