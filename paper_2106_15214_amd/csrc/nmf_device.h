@@ -226,12 +226,20 @@ constexpr int kHS = 36;  // LDS row stride of [k][32] tiles: float4 and dword re
 
 // LDS bytes a rows item needs (two H~ tiles).
 // ---------------------------------------------------------------------------
-// KL objective terms with many zero data entries.  d_1(0 | l) = l needs no
-// logarithm; the entries with v > 0 are queued per wavefront in LDS (ballot +
-// prefix count) and their float64 terms evaluated 64 at a time, so the
-// logarithms cost one round per 64 nonzero entries instead of one per register.
+// KL objective of a 32 x 32 tile in the accumulator layout.  With z the sum of
+// Lambda over the tile, d_1 summed over the tile is
+//   z + sum over the entries with v > 0 of (v log(v / Lambda) - v),
+// so entries with v = 0 need no float64 work.  z is summed per lane in float32
+// as a pairwise tree of its 16 terms (error at most 4 ulp) and added to the
+// float64 total once per tile.  The entries with v > 0 are appended to the
+// wave's LDS queue (ballot + prefix count; lanes without an entry write a spare
+// slot of their own, so no lane is masked off), and their float64 terms are
+// evaluated 64 at a time once a round is full: the logarithms cost one round
+// per 64 nonzero entries.  After a tile with at least half of its entries
+// nonzero the next tile evaluates its terms in place instead (dense data).
 // ---------------------------------------------------------------------------
-constexpr int kKlQueue = 128;  // entries per wavefront (< 64 carried + 64 added)
+constexpr int kKlQueue = 64 + 8 * 64;    // carried entries + eight accumulator registers
+constexpr int kKlSlots = kKlQueue + 64;  // + one spare slot per lane
 
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -239,57 +247,94 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ double kl_term(double v, double l) { return v * log64(div64(v, l)) - v + l; }
+// v log(v / l) - v for v > 0 (the Lambda term is summed separately)
+__device__ __forceinline__ double kl_nz(double v, double l) { return v * log64(div64(v, l)) - v; }
 
 struct KlQueue {
-  float* qv;  // [kKlQueue] data values
-  float* ql;  // [kKlQueue] Lambda values
-  int qn;     // queued entries (uniform over the wavefront)
+  float* qv;          // [kKlSlots] data values
+  float* ql;          // [kKlSlots] Lambda values
+  int qn;             // queued entries (uniform over the wavefront), < 64 between tiles
+  bool dense;         // evaluate the next tile's terms in place
 
-  // queues (ok, v > 0) entries, adds the zero entries' terms to sum; returns the
-  // number of entries with v > 0 in the wavefront
-  __device__ __forceinline__ int push(bool ok, float v, float l, double& sum) {
+  // full rounds of 64 queued terms; the remainder moves to the front
+  __device__ __forceinline__ void rounds(double& sum) {
     const int lane = threadIdx.x & 63;
-    const bool nz = ok && v > 0.f;
-    sum += (ok && !nz) ? (double)l : 0.0;
-    const unsigned long long m = __ballot(nz);
-    const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    if (nz) {
-      const int pos = qn + __popcll(m & below);
-      qv[pos] = v;
-      ql[pos] = l;
+    wave_lds_sync();
+    const int full = qn >> 6, rest = qn & 63;
+    for (int j = 0; j < full; ++j) sum += kl_nz((double)qv[64 * j + lane], (double)ql[64 * j + lane]);
+    float rv = 0.f, rl = 0.f;
+    if (lane < rest) {
+      rv = qv[64 * full + lane];
+      rl = ql[64 * full + lane];
     }
-    const int cnt = __popcll(m);
-    qn += cnt;
-    if (qn >= 64) {
-      wave_lds_sync();
-      sum += kl_term((double)qv[lane], (double)ql[lane]);
-      const int rest = qn - 64;
-      float rv = 0.f, rl = 0.f;
-      if (lane < rest) {
-        rv = qv[64 + lane];
-        rl = ql[64 + lane];
-      }
-      wave_lds_sync();
-      if (lane < rest) {
-        qv[lane] = rv;
-        ql[lane] = rl;
-      }
-      qn = rest;
+    wave_lds_sync();
+    if (lane < rest) {
+      qv[lane] = rv;
+      ql[lane] = rl;
     }
-    return cnt;
+    qn = rest;
   }
+
+  // v, l: data and Lambda (kappa included) at the 16 accumulator positions;
+  // ok: the entry lies inside F x N
+  __device__ __forceinline__ void tile(const bool (&ok)[16], const float (&v)[16], const float (&l)[16],
+                                       double& sum) {
+    const int lane = threadIdx.x & 63;
+    float z[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) z[r] = ok[r] ? l[r] : 0.f;
+#pragma unroll
+    for (int w = 8; w >= 1; w >>= 1)
+#pragma unroll
+      for (int r = 0; r < w; ++r) z[r] += z[r + w];
+    sum += (double)z[0];
+    int nnz = 0;
+    if (dense) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const bool nz = ok[r] && v[r] > 0.f;
+        nnz += __popcll(__ballot(nz));
+        const double t = kl_nz((double)v[r], (double)l[r]);
+        sum += nz ? t : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int r = 8 * h; r < 8 * h + 8; ++r) {
+          const bool nz = ok[r] && v[r] > 0.f;
+          const unsigned long long m = __ballot(nz);
+          const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+          const int pos = nz ? qn + below : kKlQueue + lane;
+          qv[pos] = v[r];
+          ql[pos] = l[r];
+          const int c = __popcll(m);
+          qn += c;
+          nnz += c;
+        }
+        if (qn >= 64) rounds(sum);
+      }
+    }
+    dense = nnz >= kTile * kTile / 2;
+  }
+
   __device__ __forceinline__ void drain(double& sum) {
     const int lane = threadIdx.x & 63;
     wave_lds_sync();
-    if (lane < qn) sum += kl_term((double)qv[lane], (double)ql[lane]);
+    if (lane < qn) sum += kl_nz((double)qv[lane], (double)ql[lane]);
     qn = 0;
     wave_lds_sync();
   }
 };
 
+// LDS of a rows item: two staged H~ tiles, then each wave's KL queue
 template <int KB>
-constexpr int rows_item_lds() { return 2 * 32 * KB * kHS * 4 + kWaves * 2 * kKlQueue * 4; }
+constexpr int rows_item_lds() { return 2 * 32 * KB * kHS * 4 + kWaves * 2 * kKlSlots * 4; }
+template <int KB>
+__device__ __forceinline__ KlQueue kl_queue_of(float* lds, int wave) {
+  float* const q = lds + 2 * 32 * KB * kHS + wave * 2 * kKlSlots;
+  return KlQueue{q, q + kKlSlots, 0, true};
+}
 
 // ---------------------------------------------------------------------------
 // rows item: W-step contractions (reduction over n) for 128 rows of V over the
@@ -318,8 +363,7 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
   const bool wave_on = f0 < a.F;
   const int K = a.K, N = a.N;
   const int K2 = (K + 1) >> 1;
-  KlQueue klq{lds + 2 * KP * kHS + wave * 2 * kKlQueue, lds + 2 * KP * kHS + wave * 2 * kKlQueue + kKlQueue, 0};
-  bool klq_dense = true;
+  KlQueue klq = kl_queue_of<KB>(lds, wave);
 
   // B operand of Lambda^T = H~^T W~^T: lane holds W~[frow][2s + hi]
   // (all loads issued before any is masked, so they are in flight together)
@@ -460,26 +504,15 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
         }
       }
       if (OBJ && BC == BC_B1) {
-        // KL: after a mostly-zero tile the next one goes through the queue,
-        // after a dense tile (and for the first tile of an item) term by term
-        int nnz = 0;
-        if (klq_dense) {
+        bool okr[16];
+        float vk[16], lk[16];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const bool ok = frow_ok && n0 + acc_row(r, hi) < N;
-            const float vk = vcur[r] + a.kappa;
-            nnz += __popcll(__ballot(ok && vk > 0.f));
-            const double d = d_beta<BC>((double)vk, (double)(lam[r] + a.kappa), a.beta);
-            objsum += ok ? d : 0.0;
-          }
-        } else {
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const bool ok = frow_ok && n0 + acc_row(r, hi) < N;
-            nnz += klq.push(ok, vcur[r] + a.kappa, lam[r] + a.kappa, objsum);
-          }
+        for (int r = 0; r < 16; ++r) {
+          okr[r] = frow_ok && n0 + acc_row(r, hi) < N;
+          vk[r] = vcur[r] + a.kappa;
+          lk[r] = lam[r] + a.kappa;
         }
-        klq_dense = nnz >= kTile * kTile / 2;
+        klq.tile(okr, vk, lk, objsum);
       }
       if (STORE_PQ) {
         // tile (slab of this wave, column tile t) as [n][f]: coalesced 32-float rows
@@ -630,6 +663,7 @@ __device__ __forceinline__ void rows_item_lp(const SweepRowsArgs& a, int item, f
   const bool frow_ok = frow < a.F;
   const bool wave_on = f0 < a.F;
   const int K = a.K, N = a.N;
+  KlQueue klq = kl_queue_of<KB>(lds, wave);
 
   bool rok = true;
   // B operand of Lambda^T: lane holds W~[frow][16s + 8hi + e], split in two
@@ -760,10 +794,21 @@ __device__ __forceinline__ void rows_item_lp(const SweepRowsArgs& a, int item, f
         const float vk = vcur[r] + a.kappa;
         beta_terms<BC>(vk, lk, a.bm2, P[r], Q[r]);
         if (!ok) { P[r] = 0.f; Q[r] = 0.f; }
-        if (OBJ) {
+        if (OBJ && BC != BC_B1) {
           const double d = d_beta<BC>((double)vk, (double)lk, a.beta);
           objsum += ok ? d : 0.0;
         }
+      }
+      if (OBJ && BC == BC_B1) {
+        bool okr[16];
+        float vk[16], lk[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          okr[r] = frow_ok && n0 + acc_row(r, hi) < N;
+          vk[r] = vcur[r] + a.kappa;
+          lk[r] = lam[r] + a.kappa;
+        }
+        klq.tile(okr, vk, lk, objsum);
       }
       if (STORE_PQ) {
         // P, Q in the product type, tile-major [n][f] as the float32 path keeps them
@@ -808,6 +853,7 @@ __device__ __forceinline__ void rows_item_lp(const SweepRowsArgs& a, int item, f
     __syncthreads();
   }
 
+  if (OBJ && BC == BC_B1 && wave_on) klq.drain(objsum);
   if (wave_on) {
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
