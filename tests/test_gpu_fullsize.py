@@ -4,6 +4,10 @@
   the whole matrix, every entry of W and H compared.  This is the size at which
   the W pass streams V with the nontemporal hint (V is 800 MB), the launch
   configuration the benchmark times.
+* A joint step just above 2^28 entries of V (16449 x 16353, ragged edges,
+  beta = 0.5): beyond that size the joint step does not keep the P and Q tiles,
+  and its H pass forms Lambda~ and its powers again from V, W~, H~.  Float32
+  and bfloat16 products, every entry of W and H compared.
 * The 512-problem batched workload at full size, in one persistent launch:
   sampled problems (the largest, the smallest and evenly spaced ones) compared
   with the oracle problem by problem; every problem's objective must be finite.
@@ -114,3 +118,36 @@ def test_batched_workload_full_size_sampled(tiles):
         eH = rel(d[i][2].cpu().numpy(), Hr)
         assert eW <= 1e-5 and eH <= 1e-5, (i, V.shape, W.shape[1], beta, eW, eH)
         assert abs(ob[i] - d0) <= 1e-6 * abs(d0), (i, ob[i], d0)
+
+
+@pytest.fixture(scope="module")
+def above_pq_limit():
+    F, N, K = 16449, 16353, 10
+    assert F * N > 2 ** 28
+    return synth.random_positive(F, N, K, seed=2028)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_joint_step_above_kept_pq_limit(above_pq_limit, precision):
+    p = above_pq_limit
+    beta = 0.5
+    F, N = p.V.shape
+    print(f"[fullsize] above the kept P/Q limit F={F} N={N} K={p.W.shape[1]} beta={beta} precision={precision}",
+          flush=True)
+    Vd, Wd, Hd = dev(p.V), dev(p.W), dev(p.H)
+    o = torch.full((1,), float("nan"), dtype=torch.float64, device=DEV)
+    nb.step(Vd, Wd, Hd, beta, "joint", precision=precision, objective_out=o, ctx=ctx())
+    torch.cuda.synchronize()
+    assert nb.get_flags(clear=True, ctx=ctx()) == 0
+    Wg, Hg, dg = Wd.cpu().numpy(), Hd.cpu().numpy(), o.item()
+    del Vd, Wd, Hd
+    V64, W64, H64 = p.V.astype(np.float64), p.W.astype(np.float64), p.H.astype(np.float64)
+    d0 = O.objective(V64, W64, H64, beta)
+    Wr, Hr = O.jmm_iteration(V64, W64, H64, beta)
+    eW, eH = rel(Wg, Wr), rel(Hg, Hr)
+    tol = 1e-5 if precision == "fp32" else 3e-3
+    assert eW <= tol, f"W rel err {eW:.3e}"
+    assert eH <= tol, f"H rel err {eH:.3e}"
+    otol = 1e-6 * abs(d0) if precision == "fp32" else max(1e-6 * abs(d0), lowp_obj_bound(V64, W64, H64, beta))
+    assert abs(dg - d0) <= otol, f"objective err {abs(dg - d0):.3e} > {otol:.3e}"
