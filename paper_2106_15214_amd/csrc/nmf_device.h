@@ -1553,7 +1553,6 @@ __device__ __forceinline__ void update_w_unit(const UpdateWArgs& a, int unit, bo
   const int64_t gstride = (int64_t)a.F * KP;
   const int64_t base = (int64_t)f * KP + k;
   const float wtf = ldz(a.W, (int64_t)f * a.ldw + k, fok && k < a.K);  // issued with the partial loads
-  float sn = 0.f, sd = 0.f;
   double dn = 0.0, dd = 0.0;
   int g = gs;
   for (; g + (U - 1) * GS < a.n_groups; g += U * GS) {
@@ -1579,7 +1578,6 @@ __device__ __forceinline__ void update_w_unit(const UpdateWArgs& a, int unit, bo
       if (g + u * GS < a.n_groups) { dn += (double)xn[u]; dd += (double)xd[u]; }
     }
   }
-  (void)sn; (void)sd;
   double* red = reinterpret_cast<double*>(lds);  // [2][GS][RU*KP]
   __syncthreads();  // red may still be read by the previous unit
   red[tid] = dn;
