@@ -1,9 +1,9 @@
 """GPU parity at the benchmark workloads' full sizes, against the FP64 oracle.
 
 * The 20000 x 10000 (K = 50, beta = 1) count workload: one outer iteration on
-  the whole matrix, every entry of W and H compared.  This is the size at which
-  the W pass streams V with the nontemporal hint (V is 800 MB), the launch
-  configuration the benchmark times.
+  the whole matrix, every entry of W and H compared, and the objective and
+  gradient calls.  This is the size at which the W pass streams V with the
+  nontemporal hint (V is 800 MB), the launch configuration the benchmark times.
 * A joint step just above 2^28 entries of V (16449 x 16353, ragged edges,
   beta = 0.5): beyond that size the joint step does not keep the P and Q tiles,
   and its H pass forms Lambda~ and its powers again from V, W~, H~.  Float32
@@ -84,6 +84,30 @@ def test_count_workload_full_size(counts, mode, precision):
         assert eH <= 3e-3, f"H rel err {eH:.3e}"
         tol = max(1e-6 * abs(d0), lowp_obj_bound(V64, W64, H64, p.beta))
         assert abs(dg - d0) <= tol, f"objective err {abs(dg - d0):.3e} > {tol:.3e}"
+
+
+@pytest.mark.timeout(600)
+def test_count_workload_full_size_objective_and_gradient(counts):
+    # the objective-only and gradient passes at the size where V is streamed
+    p = counts
+    print(f"[fullsize] counts_kl objective and gradient F={p.V.shape[0]} N={p.V.shape[1]}", flush=True)
+    Vd, Wd, Hd = dev(p.V), dev(p.W), dev(p.H)
+    d = nb.objective(Vd, Wd, Hd, p.beta, ctx=ctx()).item()
+    dW, dH = nb.grad(Vd, Wd, Hd, p.beta, scale=1.0, ctx=ctx())
+    torch.cuda.synchronize()
+    assert nb.get_flags(clear=True, ctx=ctx()) == 0
+    dW, dH = dW.cpu().numpy(), dH.cpu().numpy()
+    del Vd, Wd, Hd
+    V64, W64, H64 = p.V.astype(np.float64), p.W.astype(np.float64), p.H.astype(np.float64)
+    d0 = O.objective(V64, W64, H64, p.beta)
+    assert abs(d - d0) <= 1e-6 * abs(d0), (d, d0)
+    gW, gH = O.gradient(V64, W64, H64, p.beta)
+    # condition-scaled gates (E = Lambda^(beta-2) (Lambda - V) changes sign), as for the small shapes
+    L = W64 @ H64
+    E = np.abs(L ** (p.beta - 2) * (L - V64))
+    sW, sH = np.linalg.norm(E @ np.abs(H64.T)), np.linalg.norm(np.abs(W64.T) @ E)
+    assert np.linalg.norm(dW - gW) <= 1e-5 * sW
+    assert np.linalg.norm(dH - gH) <= 1e-5 * sH
 
 
 @pytest.mark.timeout(600)
