@@ -15,7 +15,9 @@ with the beta-divergence" (Marmin, Goulart, Fevotte).
 Contents, each following the passage cited in its docstring:
 
 * ``beta_divergence`` / ``objective``   -- Sec. 2.1, eqs. (obj_fct) and (beta-div)
-* ``gamma_exponent``                    -- Sec. 2.2, eq. (def_gamma)
+* ``gamma_exponent``                    -- Sec. 2.2, eq. (def_gamma); ``exponent="one"`` in the
+                                           two iterations replaces it by 1 (the heuristic of
+                                           Sec. 3.3.3, "Failure of heuristic updates")
 * ``chi1`` / ``chi2``                   -- Sec. 3.2, definitions under eq. (jnt_update)
 * ``bmm_iteration``                     -- Sec. 2.2, eq. (alt_update) and Algorithm 1 (BMM)
 * ``jmm_iteration``                     -- Sec. 3.2, eq. (jnt_update) and Algorithm 2 (JMM)
@@ -164,19 +166,31 @@ def normalize(W, H):
     return W, H
 
 
+def _exponent(beta: float, exponent: str) -> float:
+    """gamma(beta) (``"mm"``), or 1 for every beta (``"one"``: the heuristic that
+    sets gamma(beta) to 1 in the update even outside [1, 2], discussed for both
+    methods in Sec. 3.3.3, "Failure of heuristic updates")."""
+    if exponent == "mm":
+        return gamma_exponent(beta)
+    if exponent == "one":
+        return 1.0
+    raise ValueError(exponent)
+
+
 def bmm_iteration(V, W, H, beta: float, L_W: int = 1, L_H: int = 1, kappa: float = 0.0,
-                  norm: bool = True, return_parts: bool = False):
+                  norm: bool = True, return_parts: bool = False, exponent: str = "mm"):
     """One outer iteration of block MM (Algorithm 1, Sec. 2.2), eq. (alt_update).
 
     L_W multiplicative updates of W against the current H (each recomputes WH),
     then L_H updates of H against the new W.  Optional column normalization at
     the end (Sec. 4.1.2).  With ``return_parts`` the numerators/denominators of
-    the last W and H sub-iteration are returned as well.
+    the last W and H sub-iteration are returned as well.  ``exponent``: see
+    ``_exponent``.
     """
     V = _f64(V) + kappa
     W = _f64(W).copy()
     H = _f64(H).copy()
-    g = gamma_exponent(beta)
+    g = _exponent(beta, exponent)
     for _ in range(L_W):
         Lam = W @ H + kappa
         numW = (_pow(Lam, beta - 2.0) * V) @ H.T
@@ -194,17 +208,18 @@ def bmm_iteration(V, W, H, beta: float, L_W: int = 1, L_H: int = 1, kappa: float
 
 
 def jmm_iteration(V, Wt, Ht, beta: float, L: int = 1, kappa: float = 0.0, norm: bool = True,
-                  return_parts: bool = False):
+                  return_parts: bool = False, exponent: str = "mm"):
     """One outer iteration of joint MM (Algorithm 2, Sec. 3.2), eq. (jnt_update).
 
     V~ = W~ H~ (+ kappa) is formed once.  The L sub-iterations update W and then
     H, always multiplying the *tilde* iterates, with chi_1/chi_2 evaluated at the
     latest sub-iterate and the tilde iterate.  Optional normalization at the end.
+    ``exponent``: see ``_exponent``.
     """
     V = _f64(V) + kappa
     Wt = _f64(Wt)
     Ht = _f64(Ht)
-    g = gamma_exponent(beta)
+    g = _exponent(beta, exponent)
     Vt = Wt @ Ht + kappa
     P = V / _pow(Vt, 2.0 - beta)          # V / V~^(2-beta)
     Q = _pow(Vt, beta - 1.0)              # V~^(beta-1)

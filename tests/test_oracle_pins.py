@@ -408,3 +408,54 @@ def test_jmm_L_greater_than_one_keeps_tilde_base():
     c1 = Ht ** (2 - beta) / H1 ** (1 - beta)
     Wexp = Wt * ((P @ c1.T) / (Q @ H1.T)) ** g
     assert np.allclose(W2, Wexp, rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# the heuristic exponent gamma = 1 (Sec. 3.3.3, "Failure of heuristic updates")
+# ---------------------------------------------------------------------------
+def test_heuristic_exponent_at_beta_zero_is_the_textbook_is_update():
+    # block MM with gamma = 1 at beta = 0: the classical Itakura-Saito
+    # multiplicative rules W <- W (V/L^2 H^T) / (1/L H^T), then H likewise against
+    # the new W, written out here in plain matrix form
+    V, W, H = _small(31, 8, 11, 3)
+    L = W @ H
+    W1 = W * (((V / L**2) @ H.T) / ((1.0 / L) @ H.T))
+    L = W1 @ H
+    H1 = H * ((W1.T @ (V / L**2)) / (W1.T @ (1.0 / L)))
+    Wo, Ho = O.bmm_iteration(V, W, H, 0.0, norm=False, exponent="one")
+    assert np.allclose(Wo, W1, rtol=1e-13, atol=0) and np.allclose(Ho, H1, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("beta", [1.0, 1.2, 1.5, 2.0])
+@pytest.mark.parametrize("mode", ["bmm", "jmm"])
+def test_heuristic_exponent_changes_nothing_where_gamma_is_one(beta, mode):
+    # gamma(beta) = 1 on [1, 2] (eq. def_gamma), so both exponents give the same step
+    V, W, H = _small(32, 7, 9, 3)
+    f = O.bmm_iteration if mode == "bmm" else O.jmm_iteration
+    Wa, Ha = f(V, W, H, beta)
+    Wb, Hb = f(V, W, H, beta, exponent="one")
+    assert np.array_equal(Wa, Wb) and np.array_equal(Ha, Hb)
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.5])
+def test_heuristic_exponent_decreases_block_mm_objective_on_zero_one(beta):
+    # for beta in [0, 1] the gamma = 1 block update is a majorization-equalization
+    # scheme, which the paper cites as proven to decrease the objective
+    V, W, H = _small(33, 12, 15, 4)
+    D = [O.objective(V, W, H, beta)]
+    for _ in range(100):
+        W, H = O.bmm_iteration(V, W, H, beta, exponent="one")
+        D.append(O.objective(V, W, H, beta))
+    D = np.array(D)
+    assert np.all(np.diff(D) <= 1e-13 * D[:-1])
+
+
+@pytest.mark.parametrize("beta", [-0.5, 0.0, 0.5, 2.5])
+def test_heuristic_exponent_w_steps_coincide_at_L1(beta):
+    # at L = 1 the joint W step multiplies the same P H~^T / Q H~^T as block MM
+    V, W, H = _small(34, 7, 9, 3)
+    Wb, _ = O.bmm_iteration(V, W, H, beta, norm=False, exponent="one")
+    Wj, _ = O.jmm_iteration(V, W, H, beta, norm=False, exponent="one")
+    assert np.allclose(Wb, Wj, rtol=1e-14, atol=0)
+    Wm, _ = O.bmm_iteration(V, W, H, beta, norm=False)
+    assert not np.allclose(Wm, Wb, rtol=1e-6, atol=0)  # the exponent matters outside [1, 2]
