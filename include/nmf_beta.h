@@ -75,12 +75,22 @@ typedef enum {
                                  outside the float16 range or not finite (the step's
                                  result is then not meaningful) */
 
+/* exponent of the multiplicative updates (nmf_step_opts.exponent) */
+#define NMF_EXPONENT_MM 0  /* gamma(beta) of eq. (def_gamma): the MM step, whose
+                              objective never increases */
+#define NMF_EXPONENT_ONE 1 /* 1 for every beta: the heuristic discussed for both
+                              methods in Sec. 3.3.3 ("Failure of heuristic
+                              updates"); outside 1 <= beta <= 2 it is not an MM
+                              step, and the objective may increase */
+
 typedef struct {
   int32_t precision;   /* nmf_precision; default NMF_FP32 */
   float kappa;         /* smoothing constant of Sec. 4.1.3, >= 0; default 0 */
   int32_t inner_iters; /* sub-iterations L of Algorithms 1/2; only 1 is supported */
   int32_t normalize;   /* 1: divide W's columns by their l2 norm and scale H's rows
                           (Sec. 4.1.2) at the end of the step; default 1 */
+  int32_t exponent;    /* NMF_EXPONENT_MM (default) or NMF_EXPONENT_ONE; other
+                          values: NMF_ERR_ARG */
 } nmf_step_opts;
 
 /* Fills *opts with the defaults listed above. */
@@ -118,7 +128,8 @@ nmf_status nmf_check_step_args(int64_t F, int64_t N, int64_t K, const float* V, 
  * mode == NMF_JOINT (paper Sec. 3.2, eq. (jnt_update), Algorithm 2 with L = 1):
  *   V~ = W~H~ is formed once; W and H are both updated from the tilde iterate,
  *   the H step using chi_1(W, W~) and chi_2(W, W~) in its contractions.
- * gamma = gamma(beta) of eq. (def_gamma).  With opts->normalize the columns of W
+ * gamma = gamma(beta) of eq. (def_gamma), or 1 with opts->exponent ==
+ * NMF_EXPONENT_ONE.  With opts->normalize the columns of W
  * are scaled to unit l2 norm and the rows of H by the inverse (Sec. 4.1.2).
  * At L = 1 the W step of both modes is the same computation (Sec. 4.1.1).
  *

@@ -23,7 +23,7 @@ from typing import Optional, Tuple
 
 __all__ = [
     "NmfError", "lib", "library_path", "Context", "default_context",
-    "ALTERNATING", "JOINT", "FP32", "BF16", "FP16",
+    "ALTERNATING", "JOINT", "FP32", "BF16", "FP16", "EXPONENTS",
     "FLAG_NONFINITE", "FLAG_DOMAIN", "FLAG_BARRIER", "FLAG_RANGE", "KERNELS",
     "step", "objective", "grad", "validate", "get_flags", "check_step_args", "Batch", "batch_tune",
     "BetaDivergence", "beta_divergence",
@@ -38,6 +38,8 @@ FLAG_BARRIER = 4
 FLAG_RANGE = 8  # float16 mode: an operand outside the float16 range
 MODES = {"alternating": ALTERNATING, "bmm": ALTERNATING, "joint": JOINT, "jmm": JOINT}
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16}
+# update exponent: gamma(beta) (the MM step) or 1 (the heuristic of Sec. 3.3.3)
+EXPONENTS = {"mm": 0, "one": 1}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libnmfbeta.so")
@@ -54,7 +56,8 @@ class NmfError(RuntimeError):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("kappa", ctypes.c_float),
-                ("inner_iters", ctypes.c_int32), ("normalize", ctypes.c_int32)]
+                ("inner_iters", ctypes.c_int32), ("normalize", ctypes.c_int32),
+                ("exponent", ctypes.c_int32)]
 
 
 class _Problem(ctypes.Structure):
@@ -141,13 +144,14 @@ def _check(st: int, where: str):
         raise NmfError(st, where)
 
 
-def _opts(precision=FP32, kappa=0.0, inner_iters=1, normalize=True) -> _Opts:
+def _opts(precision=FP32, kappa=0.0, inner_iters=1, normalize=True, exponent="mm") -> _Opts:
     o = _Opts()
     lib().nmf_default_opts(ctypes.byref(o))
     o.precision = PRECISIONS.get(precision, precision) if isinstance(precision, str) else int(precision)
     o.kappa = float(kappa)
     o.inner_iters = int(inner_iters)
     o.normalize = 1 if normalize else 0
+    o.exponent = EXPONENTS.get(exponent, exponent) if isinstance(exponent, str) else int(exponent)
     return o
 
 
@@ -245,9 +249,10 @@ def check_step_args(F, N, K, V=0x10000000, ldv=None, W=0x50000000, ldw=None, H=0
 
 
 def step(V, W, H, beta: float, mode="joint", *, precision="fp32", kappa: float = 0.0, normalize: bool = True,
-         objective_out=None, stream=None, ctx: Optional[Context] = None):
+         exponent="mm", objective_out=None, stream=None, ctx: Optional[Context] = None):
     """One outer iteration in place on W and H (see nmf_beta_step).
 
+    ``exponent``: "mm" (gamma(beta)) or "one" (gamma = 1 for every beta).
     ``objective_out``: optional float64 device tensor (1 element) receiving the
     objective at the entry iterate.
     """
@@ -259,7 +264,7 @@ def step(V, W, H, beta: float, mode="joint", *, precision="fp32", kappa: float =
     K = W.shape[1]
     if W.shape[0] != F or H.shape != (K, N):
         raise ValueError("shape mismatch: V (F,N), W (F,K), H (K,N)")
-    o = _opts(precision, kappa, 1, normalize)
+    o = _opts(precision, kappa, 1, normalize, exponent)
     pobj = None
     if objective_out is not None:
         pobj = objective_out.data_ptr()
@@ -389,11 +394,11 @@ class Batch:
     (V, W, H, beta) device tensors; W and H are updated in place by step()."""
 
     def __init__(self, problems, mode="joint", *, precision="fp32", kappa: float = 0.0, normalize: bool = True,
-                 tiles_per_item: int = 0, workers: int = 0, ctx: Optional[Context] = None):
+                 exponent="mm", tiles_per_item: int = 0, workers: int = 0, ctx: Optional[Context] = None):
         self._tensors = list(problems)  # keep the caller's tensors alive
         self.count = len(problems)
         arr = _problems(problems)
-        o = _opts(precision, kappa, 1, normalize)
+        o = _opts(precision, kappa, 1, normalize, exponent)
         cfg = _BatchConfig(int(tiles_per_item), int(workers))
         h = _vp()
         _check(lib().nmf_batch_create(_ctx(ctx), arr, self.count, MODES[mode], ctypes.byref(o), ctypes.byref(cfg),

@@ -285,6 +285,7 @@ nmf_status check_opts(const nmf_step_opts* o) {
   if (!is_fin(o->kappa) || o->kappa < 0.f) return NMF_ERR_BETA;
   if (o->inner_iters != 1) return NMF_ERR_UNSUPPORTED;
   if (o->normalize != 0 && o->normalize != 1) return NMF_ERR_ARG;
+  if (o->exponent != NMF_EXPONENT_MM && o->exponent != NMF_EXPONENT_ONE) return NMF_ERR_ARG;
   return NMF_OK;
 }
 
@@ -382,7 +383,8 @@ StepArgs make_step_args(const Plan& p, char* ws, unsigned* flags, int64_t F, int
   UpdateWArgs& ua = sa.ua;
   ua.W = W; ua.ldw = ldw; ua.pnum = ra.pnum; ua.pden = ra.pden; ua.prs = ra.prs;
   ua.F = (int)F; ua.K = (int)K; ua.n_groups = p.n_groups;
-  ua.beta = beta; ua.gamma = gamma_of(beta); ua.joint = joint; ua.beta_one = beta_one;
+  const double gamma = o.exponent == NMF_EXPONENT_ONE ? 1.0 : gamma_of(beta);
+  ua.beta = beta; ua.gamma = gamma; ua.joint = joint; ua.beta_one = beta_one;
   ua.Wn = Wn; ua.C1 = C1; ua.C2 = C2; ua.pcol = (double*)(ws + p.o_pcol);
   ua.WT = (float*)(ws + p.o_wt); ua.ldt = p.ldt;
   ua.C0 = (prec != NMF_FP32 && joint && !p.pq) ? (float*)(ws + p.o_c0) : nullptr;
@@ -405,7 +407,7 @@ StepArgs make_step_args(const Plan& p, char* ws, unsigned* flags, int64_t F, int
   UpdateHArgs& ha = sa.ha;
   ha.H = H; ha.ldh = ldh; ha.pnum = ca.pnum; ha.pden = ca.pden;
   ha.F = (int)F; ha.N = (int)N; ha.K = (int)K; ha.f_groups = p.f_groups;
-  ha.gamma = gamma_of(beta); ha.beta_one = beta_one; ha.normalize = o.normalize;
+  ha.gamma = gamma; ha.beta_one = beta_one; ha.normalize = o.normalize;
   ha.pcol = ua.pcol; ha.pcol_blocks = p.fused ? p.uw_blocks : p.f_groups * p.col_parts;
   if (!p.fused) { ca.Wn = Wn; ca.pcol = ua.pcol; ca.col_parts = p.col_parts; ca.col_chunk = p.col_chunk; }
   ha.pobj = ra.pobj; ha.nobj = sa.sw_grid; ha.d_obj = d_objective;
@@ -458,6 +460,7 @@ void nmf_default_opts(nmf_step_opts* o) {
   o->kappa = 0.f;
   o->inner_iters = 1;
   o->normalize = 1;
+  o->exponent = NMF_EXPONENT_MM;
 }
 
 const char* nmf_version(void) { return "nmfbeta 0.1 (gfx950)"; }

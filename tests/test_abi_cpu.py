@@ -57,6 +57,9 @@ def test_step_argument_checks():
     assert c(100, 200, 10, kappa=-1.0) == E_BETA
     assert c(100, 200, 10, inner_iters=2) == E_UNSUP
     assert c(100, 200, 10, precision=7) == E_UNSUP
+    assert c(100, 200, 10, exponent="one") == OK
+    assert c(100, 200, 10, exponent=2) == E_ARG
+    assert c(100, 200, 10, exponent=-1) == E_ARG
 
 
 def test_alias_detection():

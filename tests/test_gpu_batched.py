@@ -175,6 +175,22 @@ def test_batched_workload_sample_matches_single_steps():
     b.close()
 
 
+@pytest.mark.parametrize("mode", ["joint", "alternating"])
+def test_batched_heuristic_exponent_matches_oracle(mode):
+    probs = make_set(WELL_POSED, seed0=1300)
+    d = to_dev(probs)
+    b = nb.Batch(d, mode, exponent="one", ctx=ctx())
+    b.step()
+    torch.cuda.synchronize()
+    assert b.flags() == 0
+    b.close()
+    f = O.jmm_iteration if mode == "joint" else O.bmm_iteration
+    for i, ((V, W, H, beta), (_, Wd, Hd, _)) in enumerate(zip(probs, d)):
+        Wr, Hr = f(V.astype(np.float64), W.astype(np.float64), H.astype(np.float64), beta, exponent="one")
+        assert rel(Wd.cpu().numpy(), Wr) <= 1e-5, i
+        assert rel(Hd.cpu().numpy(), Hr) <= 1e-5, i
+
+
 def test_batched_rejects_aliasing_and_large_k():
     a, b = to_dev(make_set([(64, 100, 5, 1.0), (64, 100, 5, 0.5)], seed0=900))
     # the second problem updates the first one's W

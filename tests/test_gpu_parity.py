@@ -124,6 +124,28 @@ def test_trajectory_per_step_parity_tiny_kl(mode):
     assert np.all(trace[1:] <= trace[:-1] * (1 + 2 * eps)), np.max(np.diff(trace) / trace[:-1])
 
 
+@pytest.mark.parametrize("beta", [-0.5, 0.0, 0.5, 1.0, 2.5])
+@pytest.mark.parametrize("mode", ["joint", "alternating"])
+@pytest.mark.parametrize("path", ["stream", "fused"])
+def test_heuristic_exponent_parity(beta, mode, path):
+    # gamma = 1 for every beta (Sec. 3.3.3): the same passes with another exponent
+    p = synth.random_positive(257, 300, 20, seed=41, zeros=0.1 if beta > 0 else 0.0)
+    print(f"[parity] heuristic exponent beta={beta} mode={mode} path={path}", flush=True)
+    Vd, Wd, Hd = dev(p.V), dev(p.W), dev(p.H)
+    o = torch.full((1,), float("nan"), dtype=torch.float64, device=DEV)
+    ctx = ctx_for(path)
+    nb.step(Vd, Wd, Hd, beta, mode, exponent="one", objective_out=o, ctx=ctx)
+    torch.cuda.synchronize()
+    assert nb.get_flags(clear=True, ctx=ctx) == 0
+    f = O.jmm_iteration if mode == "joint" else O.bmm_iteration
+    V64, W64, H64 = (a.astype(np.float64) for a in (p.V, p.W, p.H))
+    Wr, Hr = f(V64, W64, H64, beta, exponent="one")
+    assert rel(Wd.cpu().numpy(), Wr) <= TOL_FACTOR
+    assert rel(Hd.cpu().numpy(), Hr) <= TOL_FACTOR
+    d0 = ref_obj(p.V, p.W, p.H, beta)
+    assert abs(o.item() - d0) <= TOL_OBJ * abs(d0)
+
+
 @pytest.mark.parametrize("beta", [0.0, 1.0, 2.0, 0.5])
 @pytest.mark.parametrize("path", ["stream", "fused"])
 def test_w_step_bitwise_equal_between_modes(beta, path):
