@@ -249,10 +249,11 @@ def check_step_args(F, N, K, V=0x10000000, ldv=None, W=0x50000000, ldw=None, H=0
 
 
 def step(V, W, H, beta: float, mode="joint", *, precision="fp32", kappa: float = 0.0, normalize: bool = True,
-         exponent="mm", objective_out=None, stream=None, ctx: Optional[Context] = None):
+         exponent="mm", inner_iters: int = 1, objective_out=None, stream=None, ctx: Optional[Context] = None):
     """One outer iteration in place on W and H (see nmf_beta_step).
 
     ``exponent``: "mm" (gamma(beta)) or "one" (gamma = 1 for every beta).
+    ``inner_iters``: sub-iterations L (L > 1: alternating mode, float32).
     ``objective_out``: optional float64 device tensor (1 element) receiving the
     objective at the entry iterate.
     """
@@ -264,7 +265,7 @@ def step(V, W, H, beta: float, mode="joint", *, precision="fp32", kappa: float =
     K = W.shape[1]
     if W.shape[0] != F or H.shape != (K, N):
         raise ValueError("shape mismatch: V (F,N), W (F,K), H (K,N)")
-    o = _opts(precision, kappa, 1, normalize, exponent)
+    o = _opts(precision, kappa, inner_iters, normalize, exponent)
     pobj = None
     if objective_out is not None:
         pobj = objective_out.data_ptr()

@@ -148,6 +148,8 @@ constexpr int64_t kFusedMaxEntries = int64_t(1) << 24;
 // workspace between the passes (two float arrays of F N entries): the H pass
 // then contracts them instead of forming Lambda~ and its powers a second time.
 constexpr int64_t kPQMaxEntries = int64_t(1) << 28;
+// Largest number of sub-iterations L accepted in one step.
+constexpr int kMaxInnerIters = 1000;
 // V (bytes) above which the W pass loads it with the nontemporal hint: a V this
 // large does not stay in the 256 MB last-level cache between passes anyway.
 constexpr int64_t kStreamVBytes = int64_t(128) << 20;
@@ -283,7 +285,7 @@ nmf_status check_opts(const nmf_step_opts* o) {
   if (!o) return NMF_OK;
   if (o->precision != NMF_FP32 && o->precision != NMF_BF16 && o->precision != NMF_FP16) return NMF_ERR_UNSUPPORTED;
   if (!is_fin(o->kappa) || o->kappa < 0.f) return NMF_ERR_BETA;
-  if (o->inner_iters != 1) return NMF_ERR_UNSUPPORTED;
+  if (o->inner_iters < 1 || o->inner_iters > kMaxInnerIters) return NMF_ERR_ARG;
   if (o->normalize != 0 && o->normalize != 1) return NMF_ERR_ARG;
   if (o->exponent != NMF_EXPONENT_MM && o->exponent != NMF_EXPONENT_ONE) return NMF_ERR_ARG;
   return NMF_OK;
@@ -450,6 +452,44 @@ inline int batch_w_units(int KB) { return std::max(1, kBatchUpdateRows / batch_u
 inline int batch_h_units(int KB) { return std::max(1, kBatchUpdateCols / (kBlock / (32 * KB))); }
 constexpr unsigned kBatchSpinLimit = 1u << 22;
 
+// Alternating MU with L > 1 sub-iterations (Algorithm 1, float32 products): L W
+// updates, each forming WH from the latest W (the first from the caller's W,
+// the later ones from W_new in the workspace, which the update rewrites in
+// place), then L H updates against the final W_new, each forming W_new H from
+// the latest H.  Only the first W pass forms the objective of the entry
+// iterate; only the last H update normalizes, writes W and the objective.
+nmf_status inner_steps(nmf_ctx_s* c, hipStream_t s, const Plan& p, const StepArgs& sa, int bc, bool want_obj,
+                              int L) {
+  for (int l = 0; l < L; ++l) {
+    SweepRowsArgs ra = sa.ra;
+    UpdateWArgs ua = sa.ua;
+    if (l > 0) {
+      ra.W = sa.ua.Wn; ra.ldw = p.KP;
+      ua.W = sa.ua.Wn; ua.ldw = p.KP;
+    }
+    hipError_t e = timed(c, NMF_KERNEL_SWEEP_W, s, [&] {
+      return launch_sweep_rows(bc, p.KB, KIND_UPDATE, want_obj && l == 0, false, sa.sw_grid, s, ra);
+    });
+    if (e != hipSuccess) return NMF_ERR_HIP;
+    e = timed(c, NMF_KERNEL_UPDATE_W, s, [&] { return launch_update_w(p.KB, p.uw_blocks, s, ua); });
+    if (e != hipSuccess) return NMF_ERR_HIP;
+  }
+  for (int l = 0; l < L; ++l) {
+    UpdateHArgs ha = sa.ha;
+    if (l + 1 < L) {
+      ha.normalize = 0;
+      ha.d_obj = nullptr;
+    }
+    hipError_t e = timed(c, NMF_KERNEL_SWEEP_H, s, [&] {
+      return launch_sweep_cols(bc, p.KB, KIND_UPDATE, false, false, sa.sh_grid, s, sa.ca);
+    });
+    if (e != hipSuccess) return NMF_ERR_HIP;
+    e = timed(c, NMF_KERNEL_UPDATE_H, s, [&] { return launch_update_h(p.KB, p.uh_blocks, s, ha); });
+    if (e != hipSuccess) return NMF_ERR_HIP;
+  }
+  return NMF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -527,6 +567,9 @@ nmf_status nmf_check_step_args(int64_t F, int64_t N, int64_t K, const float* V, 
   st = check_opts(opts);
   if (st != NMF_OK) return st;
   if (opts && opts->precision != NMF_FP32 && K > 64) return NMF_ERR_UNSUPPORTED;
+  // L > 1 sub-iterations: alternating MU with float32 products only
+  if (opts && opts->inner_iters > 1 && (mode != NMF_ALTERNATING || opts->precision != NMF_FP32))
+    return NMF_ERR_UNSUPPORTED;
   return NMF_OK;
 }
 
@@ -547,8 +590,9 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
   // path: one cooperative launch for problems whose P, Q tiles stay cache
   // resident (not under stream capture), else four streaming launches
+  const int L = o.inner_iters;
   int fused_grid = 0;
-  if (c->path == NMF_PATH_FUSED && prec == NMF_FP32 && kblocks_for(K) <= 2 && F * N <= kFusedMaxEntries) {
+  if (c->path == NMF_PATH_FUSED && L == 1 && prec == NMF_FP32 && kblocks_for(K) <= 2 && F * N <= kFusedMaxEntries) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess) return NMF_ERR_HIP;
     if (cs == hipStreamCaptureStatusNone) fused_grid = fused_capacity(c, bc, kblocks_for(K), joint, want_obj);
@@ -595,6 +639,7 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
     ra.Qst = (float*)(ws + p.o_qst);
     ca.NT = ra.NT; ca.Pst = ra.Pst; ca.Qst = ra.Qst;
   }
+  if (L > 1) return inner_steps(c, s, p, sa, bc, want_obj, L);
   hipError_t e = timed(c, NMF_KERNEL_SWEEP_W, s, [&] {
     return prec == NMF_FP32 ? launch_sweep_rows(bc, p.KB, KIND_UPDATE, want_obj, p.pq, sw_grid, s, ra)
                             : launch_sweep_rows_lp(prec, bc, p.KB, want_obj, p.pq, sw_grid, s, ra);
@@ -790,6 +835,7 @@ nmf_status nmf_batch_create(nmf_ctx_t c, const nmf_problem* pr, int32_t count, i
   nmf_default_opts(&o);
   if (opts) o = *opts;
   if (o.precision != NMF_FP32 && o.precision != NMF_BF16) return NMF_ERR_UNSUPPORTED;
+  if (o.inner_iters != 1) return NMF_ERR_UNSUPPORTED;
   const int tiles = cfg && cfg->tiles_per_item > 0 ? cfg->tiles_per_item : kBatchTilesDefault;
   if (cfg && cfg->workers < 0) return NMF_ERR_ARG;
   for (int i = 0; i < count; ++i) {

@@ -55,7 +55,11 @@ def test_step_argument_checks():
     assert c(100, 200, 10, beta=float("inf")) == E_BETA
     assert c(100, 200, 10, mode=2) == E_ARG
     assert c(100, 200, 10, kappa=-1.0) == E_BETA
-    assert c(100, 200, 10, inner_iters=2) == E_UNSUP
+    assert c(100, 200, 10, inner_iters=2) == E_UNSUP  # joint mode: L = 1 only
+    assert c(100, 200, 10, inner_iters=2, mode=0) == OK
+    assert c(100, 200, 10, inner_iters=3, mode=0, precision=1) == E_UNSUP
+    assert c(100, 200, 10, inner_iters=0, mode=0) == E_ARG
+    assert c(100, 200, 10, inner_iters=1001, mode=0) == E_ARG
     assert c(100, 200, 10, precision=7) == E_UNSUP
     assert c(100, 200, 10, exponent="one") == OK
     assert c(100, 200, 10, exponent=2) == E_ARG

@@ -124,6 +124,36 @@ def test_trajectory_per_step_parity_tiny_kl(mode):
     assert np.all(trace[1:] <= trace[:-1] * (1 + 2 * eps)), np.max(np.diff(trace) / trace[:-1])
 
 
+@pytest.mark.parametrize("L", [2, 3])
+@pytest.mark.parametrize("beta", [0.0, 0.5, 1.0, 2.0, 2.5])
+@pytest.mark.parametrize("normalize", [True, False])
+def test_alternating_sub_iterations_parity(L, beta, normalize):
+    # Algorithm 1 with L_W = L_H = L: L W updates against the latest W, then L H updates
+    p = synth.random_positive(257, 300, 20, seed=43, zeros=0.1 if beta > 0 else 0.0)
+    print(f"[parity] alternating L={L} beta={beta} normalize={normalize}", flush=True)
+    Vd, Wd, Hd = dev(p.V), dev(p.W), dev(p.H)
+    o = torch.full((1,), float("nan"), dtype=torch.float64, device=DEV)
+    ctx = ctx_for("auto")
+    nb.step(Vd, Wd, Hd, beta, "alternating", inner_iters=L, normalize=normalize, objective_out=o, ctx=ctx)
+    torch.cuda.synchronize()
+    assert nb.get_flags(clear=True, ctx=ctx) == 0
+    V64, W64, H64 = (a.astype(np.float64) for a in (p.V, p.W, p.H))
+    Wr, Hr = O.bmm_iteration(V64, W64, H64, beta, L_W=L, L_H=L, norm=normalize)
+    assert rel(Wd.cpu().numpy(), Wr) <= TOL_FACTOR
+    assert rel(Hd.cpu().numpy(), Hr) <= TOL_FACTOR
+    d0 = ref_obj(p.V, p.W, p.H, beta)
+    assert abs(o.item() - d0) <= TOL_OBJ * abs(d0)
+
+
+def test_sub_iterations_rejected_where_unsupported():
+    p = synth.random_positive(64, 80, 6, seed=44)
+    for kw in (dict(mode="joint"), dict(mode="alternating", precision="bf16")):
+        with pytest.raises(nb.NmfError):
+            nb.step(dev(p.V), dev(p.W), dev(p.H), 1.0, inner_iters=2, ctx=ctx_for("auto"), **kw)
+    with pytest.raises(nb.NmfError):
+        nb.step(dev(p.V), dev(p.W), dev(p.H), 1.0, "alternating", inner_iters=2, ctx=ctx_for("fused"))
+
+
 @pytest.mark.parametrize("beta", [-0.5, 0.0, 0.5, 1.0, 2.5])
 @pytest.mark.parametrize("mode", ["joint", "alternating"])
 @pytest.mark.parametrize("path", ["stream", "fused"])
