@@ -86,11 +86,14 @@ typedef enum {
 typedef struct {
   int32_t precision;   /* nmf_precision; default NMF_FP32 */
   float kappa;         /* smoothing constant of Sec. 4.1.3, >= 0; default 0 */
-  int32_t inner_iters; /* sub-iterations L of Algorithm 1 (1 <= L <= 1000; else
-                          NMF_ERR_ARG): L W updates, each against the latest W,
-                          then L H updates against the final W.  L > 1 only for
-                          NMF_ALTERNATING with NMF_FP32 and not in batches
-                          (NMF_ERR_UNSUPPORTED otherwise); default 1 */
+  int32_t inner_iters; /* sub-iterations L (1 <= L <= 1000; else NMF_ERR_ARG).
+                          NMF_ALTERNATING (Algorithm 1): L W updates, each against
+                          the latest W, then L H updates against the final W.
+                          NMF_JOINT (Algorithm 2): L alternations of a W and an H
+                          update, both always multiplying the tilde iterate, with
+                          V~, P, Q formed once (F N <= 2^28).  L > 1 only with
+                          NMF_FP32, not in batches and not on the single-launch
+                          path (NMF_ERR_UNSUPPORTED otherwise); default 1 */
   int32_t normalize;   /* 1: divide W's columns by their l2 norm and scale H's rows
                           (Sec. 4.1.2) at the end of the step; default 1 */
   int32_t exponent;    /* NMF_EXPONENT_MM (default) or NMF_EXPONENT_ONE; other

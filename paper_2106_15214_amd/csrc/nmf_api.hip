@@ -76,7 +76,8 @@ struct Plan {
   int fused_grid;
   // byte offsets inside the workspace
   size_t o_pobj, o_pnum, o_pden, o_prs, o_wn, o_c1, o_c2, o_c0, o_wt, o_pcol, o_pnumh, o_pdenh, o_colsum, o_pst,
-      o_qst, total;
+      o_qst, o_c1h, o_c2h, total;
+  int64_t ldc;                        // leading dimension of the chi(H) terms of joint sub-iterations
 };
 
 int kblocks_for(int64_t K) {
@@ -116,7 +117,7 @@ int choose_groups(const nmf_ctx_s* c, int64_t tiles, int64_t blocks, int64_t out
 
 // Region sizes (bytes) of the workspace; offsets are assigned in this order.
 struct Sizes {
-  size_t pobj, pnum, prs, fk, wt, pcol, pnumh, pq;
+  size_t pobj, pnum, prs, fk, wt, pcol, pnumh, pq, kn;
 };
 
 Plan layout(const Sizes& z, Plan p) {
@@ -137,6 +138,8 @@ Plan layout(const Sizes& z, Plan p) {
   p.o_colsum = take(sizeof(float) * 2 * 128);
   p.o_pst = take(z.pq);
   p.o_qst = take(z.pq);
+  p.o_c1h = take(z.kn);
+  p.o_c2h = take(z.kn);
   p.total = o;
   return p;
 }
@@ -165,7 +168,7 @@ int fused_capacity(nmf_ctx_s* c, int bc, int kb, bool joint, bool obj) {
 // plans the single-launch path with that many workgroups.
 // Column-partial split, transposed leading dimension and workspace offsets of
 // a plan whose splits are set.
-Plan finish_plan(Plan p, int64_t F, int64_t N) {
+Plan finish_plan(Plan p, int64_t F, int64_t N, bool inner = false) {
   {
     const int64_t rows = (int64_t)p.tiles_f * kTile;
     p.col_parts = (int)std::min<int64_t>(p.col_blocks, cdiv(rows, kColChunkRows));
@@ -181,11 +184,13 @@ Plan finish_plan(Plan p, int64_t F, int64_t N) {
   z.pcol = sizeof(double) * (size_t)(p.fused ? p.uw_blocks : (int64_t)p.f_groups * p.col_parts) * 2 * p.KP;
   z.pnumh = sizeof(float) * (size_t)p.f_groups * N * p.KP;
   z.pq = (p.fused || p.pq) ? sizeof(float) * (size_t)cdiv(F, kTile) * cdiv(N, kTile) * kTile * kTile : 0;
+  p.ldc = cdiv(N, 4) * 4;
+  z.kn = inner ? sizeof(float) * (size_t)p.KP * p.ldc : 0;
   return layout(z, p);
 }
 
 Plan make_plan(const nmf_ctx_s* c, int64_t F, int64_t N, int64_t K, int cols_occ = 2, int fused_grid = 0,
-               bool pq = false) {
+               bool pq = false, bool inner = false) {
   Plan p{};
   p.pq = pq && fused_grid == 0;
   p.KB = kblocks_for(K);
@@ -201,7 +206,7 @@ Plan make_plan(const nmf_ctx_s* c, int64_t F, int64_t N, int64_t K, int cols_occ
   p.f_groups = choose_groups(c, cdiv(F, kTile), p.col_blocks, N, p.KB, cols_slots, &p.tiles_f);
   p.uw_blocks = p.fused ? fused_grid : (int)std::min<int64_t>(kUpdateWBlocks, cdiv(F, update_w_unit_rows(p.KB)));
   p.uh_blocks = p.fused ? (int)cdiv(N, kTile) : (int)cdiv(N, kBlock / p.KP);
-  return finish_plan(p, F, N);
+  return finish_plan(p, F, N, inner);
 }
 
 // Splits of a problem inside a batch: every row (column) group covers about
@@ -254,6 +259,7 @@ size_t plan_bound(const nmf_ctx_s* c, int64_t maxF, int64_t maxN, int64_t maxK) 
   // (or the smaller single-launch limit), padded to whole 32 x 32 tiles
   const int64_t pq_cap = kPQMaxEntries + kTile * (maxF + maxN) + kTile * kTile;
   z.pq = sizeof(float) * (size_t)std::min<int64_t>(ft * nt * kTile * kTile, pq_cap);
+  z.kn = sizeof(float) * (size_t)(KP * (cdiv(maxN, 4) * 4));  // chi(H) terms of joint sub-iterations
   return layout(z, Plan{}).total;
 }
 
@@ -414,6 +420,7 @@ StepArgs make_step_args(const Plan& p, char* ws, unsigned* flags, int64_t F, int
   if (!p.fused) { ca.Wn = Wn; ca.pcol = ua.pcol; ca.col_parts = p.col_parts; ca.col_chunk = p.col_chunk; }
   ha.pobj = ra.pobj; ha.nobj = sa.sw_grid; ha.d_obj = d_objective;
   ha.Wn = Wn; ha.W = W; ha.ldw = ldw; ha.flags = flags;
+  ha.beta = beta;
   return sa;
 }
 
@@ -484,6 +491,47 @@ nmf_status inner_steps(nmf_ctx_s* c, hipStream_t s, const Plan& p, const StepArg
       return launch_sweep_cols(bc, p.KB, KIND_UPDATE, false, false, sa.sh_grid, s, sa.ca);
     });
     if (e != hipSuccess) return NMF_ERR_HIP;
+    e = timed(c, NMF_KERNEL_UPDATE_H, s, [&] { return launch_update_h(p.KB, p.uh_blocks, s, ha); });
+    if (e != hipSuccess) return NMF_ERR_HIP;
+  }
+  return NMF_OK;
+}
+
+// Joint MM with L > 1 sub-iterations (Algorithm 2, float32 products, P and Q
+// kept between the passes).  Sub-iteration l updates W from W~ with the
+// contractions P chi_1(H_l, H~)^T, Q chi_2(H_l, H~)^T -- the first W pass forms
+// V~, P, Q and contracts them with H_1 = H~; later ones contract the kept tiles
+// with the chi(H) terms -- then H from H~ with chi(W_{l+1}, W~).  The H updates
+// before the last write chi_1(H_{l+1}, H~), chi_2(H_{l+1}, H~) to the workspace
+// instead of H; the last writes H, normalizes, writes W and the objective.
+nmf_status inner_steps_joint(nmf_ctx_s* c, hipStream_t s, const Plan& p, const StepArgs& sa, int bc, bool want_obj,
+                             int L) {
+  float* const C1h = (float*)(c->ws + p.o_c1h);
+  float* const C2h = (float*)(c->ws + p.o_c2h);
+  for (int l = 0; l < L; ++l) {
+    hipError_t e;
+    if (l == 0) {
+      e = timed(c, NMF_KERNEL_SWEEP_W, s, [&] {
+        return launch_sweep_rows(bc, p.KB, KIND_UPDATE, want_obj, true, sa.sw_grid, s, sa.ra);
+      });
+    } else {
+      SweepRowsArgs rq = sa.ra;
+      rq.H = C1h; rq.ldh = p.ldc;
+      rq.W = C2h; rq.ldw = p.ldc;
+      e = timed(c, NMF_KERNEL_SWEEP_W, s, [&] { return launch_sweep_rows_pq(bc, p.KB, sa.sw_grid, s, rq); });
+    }
+    if (e != hipSuccess) return NMF_ERR_HIP;
+    e = timed(c, NMF_KERNEL_UPDATE_W, s, [&] { return launch_update_w(p.KB, p.uw_blocks, s, sa.ua); });
+    if (e != hipSuccess) return NMF_ERR_HIP;
+    e = timed(c, NMF_KERNEL_SWEEP_H, s, [&] {
+      return launch_sweep_cols(bc, p.KB, KIND_UPDATE, true, true, sa.sh_grid, s, sa.ca);
+    });
+    if (e != hipSuccess) return NMF_ERR_HIP;
+    UpdateHArgs ha = sa.ha;
+    if (l + 1 < L) {
+      ha.C1h = C1h; ha.C2h = C2h; ha.ldc = p.ldc;
+      ha.W = nullptr; ha.d_obj = nullptr; ha.normalize = 0;
+    }
     e = timed(c, NMF_KERNEL_UPDATE_H, s, [&] { return launch_update_h(p.KB, p.uh_blocks, s, ha); });
     if (e != hipSuccess) return NMF_ERR_HIP;
   }
@@ -567,8 +615,9 @@ nmf_status nmf_check_step_args(int64_t F, int64_t N, int64_t K, const float* V, 
   st = check_opts(opts);
   if (st != NMF_OK) return st;
   if (opts && opts->precision != NMF_FP32 && K > 64) return NMF_ERR_UNSUPPORTED;
-  // L > 1 sub-iterations: alternating MU with float32 products only
-  if (opts && opts->inner_iters > 1 && (mode != NMF_ALTERNATING || opts->precision != NMF_FP32))
+  // L > 1 sub-iterations: float32 products; joint MM keeps P, Q between the passes
+  if (opts && opts->inner_iters > 1 &&
+      (opts->precision != NMF_FP32 || (mode == NMF_JOINT && F * N > kPQMaxEntries)))
     return NMF_ERR_UNSUPPORTED;
   return NMF_OK;
 }
@@ -599,8 +648,8 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   }
   if (c->path == NMF_PATH_FUSED && fused_grid <= 0) return NMF_ERR_UNSUPPORTED;
   const bool use_pq = joint && fused_grid == 0 && F * N <= kPQMaxEntries;
-  const Plan p =
-      make_plan(c, F, N, K, sweep_cols_occupancy(bc, kblocks_for(K), KIND_UPDATE, joint), fused_grid, use_pq);
+  const Plan p = make_plan(c, F, N, K, sweep_cols_occupancy(bc, kblocks_for(K), KIND_UPDATE, joint), fused_grid,
+                           use_pq, joint && L > 1);
   if ((st = ensure_ws(c, s, p.total)) != NMF_OK) return st;
 
   StepArgs sa = make_step_args(p, c->ws, flags_ptr(c), F, N, K, V, ldv, W, ldw, H, ldh, beta, joint, prec, o,
@@ -639,7 +688,7 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
     ra.Qst = (float*)(ws + p.o_qst);
     ca.NT = ra.NT; ca.Pst = ra.Pst; ca.Qst = ra.Qst;
   }
-  if (L > 1) return inner_steps(c, s, p, sa, bc, want_obj, L);
+  if (L > 1) return joint ? inner_steps_joint(c, s, p, sa, bc, want_obj, L) : inner_steps(c, s, p, sa, bc, want_obj, L);
   hipError_t e = timed(c, NMF_KERNEL_SWEEP_W, s, [&] {
     return prec == NMF_FP32 ? launch_sweep_rows(bc, p.KB, KIND_UPDATE, want_obj, p.pq, sw_grid, s, ra)
                             : launch_sweep_rows_lp(prec, bc, p.KB, want_obj, p.pq, sw_grid, s, ra);

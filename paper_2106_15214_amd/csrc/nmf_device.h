@@ -587,6 +587,179 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
 }
 
 // ---------------------------------------------------------------------------
+// rows item of a later joint sub-iteration (Algorithm 2, l > 1): the W-step
+// contractions P chi_1(H_l, H~)^T and Q chi_2(H_l, H~)^T over the P, Q tiles kept
+// by the first W pass (P = V + kappa re-read at beta = 2; Q = 1 at beta = 1,
+// where the denominator is the row sums of chi_2).  No V~ is formed.  a.H holds
+// chi_1 (K x N, ld a.ldh) and a.Pst / a.Qst the kept tiles; a.W (ld a.ldw)
+// holds chi_2.  Partials as rows_item writes them.
+// ---------------------------------------------------------------------------
+template <int KB>
+constexpr int rows_pq_item_lds() { return 4 * 32 * KB * kHS * 4; }
+
+template <int BC, int KB>
+__device__ __forceinline__ void rows_pq_item(const SweepRowsArgs& a, int item, float* lds) {
+  constexpr int KP = 32 * KB;
+  constexpr bool NEED_DEN = (BC != BC_B1);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, hi = lane >> 5;
+  const int rb = item / a.n_groups, g = item % a.n_groups;
+  const int f0 = rb * kBlockRows + wave * kTile;
+  const int frow = f0 + li;
+  const bool frow_ok = frow < a.F;
+  const bool wave_on = f0 < a.F;
+  const int K = a.K, N = a.N;
+  const float* const X1 = a.H;  // chi_1, ld a.ldh
+  const float* const X2 = a.W;  // chi_2, ld a.ldw
+  // staged tiles: [buffer][chi_1, chi_2][KP][kHS]
+  auto stage = [&](int b, int m) { return lds + (2 * b + m) * KP * kHS; };
+
+  f32x16 accN[KB], accD[KB];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) { accN[kb][r] = 0.f; accD[kb][r] = 0.f; }
+  }
+  float rsum[KB];
+#pragma unroll
+  for (int j = 0; j < KB; ++j) rsum[j] = 0.f;
+
+  // thread float4 j of a [KP][32] tile covers row (tid + 256 j) / 8, columns
+  // 4 ((tid + 256 j) % 8) .. + 3; entries outside K x N are finite stand-ins
+  // (they meet P = Q = 0) or exact zeros in the row sums
+  auto load_x = [&](const float* X, int64_t ldx, int n0, float4 (&r)[KB]) {
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int e4 = tid + kBlock * j;
+      const int k = e4 >> 3, n = n0 + 4 * (e4 & 7);
+      const int64_t o = (int64_t)k * ldx + n;
+      r[j].x = ldc(X, o + 0, k < K && n + 0 < N);
+      r[j].y = ldc(X, o + 1, k < K && n + 1 < N);
+      r[j].z = ldc(X, o + 2, k < K && n + 2 < N);
+      r[j].w = ldc(X, o + 3, k < K && n + 3 < N);
+    }
+  };
+  auto masked_sum = [&](int n0, const float4& x, int j) {
+    const int e4 = tid + kBlock * j;
+    const int k = e4 >> 3, n = n0 + 4 * (e4 & 7);
+    if (k >= K) return 0.f;
+    return (n + 0 < N ? x.x : 0.f) + (n + 1 < N ? x.y : 0.f) + (n + 2 < N ? x.z : 0.f) + (n + 3 < N ? x.w : 0.f);
+  };
+  auto store_x = [&](float* buf, const float4 (&r)[KB]) {
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int e4 = tid + kBlock * j;
+      *reinterpret_cast<float4*>(&buf[(e4 >> 3) * kHS + 4 * (e4 & 7)]) = r[j];
+    }
+  };
+  // P, Q of tile (slab of this wave, column tile t) at the accumulator positions
+  auto load_pq = [&](int t, float (&P)[16], float (&Q)[16]) {
+    const int64_t tb = ((int64_t)(f0 >> 5) * a.NT + t) * (kTile * kTile);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t o = tb + acc_row(r, hi) * kTile + li;
+      if (BC == BC_B2) {
+        const int n = t * kTile + acc_row(r, hi);
+        const bool ok = frow_ok && n < N;
+        P[r] = ok ? ldc(a.V, (int64_t)frow * a.ldv + n, ok) + a.kappa : 0.f;
+      } else {
+        P[r] = a.Pst[o];
+      }
+      Q[r] = NEED_DEN ? a.Qst[o] : 0.f;
+    }
+  };
+
+  const int nt_total = (N + kTile - 1) / kTile;
+  const int t0 = g * a.tiles_per_group;
+  const int t1 = min(nt_total, t0 + a.tiles_per_group);
+  float4 x1[KB], x2[KB];
+  float P[16], Q[16], Pn[16], Qn[16];
+  __syncthreads();  // LDS may still be read by the previous item
+  if (t0 < t1) {
+    load_x(X1, a.ldh, t0 * kTile, x1);
+    load_x(X2, a.ldw, t0 * kTile, x2);
+    if (wave_on) load_pq(t0, P, Q);
+    if (!NEED_DEN)
+#pragma unroll
+      for (int j = 0; j < KB; ++j) rsum[j] += masked_sum(t0 * kTile, x2[j], j);
+    store_x(stage(0, 0), x1);
+    store_x(stage(0, 1), x2);
+  }
+  __syncthreads();
+  for (int t = t0; t < t1; ++t) {
+    const int b = (t - t0) & 1;
+    const bool more = t + 1 < t1;
+    if (more) {
+      load_x(X1, a.ldh, (t + 1) * kTile, x1);
+      load_x(X2, a.ldw, (t + 1) * kTile, x2);
+      if (wave_on) load_pq(t + 1, Pn, Qn);
+    }
+    if (wave_on) {
+      const float* s1 = stage(b, 0);
+      const float* s2 = stage(b, 1);
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float4 c = *reinterpret_cast<const float4*>(&s1[(kb * 32 + li) * kHS + 8 * q + 4 * hi]);
+          accN[kb] = mfma32(P[4 * q + 0], c.x, accN[kb]);
+          accN[kb] = mfma32(P[4 * q + 1], c.y, accN[kb]);
+          accN[kb] = mfma32(P[4 * q + 2], c.z, accN[kb]);
+          accN[kb] = mfma32(P[4 * q + 3], c.w, accN[kb]);
+          if (NEED_DEN) {
+            const float4 d = *reinterpret_cast<const float4*>(&s2[(kb * 32 + li) * kHS + 8 * q + 4 * hi]);
+            accD[kb] = mfma32(Q[4 * q + 0], d.x, accD[kb]);
+            accD[kb] = mfma32(Q[4 * q + 1], d.y, accD[kb]);
+            accD[kb] = mfma32(Q[4 * q + 2], d.z, accD[kb]);
+            accD[kb] = mfma32(Q[4 * q + 3], d.w, accD[kb]);
+          }
+        }
+      }
+    }
+    if (more) {
+      store_x(stage(b ^ 1, 0), x1);
+      store_x(stage(b ^ 1, 1), x2);
+      if (!NEED_DEN)
+#pragma unroll
+        for (int j = 0; j < KB; ++j) rsum[j] += masked_sum((t + 1) * kTile, x2[j], j);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        P[r] = Pn[r];
+        Q[r] = Qn[r];
+      }
+    }
+    __syncthreads();
+  }
+
+  if (wave_on) {
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int f = f0 + acc_row(r, hi);
+        if (f < a.F) {
+          const int64_t o = ((int64_t)g * a.F + f) * KP + kb * 32 + li;
+          a.pnum[o] = accN[kb][r];
+          if (NEED_DEN) a.pden[o] = accD[kb][r];
+        }
+      }
+    }
+  }
+  if (!NEED_DEN) {
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      float x = rsum[j];
+      x += __shfl_xor(x, 1, 64);
+      x += __shfl_xor(x, 2, 64);
+      x += __shfl_xor(x, 4, 64);
+      const int e4 = tid + kBlock * j;
+      if (rb == 0 && (e4 & 7) == 0) a.prs[g * KP + (e4 >> 3)] = x;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Low-precision products (bfloat16 or float16 operands, float32 accumulation)
 // with v_mfma_f32_32x32x16_{bf16,f16}: lane (li, hi) supplies A[li][8hi..8hi+7]
 // and B[8hi..8hi+7][li]; the accumulator layout is the float32 one, so eight

@@ -105,14 +105,19 @@ struct UpdateHArgs {
   int beta_one, normalize;
   const double* pcol; int pcol_blocks;   // column partials of W_new (pcol_blocks rows)
   const double* pobj; int nobj; double* d_obj;  // objective partials of the W pass
-  const float* Wn; float* W; int64_t ldw;
+  const float* Wn; float* W; int64_t ldw;  // W: nullable (no write-back)
   unsigned* flags;
+  // joint MM, a sub-iteration before the last: instead of H, write
+  // chi_1(H_new, H~) and chi_2(H_new, H~) ([K][ldc]) for the next W step
+  float* C1h; float* C2h; int64_t ldc; double beta;
 };
 
 // launchers (nmf_kernels.hip)
 // pq: the joint W pass keeps P, Q (Pst, Qst) and the joint H pass contracts them
 hipError_t launch_sweep_rows(int bc, int kb, int kind, bool obj, bool pq, int grid, hipStream_t s,
                              const SweepRowsArgs& a);
+// W pass of a later joint sub-iteration: a.H = chi_1(H_l, H~), a.W = chi_2(H_l, H~)
+hipError_t launch_sweep_rows_pq(int bc, int kb, int grid, hipStream_t s, const SweepRowsArgs& a);
 hipError_t launch_sweep_cols(int bc, int kb, int kind, bool dual, bool pq, int grid, hipStream_t s,
                              const SweepColsArgs& a);
 // low-precision products (prec 1 = bfloat16, 2 = float16; update kind, K <= 64)

@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kBlock) void update_h_kernel(UpdateHArgs a) {
   }
   // W <- W_new / norm: the first entry from the prefetched value, the rest (when
   // the grid is smaller than F * K) by write_w
-  if (e0 < total_w) {
+  if (a.W && e0 < total_w) {
     float w = w0;
     if (a.normalize) {
       const float x = norm_s[kk0];
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void update_h_kernel(UpdateHArgs a) {
     }
     a.W[(int64_t)f0 * a.ldw + kk0] = w;
   }
-  if (e0 + estride < total_w) write_w<KB>(a, norm_s, e0 + estride, estride);
+  if (a.W && e0 + estride < total_w) write_w<KB>(a, norm_s, e0 + estride, estride);
 
   double num = 0.0, den = 0.0;
 #pragma unroll
@@ -99,6 +99,14 @@ __global__ __launch_bounds__(kBlock) void update_h_kernel(UpdateHArgs a) {
   const double dd = a.beta_one ? (double)csum_s[k] : den;
   const double ratio = num / dd;
   if (!(dd > 0.0) || !isfinite(ratio)) set_flag(a.flags, 1u);
+  if (a.C1h) {  // sub-iteration: chi terms of H_new against H~ (no normalization)
+    const double rr = pow_gamma(ratio, a.gamma);
+    float c1, c2;
+    chi_terms(a.beta, (double)hv, rr, (double)hv * rr, c1, c2);
+    a.C1h[(int64_t)k * a.ldc + n] = c1;
+    a.C2h[(int64_t)k * a.ldc + n] = c2;
+    return;
+  }
   double nk = 1.0;
   if (a.normalize) {
     const float x = norm_s[k];

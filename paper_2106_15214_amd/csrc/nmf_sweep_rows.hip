@@ -17,6 +17,36 @@ __global__ __launch_bounds__(kBlock, sweep_rows_occupancy(KB)) void sweep_rows_k
   }
 }
 
+// The W pass of a later joint sub-iteration (contractions of the kept P, Q tiles).
+template <int BC, int KB>
+__global__ __launch_bounds__(kBlock, sweep_rows_occupancy(KB)) void sweep_rows_pq_kernel(SweepRowsArgs a) {
+  __shared__ __align__(16) float lds[rows_pq_item_lds<KB>() / 4];
+  rows_pq_item<BC, KB>(a, blockIdx.x, lds);
+}
+
+template <int BC>
+static hipError_t rows_pq_bc(int kb, int grid, hipStream_t s, const SweepRowsArgs& a) {
+  switch (kb) {
+    case 1: hipLaunchKernelGGL((sweep_rows_pq_kernel<BC, 1>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((sweep_rows_pq_kernel<BC, 2>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((sweep_rows_pq_kernel<BC, 4>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_rows_pq(int bc, int kb, int grid, hipStream_t s, const SweepRowsArgs& a) {
+  switch (bc) {
+    case BC_GEN: return rows_pq_bc<BC_GEN>(kb, grid, s, a);
+    case BC_B2: return rows_pq_bc<BC_B2>(kb, grid, s, a);
+    case BC_B1: return rows_pq_bc<BC_B1>(kb, grid, s, a);
+    case BC_B0: return rows_pq_bc<BC_B0>(kb, grid, s, a);
+    case BC_B05: return rows_pq_bc<BC_B05>(kb, grid, s, a);
+    case BC_B15: return rows_pq_bc<BC_B15>(kb, grid, s, a);
+  }
+  return hipErrorInvalidValue;
+}
+
 // launchers: map runtime (beta class, K block count, kind) to instantiations
 template <int BC, int KB>
 static hipError_t rows_kb(int kind, bool obj, bool pq, int grid, hipStream_t s, const SweepRowsArgs& a) {

@@ -55,8 +55,13 @@ def test_step_argument_checks():
     assert c(100, 200, 10, beta=float("inf")) == E_BETA
     assert c(100, 200, 10, mode=2) == E_ARG
     assert c(100, 200, 10, kappa=-1.0) == E_BETA
-    assert c(100, 200, 10, inner_iters=2) == E_UNSUP  # joint mode: L = 1 only
+    assert c(100, 200, 10, inner_iters=2) == OK
     assert c(100, 200, 10, inner_iters=2, mode=0) == OK
+    # joint sub-iterations keep P and Q: at most 2^28 entries of V
+    far = dict(V=1 << 36, W=1 << 38, H=1 << 39)  # a 1.6 GB V must not overlap W, H
+    assert c(20000, 20000, 10, inner_iters=2, **far) == E_UNSUP
+    assert c(20000, 20000, 10, inner_iters=2, mode=0, **far) == OK
+    assert c(100, 200, 10, inner_iters=2, precision=1) == E_UNSUP
     assert c(100, 200, 10, inner_iters=3, mode=0, precision=1) == E_UNSUP
     assert c(100, 200, 10, inner_iters=0, mode=0) == E_ARG
     assert c(100, 200, 10, inner_iters=1001, mode=0) == E_ARG

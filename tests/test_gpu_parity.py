@@ -145,13 +145,55 @@ def test_alternating_sub_iterations_parity(L, beta, normalize):
     assert abs(o.item() - d0) <= TOL_OBJ * abs(d0)
 
 
+@pytest.mark.parametrize("L", [2, 3])
+@pytest.mark.parametrize("beta", [0.0, 0.5, 1.0, 1.5, 2.0, 2.5])
+@pytest.mark.parametrize("normalize", [True, False])
+def test_joint_sub_iterations_parity(L, beta, normalize):
+    # Algorithm 2 with L sub-iterations: later W steps contract the kept P, Q
+    # with chi(H_l, H~); every step multiplies the tilde iterate
+    p = synth.random_positive(257, 300, 20, seed=45, zeros=0.1 if beta > 0 else 0.0)
+    print(f"[parity] joint L={L} beta={beta} normalize={normalize}", flush=True)
+    Vd, Wd, Hd = dev(p.V), dev(p.W), dev(p.H)
+    o = torch.full((1,), float("nan"), dtype=torch.float64, device=DEV)
+    ctx = ctx_for("auto")
+    nb.step(Vd, Wd, Hd, beta, "joint", inner_iters=L, normalize=normalize, objective_out=o, ctx=ctx)
+    torch.cuda.synchronize()
+    assert nb.get_flags(clear=True, ctx=ctx) == 0
+    V64, W64, H64 = (a.astype(np.float64) for a in (p.V, p.W, p.H))
+    Wr, Hr = O.jmm_iteration(V64, W64, H64, beta, L=L, norm=normalize)
+    assert rel(Wd.cpu().numpy(), Wr) <= TOL_FACTOR
+    assert rel(Hd.cpu().numpy(), Hr) <= TOL_FACTOR
+    d0 = ref_obj(p.V, p.W, p.H, beta)
+    assert abs(o.item() - d0) <= TOL_OBJ * abs(d0)
+
+
+@pytest.mark.parametrize("mode", ["joint", "alternating"])
+def test_sub_iterations_large_rank(mode):
+    # K = 100 (four 32-column blocks), ragged shape
+    p = synth.random_positive(300, 197, 100, seed=46)
+    print(f"[parity] sub-iterations K=100 mode={mode}", flush=True)
+    Vd, Wd, Hd = dev(p.V), dev(p.W), dev(p.H)
+    ctx = ctx_for("auto")
+    nb.step(Vd, Wd, Hd, 0.5, mode, inner_iters=3, ctx=ctx)
+    torch.cuda.synchronize()
+    assert nb.get_flags(clear=True, ctx=ctx) == 0
+    V64, W64, H64 = (a.astype(np.float64) for a in (p.V, p.W, p.H))
+    if mode == "joint":
+        Wr, Hr = O.jmm_iteration(V64, W64, H64, 0.5, L=3)
+    else:
+        Wr, Hr = O.bmm_iteration(V64, W64, H64, 0.5, L_W=3, L_H=3)
+    assert rel(Wd.cpu().numpy(), Wr) <= TOL_FACTOR
+    assert rel(Hd.cpu().numpy(), Hr) <= TOL_FACTOR
+
+
 def test_sub_iterations_rejected_where_unsupported():
     p = synth.random_positive(64, 80, 6, seed=44)
-    for kw in (dict(mode="joint"), dict(mode="alternating", precision="bf16")):
+    for kw in (dict(mode="joint", precision="bf16"), dict(mode="alternating", precision="bf16")):
         with pytest.raises(nb.NmfError):
             nb.step(dev(p.V), dev(p.W), dev(p.H), 1.0, inner_iters=2, ctx=ctx_for("auto"), **kw)
-    with pytest.raises(nb.NmfError):
-        nb.step(dev(p.V), dev(p.W), dev(p.H), 1.0, "alternating", inner_iters=2, ctx=ctx_for("fused"))
+    for mode in ("joint", "alternating"):
+        with pytest.raises(nb.NmfError):
+            nb.step(dev(p.V), dev(p.W), dev(p.H), 1.0, mode, inner_iters=2, ctx=ctx_for("fused"))
 
 
 @pytest.mark.parametrize("beta", [-0.5, 0.0, 0.5, 1.0, 2.5])
