@@ -109,10 +109,10 @@ def measured_traffic(workload: str, precision: str, kernel: str, beta=None):
     return value
 
 
-def _run_steps(nb, V, W, H, beta, mode, n, ctx, obj=None, trace=None, precision="fp32"):
+def _run_steps(nb, V, W, H, beta, mode, n, ctx, obj=None, trace=None, precision="fp32", inner=1):
     for t in range(n):
         o = trace[t:t + 1] if trace is not None else obj
-        nb.step(V, W, H, beta, mode, precision=precision, objective_out=o, ctx=ctx)
+        nb.step(V, W, H, beta, mode, precision=precision, inner_iters=inner, objective_out=o, ctx=ctx)
 
 
 def main(argv=None):
@@ -132,6 +132,8 @@ def main(argv=None):
     ap.add_argument("--problems", type=int, default=512, help="batched workload: number of problems")
     ap.add_argument("--tune", default=None, help="batched workload: autotune, caching results in this JSON file")
     ap.add_argument("--tiles", type=int, default=0, help="batched workload: tiles per pass item (0: library default)")
+    ap.add_argument("--inner-iters", type=int, default=1,
+                    help="sub-iterations L per outer iteration (both methods; L > 1: float32)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"],
                     help="operand type of the matrix products (element-wise terms stay float32)")
     args = ap.parse_args(argv)
@@ -171,12 +173,14 @@ def main(argv=None):
 
     for mode in ("joint", "alternating"):
         W, H = W0.clone(), H0.clone()
-        _run_steps(nb, V, W, H, beta, mode, args.warmup, ctx, obj=obj, precision=args.precision)
+        _run_steps(nb, V, W, H, beta, mode, args.warmup, ctx, obj=obj, precision=args.precision,
+                   inner=args.inner_iters)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         e0.record()
-        _run_steps(nb, V, W, H, beta, mode, args.steps, ctx, obj=obj, precision=args.precision)
+        _run_steps(nb, V, W, H, beta, mode, args.steps, ctx, obj=obj, precision=args.precision,
+                   inner=args.inner_iters)
         e1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -240,7 +244,7 @@ def main(argv=None):
 
     # time-to-objective: same init, objective of every iterate, T = steps
     T = args.steps
-    tto_main = time_to_objective(nb, torch, np, ctx, V, W0, H0, beta, T, args.precision, dev)
+    tto_main = time_to_objective(nb, torch, np, ctx, V, W0, H0, beta, T, args.precision, dev, args.inner_iters)
     tto_main.pop("_traces")
     # the same for every beta of the paper's experiments on this data (at most
     # 500 iterations; beta <= 0 only when V has no zero, where d_beta is finite)
@@ -249,7 +253,7 @@ def main(argv=None):
     for b in (0.0, 0.5, 1.0, 1.5, 2.0):
         if b <= 0.0 and has_zero:
             continue
-        r = time_to_objective(nb, torch, np, ctx, V, W0, H0, b, min(T, 500), args.precision, dev)
+        r = time_to_objective(nb, torch, np, ctx, V, W0, H0, b, min(T, 500), args.precision, dev, args.inner_iters)
         r.pop("_traces")
         per_beta[str(b)] = r
 
@@ -267,6 +271,7 @@ def main(argv=None):
         "dtype": {"fp32": "f32", "bf16": "bf16", "fp16": "f16"}[args.precision],
         "data": "synthetic",
         "config": {"workload": args.workload, "F": F, "N": N, "K": K, "beta": beta, "mode": "joint",
+                   "inner_iters": args.inner_iters,
                    "precision": args.precision, "objective_every_step": True, "normalize": True,
                    "path": "fused" if "fused_step" in kern["joint"] else "stream"},
         "alternating": {"value": res["alternating"]["iters_per_s"], "ms_per_step": res["alternating"]["ms_per_step"]},
@@ -290,7 +295,7 @@ def main(argv=None):
     return 0
 
 
-def time_to_objective(nb, torch, np, ctx, V, W0, H0, beta, T, precision, dev):
+def time_to_objective(nb, torch, np, ctx, V, W0, H0, beta, T, precision, dev, inner=1):
     """Both methods from the same init for T iterations with the objective of
     every iterate: iterations and milliseconds to reach 90 / 99 / 99.9 / 100 % of
     the larger final decrease, the iteration where the 1e-5 relative-decrease
@@ -302,7 +307,7 @@ def time_to_objective(nb, torch, np, ctx, V, W0, H0, beta, T, precision, dev):
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        _run_steps(nb, V, W, H, beta, mode, T, ctx, trace=tr, precision=precision)
+        _run_steps(nb, V, W, H, beta, mode, T, ctx, trace=tr, precision=precision, inner=inner)
         e1.record()
         nb.objective(V, W, H, beta, out=tr[T:T + 1], ctx=ctx)
         torch.cuda.synchronize()
