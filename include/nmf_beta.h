@@ -45,7 +45,7 @@ typedef enum {
   NMF_ERR_ALIAS = 4,       /* two of the matrices overlap in memory */
   NMF_ERR_WORKSPACE = 5,   /* workspace too small while the stream is captured */
   NMF_ERR_HIP = 6,         /* a HIP runtime call failed */
-  NMF_ERR_UNSUPPORTED = 7, /* K > 128, inner_iters != 1, unknown precision */
+  NMF_ERR_UNSUPPORTED = 7, /* K > 128, unknown precision, an unsupported inner_iters > 1 case */
   NMF_ERR_ARG = 8,         /* other invalid argument (mode, opts field) */
   NMF_ERR_NO_DEVICE = 9    /* no usable GPU */
 } nmf_status;
@@ -130,11 +130,14 @@ nmf_status nmf_check_step_args(int64_t F, int64_t N, int64_t K, const float* V, 
 /* One outer iteration of the multiplicative-update method, in place on W and H.
  *
  * mode == NMF_ALTERNATING (paper Sec. 2.2, eq. (alt_update), Algorithm 1 with
- *   L_W = L_H = 1):  W <- W .* ((( (WH)^(b-2) .* V) H^T) / ((WH)^(b-1) H^T))^gamma,
+ *   L_W = L_H = opts->inner_iters, default 1):
+ *   W <- W .* ((( (WH)^(b-2) .* V) H^T) / ((WH)^(b-1) H^T))^gamma,
  *   then H is updated the same way against the new W (WH is formed again).
- * mode == NMF_JOINT (paper Sec. 3.2, eq. (jnt_update), Algorithm 2 with L = 1):
- *   V~ = W~H~ is formed once; W and H are both updated from the tilde iterate,
- *   the H step using chi_1(W, W~) and chi_2(W, W~) in its contractions.
+ * mode == NMF_JOINT (paper Sec. 3.2, eq. (jnt_update), Algorithm 2 with
+ *   L = opts->inner_iters, default 1): V~ = W~H~ is formed once; W and H are
+ *   both updated from the tilde iterate, the H step using chi_1(W, W~) and
+ *   chi_2(W, W~) in its contractions (and, for L > 1, the W step chi_1(H, H~)
+ *   and chi_2(H, H~)).
  * gamma = gamma(beta) of eq. (def_gamma), or 1 with opts->exponent ==
  * NMF_EXPONENT_ONE.  With opts->normalize the columns of W
  * are scaled to unit l2 norm and the rows of H by the inverse (Sec. 4.1.2).
