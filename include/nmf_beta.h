@@ -91,9 +91,9 @@ typedef struct {
                           the latest W, then L H updates against the final W.
                           NMF_JOINT (Algorithm 2): L alternations of a W and an H
                           update, both always multiplying the tilde iterate, with
-                          V~, P, Q formed once (F N <= 2^28).  L > 1 only with
-                          NMF_FP32, not in batches and not on the single-launch
-                          path (NMF_ERR_UNSUPPORTED otherwise); default 1 */
+                          V~, P, Q formed once (F N <= 2^28, NMF_FP32).  L > 1
+                          is not available in batches or on the single-launch
+                          path (NMF_ERR_UNSUPPORTED); default 1 */
   int32_t normalize;   /* 1: divide W's columns by their l2 norm and scale H's rows
                           (Sec. 4.1.2) at the end of the step; default 1 */
   int32_t exponent;    /* NMF_EXPONENT_MM (default) or NMF_EXPONENT_ONE; other

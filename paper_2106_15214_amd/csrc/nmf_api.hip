@@ -459,14 +459,14 @@ inline int batch_w_units(int KB) { return std::max(1, kBatchUpdateRows / batch_u
 inline int batch_h_units(int KB) { return std::max(1, kBatchUpdateCols / (kBlock / (32 * KB))); }
 constexpr unsigned kBatchSpinLimit = 1u << 22;
 
-// Alternating MU with L > 1 sub-iterations (Algorithm 1, float32 products): L W
+// Alternating MU with L > 1 sub-iterations (Algorithm 1, any product type): L W
 // updates, each forming WH from the latest W (the first from the caller's W,
 // the later ones from W_new in the workspace, which the update rewrites in
 // place), then L H updates against the final W_new, each forming W_new H from
 // the latest H.  Only the first W pass forms the objective of the entry
 // iterate; only the last H update normalizes, writes W and the objective.
 nmf_status inner_steps(nmf_ctx_s* c, hipStream_t s, const Plan& p, const StepArgs& sa, int bc, bool want_obj,
-                              int L) {
+                              int L, int prec) {
   for (int l = 0; l < L; ++l) {
     SweepRowsArgs ra = sa.ra;
     UpdateWArgs ua = sa.ua;
@@ -475,7 +475,9 @@ nmf_status inner_steps(nmf_ctx_s* c, hipStream_t s, const Plan& p, const StepArg
       ua.W = sa.ua.Wn; ua.ldw = p.KP;
     }
     hipError_t e = timed(c, NMF_KERNEL_SWEEP_W, s, [&] {
-      return launch_sweep_rows(bc, p.KB, KIND_UPDATE, want_obj && l == 0, false, sa.sw_grid, s, ra);
+      const bool obj = want_obj && l == 0;
+      return prec == NMF_FP32 ? launch_sweep_rows(bc, p.KB, KIND_UPDATE, obj, false, sa.sw_grid, s, ra)
+                              : launch_sweep_rows_lp(prec, bc, p.KB, obj, false, sa.sw_grid, s, ra);
     });
     if (e != hipSuccess) return NMF_ERR_HIP;
     e = timed(c, NMF_KERNEL_UPDATE_W, s, [&] { return launch_update_w(p.KB, p.uw_blocks, s, ua); });
@@ -488,7 +490,8 @@ nmf_status inner_steps(nmf_ctx_s* c, hipStream_t s, const Plan& p, const StepArg
       ha.d_obj = nullptr;
     }
     hipError_t e = timed(c, NMF_KERNEL_SWEEP_H, s, [&] {
-      return launch_sweep_cols(bc, p.KB, KIND_UPDATE, false, false, sa.sh_grid, s, sa.ca);
+      return prec == NMF_FP32 ? launch_sweep_cols(bc, p.KB, KIND_UPDATE, false, false, sa.sh_grid, s, sa.ca)
+                              : launch_sweep_cols_lp(prec, bc, p.KB, false, false, sa.sh_grid, s, sa.ca);
     });
     if (e != hipSuccess) return NMF_ERR_HIP;
     e = timed(c, NMF_KERNEL_UPDATE_H, s, [&] { return launch_update_h(p.KB, p.uh_blocks, s, ha); });
@@ -615,9 +618,9 @@ nmf_status nmf_check_step_args(int64_t F, int64_t N, int64_t K, const float* V, 
   st = check_opts(opts);
   if (st != NMF_OK) return st;
   if (opts && opts->precision != NMF_FP32 && K > 64) return NMF_ERR_UNSUPPORTED;
-  // L > 1 sub-iterations: float32 products; joint MM keeps P, Q between the passes
-  if (opts && opts->inner_iters > 1 &&
-      (opts->precision != NMF_FP32 || (mode == NMF_JOINT && F * N > kPQMaxEntries)))
+  // L > 1 sub-iterations of joint MM: float32 products, P and Q kept between the passes
+  if (opts && opts->inner_iters > 1 && mode == NMF_JOINT &&
+      (opts->precision != NMF_FP32 || F * N > kPQMaxEntries))
     return NMF_ERR_UNSUPPORTED;
   return NMF_OK;
 }
@@ -688,7 +691,8 @@ nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
     ra.Qst = (float*)(ws + p.o_qst);
     ca.NT = ra.NT; ca.Pst = ra.Pst; ca.Qst = ra.Qst;
   }
-  if (L > 1) return joint ? inner_steps_joint(c, s, p, sa, bc, want_obj, L) : inner_steps(c, s, p, sa, bc, want_obj, L);
+  if (L > 1)
+    return joint ? inner_steps_joint(c, s, p, sa, bc, want_obj, L) : inner_steps(c, s, p, sa, bc, want_obj, L, prec);
   hipError_t e = timed(c, NMF_KERNEL_SWEEP_W, s, [&] {
     return prec == NMF_FP32 ? launch_sweep_rows(bc, p.KB, KIND_UPDATE, want_obj, p.pq, sw_grid, s, ra)
                             : launch_sweep_rows_lp(prec, bc, p.KB, want_obj, p.pq, sw_grid, s, ra);

@@ -62,7 +62,7 @@ def test_step_argument_checks():
     assert c(20000, 20000, 10, inner_iters=2, **far) == E_UNSUP
     assert c(20000, 20000, 10, inner_iters=2, mode=0, **far) == OK
     assert c(100, 200, 10, inner_iters=2, precision=1) == E_UNSUP
-    assert c(100, 200, 10, inner_iters=3, mode=0, precision=1) == E_UNSUP
+    assert c(100, 200, 10, inner_iters=3, mode=0, precision=1) == OK
     assert c(100, 200, 10, inner_iters=0, mode=0) == E_ARG
     assert c(100, 200, 10, inner_iters=1001, mode=0) == E_ARG
     assert c(100, 200, 10, precision=7) == E_UNSUP

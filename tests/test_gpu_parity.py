@@ -186,11 +186,27 @@ def test_sub_iterations_large_rank(mode):
     assert rel(Hd.cpu().numpy(), Hr) <= TOL_FACTOR
 
 
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+@pytest.mark.parametrize("beta", [0.5, 1.0, 2.0])
+def test_alternating_sub_iterations_low_precision(precision, beta):
+    # low-precision products: the per-step bar of the low-precision tests (3e-3)
+    p = synth.random_positive(257, 300, 20, seed=47, zeros=0.1)
+    print(f"[parity] alternating L=2 {precision} beta={beta}", flush=True)
+    Vd, Wd, Hd = dev(p.V), dev(p.W), dev(p.H)
+    ctx = ctx_for("auto")
+    nb.step(Vd, Wd, Hd, beta, "alternating", precision=precision, inner_iters=2, ctx=ctx)
+    torch.cuda.synchronize()
+    assert nb.get_flags(clear=True, ctx=ctx) == 0
+    V64, W64, H64 = (a.astype(np.float64) for a in (p.V, p.W, p.H))
+    Wr, Hr = O.bmm_iteration(V64, W64, H64, beta, L_W=2, L_H=2)
+    assert rel(Wd.cpu().numpy(), Wr) <= 3e-3
+    assert rel(Hd.cpu().numpy(), Hr) <= 3e-3
+
+
 def test_sub_iterations_rejected_where_unsupported():
     p = synth.random_positive(64, 80, 6, seed=44)
-    for kw in (dict(mode="joint", precision="bf16"), dict(mode="alternating", precision="bf16")):
-        with pytest.raises(nb.NmfError):
-            nb.step(dev(p.V), dev(p.W), dev(p.H), 1.0, inner_iters=2, ctx=ctx_for("auto"), **kw)
+    with pytest.raises(nb.NmfError):
+        nb.step(dev(p.V), dev(p.W), dev(p.H), 1.0, "joint", precision="bf16", inner_iters=2, ctx=ctx_for("auto"))
     for mode in ("joint", "alternating"):
         with pytest.raises(nb.NmfError):
             nb.step(dev(p.V), dev(p.W), dev(p.H), 1.0, mode, inner_iters=2, ctx=ctx_for("fused"))
