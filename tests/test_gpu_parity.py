@@ -385,6 +385,39 @@ def test_workspace_regrowth_between_sizes():
         check_step(p.V, p.W, p.H, 1.0, "joint", tag="regrow")
 
 
+@pytest.mark.parametrize("mode,L", [("joint", 2), ("alternating", 3)])
+def test_sub_iterations_under_graph_capture(mode, L):
+    # after nmf_reserve a step with L sub-iterations allocates nothing and can be
+    # captured; every replay (with eager work between them) matches the oracle
+    ctx = nb.Context(0)
+    ctx.reserve(400, 500, 40)
+    q = synth.random_positive(150, 333, 17, seed=14)
+    print(f"[parity] graph capture mode={mode} L={L}", flush=True)
+    Vq, Wq, Hq = dev(q.V), dev(q.W), dev(q.H)
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        nb.step(Vq, Wq, Hq, 0.5, mode, inner_iters=L, ctx=ctx, stream=s)
+    V64, W64, H64 = (a.astype(np.float64) for a in (q.V, q.W, q.H))
+    f = O.jmm_iteration if mode == "joint" else O.bmm_iteration
+    Wr, Hr = f(V64, W64, H64, 0.5, L=L) if mode == "joint" else f(V64, W64, H64, 0.5, L_W=L, L_H=L)
+    for rep in range(3):
+        Wq.copy_(dev(q.W))
+        Hq.copy_(dev(q.H))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert rel(Wq.cpu().numpy(), Wr) <= TOL_FACTOR, rep
+        assert rel(Hq.cpu().numpy(), Hr) <= TOL_FACTOR, rep
+        # eager work between the replays
+        We, He = dev(q.W), dev(q.H)
+        nb.step(Vq, We, He, 0.5, mode, inner_iters=L, ctx=ctx)
+        torch.cuda.synchronize()
+        assert rel(We.cpu().numpy(), Wr) <= TOL_FACTOR, rep
+    assert nb.get_flags(clear=True, ctx=ctx) == 0
+    ctx.close()
+
+
 def test_reserve_then_steps_do_not_allocate():
     ctx = nb.Context(0)
     ctx.reserve(400, 500, 40)
