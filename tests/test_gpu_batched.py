@@ -191,6 +191,34 @@ def test_batched_heuristic_exponent_matches_oracle(mode):
         assert rel(Hd.cpu().numpy(), Hr) <= 1e-5, i
 
 
+def test_batched_many_initializations_of_one_problem():
+    # the evaluation protocol of Sec. 4.1.4: one V from 25 initializations, as one
+    # batch whose problems share V (read-only); every problem against the oracle
+    p = synth.make_problem("spectro_is", beta=0.5, rows=(0, 120), cols=(0, 700))
+    V = dev(p.V)
+    inits = []
+    for seed in range(25):
+        rng = np.random.default_rng(seed)
+        inits.append((rng.uniform(0.1, 1.0, p.W.shape).astype(np.float32),
+                      rng.uniform(0.1, 1.0, p.H.shape).astype(np.float32)))
+    d = [(V, dev(W), dev(H), 0.5) for W, H in inits]
+    b = nb.Batch(d, "joint", ctx=ctx())
+    obj = torch.zeros(len(d), dtype=torch.float64, device=DEV)
+    b.step(objectives=obj)
+    torch.cuda.synchronize()
+    assert b.flags() == 0
+    b.close()
+    V64 = p.V.astype(np.float64)
+    ob = obj.cpu().numpy()
+    for i, ((W, H), (_, Wd, Hd, _)) in enumerate(zip(inits, d)):
+        W64, H64 = W.astype(np.float64), H.astype(np.float64)
+        Wr, Hr = O.jmm_iteration(V64, W64, H64, 0.5)
+        assert rel(Wd.cpu().numpy(), Wr) <= 1e-5, i
+        assert rel(Hd.cpu().numpy(), Hr) <= 1e-5, i
+        d0 = O.objective(V64, W64, H64, 0.5)
+        assert abs(ob[i] - d0) <= 1e-6 * abs(d0), i
+
+
 def test_batched_rejects_aliasing_and_large_k():
     a, b = to_dev(make_set([(64, 100, 5, 1.0), (64, 100, 5, 0.5)], seed0=900))
     # the second problem updates the first one's W
