@@ -27,6 +27,7 @@ Contents, each following the passage cited in its docstring:
 * ``kkt_residuals``                     -- Sec. 4.1.5
 * ``joint_auxiliary``                   -- Sec. 3.1, Table 1, eqs. (simplif) and (jointG)
 * ``relative_decrease``                 -- Sec. 4.1.2 stopping criterion
+* ``stop_iteration``                    -- Sec. 4.1.2: first outer iteration where it fires
 
 Smoothing constant kappa (Sec. 4.1.3): the data V is replaced by V + kappa and
 every product WH (or W~H~) by WH + kappa.  The paper gives no value; the
@@ -58,6 +59,7 @@ __all__ = [
     "kkt_residuals",
     "joint_auxiliary",
     "relative_decrease",
+    "stop_iteration",
 ]
 
 
@@ -253,7 +255,13 @@ def gradient(V, W, H, beta: float, kappa: float = 0.0):
 
 
 def kkt_residuals(V, W, H, beta: float, kappa: float = 0.0):
-    """res(W), res(H) of Sec. 4.1.5: mean |min(X, grad_X D)| over the entries of X."""
+    """res(W), res(H) of Sec. 4.1.5.
+
+    res(W) = || min(W, grad_W D) ||_1 / (F K) and res(H) = || min(H, grad_H D) ||_1 / (K N):
+    the entry-wise minimum of each factor and its gradient (the bracketed
+    (WH)^(beta-2) (WH - V) terms contracted with H^T, resp. W^T), its l1 norm
+    (sum of absolute values), divided by the number of entries of that factor.
+    """
     gW, gH = gradient(V, W, H, beta, kappa)
     W = _f64(W)
     H = _f64(H)
@@ -312,5 +320,23 @@ def joint_auxiliary(V, W, H, Wt, Ht, beta: float) -> float:
 
 
 def relative_decrease(D_prev: float, D_cur: float) -> float:
-    """(D(previous iterate) - D(current iterate)) / D(current iterate), Sec. 4.1.2."""
+    """(D(previous iterate) - D(current iterate)) / D(current iterate), Sec. 4.1.2.
+
+    Positive when the objective went down.  The paper prints no absolute value,
+    so an increase gives a negative value, which is below any tolerance.
+    """
     return (D_prev - D_cur) / D_cur
+
+
+def stop_iteration(trace, eps: float = 1e-5):
+    """Stopping rule of Sec. 4.1.2 applied to an objective trace.
+
+    ``trace[t]`` is D_beta at the outer iterate t (t = 0 the initialization).
+    Returns the first t >= 1 with relative_decrease(trace[t-1], trace[t]) <= eps:
+    the algorithm stops there and iterate t is the one it returns.  None when
+    the rule does not fire within the trace.  The paper's tolerance is 1e-5.
+    """
+    for t in range(1, len(trace)):
+        if relative_decrease(float(trace[t - 1]), float(trace[t])) <= eps:
+            return t
+    return None

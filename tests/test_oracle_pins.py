@@ -459,3 +459,97 @@ def test_heuristic_exponent_w_steps_coincide_at_L1(beta):
     assert np.allclose(Wb, Wj, rtol=1e-14, atol=0)
     Wm, _ = O.bmm_iteration(V, W, H, beta, norm=False)
     assert not np.allclose(Wm, Wb, rtol=1e-6, atol=0)  # the exponent matters outside [1, 2]
+
+
+# ---------------------------------------------------------------------------
+# KKT residuals (Sec. 4.1.5) and the stopping rule (Sec. 4.1.2), against
+# hand-evaluated fixtures
+# ---------------------------------------------------------------------------
+def _mat_field(text):
+    return np.array([[float(t) for t in row.split()] for row in text.split(";")], dtype=np.float64)
+
+
+def _kkt_cases():
+    rows = []
+    with open(os.path.join(GOLD, "kkt_residuals.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            f = [x.strip() for x in line.split("|")]
+            rows.append((float(f[0]), _mat_field(f[1]), _mat_field(f[2]), _mat_field(f[3]), float(f[4]),
+                         float(f[5])))
+    return rows
+
+
+@pytest.mark.parametrize("case", range(2))
+def test_kkt_residuals_hand_cases(case):
+    beta, V, W, H, rW, rH = _kkt_cases()[case]
+    F, N = V.shape
+    K = W.shape[1]
+    assert len({F * K, K * N, F * N}) == 3 or K == 1  # normalizations distinguishable
+    got = O.kkt_residuals(V, W, H, beta)
+    assert got[0] == pytest.approx(rW, rel=1e-14)
+    assert got[1] == pytest.approx(rH, rel=1e-14)
+
+
+def test_kkt_residuals_zero_at_interior_stationary_point():
+    # an exact factorization has zero gradient, and every W, H entry is > 0 so
+    # min(X, 0) = 0: both residuals vanish (the KKT conditions hold)
+    V, W, H = _small(seed=3)
+    V = W @ H
+    for beta in (0.0, 1.0, 2.0, 0.5):
+        rW, rH = O.kkt_residuals(V, W, H, beta)
+        assert rW < 1e-12 and rH < 1e-12
+
+
+def test_kkt_residuals_boundary_point_with_positive_gradient():
+    # W entry at 0 with a positive gradient component: min(0, g) = 0 there, so
+    # the residual is not the gradient norm (complementarity, Sec. 4.1.5)
+    V = np.array([[1.0, 2.0], [3.0, 4.0]])
+    W = np.array([[0.0], [1.0]])
+    H = np.array([[5.0, 5.0]])
+    # beta = 2: E = WH - V = [[-1, -2], [2, 1]]; grad_W = E H^T = [[-15], [15]]
+    # min(W, grad_W) = [[-15], [1]] -> 16 / (F K = 2) = 8
+    # grad_H = W^T E = [[2, 1]]; min(H, grad_H) = [[2, 1]] -> 3 / (K N = 2) = 1.5
+    rW, rH = O.kkt_residuals(V, W, H, 2.0)
+    assert rW == pytest.approx(8.0, rel=1e-15)
+    assert rH == pytest.approx(1.5, rel=1e-15)
+
+
+def _stop_cases():
+    rows = []
+    with open(os.path.join(GOLD, "stop_rule.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            f = [x.strip() for x in line.split("|")]
+            rows.append((float(f[0]), [float(t) for t in f[1].split()], None if f[2] == "none" else int(f[2])))
+    return rows
+
+
+@pytest.mark.parametrize("case", range(7))
+def test_stop_rule_hand_cases(case):
+    eps, trace, want = _stop_cases()[case]
+    assert O.stop_iteration(trace, eps) == want
+
+
+def test_relative_decrease_sign_convention():
+    # positive for a decrease, negative for an increase, relative to the current value
+    assert O.relative_decrease(2.0, 1.0) == 1.0
+    assert O.relative_decrease(1.0, 2.0) == -0.5
+    assert O.relative_decrease(3.0, 3.0) == 0.0
+    assert O.relative_decrease(10.0, 8.0) == pytest.approx(0.25, rel=1e-15)  # / D_cur, not / D_prev (0.2)
+
+
+def test_stop_rule_fires_on_a_converging_oracle_run():
+    # the joint iteration on a tiny problem: the objective decreases
+    # monotonically, and the rule fires where the decrease first drops to eps
+    V, W, H = _small(seed=5, F=8, N=9, K=2)
+    trace = [O.objective(V, W, H, 1.0)]
+    for _ in range(400):
+        W, H = O.jmm_iteration(V, W, H, 1.0)
+        trace.append(O.objective(V, W, H, 1.0))
+    t = O.stop_iteration(trace, 1e-5)
+    assert t is not None
+    rd = [(trace[i - 1] - trace[i]) / trace[i] for i in range(1, t + 1)]
+    assert all(r > 1e-5 for r in rd[:-1]) and rd[-1] <= 1e-5
