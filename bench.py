@@ -7,7 +7,13 @@ the entry iterate) of the joint method on the chosen workload; the alternating
 method is timed the same way and reported beside it.  Inputs are resident in
 device memory before timing starts.
 
-    python bench.py [--steps K] [--warmup W] [--workload faces_euc]
+    python bench.py [--steps K] [--warmup W] [--workload batched]
+
+The default workload is the largest single-GPU configuration: 512 uneven
+problems (F in 128..1025, N in 200..5000, K in 8..64, beta in {0, .5, 1, 1.5, 2})
+updated by one persistent launch per outer iteration, replayed from a HIP
+graph.  `--workload counts_kl` (20000 x 10000, K = 50, beta = 1), `faces_euc`,
+`spectro_is` and `tiny_kl` time one problem instead.
 
 Prints one JSON line.  Only one GPU is used; --gpus above 1 exits.
 """
@@ -109,6 +115,25 @@ def measured_traffic(workload: str, precision: str, kernel: str, beta=None):
     return value
 
 
+# outer iterations of each workload's time-to-objective runs (the iteration
+# counts of the configurations; independent of --steps)
+TTO_ITERS = {"tiny_kl": 100, "faces_euc": 500, "spectro_is": 300, "counts_kl": 100, "batched": 200}
+DEFAULT_STEPS = {"batched": 50, "counts_kl": 50}
+
+
+def cpu_model() -> str:
+    """Host CPU model name (from /proc/cpuinfo), for the CPU-baseline record."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:  # pragma: no cover
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def _run_steps(nb, V, W, H, beta, mode, n, ctx, obj=None, trace=None, precision="fp32", inner=1):
     for t in range(n):
         o = trace[t:t + 1] if trace is not None else obj
@@ -118,9 +143,13 @@ def _run_steps(nb, V, W, H, beta, mode, n, ctx, obj=None, trace=None, precision=
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="faces_euc")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed iterations (default 50 for batched and counts_kl, else 500)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed iterations (default 5 batched, else 20)")
+    ap.add_argument("--workload", default="batched",
+                    choices=["batched", "counts_kl", "faces_euc", "spectro_is", "tiny_kl"])
+    ap.add_argument("--tto-iters", type=int, default=None,
+                    help="iterations of the time-to-objective runs (default: the workload's own count)")
     ap.add_argument("--beta", type=float, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle timing sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -137,6 +166,12 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"],
                     help="operand type of the matrix products (element-wise terms stay float32)")
     args = ap.parse_args(argv)
+    if args.steps is None:
+        args.steps = DEFAULT_STEPS.get(args.workload, 500)
+    if args.warmup is None:
+        args.warmup = 5 if args.workload == "batched" else 20
+    if args.tto_iters is None:
+        args.tto_iters = TTO_ITERS[args.workload]
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -242,8 +277,9 @@ def main(argv=None):
     torch.cuda.synchronize()
     grad_ms = e0.elapsed_time(e1) / ng
 
-    # time-to-objective: same init, objective of every iterate, T = steps
-    T = args.steps
+    # time-to-objective: same init, objective of every iterate, T = the
+    # workload's iteration count
+    T = args.tto_iters
     tto_main = time_to_objective(nb, torch, np, ctx, V, W0, H0, beta, T, args.precision, dev, args.inner_iters)
     tto_main.pop("_traces")
     # the same for every beta of the paper's experiments on this data (at most
@@ -289,7 +325,7 @@ def main(argv=None):
         out["calib_copy_bytes"] = calib_copy(torch, dev)
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds, res["joint"]["iters_per_s"])
     print(json.dumps(out), flush=True)
     ctx.close()
     return 0
@@ -348,8 +384,8 @@ def calib_copy(torch, dev):
 
 def main_batched(args, nb, synth, torch, np, dev):
     """Many uneven problems (each with its own beta and rank) updated by one
-    persistent launch per outer iteration.  A step is one outer iteration of
-    every problem; `value` is steps per second."""
+    persistent launch per outer iteration, replayed from a HIP graph.  A step is
+    one outer iteration of every problem; `value` is steps per second."""
     specs = synth.batched_specs(args.problems)
     t0 = time.perf_counter()
     probs, host = [], []
@@ -360,8 +396,13 @@ def main_batched(args, nb, synth, torch, np, dev):
                       q.beta))
     fnk = sum(q.V.shape[0] * q.V.shape[1] * q.W.shape[1] for q in host)
     fn = sum(q.V.shape[0] * q.V.shape[1] for q in host)
-    # algorithmic work of the joint step: 10 FNK (6 FNK at beta = 1), V read in both passes
-    flops = sum((6 if q.beta == 1.0 else 10) * q.V.shape[0] * q.V.shape[1] * q.W.shape[1] for q in host)
+    # algorithmic work of one outer iteration (Sec. 3.3.2, Table 3 counts of the
+    # products): joint 10 FNK (6 FNK at beta = 1: the W-step denominator is a row
+    # sum and Q = 1), alternating 12 FNK (8 FNK) with Lambda' formed again; V is
+    # read by both passes (8 FN bytes)
+    def alg_flops(mode):
+        c1, c = (6, 10) if mode == "joint" else (8, 12)
+        return sum((c1 if q.beta == 1.0 else c) * q.V.shape[0] * q.V.shape[1] * q.W.shape[1] for q in host)
     vbytes = 8 * fn
     print(f"# batched: {len(probs)} problems, sum FN = {fn:.3e}, sum FNK = {fnk:.3e} "
           f"(generated in {time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
@@ -371,12 +412,17 @@ def main_batched(args, nb, synth, torch, np, dev):
     if args.tune:
         cfg, tuned_ms = nb.batch_tune(probs, "joint", precision=args.precision, iters=3, cache=args.tune, ctx=ctx)
         print(f"# tuned: {cfg} ({tuned_ms:.3f} ms/step)", file=sys.stderr, flush=True)
-    res = {}
+    res, traces = {}, {}
     W0 = [(W.clone(), H.clone()) for _, W, H, _ in probs]
-    for mode in ("joint", "alternating"):
+
+    def reset():
         for (_, W, H, _), (Ws, Hs) in zip(probs, W0):
             W.copy_(Ws)
             H.copy_(Hs)
+
+    T = args.tto_iters
+    for mode in ("joint", "alternating"):
+        reset()
         b = nb.Batch(probs, mode, precision=args.precision, ctx=ctx, **cfg)
         obj = torch.zeros(len(probs), dtype=torch.float64, device=dev)
         for _ in range(args.warmup):
@@ -398,8 +444,21 @@ def main_batched(args, nb, synth, torch, np, dev):
         res[mode] = {"ms_per_step": ms, "steps_per_s": 1e3 / ms, "flags": fl, "graph_replay": True, **b.info()}
         print(f"# {mode}: {ms:.3f} ms/step (graph replays), flags {fl}, {b.info()}", file=sys.stderr, flush=True)
         del graph
+        # time-to-objective: T iterations from the common init, the objective of
+        # every problem's iterate 0..T recorded on the device
+        reset()
+        tr = torch.zeros((T + 1, len(probs)), dtype=torch.float64, device=dev)
+        for t in range(T + 1):
+            b.step(objectives=tr[t])
+        torch.cuda.synchronize()
+        traces[mode] = tr.cpu().numpy()
+        if b.flags(clear=True):
+            print(f"# warning: flags raised in the {mode} trajectory", file=sys.stderr, flush=True)
         b.close()
+    tto = batched_time_to_objective(np, host, traces, {m: res[m]["ms_per_step"] for m in res}, T)
+
     t = res["joint"]["ms_per_step"] * 1e-3
+    flops = alg_flops("joint")
     peak_mfma = PEAK_MFMA[args.precision]
     if flops / vbytes >= peak_mfma / PEAK_HBM:
         roof = {"bound": "mfma", "achieved": flops / t / 1e12, "peak": peak_mfma / 1e12, "unit": "TFLOP/s"}
@@ -411,6 +470,8 @@ def main_batched(args, nb, synth, torch, np, dev):
     roof["algorithmic_flops_per_launch"] = flops
     roof["algorithmic_bytes_per_launch"] = vbytes
     roof["avg_launch_us"] = res["joint"]["ms_per_step"] * 1e3
+    ta = res["alternating"]["ms_per_step"] * 1e-3
+    alt_frac = (alg_flops("alternating") / ta / peak_mfma) if roof["bound"] == "mfma" else (vbytes / ta / PEAK_HBM)
     out = {
         "metric": METRIC,
         "value": res["joint"]["steps_per_s"],
@@ -421,45 +482,54 @@ def main_batched(args, nb, synth, torch, np, dev):
         "dtype": {"fp32": "f32", "bf16": "bf16", "fp16": "f16"}[args.precision],
         "data": "synthetic",
         "config": {"workload": "batched", "problems": len(probs), "sum_FN": fn, "sum_FNK": fnk, "mode": "joint",
-                   "precision": args.precision, "objective_every_step": True, "launches_per_step": 1, **cfg},
+                   "precision": args.precision, "objective_every_step": True, "launches_per_step": 1,
+                   "graph_replay": True, **cfg},
         "problem_iterations_per_s": len(probs) * res["joint"]["steps_per_s"],
-        "alternating": {"value": res["alternating"]["steps_per_s"], "ms_per_step": res["alternating"]["ms_per_step"]},
+        "alternating": {"value": res["alternating"]["steps_per_s"], "ms_per_step": res["alternating"]["ms_per_step"],
+                        "roofline_frac": alt_frac},
+        "joint_speedup_per_iteration": res["alternating"]["ms_per_step"] / res["joint"]["ms_per_step"],
+        "time_to_objective_per_beta": tto,
         "tuned_ms": tuned_ms,
         "roofline": roof,
+        "paper_cpu_reference": PAPER_CPU_REFERENCE,
         "batch": res,
     }
     if args.calib_copy:
         out["calib_copy_bytes"] = calib_copy(torch, dev)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_batched(host, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline_batched(host, args.cpu_seconds, res["joint"]["steps_per_s"])
     print(json.dumps(out), flush=True)
     ctx.close()
     return 0
 
 
-def cpu_baseline_batched(host, budget_s):
-    """The FP64 oracle's joint iteration over the problems in order for about
-    `budget_s` seconds, scaled to one iteration of the whole batch by the share
-    of sum(FNK) covered."""
-    import numpy as np
-    import oracle
-    total = sum(q.V.shape[0] * q.V.shape[1] * q.W.shape[1] for q in host)
-    done, n = 0, 0
-    t0 = time.perf_counter()
-    for q in host:
-        V, W, H = q.V.astype(np.float64), q.W.astype(np.float64), q.H.astype(np.float64)
-        oracle.objective(V, W, H, q.beta)
-        oracle.jmm_iteration(V, W, H, q.beta)
-        done += q.V.shape[0] * q.V.shape[1] * q.W.shape[1]
-        n += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    el = time.perf_counter() - t0
-    share = done / total
-    return {"value": share / el, "unit": "iterations/s (all problems per iteration)", "cores": _blas_threads(),
-            "kind": "oracle",
-            "sample": f"{n} of {len(host)} problems, one joint iteration each (objective + update, float64 NumPy), "
-                      f"{share * 100:.1f}% of sum FNK in {el:.1f} s, scaled to the whole batch"}
+def batched_time_to_objective(np, host, traces, ms_per_iter, T):
+    """Per beta group (and for the whole batch): the summed objective of the
+    group's problems at iterates 0..T of both methods from the same init, and
+    the iterations and milliseconds (whole-batch iteration time) to reach
+    90 / 99 / 99.9 / 100 % of the larger final decrease.  Also the number of
+    per-problem objective increases."""
+    betas = np.array([q.beta for q in host])
+    groups = {str(b): betas == b for b in sorted(set(betas.tolist()))}
+    groups["all"] = np.ones_like(betas, dtype=bool)
+    out = {"T": T, "ms_per_iteration": ms_per_iter, "groups": {}}
+    for name, sel in groups.items():
+        d = {m: traces[m][:, sel].sum(axis=1) for m in traces}
+        D0 = d["joint"][0]
+        Dend = max(d["joint"][-1], d["alternating"][-1])
+        rows = {}
+        for q in (0.9, 0.99, 0.999, 1.0):
+            target = D0 - q * (D0 - Dend)
+            row = {"target": float(target)}
+            for m in d:
+                hit = np.nonzero(d[m] <= target * (1 + 1e-12))[0]
+                it = int(hit[0]) if hit.size else None
+                row[m] = {"iterations": it, "ms": (it * ms_per_iter[m]) if it is not None else None}
+            rows[str(q)] = row
+        out["groups"][name] = {"problems": int(sel.sum()), "D0": float(D0),
+                               "D_T": {m: float(d[m][-1]) for m in d}, "targets": rows}
+    out["objective_increases"] = {m: int(np.sum(traces[m][1:] > traces[m][:-1] * (1 + 1e-12))) for m in traces}
+    return out
 
 
 def _blas_threads():
@@ -470,31 +540,83 @@ def _blas_threads():
         return len(os.sched_getaffinity(0))
 
 
-def cpu_baseline(p, budget_s):
-    """The FP64 oracle's joint iteration (with the objective, as on the GPU) timed
-    on the host cores for about `budget_s` seconds from the same init."""
+def _timed_oracle(fn, budget_s, threads=None):
+    """Runs fn() repeatedly for about budget_s seconds (at least once), with the
+    BLAS pool limited to `threads` when given; returns (calls, seconds, threads used)."""
+    from contextlib import nullcontext
+    try:
+        from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(limits=threads) if threads else nullcontext()
+    except Exception:  # pragma: no cover
+        lim = nullcontext()
+    with lim:
+        used = _blas_threads()
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            fn()
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s:
+                break
+    return n, el, used
+
+
+def cpu_baseline_batched(host, budget_s, gpu_value):
+    """The FP64 oracle's joint iteration (objective + update + normalization) on a
+    fixed random sample of 16 of the problems, timed with all host cores and with
+    one thread (about budget_s / 2 seconds each), scaled to one iteration of the
+    whole batch by the sample's share of sum(FNK)."""
     import numpy as np
     import oracle
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
-    except Exception:  # pragma: no cover
-        threads = len(os.sched_getaffinity(0))
+    rng = np.random.default_rng(0)
+    idx = sorted(rng.choice(len(host), size=min(16, len(host)), replace=False).tolist())
+    sample = [(host[i].V.astype(np.float64), host[i].W.astype(np.float64), host[i].H.astype(np.float64),
+               host[i].beta) for i in idx]
+    total = sum(q.V.shape[0] * q.V.shape[1] * q.W.shape[1] for q in host)
+    share = sum(V.shape[0] * V.shape[1] * W.shape[1] for V, W, _, _ in sample) / total
+
+    def sweep():
+        for V, W, H, beta in sample:
+            oracle.objective(V, W, H, beta)
+            oracle.jmm_iteration(V, W, H, beta)
+
+    n_all, el_all, th_all = _timed_oracle(sweep, budget_s / 2)
+    n_one, el_one, _ = _timed_oracle(sweep, budget_s / 2, threads=1)
+    v_all = share * n_all / el_all
+    v_one = share * n_one / el_one
+    desc = (f"problems {idx} of {len(host)} ({share * 100:.2f}% of sum FNK), one joint iteration each "
+            f"(objective + update + normalization, float64 NumPy); {n_all} sweeps in {el_all:.1f} s on "
+            f"{th_all} threads and {n_one} in {el_one:.1f} s on 1 thread; iterations/s of the whole batch "
+            f"EXTRAPOLATED from the sample by its share of sum FNK")
+    return {"value": v_all, "unit": "iterations/s (all problems per iteration, extrapolated)", "cores": th_all,
+            "kind": "oracle", "sample": desc, "one_thread": {"value": v_one, "cores": 1},
+            "cpu_model": cpu_model(), "host_cores_available": len(os.sched_getaffinity(0)),
+            "gpu_over_cpu": gpu_value / v_all}
+
+
+def cpu_baseline(p, budget_s, gpu_value):
+    """The FP64 oracle's joint iteration (with the objective, as on the GPU) timed
+    on the host cores from the benchmark's init, for about budget_s / 2 seconds
+    with all threads and as long with one thread."""
+    import numpy as np
+    import oracle
     V = p.V.astype(np.float64)
-    W = p.W.astype(np.float64)
-    H = p.H.astype(np.float64)
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        oracle.objective(V, W, H, p.beta)
-        W, H = oracle.jmm_iteration(V, W, H, p.beta)
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or n >= 100000:
-            break
-    return {"value": n / el, "unit": "iterations/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} joint iterations (objective + update + normalization, float64 NumPy) of the "
-                      f"{p.name} workload from the benchmark's init, {el:.1f} s"}
+    state = {"W": p.W.astype(np.float64), "H": p.H.astype(np.float64)}
+
+    def one():
+        oracle.objective(V, state["W"], state["H"], p.beta)
+        state["W"], state["H"] = oracle.jmm_iteration(V, state["W"], state["H"], p.beta)
+
+    n_all, el_all, th_all = _timed_oracle(one, budget_s / 2)
+    state.update(W=p.W.astype(np.float64), H=p.H.astype(np.float64))
+    n_one, el_one, _ = _timed_oracle(one, budget_s / 2, threads=1)
+    return {"value": n_all / el_all, "unit": "iterations/s", "cores": th_all, "kind": "oracle",
+            "sample": f"{n_all} joint iterations (objective + update + normalization, float64 NumPy) of the "
+                      f"{p.name} workload from the benchmark's init in {el_all:.1f} s on {th_all} threads; "
+                      f"{n_one} in {el_one:.1f} s on 1 thread",
+            "one_thread": {"value": n_one / el_one, "cores": 1}, "cpu_model": cpu_model(),
+            "host_cores_available": len(os.sched_getaffinity(0)), "gpu_over_cpu": gpu_value / (n_all / el_all)}
 
 
 if __name__ == "__main__":

@@ -19,8 +19,11 @@
  *    ratio, a non-finite objective) sets sticky device flags read by nmf_get_flags.
  *  - Device scalars (double* d_objective ...) are caller-owned device memory.
  *  - A context owns a workspace on one device.  It grows on demand (a blocking
- *    reallocation) unless the stream is being captured, in which case a too-small
- *    workspace is NMF_ERR_WORKSPACE; call nmf_reserve first to size it once.
+ *    reallocation) until the first call recorded into a stream capture.  From
+ *    then on it never moves, since a captured graph may point into it: a call
+ *    (captured or not, nmf_reserve included) that needs a larger workspace
+ *    returns NMF_ERR_WORKSPACE.  Call nmf_reserve first to size it once for
+ *    every shape a graph will use; use another context for larger shapes.
  *  - A context must not be used by two host threads at the same time, and two
  *    calls on different streams through one context must not overlap in time
  *    (they share the workspace).
@@ -43,7 +46,8 @@ typedef enum {
   NMF_ERR_SHAPE = 2,       /* F, N or K < 1, or a leading dimension too small */
   NMF_ERR_BETA = 3,        /* beta or kappa not finite, kappa < 0 */
   NMF_ERR_ALIAS = 4,       /* two of the matrices overlap in memory */
-  NMF_ERR_WORKSPACE = 5,   /* workspace too small while the stream is captured */
+  NMF_ERR_WORKSPACE = 5,   /* workspace too small while the stream is captured, or
+                              after a call was captured (the workspace no longer moves) */
   NMF_ERR_HIP = 6,         /* a HIP runtime call failed */
   NMF_ERR_UNSUPPORTED = 7, /* K > 128, unknown precision, an unsupported inner_iters > 1 case */
   NMF_ERR_ARG = 8,         /* other invalid argument (mode, opts field) */
@@ -69,8 +73,11 @@ typedef enum {
 /* sticky numeric flags (nmf_get_flags) */
 #define NMF_FLAG_NONFINITE 1u /* an update ratio num/den was non-finite or den <= 0 */
 #define NMF_FLAG_DOMAIN 2u    /* nmf_beta_validate found data outside the domain */
-#define NMF_FLAG_BARRIER 4u   /* a single-launch step gave up waiting at a grid barrier
-                                 (results of that call are invalid) */
+#define NMF_FLAG_BARRIER 4u   /* a batched step's work item gave up waiting for its
+                                 problem's previous phase (bounded poll); the results
+                                 of that launch are invalid.  The single-launch path
+                                 synchronizes with cooperative grid barriers, which
+                                 do not give up, and never sets it. */
 #define NMF_FLAG_RANGE 8u     /* NMF_FP16 mode: an operand of a float16 product was
                                  outside the float16 range or not finite (the step's
                                  result is then not meaningful) */
@@ -157,8 +164,10 @@ nmf_status nmf_beta_objective(nmf_ctx_t ctx, void* stream, int64_t F, int64_t N,
                               const float* V, int64_t ldv, const float* W, int64_t ldw,
                               const float* H, int64_t ldh, double beta, float kappa, double* d_out);
 
-/* Gradient of D_beta(V + kappa | WH + kappa) w.r.t. W and H, times `scale`:
- *   E = (WH + kappa)^(beta-2) .* (WH - V),  dW = scale * E H^T,  dH = scale * W^T E.
+/* Gradient of D_beta(V + kappa | WH + kappa) w.r.t. W and H, times `scale` and,
+ * when d_scale (a device double) is not NULL, times *d_scale read on the device
+ * (so an upstream gradient that lives on the device needs no host sync):
+ *   E = (WH + kappa)^(beta-2) .* (WH - V),  dW = s * E H^T,  dH = s * W^T E.
  * (E is the derivative of d_beta in its second argument; these are the bracketed
  * terms of the KKT residuals of Sec. 4.1.5.)  dW is F x K (ld lddw), dH is K x N
  * (ld lddh), both caller-owned device float32.  d_objective (nullable) receives
@@ -166,7 +175,8 @@ nmf_status nmf_beta_objective(nmf_ctx_t ctx, void* stream, int64_t F, int64_t N,
 nmf_status nmf_beta_grad(nmf_ctx_t ctx, void* stream, int64_t F, int64_t N, int64_t K,
                          const float* V, int64_t ldv, const float* W, int64_t ldw,
                          const float* H, int64_t ldh, double beta, float kappa, double scale,
-                         float* dW, int64_t lddw, float* dH, int64_t lddh, double* d_objective);
+                         const double* d_scale, float* dW, int64_t lddw, float* dH, int64_t lddh,
+                         double* d_objective);
 
 /* Scans V, W, H once and sets NMF_FLAG_DOMAIN if V has a negative or non-finite
  * entry, W or H a non-positive or non-finite entry, or (beta <= 0, kappa == 0) V

@@ -105,7 +105,7 @@ def lib() -> ctypes.CDLL:
         L.nmf_beta_objective.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
                                          _dbl, _flt, _vp]
         L.nmf_beta_grad.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
-                                    _dbl, _flt, _dbl, _vp, _i64, _vp, _i64, _vp]
+                                    _dbl, _flt, _dbl, _vp, _vp, _i64, _vp, _i64, _vp]
         L.nmf_beta_validate.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
                                         _dbl, _flt]
         L.nmf_get_flags.argtypes = [_vp, _vp, ctypes.POINTER(_u32), _i32]
@@ -224,9 +224,22 @@ def _mat(t, name, writable=False):
         raise TypeError(f"{name} must be float32")
     if not t.is_cuda:
         raise ValueError(f"{name} must be a device (cuda) tensor")
-    if t.dim() != 2 or t.stride(1) != 1:
+    if t.dim() != 2 or (t.stride(1) != 1 and t.shape[1] > 1):
         raise ValueError(f"{name} must be 2-D with unit column stride")
-    return t.data_ptr(), max(t.stride(0), t.shape[1])
+    if t.shape[0] > 1 and t.stride(0) < t.shape[1]:
+        # overlapping rows (expand, as_strided): no valid leading dimension
+        raise ValueError(f"{name} has overlapping rows (row stride {t.stride(0)} < {t.shape[1]} columns)")
+    return t.data_ptr(), (t.stride(0) if t.shape[0] > 1 else t.shape[1])
+
+
+def _dev_f64(t, name, n=1):
+    """Device pointer of a float64 cuda tensor with at least n contiguous entries."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda or t.numel() < n:
+        raise ValueError(f"{name} must be a float64 device tensor with at least {n} entries")
+    if n > 1 and not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
 
 
 def _stream(stream):
@@ -253,7 +266,8 @@ def step(V, W, H, beta: float, mode="joint", *, precision="fp32", kappa: float =
     """One outer iteration in place on W and H (see nmf_beta_step).
 
     ``exponent``: "mm" (gamma(beta)) or "one" (gamma = 1 for every beta).
-    ``inner_iters``: sub-iterations L (L > 1: alternating mode, float32).
+    ``inner_iters``: sub-iterations L (Algorithm 1 or 2; joint mode with L > 1
+    needs float32 products and F N <= 2^28).
     ``objective_out``: optional float64 device tensor (1 element) receiving the
     objective at the entry iterate.
     """
@@ -266,9 +280,7 @@ def step(V, W, H, beta: float, mode="joint", *, precision="fp32", kappa: float =
     if W.shape[0] != F or H.shape != (K, N):
         raise ValueError("shape mismatch: V (F,N), W (F,K), H (K,N)")
     o = _opts(precision, kappa, inner_iters, normalize, exponent)
-    pobj = None
-    if objective_out is not None:
-        pobj = objective_out.data_ptr()
+    pobj = _dev_f64(objective_out, "objective_out") if objective_out is not None else None
     st = lib().nmf_beta_step(_ctx(ctx), _stream(stream), F, N, K, pv, ldv, pw, ldw, ph, ldh,
                              float(beta), m, ctypes.byref(o), pobj)
     _check(st, "nmf_beta_step")
@@ -288,9 +300,12 @@ def objective(V, W, H, beta: float, *, kappa: float = 0.0, out=None, stream=None
     return out
 
 
-def grad(V, W, H, beta: float, *, kappa: float = 0.0, scale: float = 1.0, dW=None, dH=None,
+def grad(V, W, H, beta: float, *, kappa: float = 0.0, scale: float = 1.0, scale_dev=None, dW=None, dH=None,
          objective_out=None, stream=None, ctx=None):
-    """(dW, dH) = scale * gradient of D_beta w.r.t. (W, H); see nmf_beta_grad."""
+    """(dW, dH) = scale * gradient of D_beta w.r.t. (W, H); see nmf_beta_grad.
+
+    ``scale_dev``: optional float64 device tensor (1 entry) multiplying the
+    gradient as well, read on the device (no host synchronization)."""
     import torch
     pv, ldv = _mat(V, "V")
     pw, ldw = _mat(W, "W")
@@ -301,9 +316,10 @@ def grad(V, W, H, beta: float, *, kappa: float = 0.0, scale: float = 1.0, dW=Non
         dH = torch.empty_like(H)
     pdw, lddw = _mat(dW, "dW")
     pdh, lddh = _mat(dH, "dH")
-    pobj = objective_out.data_ptr() if objective_out is not None else None
+    pobj = _dev_f64(objective_out, "objective_out") if objective_out is not None else None
+    psc = _dev_f64(scale_dev, "scale_dev") if scale_dev is not None else None
     st = lib().nmf_beta_grad(_ctx(ctx), _stream(stream), V.shape[0], V.shape[1], W.shape[1], pv, ldv, pw, ldw,
-                             ph, ldh, float(beta), float(kappa), float(scale), pdw, lddw, pdh, lddh, pobj)
+                             ph, ldh, float(beta), float(kappa), float(scale), psc, pdw, lddw, pdh, lddh, pobj)
     _check(st, "nmf_beta_grad")
     return dW, dH
 
@@ -330,8 +346,9 @@ def _make_autograd():
         """D_beta(V + kappa | WH + kappa) with a GPU backward w.r.t. W and H.
 
         forward(V, W, H, beta, kappa) returns a 0-d float64 tensor; the backward
-        calls nmf_beta_grad with scale = the incoming gradient.  No gradient is
-        returned for V, beta or kappa.
+        calls nmf_beta_grad with the incoming gradient as a device scale (no
+        host synchronization, so the backward can be captured in a graph).  No
+        gradient is returned for V, beta or kappa.
         """
 
         @staticmethod
@@ -346,9 +363,9 @@ def _make_autograd():
         @staticmethod
         def backward(ctx_, g):
             V, W, H = ctx_.saved_tensors
-            scale = float(g.item())
+            gd = g.detach().reshape(1).to(device=W.device, dtype=torch.float64).contiguous()
             dW, dH = grad(V.detach().contiguous(), W.detach().contiguous(), H.detach().contiguous(),
-                          ctx_.beta, kappa=ctx_.kappa, scale=scale)
+                          ctx_.beta, kappa=ctx_.kappa, scale_dev=gd)
             return None, dW.to(W.dtype), dH.to(H.dtype), None, None
 
     return BetaDivergence

@@ -31,6 +31,9 @@ struct nmf_ctx_s {
   int num_cus = 256;
   char* ws = nullptr;  // workspace base
   size_t ws_bytes = 0;
+  // A call was recorded into a stream capture: a graph may hold kernels that
+  // point into the workspace, so it is never moved again (growth is refused).
+  bool captured = false;
   int target_blocks = 0;  // 0: cost model
   int min_tiles = 1;
   int path = NMF_PATH_AUTO;
@@ -299,12 +302,15 @@ nmf_status check_opts(const nmf_step_opts* o) {
 
 nmf_status hip_status(hipError_t e) { return e == hipSuccess ? NMF_OK : NMF_ERR_HIP; }
 
-// Ensures the workspace holds `bytes`; reallocates (blocking) unless capturing.
+// Ensures the workspace holds `bytes`; reallocates (blocking) unless the stream
+// is being captured or a call was captured before (a graph may still point
+// into the current workspace, so it must stay where it is).
 nmf_status ensure_ws(nmf_ctx_s* c, hipStream_t s, size_t bytes) {
-  if (c->ws_bytes >= bytes) return NMF_OK;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess) return NMF_ERR_HIP;
-  if (cs != hipStreamCaptureStatusNone) return NMF_ERR_WORKSPACE;
+  if (cs != hipStreamCaptureStatusNone) c->captured = true;
+  if (c->ws_bytes >= bytes) return NMF_OK;
+  if (cs != hipStreamCaptureStatusNone || c->captured) return NMF_ERR_WORKSPACE;
   if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
   uint32_t flags_keep = 0;
   if (c->ws) {
@@ -563,7 +569,7 @@ const char* nmf_status_string(nmf_status s) {
     case NMF_ERR_SHAPE: return "NMF_ERR_SHAPE: bad size or leading dimension";
     case NMF_ERR_BETA: return "NMF_ERR_BETA: beta or kappa not finite (or kappa < 0)";
     case NMF_ERR_ALIAS: return "NMF_ERR_ALIAS: matrices overlap";
-    case NMF_ERR_WORKSPACE: return "NMF_ERR_WORKSPACE: workspace too small during stream capture";
+    case NMF_ERR_WORKSPACE: return "NMF_ERR_WORKSPACE: workspace too small during or after stream capture";
     case NMF_ERR_HIP: return "NMF_ERR_HIP: HIP runtime error";
     case NMF_ERR_UNSUPPORTED: return "NMF_ERR_UNSUPPORTED: unsupported size or option";
     case NMF_ERR_ARG: return "NMF_ERR_ARG: invalid argument";
@@ -737,7 +743,8 @@ nmf_status nmf_beta_objective(nmf_ctx_t c, void* stream, int64_t F, int64_t N, i
 
 nmf_status nmf_beta_grad(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K, const float* V, int64_t ldv,
                          const float* W, int64_t ldw, const float* H, int64_t ldh, double beta, float kappa,
-                         double scale, float* dW, int64_t lddw, float* dH, int64_t lddh, double* d_objective) {
+                         double scale, const double* d_scale, float* dW, int64_t lddw, float* dH, int64_t lddh,
+                         double* d_objective) {
   if (!c || !dW || !dH) return NMF_ERR_NULL;
   nmf_status st = check_mats(F, N, K, V, ldv, W, ldw, H, ldh);
   if (st != NMF_OK) return st;
@@ -782,9 +789,10 @@ nmf_status nmf_beta_grad(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   e = launch_sweep_cols(bc, p.KB, KIND_GRAD, false, false, p.col_blocks * p.f_groups, s, ca);
   if (e != hipSuccess) return NMF_ERR_HIP;
   const int gw = (int)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(F * K, kBlock)));
-  if ((e = launch_grad_w(p.KB, gw, s, ra.pnum, (int)F, (int)K, p.n_groups, scale, dW, lddw)) != hipSuccess)
+  if ((e = launch_grad_w(p.KB, gw, s, ra.pnum, (int)F, (int)K, p.n_groups, scale, d_scale, dW, lddw)) != hipSuccess)
     return NMF_ERR_HIP;
-  if ((e = launch_grad_h(p.KB, (int)cdiv(N, kTile), s, ca.pnum, (int)N, (int)K, p.f_groups, scale, dH, lddh)) !=
+  if ((e = launch_grad_h(p.KB, (int)cdiv(N, kTile), s, ca.pnum, (int)N, (int)K, p.f_groups, scale, d_scale, dH,
+                         lddh)) !=
       hipSuccess)
     return NMF_ERR_HIP;
   if (d_objective) return hip_status(launch_finalize_objective(s, ra.pobj, sw_grid, d_objective, flags_ptr(c)));

@@ -8,8 +8,10 @@
 //                 outer iteration, as in Algorithm 2; alternating mode forms
 //                 Lambda' = W_new H~ again, as in Algorithm 1)
 //   4. H update  (partials reduced; normalization; objective total)
-// separated by grid barriers.  Removing three launches and keeping the
-// reductions on the whole chip is what makes small and medium problems fast.
+// separated by grid barriers.  It replaces three launches by grid barriers; on
+// MI355X the barriers cost more than the launches they replace, so the default
+// path selection uses the four-launch streaming path, and this one is kept as an
+// opt-in alternative (same results to rounding).
 #include <hip/hip_cooperative_groups.h>
 
 #include "nmf_device.h"

@@ -128,10 +128,11 @@ hipError_t launch_sweep_cols_lp(int prec, int bc, int kb, bool dual, bool pq, in
 hipError_t launch_update_w(int kb, int grid, hipStream_t s, const UpdateWArgs& a);
 hipError_t launch_update_h(int kb, int grid, hipStream_t s, const UpdateHArgs& a);
 hipError_t launch_finalize_objective(hipStream_t s, const double* pobj, int n, double* out, unsigned* flags);
+// dscale (nullable, device): the gradient is multiplied by scale * *dscale
 hipError_t launch_grad_w(int kb, int grid, hipStream_t s, const float* pnum, int F, int K, int n_groups,
-                         double scale, float* dW, int64_t lddw);
+                         double scale, const double* dscale, float* dW, int64_t lddw);
 hipError_t launch_grad_h(int kb, int grid, hipStream_t s, const float* pnum, int N, int K, int f_groups,
-                         double scale, float* dH, int64_t lddh);
+                         double scale, const double* dscale, float* dH, int64_t lddh);
 hipError_t launch_transpose(hipStream_t s, const float* W, int64_t ldw, int F, int K, int KP, float* WT,
                             int64_t ldt, float* Wp);
 // Fused single-launch outer iteration (cooperative; grid barriers between the

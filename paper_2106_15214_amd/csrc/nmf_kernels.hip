@@ -153,8 +153,10 @@ __global__ __launch_bounds__(kBlock) void finalize_objective_kernel(const double
 
 template <int KB>
 __global__ __launch_bounds__(kBlock) void grad_w_kernel(const float* pnum, int F, int K, int n_groups,
-                                                        double scale, float* dW, int64_t lddw) {
+                                                        double scale, const double* dscale, float* dW,
+                                                        int64_t lddw) {
   constexpr int KP = 32 * KB;
+  if (dscale) scale *= *dscale;
   const int64_t total = (int64_t)F * K;
   for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += (int64_t)gridDim.x * kBlock) {
     const int f = (int)(e / K), k = (int)(e % K);
@@ -166,8 +168,10 @@ __global__ __launch_bounds__(kBlock) void grad_w_kernel(const float* pnum, int F
 
 template <int KB>
 __global__ __launch_bounds__(kBlock) void grad_h_kernel(const float* pnum, int N, int K, int f_groups,
-                                                        double scale, float* dH, int64_t lddh) {
+                                                        double scale, const double* dscale, float* dH,
+                                                        int64_t lddh) {
   constexpr int KP = 32 * KB;
+  if (dscale) scale *= *dscale;
   __shared__ float S[KP * 33];
   const int n0 = blockIdx.x * kTile;
   for (int e = threadIdx.x; e < kTile * KP; e += kBlock) {
@@ -244,22 +248,22 @@ hipError_t launch_finalize_objective(hipStream_t s, const double* pobj, int n, d
 }
 
 hipError_t launch_grad_w(int kb, int grid, hipStream_t s, const float* pnum, int F, int K, int n_groups,
-                         double scale, float* dW, int64_t lddw) {
+                         double scale, const double* dscale, float* dW, int64_t lddw) {
   switch (kb) {
-    case 1: hipLaunchKernelGGL(grad_w_kernel<1>, dim3(grid), dim3(kBlock), 0, s, pnum, F, K, n_groups, scale, dW, lddw); break;
-    case 2: hipLaunchKernelGGL(grad_w_kernel<2>, dim3(grid), dim3(kBlock), 0, s, pnum, F, K, n_groups, scale, dW, lddw); break;
-    case 4: hipLaunchKernelGGL(grad_w_kernel<4>, dim3(grid), dim3(kBlock), 0, s, pnum, F, K, n_groups, scale, dW, lddw); break;
+    case 1: hipLaunchKernelGGL(grad_w_kernel<1>, dim3(grid), dim3(kBlock), 0, s, pnum, F, K, n_groups, scale, dscale, dW, lddw); break;
+    case 2: hipLaunchKernelGGL(grad_w_kernel<2>, dim3(grid), dim3(kBlock), 0, s, pnum, F, K, n_groups, scale, dscale, dW, lddw); break;
+    case 4: hipLaunchKernelGGL(grad_w_kernel<4>, dim3(grid), dim3(kBlock), 0, s, pnum, F, K, n_groups, scale, dscale, dW, lddw); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_grad_h(int kb, int grid, hipStream_t s, const float* pnum, int N, int K, int f_groups,
-                         double scale, float* dH, int64_t lddh) {
+                         double scale, const double* dscale, float* dH, int64_t lddh) {
   switch (kb) {
-    case 1: hipLaunchKernelGGL(grad_h_kernel<1>, dim3(grid), dim3(kBlock), 0, s, pnum, N, K, f_groups, scale, dH, lddh); break;
-    case 2: hipLaunchKernelGGL(grad_h_kernel<2>, dim3(grid), dim3(kBlock), 0, s, pnum, N, K, f_groups, scale, dH, lddh); break;
-    case 4: hipLaunchKernelGGL(grad_h_kernel<4>, dim3(grid), dim3(kBlock), 0, s, pnum, N, K, f_groups, scale, dH, lddh); break;
+    case 1: hipLaunchKernelGGL(grad_h_kernel<1>, dim3(grid), dim3(kBlock), 0, s, pnum, N, K, f_groups, scale, dscale, dH, lddh); break;
+    case 2: hipLaunchKernelGGL(grad_h_kernel<2>, dim3(grid), dim3(kBlock), 0, s, pnum, N, K, f_groups, scale, dscale, dH, lddh); break;
+    case 4: hipLaunchKernelGGL(grad_h_kernel<4>, dim3(grid), dim3(kBlock), 0, s, pnum, N, K, f_groups, scale, dscale, dH, lddh); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

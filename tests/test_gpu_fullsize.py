@@ -1,21 +1,21 @@
 """GPU parity at the benchmark workloads' full sizes, against the FP64 oracle.
 
 * The 20000 x 10000 (K = 50, beta = 1) count workload: one outer iteration on
-  the whole matrix, every entry of W and H compared, and the objective and
-  gradient calls.  This is the size at which the W pass streams V with the
+  the whole matrix, every entry of W and H compared entry-wise (and in
+  Frobenius norm), and the objective and gradient calls.  This is the size at which the W pass streams V with the
   nontemporal hint (V is 800 MB), the launch configuration the benchmark times.
 * A joint step just above 2^28 entries of V (16449 x 16353, ragged edges,
   beta = 0.5): beyond that size the joint step does not keep the P and Q tiles,
   and its H pass forms Lambda~ and its powers again from V, W~, H~.  Float32
   and bfloat16 products, every entry of W and H compared.
 * The 512-problem batched workload at full size, in one persistent launch:
-  sampled problems (the largest, the smallest and evenly spaced ones) compared
-  with the oracle problem by problem; every problem's objective must be finite.
+  every problem compared with the oracle, problem by problem.
 
-Gates as in the other parity tests: float32 products W, H <= 1e-5 relative
-(Frobenius), objective <= 1e-6; bfloat16 products W, H <= 3e-3 and the
-objective within max(1e-6 D, 2^-14 S) (S: first-order change of D under a
-2^-14 relative change of every Lambda entry).
+Gates as in the other parity tests (tests/gates.py): float32 products W, H
+<= 1e-5 relative (Frobenius) and <= 1e-4 entry-wise, objective <= 1e-6;
+bfloat16 products W, H <= 3e-3 and 4 u (2 + |beta - 2|) entry-wise
+(u = 2^-9), the objective within max(1e-6 D, 2^-14 S) (S: first-order change
+of D under a 2^-14 relative change of every Lambda entry).
 """
 import numpy as np
 import pytest
@@ -24,6 +24,7 @@ import torch
 import oracle as O
 import synth
 import paper_2106_15214_amd as nb
+from gates import check_pair
 
 pytestmark = pytest.mark.gpu
 
@@ -39,10 +40,6 @@ def ctx():
 
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
-
-
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
 
 
 @pytest.fixture(scope="module")
@@ -74,14 +71,10 @@ def test_count_workload_full_size(counts, mode, precision):
     d0 = O.objective(V64, W64, H64, p.beta)
     step = O.jmm_iteration if mode == "joint" else O.bmm_iteration
     Wr, Hr = step(V64, W64, H64, p.beta)
-    eW, eH = rel(Wg, Wr), rel(Hg, Hr)
+    check_pair(Wg, Hg, Wr, Hr, precision, p.beta, tag=f"counts {mode} {precision}")
     if precision == "fp32":
-        assert eW <= 1e-5, f"W rel err {eW:.3e}"
-        assert eH <= 1e-5, f"H rel err {eH:.3e}"
         assert abs(dg - d0) <= 1e-6 * abs(d0), f"objective {dg} vs {d0}"
     else:
-        assert eW <= 3e-3, f"W rel err {eW:.3e}"
-        assert eH <= 3e-3, f"H rel err {eH:.3e}"
         tol = max(1e-6 * abs(d0), lowp_obj_bound(V64, W64, H64, p.beta))
         assert abs(dg - d0) <= tol, f"objective err {abs(dg - d0):.3e} > {tol:.3e}"
 
@@ -110,15 +103,25 @@ def test_count_workload_full_size_objective_and_gradient(counts):
     assert np.linalg.norm(dH - gH) <= 1e-5 * sH
 
 
-@pytest.mark.timeout(600)
-@pytest.mark.parametrize("tiles", [0, 128])
-def test_batched_workload_full_size_sampled(tiles):
-    specs = synth.batched_specs()
-    print(f"[fullsize] batched {len(specs)} problems tiles_per_item={tiles}", flush=True)
-    host = []
-    for sp in specs:
+@pytest.fixture(scope="module")
+def batched_full():
+    """The 512 problems and the oracle's joint step of each (computed once)."""
+    host, ref = [], []
+    for i, sp in enumerate(synth.batched_specs()):
+        if i % 64 == 0:
+            print(f"[fullsize] oracle steps of the batched workload: problem {i}", flush=True)
         q = synth.make_batched_problem(sp)
         host.append((q.V, q.W, q.H, q.beta))
+        V64, W64, H64 = q.V.astype(np.float64), q.W.astype(np.float64), q.H.astype(np.float64)
+        ref.append(O.jmm_iteration(V64, W64, H64, q.beta) + (O.objective(V64, W64, H64, q.beta),))
+    return host, ref
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("tiles", [0, 128])
+def test_batched_workload_full_size_all_problems(batched_full, tiles):
+    host, ref = batched_full
+    print(f"[fullsize] batched {len(host)} problems tiles_per_item={tiles}", flush=True)
     d = [(dev(V), dev(W), dev(H), b) for V, W, H, b in host]
     b = nb.Batch(d, "joint", tiles_per_item=tiles, ctx=ctx())
     print(f"[fullsize] batched {b.info()}", flush=True)
@@ -129,19 +132,14 @@ def test_batched_workload_full_size_sampled(tiles):
     b.close()
     ob = obj.cpu().numpy()
     assert np.all(np.isfinite(ob))
-    size = [V.size for V, _, _, _ in host]
-    pick = {int(np.argmax(size)), int(np.argmin(size))} | set(range(0, len(host), 43))
-    for i in sorted(pick):
-        V, W, H, beta = host[i]
-        V64, W64, H64 = V.astype(np.float64), W.astype(np.float64), H.astype(np.float64)
-        if W.shape[1] >= min(V.shape):
-            continue  # exact fits have no unique next iterate to compare
-        d0 = O.objective(V64, W64, H64, beta)
-        Wr, Hr = O.jmm_iteration(V64, W64, H64, beta)
-        eW = rel(d[i][1].cpu().numpy(), Wr)
-        eH = rel(d[i][2].cpu().numpy(), Hr)
-        assert eW <= 1e-5 and eH <= 1e-5, (i, V.shape, W.shape[1], beta, eW, eH)
+    worst = [0.0, 0.0]
+    for i, ((V, W, H, beta), (Wr, Hr, d0)) in enumerate(zip(host, ref)):
+        assert W.shape[1] < min(V.shape)  # no exact fit: the next iterate is unique
+        (fw, ew), (fh, eh) = check_pair(d[i][1].cpu().numpy(), d[i][2].cpu().numpy(), Wr, Hr,
+                                        tag=f"problem {i} {V.shape} K={W.shape[1]} beta={beta}")
+        worst = [max(worst[0], fw, fh), max(worst[1], ew, eh)]
         assert abs(ob[i] - d0) <= 1e-6 * abs(d0), (i, ob[i], d0)
+    print(f"[fullsize] batched worst Frobenius {worst[0]:.2e}, entry-wise {worst[1]:.2e}", flush=True)
 
 
 @pytest.fixture(scope="module")
@@ -169,9 +167,6 @@ def test_joint_step_above_kept_pq_limit(above_pq_limit, precision):
     V64, W64, H64 = p.V.astype(np.float64), p.W.astype(np.float64), p.H.astype(np.float64)
     d0 = O.objective(V64, W64, H64, beta)
     Wr, Hr = O.jmm_iteration(V64, W64, H64, beta)
-    eW, eH = rel(Wg, Wr), rel(Hg, Hr)
-    tol = 1e-5 if precision == "fp32" else 3e-3
-    assert eW <= tol, f"W rel err {eW:.3e}"
-    assert eH <= tol, f"H rel err {eH:.3e}"
+    check_pair(Wg, Hg, Wr, Hr, precision, beta, tag=f"above P/Q limit {precision}")
     otol = 1e-6 * abs(d0) if precision == "fp32" else max(1e-6 * abs(d0), lowp_obj_bound(V64, W64, H64, beta))
     assert abs(dg - d0) <= otol, f"objective err {abs(dg - d0):.3e} > {otol:.3e}"
