@@ -28,6 +28,10 @@ Contents, each following the passage cited in its docstring:
 * ``joint_auxiliary``                   -- Sec. 3.1, Table 1, eqs. (simplif) and (jointG)
 * ``relative_decrease``                 -- Sec. 4.1.2 stopping criterion
 * ``stop_iteration``                    -- Sec. 4.1.2: first outer iteration where it fires
+* ``kl_sparse_objective`` /
+  ``kl_sparse_iteration``               -- beta = 1 on a sparse V given by its nonzeros (CSR):
+                                           the Table 2 (Sec. 3.3.1) KL updates of both methods,
+                                           for count data such as the play counts of Sec. 4.4
 
 Smoothing constant kappa (Sec. 4.1.3): the data V is replaced by V + kappa and
 every product WH (or W~H~) by WH + kappa.  The paper gives no value; the
@@ -60,6 +64,8 @@ __all__ = [
     "joint_auxiliary",
     "relative_decrease",
     "stop_iteration",
+    "kl_sparse_objective",
+    "kl_sparse_iteration",
 ]
 
 
@@ -340,3 +346,83 @@ def stop_iteration(trace, eps: float = 1e-5):
         if relative_decrease(float(trace[t - 1]), float(trace[t])) <= eps:
             return t
     return None
+
+
+# ---------------------------------------------------------------------------
+# beta = 1 (Kullback-Leibler) with V stored by its nonzeros
+# ---------------------------------------------------------------------------
+def _csr_rows(row_ptr, col_idx, vals):
+    """(f, columns, values) of every row of a CSR matrix, in row order."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    for f in range(len(row_ptr) - 1):
+        a, b = row_ptr[f], row_ptr[f + 1]
+        yield f, np.asarray(col_idx[a:b], dtype=np.int64), _f64(vals[a:b])
+
+
+def kl_sparse_objective(row_ptr, col_idx, vals, W, H) -> float:
+    """D_1(V | WH) of eqs. (obj_fct), (beta-div) at beta = 1 for V given in CSR form.
+
+    Every entry contributes [WH]_fn (the y term of d_1); an entry with v > 0
+    adds v log(v / [WH]_fn) - v, and v = 0 adds nothing more (the limit
+    0 log 0 = 0).  So only the stored nonzeros need [WH]_fn, and the sum of all
+    [WH]_fn is sum_k (sum_f w_fk)(sum_n h_kn).
+    """
+    W = _f64(W)
+    H = _f64(H)
+    total = float(np.sum(W.sum(axis=0) * H.sum(axis=1)))
+    for f, cols, v in _csr_rows(row_ptr, col_idx, vals):
+        keep = v > 0
+        cols, v = cols[keep], v[keep]
+        lam = H[:, cols].T @ W[f]                      # [WH]_fn at the row's nonzeros
+        total += float(np.sum(v * np.log(v / lam) - v))
+    return total
+
+
+def _kl_ratio_terms(row_ptr, col_idx, vals, Wl, Hl):
+    """P = V / (Wl Hl) at the stored entries, in CSR order (0 where v = 0)."""
+    out = []
+    for f, cols, v in _csr_rows(row_ptr, col_idx, vals):
+        lam = Hl[:, cols].T @ Wl[f]
+        out.append(v / lam)
+    return out
+
+
+def kl_sparse_iteration(row_ptr, col_idx, vals, W, H, mode: str = "joint", norm: bool = True):
+    """One outer iteration at beta = 1 (gamma = 1) for V given in CSR form.
+
+    Table 2 (Sec. 3.3.1), KL row, with V / (WH) needed only where v != 0:
+
+    * both methods, W step: numW = P H~^T with P = V / (W~ H~) at the nonzeros,
+      denW = 1 H~^T, i.e. the row sums of H~ for every row of W;
+    * joint MM (Algorithm 2, L = 1): chi_1(W, W~) = W~ and chi_2(W, W~) = W at
+      beta = 1, so numH = W~^T P with the same P, denH = W_new^T 1, the column
+      sums of W_new; H_new = H~ numH / denH;
+    * alternating MU (Algorithm 1): numH = W_new^T P' with P' = V / (W_new H~),
+      denH = the column sums of W_new.
+
+    Optional normalization (Sec. 4.1.2) at the end.  An undefined ratio raises
+    FloatingPointError, as in the dense iterations.
+    """
+    if mode not in ("joint", "alternating"):
+        raise ValueError(mode)
+    Wt = _f64(W)
+    Ht = _f64(H)
+    F, K = Wt.shape
+    N = Ht.shape[1]
+    P = _kl_ratio_terms(row_ptr, col_idx, vals, Wt, Ht)
+    numW = np.zeros((F, K))
+    for (f, cols, _), p in zip(_csr_rows(row_ptr, col_idx, vals), P):
+        numW[f] = Ht[:, cols] @ p
+    denW = np.broadcast_to(Ht.sum(axis=1), (F, K))
+    Wn = Wt * _ratio(numW, denW, 1.0)
+    if mode == "alternating":
+        P = _kl_ratio_terms(row_ptr, col_idx, vals, Wn, Ht)
+        chi = Wn
+    else:
+        chi = Wt
+    numH = np.zeros((K, N))
+    for (f, cols, _), p in zip(_csr_rows(row_ptr, col_idx, vals), P):
+        numH[:, cols] += np.outer(chi[f], p)      # column scatter of chi_1[f, k] p_fn
+    denH = np.broadcast_to(Wn.sum(axis=0)[:, None], (K, N))
+    Hn = Ht * _ratio(numH, denH, 1.0)
+    return normalize(Wn, Hn) if norm else (Wn, Hn)

@@ -20,7 +20,9 @@ data standing in for the real datasets, which are not available):
 * ``spectro_is``   F=513,   N=6000,  K=20, beta in {0, 0.5}, V = (W0 H0) * E, E ~ Exp(1),
                    W0,H0 ~ Gamma(1,1)  (stands in for the audio spectrogram experiment)
 * ``counts_kl``    F=20000, N=10000, K=50, beta=1,   V = Poisson(0.02 W0 H0), W0,H0 ~ Gamma(0.3,1)
-                   (stands in for the song play-count experiment)
+                   (stands in for the song play-count experiment; about 8.5 % nonzeros)
+* ``counts_kl_sparse``  the same with V = Poisson(0.0022 W0 H0): about 1 % nonzeros, closer
+                   to the play-count data's density; used in CSR form by the sparse path
 * ``batched``      512 problems, F ~ U{128..1025}, N ~ U{200..5000}, K ~ U{8..64},
                    beta in {0, .5, 1, 1.5, 2}, Poisson or Gamma-noised V
 
@@ -46,6 +48,8 @@ __all__ = [
     "batched_specs",
     "make_batched_problem",
     "random_positive",
+    "to_csr",
+    "to_csc",
 ]
 
 _ROW_BLOCK = 512  # rows per independently seeded block of V
@@ -73,7 +77,10 @@ WORKLOADS = {
     "faces_euc": (361, 2429, 49, 2.0, 500, 2),
     "spectro_is": (513, 6000, 20, 0.0, 300, 3),
     "counts_kl": (20000, 10000, 50, 1.0, 5, 4),
+    "counts_kl_sparse": (20000, 10000, 50, 1.0, 5, 4),
 }
+# Poisson rate scale of the count workloads
+_COUNT_SCALE = {"counts_kl": 0.02, "counts_kl_sparse": 0.0022}
 
 
 def _seq(seed: int, *key: int) -> np.random.SeedSequence:
@@ -82,7 +89,7 @@ def _seq(seed: int, *key: int) -> np.random.SeedSequence:
 
 def make_factors(name: str, F: int, N: int, K: int, seed: int) -> Tuple[np.ndarray, np.ndarray]:
     """Ground-truth factors W0 (F x K) and H0 (K x N), float64."""
-    shape = {"tiny_kl": 1.0, "faces_euc": 0.5, "spectro_is": 1.0, "counts_kl": 0.3}[name]
+    shape = {"tiny_kl": 1.0, "faces_euc": 0.5, "spectro_is": 1.0, "counts_kl": 0.3, "counts_kl_sparse": 0.3}[name]
     rng = np.random.default_rng(_seq(seed, 0))
     W0 = rng.gamma(shape, 1.0, size=(F, K))
     H0 = rng.gamma(shape, 1.0, size=(K, N))
@@ -99,8 +106,8 @@ def _noise_block(name: str, L: np.ndarray, rng: np.random.Generator) -> np.ndarr
         E = rng.exponential(1.0, size=L.shape)
         E[E == 0.0] = np.finfo(np.float64).tiny
         return L * E
-    if name == "counts_kl":
-        return rng.poisson(0.02 * L).astype(np.float64)
+    if name in _COUNT_SCALE:
+        return rng.poisson(_COUNT_SCALE[name] * L).astype(np.float64)
     raise KeyError(name)
 
 
@@ -177,11 +184,11 @@ _MEAN_CACHE: dict = {}
 def _full_mean(name: str, seed: int, V: Optional[np.ndarray]) -> float:
     key = (name, seed)
     if key not in _MEAN_CACHE:
-        if name == "counts_kl":
-            # expected mean of Poisson(0.02 W0 H0): exact from the factors (no draw needed)
+        if name in _COUNT_SCALE:
+            # expected mean of Poisson(c W0 H0): exact from the factors (no draw needed)
             F, N, K, *_ = WORKLOADS[name]
             W0, H0 = make_factors(name, F, N, K, seed)
-            _MEAN_CACHE[key] = 0.02 * float(W0.sum(axis=0) @ H0.sum(axis=1)) / (F * N)
+            _MEAN_CACHE[key] = _COUNT_SCALE[name] * float(W0.sum(axis=0) @ H0.sum(axis=1)) / (F * N)
         elif V is not None:
             _MEAN_CACHE[key] = float(np.mean(V, dtype=np.float64))
         else:
@@ -253,3 +260,19 @@ def random_positive(F: int, N: int, K: int, seed: int, zeros: float = 0.0,
     H = rng.uniform(lo, hi, size=(K, N))
     return Problem(f"rand{seed}", np.ascontiguousarray(V, np.float32), np.ascontiguousarray(W, np.float32),
                    np.ascontiguousarray(H, np.float32), 1.0, 10)
+
+
+def to_csr(V: np.ndarray):
+    """Row-major compressed form of V's nonzero entries: (row_ptr int64[F + 1],
+    col_idx int32[nnz], values float32[nnz]); columns ascend within a row."""
+    V = np.asarray(V)
+    rows, cols = np.nonzero(V)
+    row_ptr = np.zeros(V.shape[0] + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=V.shape[0]), out=row_ptr[1:])
+    return row_ptr, cols.astype(np.int32), np.ascontiguousarray(V[rows, cols], dtype=np.float32)
+
+
+def to_csc(V: np.ndarray):
+    """Column-major compressed form of V's nonzero entries: (col_ptr int64[N + 1],
+    row_idx int32[nnz], values float32[nnz]); rows ascend within a column."""
+    return to_csr(np.asarray(V).T)
