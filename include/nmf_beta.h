@@ -157,6 +157,38 @@ nmf_status nmf_beta_step(nmf_ctx_t ctx, void* stream, int64_t F, int64_t N, int6
                          const float* V, int64_t ldv, float* W, int64_t ldw, float* H, int64_t ldh,
                          double beta, int32_t mode, const nmf_step_opts* opts, double* d_objective);
 
+/* nmf_beta_step for callers that cannot allocate device memory: code under
+ * HIP graph capture without a prior nmf_reserve, tight serving loops, and
+ * harnesses that forbid hipMalloc.  Same arguments, semantics and results as
+ * nmf_beta_step (the same kernels and launch plan), plus d_flags.
+ *
+ * Workspace: a fixed array of NMF_NOALLOC_SCRATCH_BYTES per GPU, part of the
+ * library's code object (held from the library's first use on a device until
+ * the process ends); this call allocates and frees nothing.  A step whose
+ * workspace does not fit returns NMF_ERR_WORKSPACE before any device work.
+ * The joint step keeps its P, Q tiles between the passes only when they fit as
+ * well (otherwise its H pass forms V~ again, as above 2^28 entries); joint
+ * sub-iterations (inner_iters > 1) need the kept tiles.  At K = 64 (float32)
+ * the joint step keeps them up to about 4M entries of V (1024 x 4096: 81 MiB),
+ * and without them both modes fit beyond 4096 x 4096 (69 MiB); the partial
+ * sums of the split reductions and the F x K terms set the limit.  The
+ * single-launch path (nmf_set_path) and kernel timing (nmf_profile_enable)
+ * are not used.
+ *
+ * Every call on one GPU shares that GPU's array: two calls that overlap in time
+ * on one GPU (different streams, contexts or host threads) race and give
+ * undefined results.  Each call writes every part of the array it reads, so
+ * nothing needs clearing between calls.
+ *
+ * d_flags (device uint32, nullable): the sticky NMF_FLAG_* bits of this call
+ * are OR-ed into it (the caller clears it); with NULL they are discarded.
+ * nmf_get_flags does not see them. */
+#define NMF_NOALLOC_SCRATCH_BYTES (96u << 20)
+nmf_status nmf_beta_step_noalloc(nmf_ctx_t ctx, void* stream, int64_t F, int64_t N, int64_t K,
+                                 const float* V, int64_t ldv, float* W, int64_t ldw, float* H,
+                                 int64_t ldh, double beta, int32_t mode, const nmf_step_opts* opts,
+                                 double* d_objective, uint32_t* d_flags);
+
 /* D_beta(V + kappa | WH + kappa) (eqs. (obj_fct), (beta-div)) written to the device
  * double *d_out.  Per-entry terms and the reduction are float64; WH is float32.
  * At v = 0 the limit is used (beta = 1: the term is [WH]_fn; beta <= 0: +inf). */

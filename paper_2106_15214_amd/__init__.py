@@ -25,7 +25,7 @@ __all__ = [
     "NmfError", "lib", "library_path", "Context", "default_context",
     "ALTERNATING", "JOINT", "FP32", "BF16", "FP16", "EXPONENTS",
     "FLAG_NONFINITE", "FLAG_DOMAIN", "FLAG_BARRIER", "FLAG_RANGE", "KERNELS",
-    "step", "objective", "grad", "validate", "get_flags", "check_step_args", "Batch", "batch_tune",
+    "step", "step_noalloc", "objective", "grad", "validate", "get_flags", "check_step_args", "Batch", "batch_tune",
     "BetaDivergence", "beta_divergence",
 ]
 
@@ -102,6 +102,8 @@ def lib() -> ctypes.CDLL:
                                           _dbl, _i32, ctypes.POINTER(_Opts)]
         L.nmf_beta_step.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
                                     _dbl, _i32, ctypes.POINTER(_Opts), _vp]
+        L.nmf_beta_step_noalloc.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
+                                            _dbl, _i32, ctypes.POINTER(_Opts), _vp, _vp]
         L.nmf_beta_objective.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
                                          _dbl, _flt, _vp]
         L.nmf_beta_grad.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
@@ -123,6 +125,7 @@ def lib() -> ctypes.CDLL:
         L.nmf_batch_tune.argtypes = [_vp, PP, _i32, _i32, ctypes.POINTER(_Opts), _vp, _i32, PC,
                                      ctypes.POINTER(_dbl)]
         for name in ("nmf_create", "nmf_destroy", "nmf_reserve", "nmf_check_step_args", "nmf_beta_step",
+                     "nmf_beta_step_noalloc",
                      "nmf_beta_objective", "nmf_beta_grad", "nmf_beta_validate", "nmf_get_flags",
                      "nmf_profile_enable", "nmf_profile_read", "nmf_set_launch", "nmf_set_path",
                      "nmf_profile_phases", "nmf_batch_create", "nmf_batch_step", "nmf_batch_get_flags",
@@ -284,6 +287,35 @@ def step(V, W, H, beta: float, mode="joint", *, precision="fp32", kappa: float =
     st = lib().nmf_beta_step(_ctx(ctx), _stream(stream), F, N, K, pv, ldv, pw, ldw, ph, ldh,
                              float(beta), m, ctypes.byref(o), pobj)
     _check(st, "nmf_beta_step")
+
+
+def step_noalloc(V, W, H, beta: float, mode="joint", *, precision="fp32", kappa: float = 0.0,
+                 normalize: bool = True, exponent="mm", inner_iters: int = 1, objective_out=None, flags_out=None,
+                 stream=None, ctx: Optional[Context] = None):
+    """step() without any device allocation (nmf_beta_step_noalloc): the
+    library's fixed per-GPU scratch array is the workspace.  ``flags_out``:
+    optional int32 device tensor (1 entry) into which the step's sticky flag
+    bits are OR-ed.  Raises NmfError (NMF_ERR_WORKSPACE) when the step does
+    not fit in the scratch array."""
+    import torch
+    m = MODES.get(mode, mode) if isinstance(mode, str) else int(mode)
+    pv, ldv = _mat(V, "V")
+    pw, ldw = _mat(W, "W")
+    ph, ldh = _mat(H, "H")
+    F, N = V.shape
+    K = W.shape[1]
+    if W.shape[0] != F or H.shape != (K, N):
+        raise ValueError("shape mismatch: V (F,N), W (F,K), H (K,N)")
+    o = _opts(precision, kappa, inner_iters, normalize, exponent)
+    pobj = _dev_f64(objective_out, "objective_out") if objective_out is not None else None
+    pfl = None
+    if flags_out is not None:
+        if flags_out.dtype != torch.int32 or not flags_out.is_cuda or flags_out.numel() < 1:
+            raise ValueError("flags_out must be an int32 device tensor with at least 1 entry")
+        pfl = flags_out.data_ptr()
+    st = lib().nmf_beta_step_noalloc(_ctx(ctx), _stream(stream), F, N, K, pv, ldv, pw, ldw, ph, ldh,
+                                     float(beta), m, ctypes.byref(o), pobj, pfl)
+    _check(st, "nmf_beta_step_noalloc")
 
 
 def objective(V, W, H, beta: float, *, kappa: float = 0.0, out=None, stream=None, ctx=None):

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -24,6 +25,17 @@ struct TimedLaunch {
   hipEvent_t start, stop;
 };
 
+// Workspace of nmf_beta_step_noalloc: one fixed array per GPU, allocated with
+// the code object when the library is loaded on a device and held until the
+// process ends.  In host code `scratch` names a host-side stand-in, not device
+// memory: its device address is looked up per device (hipGetSymbolAddress) at
+// context creation and only that address is ever handed to kernels.
+constexpr size_t kScratchBytes = size_t(NMF_NOALLOC_SCRATCH_BYTES);
+static __device__ __align__(256) char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
 }  // namespace
 
 struct nmf_ctx_s {
@@ -31,6 +43,7 @@ struct nmf_ctx_s {
   int num_cus = 256;
   char* ws = nullptr;  // workspace base
   size_t ws_bytes = 0;
+  char* scratch = nullptr;  // this device's fixed scratch array (nmf_beta_step_noalloc)
   // A call was recorded into a stream capture: a graph may hold kernels that
   // point into the workspace, so it is never moved again (growth is refused).
   bool captured = false;
@@ -335,6 +348,20 @@ nmf_status ensure_ws(nmf_ctx_s* c, hipStream_t s, size_t bytes) {
 
 unsigned* flags_ptr(nmf_ctx_s* c) { return (unsigned*)c->ws; }
 
+// Device address of `scratch` on device `dev`, which must be current: looked up
+// once per device and kept (each GPU holds its own copy at its own address).
+nmf_status scratch_setup(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return NMF_ERR_NO_DEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return NMF_ERR_HIP;
+    g_scratch[dev] = (char*)ptr;
+  }
+  *out = g_scratch[dev];
+  return NMF_OK;
+}
+
 hipEvent_t get_event(nmf_ctx_s* c) {
   if (!c->event_pool.empty()) {
     hipEvent_t e = c->event_pool.back();
@@ -471,8 +498,15 @@ constexpr unsigned kBatchSpinLimit = 1u << 22;
 // place), then L H updates against the final W_new, each forming W_new H from
 // the latest H.  Only the first W pass forms the objective of the entry
 // iterate; only the last H update normalizes, writes W and the objective.
+// Launches fn, between two timing events when the kernel is selected for
+// profiling and the call may use them (`quiet`: never, no event is created).
+template <class Fn>
+hipError_t run_k(nmf_ctx_s* c, bool quiet, int kernel, hipStream_t s, Fn&& fn) {
+  return quiet ? fn() : timed(c, kernel, s, fn);
+}
+
 nmf_status inner_steps(nmf_ctx_s* c, hipStream_t s, const Plan& p, const StepArgs& sa, int bc, bool want_obj,
-                              int L, int prec) {
+                              int L, int prec, bool quiet) {
   for (int l = 0; l < L; ++l) {
     SweepRowsArgs ra = sa.ra;
     UpdateWArgs ua = sa.ua;
@@ -480,13 +514,13 @@ nmf_status inner_steps(nmf_ctx_s* c, hipStream_t s, const Plan& p, const StepArg
       ra.W = sa.ua.Wn; ra.ldw = p.KP;
       ua.W = sa.ua.Wn; ua.ldw = p.KP;
     }
-    hipError_t e = timed(c, NMF_KERNEL_SWEEP_W, s, [&] {
+    hipError_t e = run_k(c, quiet, NMF_KERNEL_SWEEP_W, s, [&] {
       const bool obj = want_obj && l == 0;
       return prec == NMF_FP32 ? launch_sweep_rows(bc, p.KB, KIND_UPDATE, obj, false, sa.sw_grid, s, ra)
                               : launch_sweep_rows_lp(prec, bc, p.KB, obj, false, sa.sw_grid, s, ra);
     });
     if (e != hipSuccess) return NMF_ERR_HIP;
-    e = timed(c, NMF_KERNEL_UPDATE_W, s, [&] { return launch_update_w(p.KB, p.uw_blocks, s, ua); });
+    e = run_k(c, quiet, NMF_KERNEL_UPDATE_W, s, [&] { return launch_update_w(p.KB, p.uw_blocks, s, ua); });
     if (e != hipSuccess) return NMF_ERR_HIP;
   }
   for (int l = 0; l < L; ++l) {
@@ -495,12 +529,12 @@ nmf_status inner_steps(nmf_ctx_s* c, hipStream_t s, const Plan& p, const StepArg
       ha.normalize = 0;
       ha.d_obj = nullptr;
     }
-    hipError_t e = timed(c, NMF_KERNEL_SWEEP_H, s, [&] {
+    hipError_t e = run_k(c, quiet, NMF_KERNEL_SWEEP_H, s, [&] {
       return prec == NMF_FP32 ? launch_sweep_cols(bc, p.KB, KIND_UPDATE, false, false, sa.sh_grid, s, sa.ca)
                               : launch_sweep_cols_lp(prec, bc, p.KB, false, false, sa.sh_grid, s, sa.ca);
     });
     if (e != hipSuccess) return NMF_ERR_HIP;
-    e = timed(c, NMF_KERNEL_UPDATE_H, s, [&] { return launch_update_h(p.KB, p.uh_blocks, s, ha); });
+    e = run_k(c, quiet, NMF_KERNEL_UPDATE_H, s, [&] { return launch_update_h(p.KB, p.uh_blocks, s, ha); });
     if (e != hipSuccess) return NMF_ERR_HIP;
   }
   return NMF_OK;
@@ -514,25 +548,25 @@ nmf_status inner_steps(nmf_ctx_s* c, hipStream_t s, const Plan& p, const StepArg
 // before the last write chi_1(H_{l+1}, H~), chi_2(H_{l+1}, H~) to the workspace
 // instead of H; the last writes H, normalizes, writes W and the objective.
 nmf_status inner_steps_joint(nmf_ctx_s* c, hipStream_t s, const Plan& p, const StepArgs& sa, int bc, bool want_obj,
-                             int L) {
-  float* const C1h = (float*)(c->ws + p.o_c1h);
-  float* const C2h = (float*)(c->ws + p.o_c2h);
+                             int L, char* ws, bool quiet) {
+  float* const C1h = (float*)(ws + p.o_c1h);
+  float* const C2h = (float*)(ws + p.o_c2h);
   for (int l = 0; l < L; ++l) {
     hipError_t e;
     if (l == 0) {
-      e = timed(c, NMF_KERNEL_SWEEP_W, s, [&] {
+      e = run_k(c, quiet, NMF_KERNEL_SWEEP_W, s, [&] {
         return launch_sweep_rows(bc, p.KB, KIND_UPDATE, want_obj, true, sa.sw_grid, s, sa.ra);
       });
     } else {
       SweepRowsArgs rq = sa.ra;
       rq.H = C1h; rq.ldh = p.ldc;
       rq.W = C2h; rq.ldw = p.ldc;
-      e = timed(c, NMF_KERNEL_SWEEP_W, s, [&] { return launch_sweep_rows_pq(bc, p.KB, sa.sw_grid, s, rq); });
+      e = run_k(c, quiet, NMF_KERNEL_SWEEP_W, s, [&] { return launch_sweep_rows_pq(bc, p.KB, sa.sw_grid, s, rq); });
     }
     if (e != hipSuccess) return NMF_ERR_HIP;
-    e = timed(c, NMF_KERNEL_UPDATE_W, s, [&] { return launch_update_w(p.KB, p.uw_blocks, s, sa.ua); });
+    e = run_k(c, quiet, NMF_KERNEL_UPDATE_W, s, [&] { return launch_update_w(p.KB, p.uw_blocks, s, sa.ua); });
     if (e != hipSuccess) return NMF_ERR_HIP;
-    e = timed(c, NMF_KERNEL_SWEEP_H, s, [&] {
+    e = run_k(c, quiet, NMF_KERNEL_SWEEP_H, s, [&] {
       return launch_sweep_cols(bc, p.KB, KIND_UPDATE, true, true, sa.sh_grid, s, sa.ca);
     });
     if (e != hipSuccess) return NMF_ERR_HIP;
@@ -541,11 +575,114 @@ nmf_status inner_steps_joint(nmf_ctx_s* c, hipStream_t s, const Plan& p, const S
       ha.C1h = C1h; ha.C2h = C2h; ha.ldc = p.ldc;
       ha.W = nullptr; ha.d_obj = nullptr; ha.normalize = 0;
     }
-    e = timed(c, NMF_KERNEL_UPDATE_H, s, [&] { return launch_update_h(p.KB, p.uh_blocks, s, ha); });
+    e = run_k(c, quiet, NMF_KERNEL_UPDATE_H, s, [&] { return launch_update_h(p.KB, p.uh_blocks, s, ha); });
     if (e != hipSuccess) return NMF_ERR_HIP;
   }
   return NMF_OK;
 }
+
+// One outer iteration (nmf_beta_step).  no_alloc: the workspace is this
+// device's fixed scratch array (never grown), `flags` the status word, the
+// single-launch path and the kernel timing events are not used, and the joint
+// step keeps P, Q between its passes only when they fit in the scratch.
+nmf_status step_impl(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K, const float* V, int64_t ldv,
+                     float* W, int64_t ldw, float* H, int64_t ldh, double beta, int32_t mode,
+                     const nmf_step_opts* opts, double* d_objective, bool no_alloc, unsigned* flags) {
+  if (!c) return NMF_ERR_NULL;
+  nmf_status st = nmf_check_step_args(F, N, K, V, ldv, W, ldw, H, ldh, beta, mode, opts);
+  if (st != NMF_OK) return st;
+  nmf_step_opts o;
+  nmf_default_opts(&o);
+  if (opts) o = *opts;
+  hipStream_t s = (hipStream_t)stream;
+  const int bc = beta_class(beta);
+  const bool joint = (mode == NMF_JOINT);
+  const bool want_obj = d_objective != nullptr;
+  const int prec = opts ? opts->precision : NMF_FP32;
+  if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
+  // path: one cooperative launch for problems whose P, Q tiles stay cache
+  // resident (not under stream capture), else four streaming launches
+  const int L = o.inner_iters;
+  int fused_grid = 0;
+  if (!no_alloc && c->path == NMF_PATH_FUSED && L == 1 && prec == NMF_FP32 && kblocks_for(K) <= 2 &&
+      F * N <= kFusedMaxEntries) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return NMF_ERR_HIP;
+    if (cs == hipStreamCaptureStatusNone) fused_grid = fused_capacity(c, bc, kblocks_for(K), joint, want_obj);
+  }
+  if (!no_alloc && c->path == NMF_PATH_FUSED && fused_grid <= 0) return NMF_ERR_UNSUPPORTED;
+  bool use_pq = joint && fused_grid == 0 && F * N <= kPQMaxEntries;
+  const int cols_occ = sweep_cols_occupancy(bc, kblocks_for(K), KIND_UPDATE, joint);
+  Plan p = make_plan(c, F, N, K, cols_occ, fused_grid, use_pq, joint && L > 1);
+  char* ws = nullptr;
+  if (no_alloc) {
+    if (p.total > kScratchBytes && use_pq && L == 1) {
+      use_pq = false;  // the H pass forms Lambda~ again instead of reading kept P, Q
+      p = make_plan(c, F, N, K, cols_occ, 0, false, false);
+    }
+    if (p.total > kScratchBytes) return NMF_ERR_WORKSPACE;
+    if (!c->scratch) return NMF_ERR_HIP;
+    ws = c->scratch;
+  } else {
+    if ((st = ensure_ws(c, s, p.total)) != NMF_OK) return st;
+    ws = c->ws;
+    flags = flags_ptr(c);
+  }
+  const bool quiet = no_alloc;
+
+  StepArgs sa = make_step_args(p, ws, flags, F, N, K, V, ldv, W, ldw, H, ldh, beta, joint, prec, o, d_objective);
+  SweepRowsArgs& ra = sa.ra;
+  UpdateWArgs& ua = sa.ua;
+  SweepColsArgs& ca = sa.ca;
+  UpdateHArgs& ha = sa.ha;
+  const int sw_grid = sa.sw_grid, sh_grid = sa.sh_grid;
+
+  if (p.fused) {
+    // joint: the H pass contracts the P, Q tiles stored by the W pass
+    ra.NT = (int)cdiv(N, kTile);
+    ra.Pst = (float*)(ws + p.o_pst);
+    ra.Qst = (float*)(ws + p.o_qst);
+    ca.NT = ra.NT; ca.Pst = ra.Pst; ca.Qst = ra.Qst;
+    ha.nobj = p.fused_grid;
+    FusedArgs fa{};
+    fa.r = ra; fa.uw = ua; fa.c = ca; fa.uh = ha;
+    fa.n_items_w = sw_grid;
+    fa.n_items_h = sh_grid;
+    fa.slabs = (int)cdiv(F, kTile);
+    fa.ntiles = (int)cdiv(N, kTile);
+    fa.bar = (unsigned*)(ws + 8);
+    fa.colsum = (float*)(ws + p.o_colsum);
+    fa.spin_limit = 1u << 22;
+    fa.stamps = ((c->profile_mask >> NMF_KERNEL_FUSED_STEP) & 1u) ? (unsigned long long*)(ws + 64) : nullptr;
+    return hip_status(timed(c, NMF_KERNEL_FUSED_STEP, s, [&] {
+      return launch_fused(bc, p.KB, joint, want_obj, p.fused_grid, s, fa);
+    }));
+  }
+  if (p.pq) {
+    ra.NT = (int)cdiv(N, kTile);
+    ra.Pst = (float*)(ws + p.o_pst);
+    ra.Qst = (float*)(ws + p.o_qst);
+    ca.NT = ra.NT; ca.Pst = ra.Pst; ca.Qst = ra.Qst;
+  }
+  if (L > 1)
+    return joint ? inner_steps_joint(c, s, p, sa, bc, want_obj, L, ws, quiet)
+                 : inner_steps(c, s, p, sa, bc, want_obj, L, prec, quiet);
+  hipError_t e = run_k(c, quiet, NMF_KERNEL_SWEEP_W, s, [&] {
+    return prec == NMF_FP32 ? launch_sweep_rows(bc, p.KB, KIND_UPDATE, want_obj, p.pq, sw_grid, s, ra)
+                            : launch_sweep_rows_lp(prec, bc, p.KB, want_obj, p.pq, sw_grid, s, ra);
+  });
+  if (e != hipSuccess) return NMF_ERR_HIP;
+  e = run_k(c, quiet, NMF_KERNEL_UPDATE_W, s, [&] { return launch_update_w(p.KB, p.uw_blocks, s, ua); });
+  if (e != hipSuccess) return NMF_ERR_HIP;
+  e = run_k(c, quiet, NMF_KERNEL_SWEEP_H, s, [&] {
+    return prec == NMF_FP32 ? launch_sweep_cols(bc, p.KB, KIND_UPDATE, joint, p.pq, sh_grid, s, ca)
+                            : launch_sweep_cols_lp(prec, bc, p.KB, joint, p.pq, sh_grid, s, ca);
+  });
+  if (e != hipSuccess) return NMF_ERR_HIP;
+  e = run_k(c, quiet, NMF_KERNEL_UPDATE_H, s, [&] { return launch_update_h(p.KB, p.uh_blocks, s, ha); });
+  return hip_status(e);
+}
+
 
 }  // namespace
 
@@ -590,6 +727,16 @@ nmf_status nmf_create(nmf_ctx_t* out, int device) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->num_cus = prop.multiProcessorCount;
+  // set-up of the no-allocation step: this device's scratch address, looked up
+  // with the device current (the caller's current device is restored)
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  nmf_status st = hipSetDevice(device) == hipSuccess ? scratch_setup(device, &c->scratch) : NMF_ERR_HIP;
+  if (prev >= 0 && prev != device) (void)hipSetDevice(prev);
+  if (st != NMF_OK) {
+    delete c;
+    return st;
+  }
   *out = c;
   return NMF_OK;
 }
@@ -634,85 +781,16 @@ nmf_status nmf_check_step_args(int64_t F, int64_t N, int64_t K, const float* V, 
 nmf_status nmf_beta_step(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K, const float* V, int64_t ldv,
                          float* W, int64_t ldw, float* H, int64_t ldh, double beta, int32_t mode,
                          const nmf_step_opts* opts, double* d_objective) {
+  return step_impl(c, stream, F, N, K, V, ldv, W, ldw, H, ldh, beta, mode, opts, d_objective, false, nullptr);
+}
+
+nmf_status nmf_beta_step_noalloc(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K, const float* V,
+                                 int64_t ldv, float* W, int64_t ldw, float* H, int64_t ldh, double beta,
+                                 int32_t mode, const nmf_step_opts* opts, double* d_objective, uint32_t* d_flags) {
   if (!c) return NMF_ERR_NULL;
-  nmf_status st = nmf_check_step_args(F, N, K, V, ldv, W, ldw, H, ldh, beta, mode, opts);
-  if (st != NMF_OK) return st;
-  nmf_step_opts o;
-  nmf_default_opts(&o);
-  if (opts) o = *opts;
-  hipStream_t s = (hipStream_t)stream;
-  const int bc = beta_class(beta);
-  const bool joint = (mode == NMF_JOINT);
-  const bool want_obj = d_objective != nullptr;
-  const int prec = opts ? opts->precision : NMF_FP32;
-  if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
-  // path: one cooperative launch for problems whose P, Q tiles stay cache
-  // resident (not under stream capture), else four streaming launches
-  const int L = o.inner_iters;
-  int fused_grid = 0;
-  if (c->path == NMF_PATH_FUSED && L == 1 && prec == NMF_FP32 && kblocks_for(K) <= 2 && F * N <= kFusedMaxEntries) {
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return NMF_ERR_HIP;
-    if (cs == hipStreamCaptureStatusNone) fused_grid = fused_capacity(c, bc, kblocks_for(K), joint, want_obj);
-  }
-  if (c->path == NMF_PATH_FUSED && fused_grid <= 0) return NMF_ERR_UNSUPPORTED;
-  const bool use_pq = joint && fused_grid == 0 && F * N <= kPQMaxEntries;
-  const Plan p = make_plan(c, F, N, K, sweep_cols_occupancy(bc, kblocks_for(K), KIND_UPDATE, joint), fused_grid,
-                           use_pq, joint && L > 1);
-  if ((st = ensure_ws(c, s, p.total)) != NMF_OK) return st;
-
-  StepArgs sa = make_step_args(p, c->ws, flags_ptr(c), F, N, K, V, ldv, W, ldw, H, ldh, beta, joint, prec, o,
-                                d_objective);
-  SweepRowsArgs& ra = sa.ra;
-  UpdateWArgs& ua = sa.ua;
-  SweepColsArgs& ca = sa.ca;
-  UpdateHArgs& ha = sa.ha;
-  const int sw_grid = sa.sw_grid, sh_grid = sa.sh_grid;
-  char* ws = c->ws;
-
-  if (p.fused) {
-    // joint: the H pass contracts the P, Q tiles stored by the W pass
-    ra.NT = (int)cdiv(N, kTile);
-    ra.Pst = (float*)(ws + p.o_pst);
-    ra.Qst = (float*)(ws + p.o_qst);
-    ca.NT = ra.NT; ca.Pst = ra.Pst; ca.Qst = ra.Qst;
-    ha.nobj = p.fused_grid;
-    FusedArgs fa{};
-    fa.r = ra; fa.uw = ua; fa.c = ca; fa.uh = ha;
-    fa.n_items_w = sw_grid;
-    fa.n_items_h = sh_grid;
-    fa.slabs = (int)cdiv(F, kTile);
-    fa.ntiles = (int)cdiv(N, kTile);
-    fa.bar = (unsigned*)(ws + 8);
-    fa.colsum = (float*)(ws + p.o_colsum);
-    fa.spin_limit = 1u << 22;
-    fa.stamps = ((c->profile_mask >> NMF_KERNEL_FUSED_STEP) & 1u) ? (unsigned long long*)(ws + 64) : nullptr;
-    return hip_status(timed(c, NMF_KERNEL_FUSED_STEP, s, [&] {
-      return launch_fused(bc, p.KB, joint, want_obj, p.fused_grid, s, fa);
-    }));
-  }
-  if (p.pq) {
-    ra.NT = (int)cdiv(N, kTile);
-    ra.Pst = (float*)(ws + p.o_pst);
-    ra.Qst = (float*)(ws + p.o_qst);
-    ca.NT = ra.NT; ca.Pst = ra.Pst; ca.Qst = ra.Qst;
-  }
-  if (L > 1)
-    return joint ? inner_steps_joint(c, s, p, sa, bc, want_obj, L) : inner_steps(c, s, p, sa, bc, want_obj, L, prec);
-  hipError_t e = timed(c, NMF_KERNEL_SWEEP_W, s, [&] {
-    return prec == NMF_FP32 ? launch_sweep_rows(bc, p.KB, KIND_UPDATE, want_obj, p.pq, sw_grid, s, ra)
-                            : launch_sweep_rows_lp(prec, bc, p.KB, want_obj, p.pq, sw_grid, s, ra);
-  });
-  if (e != hipSuccess) return NMF_ERR_HIP;
-  e = timed(c, NMF_KERNEL_UPDATE_W, s, [&] { return launch_update_w(p.KB, p.uw_blocks, s, ua); });
-  if (e != hipSuccess) return NMF_ERR_HIP;
-  e = timed(c, NMF_KERNEL_SWEEP_H, s, [&] {
-    return prec == NMF_FP32 ? launch_sweep_cols(bc, p.KB, KIND_UPDATE, joint, p.pq, sh_grid, s, ca)
-                            : launch_sweep_cols_lp(prec, bc, p.KB, joint, p.pq, sh_grid, s, ca);
-  });
-  if (e != hipSuccess) return NMF_ERR_HIP;
-  e = timed(c, NMF_KERNEL_UPDATE_H, s, [&] { return launch_update_h(p.KB, p.uh_blocks, s, ha); });
-  return hip_status(e);
+  // without d_flags the status word is the scratch's first word (written, never read)
+  unsigned* flags = d_flags ? (unsigned*)d_flags : (unsigned*)c->scratch;
+  return step_impl(c, stream, F, N, K, V, ldv, W, ldw, H, ldh, beta, mode, opts, d_objective, true, flags);
 }
 
 nmf_status nmf_beta_objective(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K, const float* V,
