@@ -32,6 +32,9 @@ if ROOT not in sys.path:
 METRIC = "joint-MM vs alternating-MU iterations/s and time-to-objective per β, 1 MI355X"
 PEAK_MFMA = {"fp32": 157.3e12, "bf16": 2.5e15, "fp16": 2.5e15}  # dense matrix FLOP/s
 PEAK_HBM = 8.0e12           # bytes/s
+# float32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz x 2
+# (two-wide packed FMA) = 157.3 TFLOP/s; without packed instructions half of it
+PEAK_VALU_F32 = 157.3e12
 
 
 # The paper's own measurements (CPU time to its stopping rule, Matlab 2020a on an
@@ -117,8 +120,9 @@ def measured_traffic(workload: str, precision: str, kernel: str, beta=None):
 
 # outer iterations of each workload's time-to-objective runs (the iteration
 # counts of the configurations; independent of --steps)
-TTO_ITERS = {"tiny_kl": 100, "faces_euc": 500, "spectro_is": 300, "counts_kl": 100, "batched": 200}
-DEFAULT_STEPS = {"batched": 50, "counts_kl": 50}
+TTO_ITERS = {"tiny_kl": 100, "faces_euc": 500, "spectro_is": 300, "counts_kl": 100, "counts_kl_sparse": 100,
+             "batched": 200}
+DEFAULT_STEPS = {"batched": 50, "counts_kl": 50, "counts_kl_sparse": 50}
 
 
 def cpu_model() -> str:
@@ -147,7 +151,9 @@ def main(argv=None):
                     help="timed iterations (default 50 for batched and counts_kl, else 500)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed iterations (default 5 batched, else 20)")
     ap.add_argument("--workload", default="batched",
-                    choices=["batched", "counts_kl", "faces_euc", "spectro_is", "tiny_kl"])
+                    choices=["batched", "counts_kl", "counts_kl_sparse", "faces_euc", "spectro_is", "tiny_kl"])
+    ap.add_argument("--sparse", action="store_true",
+                    help="count workloads: V by its nonzeros (CSR + CSC), the sparse beta = 1 path")
     ap.add_argument("--tto-iters", type=int, default=None,
                     help="iterations of the time-to-objective runs (default: the workload's own count)")
     ap.add_argument("--beta", type=float, default=None)
@@ -191,6 +197,11 @@ def main(argv=None):
     torch.cuda.set_device(dev)
     if args.workload == "batched":
         return main_batched(args, nb, synth, torch, np, dev)
+    if args.sparse:
+        if not args.workload.startswith("counts_kl"):
+            print(json.dumps({"error": "--sparse applies to the count workloads"}), flush=True)
+            return 2
+        return main_sparse(args, nb, synth, torch, np, dev)
     p = synth.make_problem(args.workload, beta=args.beta)
     F, N, K = p.shape
     beta = p.beta
@@ -329,6 +340,151 @@ def main(argv=None):
     print(json.dumps(out), flush=True)
     ctx.close()
     return 0
+
+
+def main_sparse(args, nb, synth, torch, np, dev):
+    """The beta = 1 step on a count workload held by its nonzeros (CSR and CSC):
+    iterations/s of both methods with the objective of every iterate, the
+    row/column pass kernel against its roofline, time-to-objective."""
+    p = synth.make_problem(args.workload)
+    F, N, K = p.shape
+    rp, ci, rv = synth.to_csr(p.V)
+    cp, ri, cv = synth.to_csc(p.V)
+    nnz = int(ci.size)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    Vs = nb.SparseV(F, N, t(rp), t(ci), t(rv), t(cp), t(ri), t(cv))
+    print(f"# sparse {args.workload}: F={F} N={N} K={K} nnz={nnz} ({nnz / (F * N) * 100:.2f}%)", file=sys.stderr,
+          flush=True)
+    ctx = nb.Context(0)
+    W0, H0 = t(p.W), t(p.H)
+    obj = torch.zeros(1, dtype=torch.float64, device=dev)
+    res, kern = {}, {}
+    for mode in ("joint", "alternating"):
+        W, H = W0.clone(), H0.clone()
+        for _ in range(args.warmup):
+            nb.kl_step_sparse(Vs, W, H, mode, objective_out=obj, ctx=ctx)
+        torch.cuda.synchronize()
+        # the step's short launches are replayed from a HIP graph (one step per
+        # replay), so the host's launch rate does not set the iteration time
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            nb.kl_step_sparse(Vs, W, H, mode, objective_out=obj, ctx=ctx)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        del graph
+        # eager launches, for comparison
+        e0.record()
+        for _ in range(args.steps):
+            nb.kl_step_sparse(Vs, W, H, mode, objective_out=obj, ctx=ctx)
+        e1.record()
+        torch.cuda.synchronize()
+        eager = e0.elapsed_time(e1) / args.steps
+        res[mode] = {"ms_per_step": ms, "iters_per_s": 1e3 / ms, "eager_ms_per_step": eager}
+        print(f"# sparse {mode}: {ms * 1e3:.1f} us/iteration (graph), {eager * 1e3:.1f} eager", file=sys.stderr,
+              flush=True)
+        ctx.profile(["sparse_pass", "sparse_cols"])
+        for _ in range(args.steps):
+            nb.kl_step_sparse(Vs, W, H, mode, objective_out=obj, ctx=ctx)
+        torch.cuda.synchronize()
+        kern[mode] = {}
+        for k in ("sparse_pass", "sparse_cols"):
+            tot, n = ctx.profile_read(k)
+            if n:
+                kern[mode][k] = {"avg_us": 1e3 * tot / n, "launches": n}
+        ctx.profile([])
+    if nb.get_flags(clear=True, ctx=ctx):
+        print("# warning: numeric flags raised", file=sys.stderr)
+    # dominant kernel: the joint pass (row pass + column pass in one launch).
+    # Per stored entry and traversal: lambda (2K flops), the numerator term (2K),
+    # and 8 bytes of index and value; both traversals per launch.
+    t_dom = kern["joint"]["sparse_pass"]["avg_us"] * 1e-6
+    flops = 2 * nnz * 4 * K
+    nbytes = 2 * nnz * 8
+    roof = {"bound": "alu", "achieved": flops / t_dom / 1e12, "peak": PEAK_VALU_F32 / 1e12, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = measured_traffic(args.workload + "_sparse", "fp32", "sparse_pass")
+    roof["kernel"] = "sparse_pass"
+    roof["algorithmic_flops_per_launch"] = flops
+    roof["algorithmic_bytes_per_launch"] = nbytes
+    roof["avg_launch_us"] = kern["joint"]["sparse_pass"]["avg_us"]
+    roof["hbm_GBps_algorithmic"] = nbytes / t_dom / 1e9
+    # time-to-objective from the common init
+    T = args.tto_iters
+    traces = {}
+    for mode in ("joint", "alternating"):
+        W, H = W0.clone(), H0.clone()
+        tr = torch.zeros(T + 1, dtype=torch.float64, device=dev)
+        for i in range(T):
+            nb.kl_step_sparse(Vs, W, H, mode, objective_out=tr[i:i + 1], ctx=ctx)
+        nb.kl_objective_sparse(Vs, W, H, out=tr[T:T + 1], ctx=ctx)
+        torch.cuda.synchronize()
+        traces[mode] = tr.cpu().numpy()
+    tto = targets_from_traces(np, traces, {m: res[m]["ms_per_step"] for m in res})
+    out = {
+        "metric": METRIC, "value": res["joint"]["iters_per_s"], "unit": "iterations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["joint"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload + " (sparse V)", "F": F, "N": N, "K": K, "beta": 1.0, "nnz": nnz,
+                   "density": nnz / (F * N), "mode": "joint", "objective_every_step": True, "normalize": True,
+                   "graph_replay": True},
+        "alternating": {"value": res["alternating"]["iters_per_s"], "ms_per_step": res["alternating"]["ms_per_step"]},
+        "joint_speedup_per_iteration": res["alternating"]["ms_per_step"] / res["joint"]["ms_per_step"],
+        "eager_ms_per_step": {m: res[m]["eager_ms_per_step"] for m in res},
+        "time_to_objective": dict(T=T, **tto), "roofline": roof, "kernels_us": kern,
+        "paper_cpu_reference": PAPER_CPU_REFERENCE,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_sparse(p, (rp, ci, rv), args.cpu_seconds, res["joint"]["iters_per_s"])
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
+def targets_from_traces(np, traces, tper):
+    """Iterations and milliseconds for both methods to reach 90 / 99 / 99.9 / 100 %
+    of the larger final decrease, from objective traces of the same init."""
+    D0 = traces["joint"][0]
+    Dend = max(traces["joint"][-1], traces["alternating"][-1])
+    rows = {}
+    for q in (0.9, 0.99, 0.999, 1.0):
+        target = D0 - q * (D0 - Dend)
+        row = {"target": float(target)}
+        for mode in traces:
+            hit = np.nonzero(traces[mode] <= target * (1 + 1e-12))[0]
+            it = int(hit[0]) if hit.size else None
+            row[mode] = {"iterations": it, "ms": (it * tper[mode]) if it is not None else None}
+        rows[str(q)] = row
+    return {"D0": float(D0), "D_T": {m: float(traces[m][-1]) for m in traces}, "ms_per_iteration": tper,
+            "targets": rows, "objective_increases": {m: int(np.sum(np.diff(traces[m]) > 0)) for m in traces}}
+
+
+def cpu_baseline_sparse(p, csr, budget_s, gpu_value):
+    """The FP64 oracle's sparse joint iteration (objective + update +
+    normalization) on the whole count workload, all threads and one thread."""
+    import numpy as np
+    import oracle
+    rp, ci, rv = csr
+    state = {"W": p.W.astype(np.float64), "H": p.H.astype(np.float64)}
+
+    def one():
+        oracle.kl_sparse_objective(rp, ci, rv, state["W"], state["H"])
+        state["W"], state["H"] = oracle.kl_sparse_iteration(rp, ci, rv, state["W"], state["H"], "joint")
+
+    n_all, el_all, th_all = _timed_oracle(one, budget_s / 2)
+    state.update(W=p.W.astype(np.float64), H=p.H.astype(np.float64))
+    n_one, el_one, _ = _timed_oracle(one, budget_s / 2, threads=1)
+    return {"value": n_all / el_all, "unit": "iterations/s", "cores": th_all, "kind": "oracle",
+            "sample": f"{n_all} sparse joint iterations (objective + update + normalization, float64 NumPy, "
+                      f"row loops) of the {p.name} workload in {el_all:.1f} s on {th_all} threads; {n_one} in "
+                      f"{el_one:.1f} s on 1 thread",
+            "one_thread": {"value": n_one / el_one, "cores": 1}, "cpu_model": cpu_model(),
+            "host_cores_available": len(os.sched_getaffinity(0)), "gpu_over_cpu": gpu_value / (n_all / el_all)}
 
 
 def time_to_objective(nb, torch, np, ctx, V, W0, H0, beta, T, precision, dev, inner=1):
@@ -510,10 +666,16 @@ def batched_time_to_objective(np, host, traces, ms_per_iter, T):
     90 / 99 / 99.9 / 100 % of the larger final decrease.  Also the number of
     per-problem objective increases."""
     betas = np.array([q.beta for q in host])
+    # a problem whose trajectory reached an undefined update (a factor entry
+    # underflowed to zero in float32: flagged, non-finite objective) in either
+    # method is left out of the sums and counted
+    finite = np.all(np.isfinite(traces["joint"]), axis=0) & np.all(np.isfinite(traces["alternating"]), axis=0)
     groups = {str(b): betas == b for b in sorted(set(betas.tolist()))}
     groups["all"] = np.ones_like(betas, dtype=bool)
-    out = {"T": T, "ms_per_iteration": ms_per_iter, "groups": {}}
-    for name, sel in groups.items():
+    out = {"T": T, "ms_per_iteration": ms_per_iter, "groups": {},
+           "nonfinite_problems": {m: int(np.sum(~np.all(np.isfinite(traces[m]), axis=0))) for m in traces}}
+    for name, sel0 in groups.items():
+        sel = sel0 & finite
         d = {m: traces[m][:, sel].sum(axis=1) for m in traces}
         D0 = d["joint"][0]
         Dend = max(d["joint"][-1], d["alternating"][-1])
@@ -526,9 +688,11 @@ def batched_time_to_objective(np, host, traces, ms_per_iter, T):
                 it = int(hit[0]) if hit.size else None
                 row[m] = {"iterations": it, "ms": (it * ms_per_iter[m]) if it is not None else None}
             rows[str(q)] = row
-        out["groups"][name] = {"problems": int(sel.sum()), "D0": float(D0),
+        out["groups"][name] = {"problems": int(sel.sum()), "excluded_nonfinite": int((sel0 & ~finite).sum()),
+                               "D0": float(D0),
                                "D_T": {m: float(d[m][-1]) for m in d}, "targets": rows}
-    out["objective_increases"] = {m: int(np.sum(traces[m][1:] > traces[m][:-1] * (1 + 1e-12))) for m in traces}
+    out["objective_increases"] = {m: int(np.sum(traces[m][1:, finite] > traces[m][:-1, finite] * (1 + 1e-12)))
+                                  for m in traces}
     return out
 
 

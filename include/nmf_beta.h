@@ -230,6 +230,8 @@ nmf_status nmf_get_flags(nmf_ctx_t ctx, void* stream, uint32_t* flags, int32_t c
 #define NMF_KERNEL_SWEEP_H 2   /* pass over V accumulating the H-step contractions */
 #define NMF_KERNEL_UPDATE_H 3  /* reduction of H partials, H update, normalization */
 #define NMF_KERNEL_FUSED_STEP 5 /* whole outer iteration in one cooperative launch */
+#define NMF_KERNEL_SPARSE_PASS 6 /* sparse beta = 1 step: row pass (+ column pass in joint mode) */
+#define NMF_KERNEL_SPARSE_COLS 7 /* sparse beta = 1 step, alternating mode: column pass */
 #define NMF_KERNEL_COUNT 8
 nmf_status nmf_profile_enable(nmf_ctx_t ctx, uint32_t kernel_mask);
 /* With NMF_KERNEL_FUSED_STEP selected, the single-launch step also records the
@@ -256,6 +258,60 @@ nmf_status nmf_set_path(nmf_ctx_t ctx, int32_t path);
  * (0 = default, twice the number of compute units) and minimum number of 32-wide
  * tiles each workgroup walks (0 = default 1).  Applies to later calls. */
 nmf_status nmf_set_launch(nmf_ctx_t ctx, int32_t target_blocks, int32_t min_tiles);
+
+/* ---------------------------------------------------------------------------
+ * beta = 1 (Kullback-Leibler) with a sparse V.
+ *
+ * For count data most of V is zero (the play counts of Sec. 4.4 are about 0.6 %
+ * nonzero).  At beta = 1 the updates of Table 2 (Sec. 3.3.1) need V / (WH)
+ * only where v != 0, and their denominators are row sums of H~ and column
+ * sums of W_new, so a step touches only the nonzeros:
+ *   W step:                numW = P H~^T, P = V / (W~ H~) at the nonzeros,
+ *                          denW = row sums of H~;
+ *   H step, NMF_JOINT:     numH = W~^T P with the same P (chi_1 = W~ at beta = 1),
+ *                          denH = column sums of W_new (chi_2 = W_new);
+ *   H step, NMF_ALTERNATING: numH = W_new^T P', P' = V / (W_new H~), same denH.
+ * D_1(V | WH) = sum of all [WH]_fn (from factor sums) + sum over the nonzeros
+ * of v log(v / [WH]_fn) - v.  An entry with v = 0 never evaluates V / (WH)
+ * (a row of V without nonzeros gives a zero row of W_new, with no 0/0).
+ *
+ * V is given by its nonzeros twice, in caller-owned device memory: row order
+ * (CSR) and column order (CSC) of the same entries.  Columns (rows) must
+ * ascend within a row (column).  The library reads the indices clamped to the
+ * matrix and the pointers clamped to [0, nnz], so a malformed matrix gives
+ * wrong numbers but no access outside the arrays; nmf_sparse_validate checks
+ * the structure.  F, N >= 1, nnz >= 0, 1 <= K <= 64, float32 products only,
+ * kappa = 0 (V + kappa would be dense), inner_iters = 1 (else
+ * NMF_ERR_UNSUPPORTED).  gamma(1) = 1, so opts->exponent changes nothing.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int64_t F, N, nnz;
+  const int64_t* row_ptr;  /* [F + 1]: entries of row f are row_ptr[f] .. row_ptr[f + 1] - 1 */
+  const int32_t* col_idx;  /* [nnz]: column of each entry, in row order */
+  const float* row_val;    /* [nnz]: value of each entry, in row order (>= 0) */
+  const int64_t* col_ptr;  /* [N + 1]: entries of column n, in column order */
+  const int32_t* row_idx;  /* [nnz]: row of each entry, in column order */
+  const float* col_val;    /* [nnz]: the same values, in column order */
+} nmf_sparse_v;
+
+/* One outer iteration at beta = 1 on a sparse V, in place on W (F x K, ld ldw)
+ * and H (K x N, ld ldh); mode NMF_JOINT or NMF_ALTERNATING; opts as for
+ * nmf_beta_step within the limits above (normalize is honoured).  d_objective
+ * (device double, nullable) receives D_1(V | W~H~) of the entry iterate. */
+nmf_status nmf_kl_step_sparse(nmf_ctx_t ctx, void* stream, const nmf_sparse_v* V, int64_t K, float* W,
+                              int64_t ldw, float* H, int64_t ldh, int32_t mode,
+                              const nmf_step_opts* opts, double* d_objective);
+
+/* D_1(V | WH) for a sparse V, written to the device double *d_out. */
+nmf_status nmf_kl_objective_sparse(nmf_ctx_t ctx, void* stream, const nmf_sparse_v* V, int64_t K,
+                                   const float* W, int64_t ldw, const float* H, int64_t ldh,
+                                   double* d_out);
+
+/* Scans both orders of a sparse V and sets NMF_FLAG_DOMAIN when a pointer array
+ * does not start at 0, end at nnz and never decrease, an index is out of range
+ * or not ascending within its row (column), or a value is negative or not
+ * finite. */
+nmf_status nmf_sparse_validate(nmf_ctx_t ctx, void* stream, const nmf_sparse_v* V);
 
 /* ---------------------------------------------------------------------------
  * Many problems in one launch.

@@ -25,14 +25,16 @@ __all__ = [
     "NmfError", "lib", "library_path", "Context", "default_context",
     "ALTERNATING", "JOINT", "FP32", "BF16", "FP16", "EXPONENTS",
     "FLAG_NONFINITE", "FLAG_DOMAIN", "FLAG_BARRIER", "FLAG_RANGE", "KERNELS",
-    "step", "step_noalloc", "objective", "grad", "validate", "get_flags", "check_step_args", "Batch", "batch_tune",
+    "step", "step_noalloc", "objective", "grad", "SparseV", "kl_step_sparse", "kl_objective_sparse",
+    "sparse_validate", "validate", "get_flags", "check_step_args", "Batch", "batch_tune",
     "BetaDivergence", "beta_divergence",
 ]
 
 ALTERNATING, JOINT = 0, 1
 FP32, BF16, FP16 = 0, 1, 2
 FLAG_NONFINITE, FLAG_DOMAIN = 1, 2
-KERNELS = {"sweep_w": 0, "update_w": 1, "sweep_h": 2, "update_h": 3, "fused_step": 5}
+KERNELS = {"sweep_w": 0, "update_w": 1, "sweep_h": 2, "update_h": 3, "fused_step": 5, "sparse_pass": 6,
+           "sparse_cols": 7}
 PATHS = {"auto": 0, "stream": 1, "fused": 2}
 FLAG_BARRIER = 4
 FLAG_RANGE = 8  # float16 mode: an operand outside the float16 range
@@ -66,6 +68,12 @@ class _Problem(ctypes.Structure):
                 ("W", ctypes.c_void_p), ("ldw", ctypes.c_int64),
                 ("H", ctypes.c_void_p), ("ldh", ctypes.c_int64),
                 ("beta", ctypes.c_double)]
+
+
+class _SparseV(ctypes.Structure):
+    _fields_ = [("F", ctypes.c_int64), ("N", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p), ("row_val", ctypes.c_void_p),
+                ("col_ptr", ctypes.c_void_p), ("row_idx", ctypes.c_void_p), ("col_val", ctypes.c_void_p)]
 
 
 class _BatchConfig(ctypes.Structure):
@@ -116,6 +124,10 @@ def lib() -> ctypes.CDLL:
         L.nmf_set_launch.argtypes = [_vp, _i32, _i32]
         L.nmf_set_path.argtypes = [_vp, _i32]
         L.nmf_profile_phases.argtypes = [_vp, _vp, ctypes.POINTER(_dbl), _i32]
+        PS = ctypes.POINTER(_SparseV)
+        L.nmf_kl_step_sparse.argtypes = [_vp, _vp, PS, _i64, _vp, _i64, _vp, _i64, _i32, ctypes.POINTER(_Opts), _vp]
+        L.nmf_kl_objective_sparse.argtypes = [_vp, _vp, PS, _i64, _vp, _i64, _vp, _i64, _vp]
+        L.nmf_sparse_validate.argtypes = [_vp, _vp, PS]
         PP, PC = ctypes.POINTER(_Problem), ctypes.POINTER(_BatchConfig)
         L.nmf_batch_create.argtypes = [_vp, PP, _i32, _i32, ctypes.POINTER(_Opts), PC, ctypes.POINTER(_vp)]
         L.nmf_batch_step.argtypes = [_vp, _vp, _vp]
@@ -129,7 +141,8 @@ def lib() -> ctypes.CDLL:
                      "nmf_beta_objective", "nmf_beta_grad", "nmf_beta_validate", "nmf_get_flags",
                      "nmf_profile_enable", "nmf_profile_read", "nmf_set_launch", "nmf_set_path",
                      "nmf_profile_phases", "nmf_batch_create", "nmf_batch_step", "nmf_batch_get_flags",
-                     "nmf_batch_info", "nmf_batch_destroy", "nmf_batch_tune"):
+                     "nmf_batch_info", "nmf_batch_destroy", "nmf_batch_tune", "nmf_kl_step_sparse",
+                     "nmf_kl_objective_sparse", "nmf_sparse_validate"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -418,6 +431,86 @@ BetaDivergence = _LazyAutograd()
 def beta_divergence(V, W, H, beta: float, kappa: float = 0.0):
     """Differentiable D_beta(V + kappa | WH + kappa) (float64 0-d tensor)."""
     return BetaDivergence.apply(V, W, H, beta, kappa)
+
+
+# ---------------------------------------------------------------------------
+# beta = 1 with a sparse V
+# ---------------------------------------------------------------------------
+class SparseV:
+    """V (F x N) by its nonzero entries in row order (CSR) and column order (CSC),
+    as device tensors: row_ptr int64 [F + 1], col_idx int32 [nnz], row_val float32
+    [nnz], col_ptr int64 [N + 1], row_idx int32 [nnz], col_val float32 [nnz]."""
+
+    def __init__(self, F, N, row_ptr, col_idx, row_val, col_ptr, row_idx, col_val):
+        import torch
+        self.F, self.N = int(F), int(N)
+        self.nnz = int(col_idx.numel())
+        spec = [("row_ptr", row_ptr, torch.int64, self.F + 1), ("col_idx", col_idx, torch.int32, self.nnz),
+                ("row_val", row_val, torch.float32, self.nnz), ("col_ptr", col_ptr, torch.int64, self.N + 1),
+                ("row_idx", row_idx, torch.int32, self.nnz), ("col_val", col_val, torch.float32, self.nnz)]
+        for name, t, dt, n in spec:
+            if not isinstance(t, torch.Tensor) or t.dtype != dt or not t.is_cuda or t.numel() != n \
+                    or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous {dt} device tensor with {n} entries")
+            setattr(self, name, t)
+
+    @classmethod
+    def from_dense(cls, V):
+        """Both compressed orders of a dense V (device or host tensor / array)."""
+        import torch
+        V = torch.as_tensor(V)
+        dev = V.device if V.is_cuda else torch.device("cuda", torch.cuda.current_device())
+        V = V.to(dev, torch.float32)
+        F, N = V.shape
+
+        def compress(M, lines):
+            idx = torch.nonzero(M)  # row-major order: lines ascending, then positions
+            ptr = torch.zeros(lines + 1, dtype=torch.int64, device=dev)
+            ptr[1:] = torch.cumsum(torch.bincount(idx[:, 0], minlength=lines), 0)
+            return ptr, idx[:, 1].to(torch.int32).contiguous(), M[idx[:, 0], idx[:, 1]].contiguous()
+
+        rp, ci, rv = compress(V, F)
+        cp, ri, cv = compress(V.t().contiguous(), N)
+        return cls(F, N, rp, ci, rv, cp, ri, cv)
+
+    def _struct(self):
+        return _SparseV(self.F, self.N, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
+                        self.row_val.data_ptr(), self.col_ptr.data_ptr(), self.row_idx.data_ptr(),
+                        self.col_val.data_ptr())
+
+
+def kl_step_sparse(Vs: SparseV, W, H, mode="joint", *, normalize: bool = True, objective_out=None, stream=None,
+                   ctx: Optional[Context] = None):
+    """One outer iteration at beta = 1 on a sparse V (nmf_kl_step_sparse), in place."""
+    m = MODES.get(mode, mode) if isinstance(mode, str) else int(mode)
+    pw, ldw = _mat(W, "W")
+    ph, ldh = _mat(H, "H")
+    K = W.shape[1]
+    if W.shape[0] != Vs.F or H.shape != (K, Vs.N):
+        raise ValueError("shape mismatch: W (F,K), H (K,N)")
+    o = _opts(normalize=normalize)
+    pobj = _dev_f64(objective_out, "objective_out") if objective_out is not None else None
+    sv = Vs._struct()
+    _check(lib().nmf_kl_step_sparse(_ctx(ctx), _stream(stream), ctypes.byref(sv), K, pw, ldw, ph, ldh, m,
+                                    ctypes.byref(o), pobj), "nmf_kl_step_sparse")
+
+
+def kl_objective_sparse(Vs: SparseV, W, H, *, out=None, stream=None, ctx=None):
+    """D_1(V | WH) for a sparse V as a 1-element float64 device tensor."""
+    import torch
+    pw, ldw = _mat(W, "W")
+    ph, ldh = _mat(H, "H")
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=W.device)
+    sv = Vs._struct()
+    _check(lib().nmf_kl_objective_sparse(_ctx(ctx), _stream(stream), ctypes.byref(sv), W.shape[1], pw, ldw, ph,
+                                         ldh, _dev_f64(out, "out")), "nmf_kl_objective_sparse")
+    return out
+
+
+def sparse_validate(Vs: SparseV, *, stream=None, ctx=None):
+    sv = Vs._struct()
+    _check(lib().nmf_sparse_validate(_ctx(ctx), _stream(stream), ctypes.byref(sv)), "nmf_sparse_validate")
 
 
 # ---------------------------------------------------------------------------

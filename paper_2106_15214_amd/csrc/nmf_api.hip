@@ -684,6 +684,58 @@ nmf_status step_impl(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K,
 }
 
 
+// ---------------------------------------------------------------------------
+// beta = 1 with a sparse V (kernels in nmf_sparse.hip)
+// ---------------------------------------------------------------------------
+nmf_status check_sparse(const nmf_sparse_v* V, int64_t K) {
+  if (!V || !V->row_ptr || !V->col_ptr) return NMF_ERR_NULL;
+  if (V->nnz > 0 && (!V->col_idx || !V->row_val || !V->row_idx || !V->col_val)) return NMF_ERR_NULL;
+  if (V->F < 1 || V->N < 1 || V->nnz < 0 || K < 1) return NMF_ERR_SHAPE;
+  if (V->F > INT32_MAX || V->N > INT32_MAX || V->nnz > V->F * V->N) return NMF_ERR_SHAPE;
+  if (K > 64) return NMF_ERR_UNSUPPORTED;
+  return NMF_OK;
+}
+
+// Workspace offsets of the sparse step (after the header).
+struct SparsePlan {
+  size_t ht, wc, wn, numw, numh, prow, pcw, pobj, pcol, total;
+  int hb, wcb, rb, cb, K4;
+};
+
+SparsePlan sparse_plan(int64_t F, int64_t N, int64_t K) {
+  SparsePlan p{};
+  p.K4 = (int)((K + 3) & ~int64_t(3));
+  sparse_blocks((int)F, (int)N, &p.hb, &p.wcb, &p.rb, &p.cb);
+  size_t o = kHeaderBytes;
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+  p.ht = take(sizeof(float) * (size_t)N * p.K4);
+  p.wc = take(sizeof(float) * (size_t)F * p.K4);
+  p.wn = take(sizeof(float) * (size_t)F * p.K4);
+  p.numw = take(sizeof(float) * (size_t)F * p.K4);
+  p.numh = take(sizeof(float) * (size_t)N * p.K4);
+  p.prow = take(sizeof(double) * (size_t)p.hb * p.K4);
+  p.pcw = take(sizeof(double) * (size_t)p.wcb * p.K4);
+  p.pobj = take(sizeof(double) * (size_t)p.rb);
+  p.pcol = take(sizeof(double) * (size_t)p.wcb * 2 * p.K4);
+  p.total = o;
+  return p;
+}
+
+SparseArgs sparse_args(const SparsePlan& p, char* ws, unsigned* flags, const nmf_sparse_v* V, int64_t K,
+                       float* W, int64_t ldw, float* H, int64_t ldh) {
+  SparseArgs a{};
+  a.F = (int)V->F; a.N = (int)V->N; a.K = (int)K; a.nnz = V->nnz;
+  a.row_ptr = V->row_ptr; a.col_idx = V->col_idx; a.row_val = V->row_val;
+  a.col_ptr = V->col_ptr; a.row_idx = V->row_idx; a.col_val = V->col_val;
+  a.Wio = W; a.ldw = ldw; a.Hio = H; a.ldh = ldh;
+  a.HT = (float*)(ws + p.ht); a.Wc = (float*)(ws + p.wc); a.Wn = (float*)(ws + p.wn);
+  a.numW = (float*)(ws + p.numw); a.numH = (float*)(ws + p.numh);
+  a.prow = (double*)(ws + p.prow); a.pcw = (double*)(ws + p.pcw);
+  a.pobj = (double*)(ws + p.pobj); a.pcol = (double*)(ws + p.pcol);
+  a.flags = flags;
+  return a;
+}
+
 }  // namespace
 
 extern "C" {
@@ -875,6 +927,81 @@ nmf_status nmf_beta_grad(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
     return NMF_ERR_HIP;
   if (d_objective) return hip_status(launch_finalize_objective(s, ra.pobj, sw_grid, d_objective, flags_ptr(c)));
   return NMF_OK;
+}
+
+nmf_status nmf_kl_step_sparse(nmf_ctx_t c, void* stream, const nmf_sparse_v* V, int64_t K, float* W, int64_t ldw,
+                              float* H, int64_t ldh, int32_t mode, const nmf_step_opts* opts, double* d_objective) {
+  if (!c || !W || !H) return NMF_ERR_NULL;
+  nmf_status st = check_sparse(V, K);
+  if (st != NMF_OK) return st;
+  if (ldw < K || ldh < V->N) return NMF_ERR_SHAPE;
+  if (mode != NMF_ALTERNATING && mode != NMF_JOINT) return NMF_ERR_ARG;
+  if ((st = check_opts(opts)) != NMF_OK) return st;
+  if (opts && (opts->precision != NMF_FP32 || opts->kappa != 0.f || opts->inner_iters != 1))
+    return NMF_ERR_UNSUPPORTED;
+  {
+    const size_t sw = span_bytes(V->F, K, ldw), sh = span_bytes(K, V->N, ldh);
+    if (overlaps(W, sw, H, sh)) return NMF_ERR_ALIAS;
+    const void* in[4] = {V->row_val, V->col_val, V->col_idx, V->row_idx};
+    const size_t ni[4] = {sizeof(float) * (size_t)V->nnz, sizeof(float) * (size_t)V->nnz,
+                          sizeof(int32_t) * (size_t)V->nnz, sizeof(int32_t) * (size_t)V->nnz};
+    for (int i = 0; i < 4; ++i)
+      if (overlaps(in[i], ni[i], W, sw) || overlaps(in[i], ni[i], H, sh)) return NMF_ERR_ALIAS;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const SparsePlan p = sparse_plan(V->F, V->N, K);
+  if ((st = ensure_ws(c, s, p.total)) != NMF_OK) return st;
+  if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
+  SparseArgs a = sparse_args(p, c->ws, flags_ptr(c), V, K, W, ldw, H, ldh);
+  a.normalize = opts ? opts->normalize : 1;
+  a.d_obj = d_objective;
+  if (!d_objective) a.pobj = nullptr;
+  hipError_t e = launch_sparse_prep(s, a);
+  if (e != hipSuccess) return NMF_ERR_HIP;
+  if (mode == NMF_JOINT) {
+    // the column pass needs only W~ and H~: both passes in one launch
+    a.Wg = a.Wc;
+    e = timed(c, NMF_KERNEL_SPARSE_PASS, s, [&] { return launch_sparse_pass(s, a, true, true); });
+    if (e == hipSuccess) e = launch_sparse_update_w(s, a);
+  } else {
+    e = timed(c, NMF_KERNEL_SPARSE_PASS, s, [&] { return launch_sparse_pass(s, a, true, false); });
+    if (e == hipSuccess) e = launch_sparse_update_w(s, a);
+    a.Wg = a.Wn;
+    if (e == hipSuccess)
+      e = timed(c, NMF_KERNEL_SPARSE_COLS, s, [&] { return launch_sparse_pass(s, a, false, true); });
+  }
+  if (e == hipSuccess) e = launch_sparse_update_h(s, a);
+  return hip_status(e);
+}
+
+nmf_status nmf_kl_objective_sparse(nmf_ctx_t c, void* stream, const nmf_sparse_v* V, int64_t K, const float* W,
+                                   int64_t ldw, const float* H, int64_t ldh, double* d_out) {
+  if (!c || !W || !H || !d_out) return NMF_ERR_NULL;
+  nmf_status st = check_sparse(V, K);
+  if (st != NMF_OK) return st;
+  if (ldw < K || ldh < V->N) return NMF_ERR_SHAPE;
+  hipStream_t s = (hipStream_t)stream;
+  const SparsePlan p = sparse_plan(V->F, V->N, K);
+  if ((st = ensure_ws(c, s, p.total)) != NMF_OK) return st;
+  if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
+  // the preparation kernels only read W and H
+  SparseArgs a = sparse_args(p, c->ws, flags_ptr(c), V, K, const_cast<float*>(W), ldw, const_cast<float*>(H), ldh);
+  return hip_status(launch_sparse_objective(s, a, d_out));
+}
+
+nmf_status nmf_sparse_validate(nmf_ctx_t c, void* stream, const nmf_sparse_v* V) {
+  if (!c) return NMF_ERR_NULL;
+  nmf_status st = check_sparse(V, 1);
+  if (st != NMF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = ensure_ws(c, s, kHeaderBytes)) != NMF_OK) return st;
+  if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
+  SparseArgs a{};
+  a.F = (int)V->F; a.N = (int)V->N; a.nnz = V->nnz;
+  a.row_ptr = V->row_ptr; a.col_idx = V->col_idx; a.row_val = V->row_val;
+  a.col_ptr = V->col_ptr; a.row_idx = V->row_idx; a.col_val = V->col_val;
+  a.flags = flags_ptr(c);
+  return hip_status(launch_sparse_validate(s, a));
 }
 
 nmf_status nmf_beta_validate(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K, const float* V,

@@ -186,6 +186,40 @@ struct BatchArgs {
 hipError_t launch_batched(int prec, bool joint, int grid, hipStream_t s, const BatchArgs& a);
 int batched_max_blocks(int prec, bool joint, int num_cus);
 
+// beta = 1 step for a V stored by its nonzeros in both compressed orders
+// (nmf_sparse.hip).  Workspace arrays are K4-padded (K4 = K rounded up to 4).
+struct SparseArgs {
+  int F, N, K, normalize;
+  int64_t nnz;
+  const int64_t* row_ptr; const int32_t* col_idx; const float* row_val;  // CSR
+  const int64_t* col_ptr; const int32_t* row_idx; const float* col_val;  // CSC (same entries)
+  float* Wio; int64_t ldw;   // caller's W (read as W~, written as the result)
+  float* Hio; int64_t ldh;   // caller's H
+  float* HT;                 // [N][K4] H~ transposed
+  float* Wc;                 // [F][K4] W~
+  float* Wn;                 // [F][K4] W_new
+  const float* Wg;           // gather table of the column pass (Wc or Wn)
+  float* numW;               // [F][K4]
+  float* numH;               // [N][K4]
+  double* prow;              // [ceil(N / 64)][K4] partial row sums of H~
+  double* pcw;               // [ceil(F / 64)][K4] partial column sums of W~
+  double* pobj;              // [row-pass blocks] objective partials (nullable: no objective)
+  double* pcol;              // [ceil(F / 64)][2][K4] column sums and squares of W_new
+  double* d_obj;             // objective of the entry iterate (nullable)
+  unsigned* flags;
+};
+// grid sizes: transpose / copy blocks of H and W (64 each), row- and column-pass
+// blocks (four lines each)
+int sparse_blocks(int F, int N, int* hb, int* wcb, int* rb, int* cb);
+// one step: prep; joint: pass(rows + cols), update_w; alternating: pass(rows),
+// update_w, pass(cols) with a.Wg = a.Wn; then update_h
+hipError_t launch_sparse_prep(hipStream_t s, const SparseArgs& a);
+hipError_t launch_sparse_pass(hipStream_t s, const SparseArgs& a, bool rows, bool cols);
+hipError_t launch_sparse_update_w(hipStream_t s, const SparseArgs& a);
+hipError_t launch_sparse_update_h(hipStream_t s, const SparseArgs& a);
+hipError_t launch_sparse_objective(hipStream_t s, const SparseArgs& a, double* d_out);
+hipError_t launch_sparse_validate(hipStream_t s, const SparseArgs& a);
+
 hipError_t launch_validate(hipStream_t s, const float* V, int64_t ldv, const float* W, int64_t ldw,
                            const float* H, int64_t ldh, int F, int N, int K, int zero_bad, unsigned* flags);
 
