@@ -516,12 +516,14 @@ def time_to_objective(nb, torch, np, ctx, V, W0, H0, beta, T, precision, dev, in
             it = int(hit[0]) if hit.size else None
             row[mode] = {"iterations": it, "ms": (it * tper[mode]) if it is not None else None}
         tto[str(q)] = row
+    # the stopping rule of Sec. 4.1.2 (eps = 1e-5) evaluated on the device by
+    # the library's run call, from the same init, within the same T iterations
     stop = {}
     for mode in ("joint", "alternating"):
-        d = traces[mode]
-        rd = (d[:-1] - d[1:]) / d[1:]
-        hit = np.nonzero(rd <= 1e-5)[0]
-        stop[mode] = int(hit[0] + 1) if hit.size else None
+        W, H = W0.clone(), H0.clone()
+        _, st = nb.run(V, W, H, beta, mode, max_iters=T, eps=1e-5, precision=precision, inner_iters=inner, ctx=ctx)
+        t_stop = int(st.item())
+        stop[mode] = t_stop if t_stop >= 0 else None
     mono = {m: int(np.sum(np.diff(traces[m]) > 0)) for m in traces}
     return {"T": T, "D0": float(D0), "D_T": {m: float(traces[m][-1]) for m in traces}, "ms_per_iteration": tper,
             "targets": tto, "stop_rule_1e-5_iteration": stop, "objective_increases": mono, "_traces": traces}

@@ -210,6 +210,32 @@ nmf_status nmf_beta_grad(nmf_ctx_t ctx, void* stream, int64_t F, int64_t N, int6
                          const double* d_scale, float* dW, int64_t lddw, float* dH, int64_t lddh,
                          double* d_objective);
 
+/* KKT residuals of Sec. 4.1.5 at (W, H), written to the device doubles
+ * d_res[0] = || min(W, grad_W D) ||_1 / (F K) and d_res[1] = || min(H, grad_H D) ||_1 / (K N),
+ * with D = D_beta(V + kappa | WH + kappa) and the gradients of nmf_beta_grad
+ * (float32 passes, float64 minimum, absolute value and sums). */
+nmf_status nmf_beta_kkt(nmf_ctx_t ctx, void* stream, int64_t F, int64_t N, int64_t K,
+                        const float* V, int64_t ldv, const float* W, int64_t ldw,
+                        const float* H, int64_t ldh, double beta, float kappa, double* d_res);
+
+/* Up to max_iters outer iterations (nmf_beta_step with these mode and opts) with
+ * the stopping rule of Sec. 4.1.2 evaluated on the device, so that the whole
+ * run can be captured in one graph and needs no host synchronization:
+ *   d_trace[t] = D_beta(V + kappa | W_t H_t + kappa) of iterate t (t = 0 the
+ *   caller's W, H), formed in iterate t's own pass over V;
+ *   the run stops at the first t >= 1 with (d_trace[t-1] - d_trace[t]) / d_trace[t]
+ *   <= eps (as printed, no absolute value; the paper uses eps = 1e-5): W, H then
+ *   hold iterate t, *d_stop = t, and d_trace[t+1 ..] are not written.  Without a
+ *   stop, W, H hold iterate max_iters, d_trace[max_iters] its objective, and
+ *   *d_stop = -1.
+ * Every launch after the stop does nothing (each kernel reads the halt word).
+ * d_trace (device double[max_iters + 1]) and d_stop (device int32) are caller
+ * memory.  The single-launch path is not used.  max_iters >= 0. */
+nmf_status nmf_beta_run(nmf_ctx_t ctx, void* stream, int64_t F, int64_t N, int64_t K,
+                        const float* V, int64_t ldv, float* W, int64_t ldw, float* H, int64_t ldh,
+                        double beta, int32_t mode, const nmf_step_opts* opts, int32_t max_iters,
+                        double eps, double* d_trace, int32_t* d_stop);
+
 /* Scans V, W, H once and sets NMF_FLAG_DOMAIN if V has a negative or non-finite
  * entry, W or H a non-positive or non-finite entry, or (beta <= 0, kappa == 0) V
  * has a zero (where d_beta is infinite, Sec. 4.1.3). */

@@ -25,7 +25,7 @@ __all__ = [
     "NmfError", "lib", "library_path", "Context", "default_context",
     "ALTERNATING", "JOINT", "FP32", "BF16", "FP16", "EXPONENTS",
     "FLAG_NONFINITE", "FLAG_DOMAIN", "FLAG_BARRIER", "FLAG_RANGE", "KERNELS",
-    "step", "step_noalloc", "objective", "grad", "SparseV", "kl_step_sparse", "kl_objective_sparse",
+    "step", "step_noalloc", "run", "kkt", "objective", "grad", "SparseV", "kl_step_sparse", "kl_objective_sparse",
     "sparse_validate", "validate", "get_flags", "check_step_args", "Batch", "batch_tune",
     "BetaDivergence", "beta_divergence",
 ]
@@ -116,6 +116,9 @@ def lib() -> ctypes.CDLL:
                                          _dbl, _flt, _vp]
         L.nmf_beta_grad.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
                                     _dbl, _flt, _dbl, _vp, _vp, _i64, _vp, _i64, _vp]
+        L.nmf_beta_kkt.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _dbl, _flt, _vp]
+        L.nmf_beta_run.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _dbl, _i32,
+                                   ctypes.POINTER(_Opts), _i32, _dbl, _vp, _vp]
         L.nmf_beta_validate.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
                                         _dbl, _flt]
         L.nmf_get_flags.argtypes = [_vp, _vp, ctypes.POINTER(_u32), _i32]
@@ -137,7 +140,7 @@ def lib() -> ctypes.CDLL:
         L.nmf_batch_tune.argtypes = [_vp, PP, _i32, _i32, ctypes.POINTER(_Opts), _vp, _i32, PC,
                                      ctypes.POINTER(_dbl)]
         for name in ("nmf_create", "nmf_destroy", "nmf_reserve", "nmf_check_step_args", "nmf_beta_step",
-                     "nmf_beta_step_noalloc",
+                     "nmf_beta_step_noalloc", "nmf_beta_kkt", "nmf_beta_run",
                      "nmf_beta_objective", "nmf_beta_grad", "nmf_beta_validate", "nmf_get_flags",
                      "nmf_profile_enable", "nmf_profile_read", "nmf_set_launch", "nmf_set_path",
                      "nmf_profile_phases", "nmf_batch_create", "nmf_batch_step", "nmf_batch_get_flags",
@@ -367,6 +370,50 @@ def grad(V, W, H, beta: float, *, kappa: float = 0.0, scale: float = 1.0, scale_
                              ph, ldh, float(beta), float(kappa), float(scale), psc, pdw, lddw, pdh, lddh, pobj)
     _check(st, "nmf_beta_grad")
     return dW, dH
+
+
+def kkt(V, W, H, beta: float, *, kappa: float = 0.0, out=None, stream=None, ctx=None):
+    """KKT residuals (res(W), res(H)) of Sec. 4.1.5 as a 2-element float64 device tensor."""
+    import torch
+    pv, ldv = _mat(V, "V")
+    pw, ldw = _mat(W, "W")
+    ph, ldh = _mat(H, "H")
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=V.device)
+    st = lib().nmf_beta_kkt(_ctx(ctx), _stream(stream), V.shape[0], V.shape[1], W.shape[1], pv, ldv, pw, ldw,
+                            ph, ldh, float(beta), float(kappa), _dev_f64(out, "out", 2))
+    _check(st, "nmf_beta_kkt")
+    return out
+
+
+def run(V, W, H, beta: float, mode="joint", max_iters: int = 1000, eps: float = 1e-5, *, precision="fp32",
+        kappa: float = 0.0, normalize: bool = True, exponent="mm", inner_iters: int = 1, trace=None, stop=None,
+        stream=None, ctx: Optional[Context] = None):
+    """Up to max_iters outer iterations with the stopping rule of Sec. 4.1.2 on
+    the device (nmf_beta_run).  Returns (trace, stop): a float64 device tensor of
+    max_iters + 1 objectives (entries after the stop are left as given) and an
+    int32 device tensor holding the stop iteration or -1."""
+    import torch
+    m = MODES.get(mode, mode) if isinstance(mode, str) else int(mode)
+    pv, ldv = _mat(V, "V")
+    pw, ldw = _mat(W, "W")
+    ph, ldh = _mat(H, "H")
+    F, N = V.shape
+    K = W.shape[1]
+    if W.shape[0] != F or H.shape != (K, N):
+        raise ValueError("shape mismatch: V (F,N), W (F,K), H (K,N)")
+    if trace is None:
+        trace = torch.full((int(max_iters) + 1,), float("nan"), dtype=torch.float64, device=V.device)
+    if stop is None:
+        stop = torch.empty(1, dtype=torch.int32, device=V.device)
+    if stop.dtype != torch.int32 or not stop.is_cuda or stop.numel() < 1:
+        raise ValueError("stop must be an int32 device tensor")
+    o = _opts(precision, kappa, inner_iters, normalize, exponent)
+    st = lib().nmf_beta_run(_ctx(ctx), _stream(stream), F, N, K, pv, ldv, pw, ldw, ph, ldh, float(beta), m,
+                            ctypes.byref(o), int(max_iters), float(eps), _dev_f64(trace, "trace", int(max_iters) + 1),
+                            stop.data_ptr())
+    _check(st, "nmf_beta_run")
+    return trace, stop
 
 
 def validate(V, W, H, beta: float, *, kappa: float = 0.0, stream=None, ctx=None):

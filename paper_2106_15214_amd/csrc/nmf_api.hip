@@ -74,8 +74,10 @@ namespace {
 
 // Workspace header (zeroed at allocation): the sticky flags word at byte 0,
 // the fused kernel's grid-barrier words (arrivals, generation) at bytes 8, 12,
-// and its eight phase stamps (uint64) at bytes 64..127.
+// its eight phase stamps (uint64) at bytes 64..127, and the halt word of the
+// device-side outer loop at byte 128.
 constexpr size_t kHeaderBytes = 256;
+constexpr size_t kHaltOffset = 128;  // halt word of the device-side outer loop (nmf_beta_run)
 constexpr int kFusedMaxPerCU = 8;      // bound on co-resident fused workgroups per CU (workspace sizing)
 constexpr int kUpdateWBlocks = 4096;  // W-update workgroups at most (one unit of rows each, or more)
 constexpr int kColChunkRows = 512;  // rows of W_new per column-partial workgroup of the H pass
@@ -498,6 +500,23 @@ constexpr unsigned kBatchSpinLimit = 1u << 22;
 // place), then L H updates against the final W_new, each forming W_new H from
 // the latest H.  Only the first W pass forms the objective of the entry
 // iterate; only the last H update normalizes, writes W and the objective.
+// Device-side outer loop (nmf_beta_run): every step kernel is gated by *halt,
+// and after the W pass of iterate t (which forms its objective partials) a
+// decide kernel writes trace[t] and applies the stopping rule.
+struct RunCtl {
+  unsigned* halt;
+  double* trace;
+  int t;
+  double eps;
+  int32_t* stop;
+};
+
+hipError_t run_decide_after_w(const RunCtl* run, hipStream_t s, const StepArgs& sa) {
+  if (!run) return hipSuccess;
+  return launch_run_decide(s, sa.ra.pobj, sa.sw_grid, run->trace, run->t, run->eps, run->halt, run->stop,
+                           sa.ra.flags);
+}
+
 // Launches fn, between two timing events when the kernel is selected for
 // profiling and the call may use them (`quiet`: never, no event is created).
 template <class Fn>
@@ -506,7 +525,7 @@ hipError_t run_k(nmf_ctx_s* c, bool quiet, int kernel, hipStream_t s, Fn&& fn) {
 }
 
 nmf_status inner_steps(nmf_ctx_s* c, hipStream_t s, const Plan& p, const StepArgs& sa, int bc, bool want_obj,
-                              int L, int prec, bool quiet) {
+                              int L, int prec, bool quiet, const RunCtl* run) {
   for (int l = 0; l < L; ++l) {
     SweepRowsArgs ra = sa.ra;
     UpdateWArgs ua = sa.ua;
@@ -519,6 +538,7 @@ nmf_status inner_steps(nmf_ctx_s* c, hipStream_t s, const Plan& p, const StepArg
       return prec == NMF_FP32 ? launch_sweep_rows(bc, p.KB, KIND_UPDATE, obj, false, sa.sw_grid, s, ra)
                               : launch_sweep_rows_lp(prec, bc, p.KB, obj, false, sa.sw_grid, s, ra);
     });
+    if (e == hipSuccess && l == 0) e = run_decide_after_w(run, s, sa);
     if (e != hipSuccess) return NMF_ERR_HIP;
     e = run_k(c, quiet, NMF_KERNEL_UPDATE_W, s, [&] { return launch_update_w(p.KB, p.uw_blocks, s, ua); });
     if (e != hipSuccess) return NMF_ERR_HIP;
@@ -548,7 +568,7 @@ nmf_status inner_steps(nmf_ctx_s* c, hipStream_t s, const Plan& p, const StepArg
 // before the last write chi_1(H_{l+1}, H~), chi_2(H_{l+1}, H~) to the workspace
 // instead of H; the last writes H, normalizes, writes W and the objective.
 nmf_status inner_steps_joint(nmf_ctx_s* c, hipStream_t s, const Plan& p, const StepArgs& sa, int bc, bool want_obj,
-                             int L, char* ws, bool quiet) {
+                             int L, char* ws, bool quiet, const RunCtl* run) {
   float* const C1h = (float*)(ws + p.o_c1h);
   float* const C2h = (float*)(ws + p.o_c2h);
   for (int l = 0; l < L; ++l) {
@@ -557,6 +577,7 @@ nmf_status inner_steps_joint(nmf_ctx_s* c, hipStream_t s, const Plan& p, const S
       e = run_k(c, quiet, NMF_KERNEL_SWEEP_W, s, [&] {
         return launch_sweep_rows(bc, p.KB, KIND_UPDATE, want_obj, true, sa.sw_grid, s, sa.ra);
       });
+      if (e == hipSuccess) e = run_decide_after_w(run, s, sa);
     } else {
       SweepRowsArgs rq = sa.ra;
       rq.H = C1h; rq.ldh = p.ldc;
@@ -587,7 +608,8 @@ nmf_status inner_steps_joint(nmf_ctx_s* c, hipStream_t s, const Plan& p, const S
 // step keeps P, Q between its passes only when they fit in the scratch.
 nmf_status step_impl(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K, const float* V, int64_t ldv,
                      float* W, int64_t ldw, float* H, int64_t ldh, double beta, int32_t mode,
-                     const nmf_step_opts* opts, double* d_objective, bool no_alloc, unsigned* flags) {
+                     const nmf_step_opts* opts, double* d_objective, bool no_alloc, unsigned* flags,
+                     const RunCtl* run = nullptr) {
   if (!c) return NMF_ERR_NULL;
   nmf_status st = nmf_check_step_args(F, N, K, V, ldv, W, ldw, H, ldh, beta, mode, opts);
   if (st != NMF_OK) return st;
@@ -597,20 +619,20 @@ nmf_status step_impl(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K,
   hipStream_t s = (hipStream_t)stream;
   const int bc = beta_class(beta);
   const bool joint = (mode == NMF_JOINT);
-  const bool want_obj = d_objective != nullptr;
+  const bool want_obj = d_objective != nullptr || run != nullptr;
   const int prec = opts ? opts->precision : NMF_FP32;
   if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
   // path: one cooperative launch for problems whose P, Q tiles stay cache
   // resident (not under stream capture), else four streaming launches
   const int L = o.inner_iters;
   int fused_grid = 0;
-  if (!no_alloc && c->path == NMF_PATH_FUSED && L == 1 && prec == NMF_FP32 && kblocks_for(K) <= 2 &&
+  if (!no_alloc && !run && c->path == NMF_PATH_FUSED && L == 1 && prec == NMF_FP32 && kblocks_for(K) <= 2 &&
       F * N <= kFusedMaxEntries) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess) return NMF_ERR_HIP;
     if (cs == hipStreamCaptureStatusNone) fused_grid = fused_capacity(c, bc, kblocks_for(K), joint, want_obj);
   }
-  if (!no_alloc && c->path == NMF_PATH_FUSED && fused_grid <= 0) return NMF_ERR_UNSUPPORTED;
+  if (!no_alloc && !run && c->path == NMF_PATH_FUSED && fused_grid <= 0) return NMF_ERR_UNSUPPORTED;
   bool use_pq = joint && fused_grid == 0 && F * N <= kPQMaxEntries;
   const int cols_occ = sweep_cols_occupancy(bc, kblocks_for(K), KIND_UPDATE, joint);
   Plan p = make_plan(c, F, N, K, cols_occ, fused_grid, use_pq, joint && L > 1);
@@ -635,6 +657,10 @@ nmf_status step_impl(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K,
   UpdateWArgs& ua = sa.ua;
   SweepColsArgs& ca = sa.ca;
   UpdateHArgs& ha = sa.ha;
+  if (run) {
+    ra.halt = ua.halt = ca.halt = ha.halt = run->halt;
+    ha.d_obj = nullptr;  // the decide kernel writes the trace
+  }
   const int sw_grid = sa.sw_grid, sh_grid = sa.sh_grid;
 
   if (p.fused) {
@@ -665,12 +691,13 @@ nmf_status step_impl(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K,
     ca.NT = ra.NT; ca.Pst = ra.Pst; ca.Qst = ra.Qst;
   }
   if (L > 1)
-    return joint ? inner_steps_joint(c, s, p, sa, bc, want_obj, L, ws, quiet)
-                 : inner_steps(c, s, p, sa, bc, want_obj, L, prec, quiet);
+    return joint ? inner_steps_joint(c, s, p, sa, bc, want_obj, L, ws, quiet, run)
+                 : inner_steps(c, s, p, sa, bc, want_obj, L, prec, quiet, run);
   hipError_t e = run_k(c, quiet, NMF_KERNEL_SWEEP_W, s, [&] {
     return prec == NMF_FP32 ? launch_sweep_rows(bc, p.KB, KIND_UPDATE, want_obj, p.pq, sw_grid, s, ra)
                             : launch_sweep_rows_lp(prec, bc, p.KB, want_obj, p.pq, sw_grid, s, ra);
   });
+  if (e == hipSuccess) e = run_decide_after_w(run, s, sa);
   if (e != hipSuccess) return NMF_ERR_HIP;
   e = run_k(c, quiet, NMF_KERNEL_UPDATE_W, s, [&] { return launch_update_w(p.KB, p.uw_blocks, s, ua); });
   if (e != hipSuccess) return NMF_ERR_HIP;
@@ -734,6 +761,47 @@ SparseArgs sparse_args(const SparsePlan& p, char* ws, unsigned* flags, const nmf
   a.pobj = (double*)(ws + p.pobj); a.pcol = (double*)(ws + p.pcol);
   a.flags = flags;
   return a;
+}
+
+// The two gradient passes of nmf_beta_grad / nmf_beta_kkt: E = Lambda^(beta-2)
+// (Lambda - V) contracted with H^T (row pass) and W^T (column pass), as partial
+// sums in the workspace of plan p (and the objective partials with want_obj).
+struct GradParts {
+  hipError_t e;
+  const float* pnumw;
+  const float* pnumh;
+  double* pobj;
+  int sw_grid;
+};
+
+GradParts grad_passes(nmf_ctx_s* c, hipStream_t s, const Plan& p, int64_t F, int64_t N, int64_t K, const float* V,
+                      int64_t ldv, const float* W, int64_t ldw, const float* H, int64_t ldh, double beta,
+                      float kappa, bool want_obj) {
+  const int bc = beta_class(beta);
+  char* ws = c->ws;
+  SweepRowsArgs ra{};
+  ra.V = V; ra.ldv = ldv; ra.W = W; ra.ldw = ldw; ra.H = H; ra.ldh = ldh;
+  ra.F = (int)F; ra.N = (int)N; ra.K = (int)K;
+  ra.bm2 = (float)(beta - 2.0); ra.kappa = kappa; ra.beta = beta;
+  ra.n_groups = p.n_groups; ra.tiles_per_group = p.tiles_n;
+  ra.pnum = (float*)(ws + p.o_pnum); ra.pobj = (double*)(ws + p.o_pobj);
+  ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
+  ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
+  ra.vstream = stream_v(F, N);
+  GradParts g{hipSuccess, ra.pnum, (float*)(ws + p.o_pnumh), ra.pobj, p.row_blocks * p.n_groups};
+  g.e = launch_sweep_rows(bc, p.KB, KIND_GRAD, want_obj, false, g.sw_grid, s, ra);
+  if (g.e != hipSuccess) return g;
+  float* WT = (float*)(ws + p.o_wt);
+  float* Wp = (float*)(ws + p.o_wn);
+  if ((g.e = launch_transpose(s, W, ldw, (int)F, (int)K, p.KP, WT, p.ldt, Wp)) != hipSuccess) return g;
+  SweepColsArgs ca{};
+  ca.V = V; ca.ldv = ldv; ca.WT = WT; ca.ldwt = p.ldt; ca.C1 = Wp; ca.C2 = Wp;
+  ca.H = H; ca.ldh = ldh; ca.F = (int)F; ca.N = (int)N; ca.K = (int)K;
+  ca.bm2 = (float)(beta - 2.0); ca.kappa = kappa;
+  ca.f_groups = p.f_groups; ca.tiles_per_group = p.tiles_f;
+  ca.pnum = (float*)(ws + p.o_pnumh);
+  g.e = launch_sweep_cols(bc, p.KB, KIND_GRAD, false, false, p.col_blocks * p.f_groups, s, ca);
+  return g;
 }
 
 }  // namespace
@@ -893,40 +961,81 @@ nmf_status nmf_beta_grad(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_
   const Plan p = make_plan(c, F, N, K);
   if ((st = ensure_ws(c, s, p.total)) != NMF_OK) return st;
   if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
-  const int bc = beta_class(beta);
-  char* ws = c->ws;
+  GradParts g = grad_passes(c, s, p, F, N, K, V, ldv, W, ldw, H, ldh, beta, kappa, d_objective != nullptr);
+  if (g.e != hipSuccess) return NMF_ERR_HIP;
+  hipError_t e;
+  const int gw = (int)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(F * K, kBlock)));
+  if ((e = launch_grad_w(p.KB, gw, s, g.pnumw, (int)F, (int)K, p.n_groups, scale, d_scale, dW, lddw)) != hipSuccess)
+    return NMF_ERR_HIP;
+  if ((e = launch_grad_h(p.KB, (int)cdiv(N, kTile), s, g.pnumh, (int)N, (int)K, p.f_groups, scale, d_scale, dH,
+                         lddh)) != hipSuccess)
+    return NMF_ERR_HIP;
+  if (d_objective) return hip_status(launch_finalize_objective(s, g.pobj, g.sw_grid, d_objective, flags_ptr(c)));
+  return NMF_OK;
+}
+
+nmf_status nmf_beta_kkt(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K, const float* V, int64_t ldv,
+                        const float* W, int64_t ldw, const float* H, int64_t ldh, double beta, float kappa,
+                        double* d_res) {
+  if (!c || !d_res) return NMF_ERR_NULL;
+  nmf_status st = check_mats(F, N, K, V, ldv, W, ldw, H, ldh);
+  if (st != NMF_OK) return st;
+  if (!is_fin(beta) || !std::isfinite(kappa) || kappa < 0.f) return NMF_ERR_BETA;
+  hipStream_t s = (hipStream_t)stream;
+  const Plan p = make_plan(c, F, N, K);
+  const size_t part_off = align_up(p.total);
+  if ((st = ensure_ws(c, s, part_off + sizeof(double) * (size_t)kkt_parts())) != NMF_OK) return st;
+  if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
+  GradParts g = grad_passes(c, s, p, F, N, K, V, ldv, W, ldw, H, ldh, beta, kappa, false);
+  if (g.e != hipSuccess) return NMF_ERR_HIP;
+  return hip_status(launch_kkt(p.KB, s, g.pnumw, p.n_groups, g.pnumh, p.f_groups, W, ldw, H, ldh, (int)F, (int)N,
+                               (int)K, (double*)(c->ws + part_off), d_res));
+}
+
+nmf_status nmf_beta_run(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K, const float* V, int64_t ldv,
+                        float* W, int64_t ldw, float* H, int64_t ldh, double beta, int32_t mode,
+                        const nmf_step_opts* opts, int32_t max_iters, double eps, double* d_trace, int32_t* d_stop) {
+  if (!c || !d_trace || !d_stop) return NMF_ERR_NULL;
+  if (max_iters < 0 || !std::isfinite(eps)) return NMF_ERR_ARG;
+  nmf_status st = nmf_check_step_args(F, N, K, V, ldv, W, ldw, H, ldh, beta, mode, opts);
+  if (st != NMF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  // the workspace of the steps (reserved before the first launch, so that the
+  // steps below never reallocate it) plus the objective-only pass
+  {
+    nmf_step_opts o;
+    nmf_default_opts(&o);
+    if (opts) o = *opts;
+    const bool joint = mode == NMF_JOINT;
+    const bool pq = joint && F * N <= kPQMaxEntries;
+    const Plan p = make_plan(c, F, N, K, sweep_cols_occupancy(beta_class(beta), kblocks_for(K), KIND_UPDATE, joint),
+                             0, pq, joint && o.inner_iters > 1);
+    if ((st = ensure_ws(c, s, std::max(p.total, make_plan(c, F, N, K).total))) != NMF_OK) return st;
+  }
+  if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
+  RunCtl run{(unsigned*)(c->ws + kHaltOffset), d_trace, 0, eps, d_stop};
+  if (launch_run_init(s, run.halt, d_stop) != hipSuccess) return NMF_ERR_HIP;
+  for (int t = 0; t < max_iters; ++t) {
+    run.t = t;
+    st = step_impl(c, stream, F, N, K, V, ldv, W, ldw, H, ldh, beta, mode, opts, nullptr, false, nullptr, &run);
+    if (st != NMF_OK) return st;
+  }
+  // the objective of the last iterate and the rule at t = max_iters
+  const Plan p = make_plan(c, F, N, K);
   SweepRowsArgs ra{};
   ra.V = V; ra.ldv = ldv; ra.W = W; ra.ldw = ldw; ra.H = H; ra.ldh = ldh;
   ra.F = (int)F; ra.N = (int)N; ra.K = (int)K;
-  ra.bm2 = (float)(beta - 2.0); ra.kappa = kappa; ra.beta = beta;
+  ra.bm2 = (float)(beta - 2.0); ra.kappa = opts ? opts->kappa : 0.f; ra.beta = beta;
   ra.n_groups = p.n_groups; ra.tiles_per_group = p.tiles_n;
-  ra.pnum = (float*)(ws + p.o_pnum); ra.pobj = (double*)(ws + p.o_pobj);
+  ra.pobj = (double*)(c->ws + p.o_pobj);
   ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
   ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
   ra.vstream = stream_v(F, N);
-  const int sw_grid = p.row_blocks * p.n_groups;
-  hipError_t e = launch_sweep_rows(bc, p.KB, KIND_GRAD, d_objective != nullptr, false, sw_grid, s, ra);
+  ra.halt = run.halt;
+  const int grid = p.row_blocks * p.n_groups;
+  hipError_t e = launch_sweep_rows(beta_class(beta), p.KB, KIND_OBJ, true, false, grid, s, ra);
   if (e != hipSuccess) return NMF_ERR_HIP;
-  float* WT = (float*)(ws + p.o_wt);
-  float* Wp = (float*)(ws + p.o_wn);
-  if ((e = launch_transpose(s, W, ldw, (int)F, (int)K, p.KP, WT, p.ldt, Wp)) != hipSuccess) return NMF_ERR_HIP;
-  SweepColsArgs ca{};
-  ca.V = V; ca.ldv = ldv; ca.WT = WT; ca.ldwt = p.ldt; ca.C1 = Wp; ca.C2 = Wp;
-  ca.H = H; ca.ldh = ldh; ca.F = (int)F; ca.N = (int)N; ca.K = (int)K;
-  ca.bm2 = (float)(beta - 2.0); ca.kappa = kappa;
-  ca.f_groups = p.f_groups; ca.tiles_per_group = p.tiles_f;
-  ca.pnum = (float*)(ws + p.o_pnumh);
-  e = launch_sweep_cols(bc, p.KB, KIND_GRAD, false, false, p.col_blocks * p.f_groups, s, ca);
-  if (e != hipSuccess) return NMF_ERR_HIP;
-  const int gw = (int)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(F * K, kBlock)));
-  if ((e = launch_grad_w(p.KB, gw, s, ra.pnum, (int)F, (int)K, p.n_groups, scale, d_scale, dW, lddw)) != hipSuccess)
-    return NMF_ERR_HIP;
-  if ((e = launch_grad_h(p.KB, (int)cdiv(N, kTile), s, ca.pnum, (int)N, (int)K, p.f_groups, scale, d_scale, dH,
-                         lddh)) !=
-      hipSuccess)
-    return NMF_ERR_HIP;
-  if (d_objective) return hip_status(launch_finalize_objective(s, ra.pobj, sw_grid, d_objective, flags_ptr(c)));
-  return NMF_OK;
+  return hip_status(launch_run_decide(s, ra.pobj, grid, d_trace, max_iters, eps, run.halt, d_stop, flags_ptr(c)));
 }
 
 nmf_status nmf_kl_step_sparse(nmf_ctx_t c, void* stream, const nmf_sparse_v* V, int64_t K, float* W, int64_t ldw,

@@ -64,6 +64,7 @@ struct SweepRowsArgs {
   int vstream;                     // V loads with the nontemporal hint (V larger than the cache)
   unsigned* flags;                 // status word (float16 range check)
   float* Pst; float* Qst; int NT;  // P, Q tiles [row tile * NT + column tile][32 n][32 f] (fused joint pass)
+  const unsigned* halt;            // nullable: the launch does nothing when *halt != 0 (stopped run)
 };
 
 struct SweepColsArgs {
@@ -82,6 +83,7 @@ struct SweepColsArgs {
   // the first `col_parts` column blocks each cover `col_chunk` rows of their
   // row group and write pcol[g * col_parts + cb][2][KP]
   const float* Wn; double* pcol; int col_parts, col_chunk;
+  const unsigned* halt;            // nullable: the launch does nothing when *halt != 0
 };
 
 struct UpdateWArgs {
@@ -95,6 +97,7 @@ struct UpdateWArgs {
   float* C0;                       // nullable: W~ row-major, ld KP (joint, low-precision products)
   double* pcol;                    // [grid][2][KP] column norm^2 and sum partials
   unsigned* flags;
+  const unsigned* halt;            // nullable: the launch does nothing when *halt != 0
 };
 
 struct UpdateHArgs {
@@ -110,6 +113,7 @@ struct UpdateHArgs {
   // joint MM, a sub-iteration before the last: instead of H, write
   // chi_1(H_new, H~) and chi_2(H_new, H~) ([K][ldc]) for the next W step
   float* C1h; float* C2h; int64_t ldc; double beta;
+  const unsigned* halt;            // nullable: the launch does nothing when *halt != 0
 };
 
 // launchers (nmf_kernels.hip)
@@ -219,6 +223,22 @@ hipError_t launch_sparse_update_w(hipStream_t s, const SparseArgs& a);
 hipError_t launch_sparse_update_h(hipStream_t s, const SparseArgs& a);
 hipError_t launch_sparse_objective(hipStream_t s, const SparseArgs& a, double* d_out);
 hipError_t launch_sparse_validate(hipStream_t s, const SparseArgs& a);
+
+// Device-side outer loop (Sec. 4.1.2): the objective trace and the stopping
+// rule.  run_init sets *halt = 0 and *stop = -1.  run_decide sums the n objective
+// partials of iterate t (fixed order), writes trace[t], and for t >= 1 sets
+// *halt = 1 and *stop = t when (trace[t-1] - trace[t]) / trace[t] <= eps; it does
+// nothing once *halt is set.
+hipError_t launch_run_init(hipStream_t s, unsigned* halt, int32_t* stop);
+hipError_t launch_run_decide(hipStream_t s, const double* pobj, int n, double* trace, int t, double eps,
+                             unsigned* halt, int32_t* stop, unsigned* flags);
+// KKT residuals of Sec. 4.1.5 from the gradient partials of the grad passes:
+// res[0] = sum |min(W, grad_W)| / (F K), res[1] = sum |min(H, grad_H)| / (K N).
+// `part` holds kkt_parts() float64 block partials.
+int kkt_parts();
+hipError_t launch_kkt(int kb, hipStream_t s, const float* pnumw, int n_groups, const float* pnumh, int f_groups,
+                      const float* W, int64_t ldw, const float* H, int64_t ldh, int F, int N, int K, double* part,
+                      double* res);
 
 hipError_t launch_validate(hipStream_t s, const float* V, int64_t ldv, const float* W, int64_t ldw,
                            const float* H, int64_t ldh, int F, int N, int K, int zero_bad, unsigned* flags);

@@ -15,6 +15,7 @@ constexpr int kUpdateWThreadsWide = 1024;
 
 template <int KB, int BT, int SL>
 __global__ __launch_bounds__(BT) void update_w_kernel(UpdateWArgs a) {
+  if (a.halt && *a.halt) return;
   constexpr int RU = unit_rows<KB, SL, BT>();
   static_assert(RU == unit_rows<KB>(), "rows per unit must match the host plan");
   __shared__ double lds[2 * BT];
@@ -32,6 +33,7 @@ __global__ __launch_bounds__(BT) void update_w_kernel(UpdateWArgs a) {
 // reduction.
 template <int KB>
 __global__ __launch_bounds__(kBlock) void update_h_kernel(UpdateHArgs a) {
+  if (a.halt && *a.halt) return;
   constexpr int KP = 32 * KB;
   constexpr int UC = kBlock / KP;
   constexpr int U = 16;
@@ -239,6 +241,111 @@ hipError_t launch_update_h(int kb, int grid, hipStream_t s, const UpdateHArgs& a
     case 4: hipLaunchKernelGGL(update_h_kernel<4>, dim3(grid), dim3(kBlock), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Device-side outer loop: stopping rule of Sec. 4.1.2 on the objective trace
+// ---------------------------------------------------------------------------
+__global__ void run_init_kernel(unsigned* halt, int32_t* stop) {
+  if (threadIdx.x == 0) {
+    *halt = 0u;
+    *stop = -1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void run_decide_kernel(const double* pobj, int n, double* trace, int t,
+                                                            double eps, unsigned* halt, int32_t* stop,
+                                                            unsigned* flags) {
+  __shared__ double red[kWaves];
+  if (*halt) return;  // uniform: the run stopped at an earlier iterate
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) s += pobj[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    trace[t] = s;
+    if (!isfinite(s)) set_flag(flags, 1u);
+    // relative decrease (D(previous) - D(current)) / D(current), as printed (no
+    // absolute value): an increase also stops the run
+    if (t >= 1 && (trace[t - 1] - s) / s <= eps) {
+      *halt = 1u;
+      *stop = t;
+    }
+  }
+}
+
+hipError_t launch_run_init(hipStream_t s, unsigned* halt, int32_t* stop) {
+  hipLaunchKernelGGL(run_init_kernel, dim3(1), dim3(64), 0, s, halt, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_run_decide(hipStream_t s, const double* pobj, int n, double* trace, int t, double eps,
+                             unsigned* halt, int32_t* stop, unsigned* flags) {
+  hipLaunchKernelGGL(run_decide_kernel, dim3(1), dim3(kBlock), 0, s, pobj, n, trace, t, eps, halt, stop, flags);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// KKT residuals (Sec. 4.1.5) from the gradient partials of the two passes:
+// blocks [0, kKktBlocks) sum |min(w_fk, g_fk)| over W's entries, blocks
+// [kKktBlocks, 2 kKktBlocks) |min(h_kn, g_kn)| over H's; block partials in
+// float64, then one block adds them in a fixed order and divides by the entry
+// counts F K and K N.
+// ---------------------------------------------------------------------------
+constexpr int kKktBlocks = 256;
+int kkt_parts() { return 2 * kKktBlocks; }
+
+template <int KB>
+__global__ __launch_bounds__(kBlock) void kkt_kernel(const float* pnumw, int n_groups, const float* pnumh,
+                                                     int f_groups, const float* W, int64_t ldw, const float* H,
+                                                     int64_t ldh, int F, int N, int K, double* part) {
+  constexpr int KP = 32 * KB;
+  __shared__ double red[kWaves];
+  const bool wpart = (int)blockIdx.x < kKktBlocks;
+  const int b = wpart ? blockIdx.x : blockIdx.x - kKktBlocks;
+  double s = 0.0;
+  if (wpart) {
+    const int64_t total = (int64_t)F * K;
+    for (int64_t e = (int64_t)b * kBlock + threadIdx.x; e < total; e += (int64_t)kKktBlocks * kBlock) {
+      const int f = (int)(e / K), k = (int)(e % K);
+      double g = 0.0;
+      for (int q = 0; q < n_groups; ++q) g += (double)pnumw[((int64_t)q * F + f) * KP + k];
+      s += fabs(fmin((double)W[(int64_t)f * ldw + k], g));
+    }
+  } else {
+    const int64_t total = (int64_t)K * N;
+    for (int64_t e = (int64_t)b * kBlock + threadIdx.x; e < total; e += (int64_t)kKktBlocks * kBlock) {
+      const int k = (int)(e / N), n = (int)(e % N);
+      double g = 0.0;
+      for (int q = 0; q < f_groups; ++q) g += (double)pnumh[((int64_t)q * N + n) * KP + k];
+      s += fabs(fmin((double)H[(int64_t)k * ldh + n], g));
+    }
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void kkt_finalize_kernel(const double* part, int F, int N, int K,
+                                                              double* res) {
+  __shared__ double red[kWaves];
+  for (int h = 0; h < 2; ++h) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < kKktBlocks; i += kBlock) s += part[h * kKktBlocks + i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) res[h] = s / (h == 0 ? (double)F * K : (double)K * N);
+  }
+}
+
+hipError_t launch_kkt(int kb, hipStream_t s, const float* pnumw, int n_groups, const float* pnumh, int f_groups,
+                      const float* W, int64_t ldw, const float* H, int64_t ldh, int F, int N, int K, double* part,
+                      double* res) {
+  switch (kb) {
+    case 1: hipLaunchKernelGGL(kkt_kernel<1>, dim3(2 * kKktBlocks), dim3(kBlock), 0, s, pnumw, n_groups, pnumh, f_groups, W, ldw, H, ldh, F, N, K, part); break;
+    case 2: hipLaunchKernelGGL(kkt_kernel<2>, dim3(2 * kKktBlocks), dim3(kBlock), 0, s, pnumw, n_groups, pnumh, f_groups, W, ldw, H, ldh, F, N, K, part); break;
+    case 4: hipLaunchKernelGGL(kkt_kernel<4>, dim3(2 * kKktBlocks), dim3(kBlock), 0, s, pnumw, n_groups, pnumh, f_groups, W, ldw, H, ldh, F, N, K, part); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(kkt_finalize_kernel, dim3(1), dim3(kBlock), 0, s, part, F, N, K, res);
   return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@ namespace nmf {
 
 template <int BC, int KB, bool DUAL, class T>
 __global__ __launch_bounds__(kBlock, 2) void sweep_cols_lp_kernel(SweepColsArgs a) {
+  if (a.halt && *a.halt) return;
   __shared__ __align__(16) float lds[cols_item_lp_lds<KB, DUAL && (BC != BC_B1)>() / 4];
   static_assert(cols_item_lp_lds<KB, DUAL && (BC != BC_B1)>() >= 2 * kBlock * 8, "column partial scratch");
   cols_prologue<KB>(a, blockIdx.x, lds);
@@ -15,6 +16,7 @@ __global__ __launch_bounds__(kBlock, 2) void sweep_cols_lp_kernel(SweepColsArgs 
 
 template <int BC, int KB, class T>
 __global__ __launch_bounds__(kBlock, 2) void sweep_cols_lp_pq_kernel(SweepColsArgs a) {
+  if (a.halt && *a.halt) return;
   __shared__ __align__(16) float lds[cols_item_lp_lds<KB, BC != BC_B1>() / 4];
   static_assert(cols_item_lp_lds<KB, BC != BC_B1>() >= 2 * kBlock * 8, "column partial scratch");
   cols_prologue<KB>(a, blockIdx.x, lds);

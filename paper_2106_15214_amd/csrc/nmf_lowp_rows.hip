@@ -7,6 +7,7 @@ namespace nmf {
 
 template <int BC, int KB, bool OBJ, class T, bool PQ>
 __global__ __launch_bounds__(kBlock, 2) void sweep_rows_lp_kernel(SweepRowsArgs a) {
+  if (a.halt && *a.halt) return;
   __shared__ __align__(16) float lds[rows_item_lds<KB>() / 4];
   __shared__ double dred[kWaves];
   double objsum = 0.0;

@@ -8,6 +8,7 @@ namespace nmf {
 template <int BC, int KB, int KIND, bool DUAL, bool LOAD_PQ>
 __global__ __launch_bounds__(kBlock, sweep_cols_occupancy(BC, KB, KIND, DUAL)) void sweep_cols_kernel(
     SweepColsArgs a) {
+  if (a.halt && *a.halt) return;
   constexpr bool C2_TILE = DUAL && (KIND == KIND_UPDATE) && (BC != BC_B1);
   __shared__ __align__(16) float lds[cols_item_lds<KB, C2_TILE>() / 4];
   static_assert(cols_item_lds<KB, C2_TILE>() >= 2 * kBlock * 8, "column partial scratch");

@@ -7,6 +7,7 @@ namespace nmf {
 
 template <int BC, int KB, int KIND, bool OBJ, bool STORE_PQ>
 __global__ __launch_bounds__(kBlock, sweep_rows_occupancy(KB)) void sweep_rows_kernel(SweepRowsArgs a) {
+  if (a.halt && *a.halt) return;
   __shared__ __align__(16) float lds[rows_item_lds<KB>() / 4];
   __shared__ double dred[kWaves];
   double objsum = 0.0;
@@ -20,6 +21,7 @@ __global__ __launch_bounds__(kBlock, sweep_rows_occupancy(KB)) void sweep_rows_k
 // The W pass of a later joint sub-iteration (contractions of the kept P, Q tiles).
 template <int BC, int KB>
 __global__ __launch_bounds__(kBlock, sweep_rows_occupancy(KB)) void sweep_rows_pq_kernel(SweepRowsArgs a) {
+  if (a.halt && *a.halt) return;
   __shared__ __align__(16) float lds[rows_pq_item_lds<KB>() / 4];
   rows_pq_item<BC, KB>(a, blockIdx.x, lds);
 }
