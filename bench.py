@@ -138,10 +138,14 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
+_GRAM = {"on": False}  # --gram: the Gram-form denominators at beta = 2
+
+
 def _run_steps(nb, V, W, H, beta, mode, n, ctx, obj=None, trace=None, precision="fp32", inner=1):
+    gram = _GRAM["on"] and beta == 2.0
     for t in range(n):
         o = trace[t:t + 1] if trace is not None else obj
-        nb.step(V, W, H, beta, mode, precision=precision, inner_iters=inner, objective_out=o, ctx=ctx)
+        nb.step(V, W, H, beta, mode, precision=precision, inner_iters=inner, gram=gram, objective_out=o, ctx=ctx)
 
 
 def main(argv=None):
@@ -152,6 +156,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=None, help="untimed iterations (default 5 batched, else 20)")
     ap.add_argument("--workload", default="batched",
                     choices=["batched", "counts_kl", "counts_kl_sparse", "faces_euc", "spectro_is", "tiny_kl"])
+    ap.add_argument("--gram", action="store_true",
+                    help="beta = 2: Gram-form denominators (K x K products) instead of the Q contractions")
     ap.add_argument("--sparse", action="store_true",
                     help="count workloads: V by its nonzeros (CSR + CSC), the sparse beta = 1 path")
     ap.add_argument("--tto-iters", type=int, default=None,
@@ -178,6 +184,7 @@ def main(argv=None):
         args.warmup = 5 if args.workload == "batched" else 20
     if args.tto_iters is None:
         args.tto_iters = TTO_ITERS[args.workload]
+    _GRAM["on"] = bool(args.gram)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -320,6 +327,7 @@ def main(argv=None):
         "config": {"workload": args.workload, "F": F, "N": N, "K": K, "beta": beta, "mode": "joint",
                    "inner_iters": args.inner_iters,
                    "precision": args.precision, "objective_every_step": True, "normalize": True,
+                   "gram_denominators": bool(args.gram and beta == 2.0),
                    "path": "fused" if "fused_step" in kern["joint"] else "stream"},
         "alternating": {"value": res["alternating"]["iters_per_s"], "ms_per_step": res["alternating"]["ms_per_step"]},
         "joint_speedup_per_iteration": res["alternating"]["ms_per_step"] / res["joint"]["ms_per_step"],
@@ -521,7 +529,8 @@ def time_to_objective(nb, torch, np, ctx, V, W0, H0, beta, T, precision, dev, in
     stop = {}
     for mode in ("joint", "alternating"):
         W, H = W0.clone(), H0.clone()
-        _, st = nb.run(V, W, H, beta, mode, max_iters=T, eps=1e-5, precision=precision, inner_iters=inner, ctx=ctx)
+        _, st = nb.run(V, W, H, beta, mode, max_iters=T, eps=1e-5, precision=precision, inner_iters=inner,
+                       gram=_GRAM["on"] and beta == 2.0, ctx=ctx)
         t_stop = int(st.item())
         stop[mode] = t_stop if t_stop >= 0 else None
     mono = {m: int(np.sum(np.diff(traces[m]) > 0)) for m in traces}

@@ -105,6 +105,14 @@ typedef struct {
                           (Sec. 4.1.2) at the end of the step; default 1 */
   int32_t exponent;    /* NMF_EXPONENT_MM (default) or NMF_EXPONENT_ONE; other
                           values: NMF_ERR_ARG */
+  int32_t gram;        /* 1: at beta = 2, the denominators in the Gram form of
+                          Table 2 (Sec. 3.3.1): Q H~^T = W~ (H~ H~^T) and
+                          chi_2^T Q = (chi_2^T W~) H~ (joint; W_new^T W_new H~
+                          alternating), with the K x K products formed in float64,
+                          so both passes over V contract P = V only and the H pass
+                          forms no Lambda.  Needs beta = 2, kappa = 0, NMF_FP32,
+                          inner_iters = 1, K <= 64 (else NMF_ERR_UNSUPPORTED); not
+                          in batches.  0 (default): the contraction form. */
 } nmf_step_opts;
 
 /* Fills *opts with the defaults listed above. */

@@ -59,7 +59,7 @@ class NmfError(RuntimeError):
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("kappa", ctypes.c_float),
                 ("inner_iters", ctypes.c_int32), ("normalize", ctypes.c_int32),
-                ("exponent", ctypes.c_int32)]
+                ("exponent", ctypes.c_int32), ("gram", ctypes.c_int32)]
 
 
 class _Problem(ctypes.Structure):
@@ -163,7 +163,7 @@ def _check(st: int, where: str):
         raise NmfError(st, where)
 
 
-def _opts(precision=FP32, kappa=0.0, inner_iters=1, normalize=True, exponent="mm") -> _Opts:
+def _opts(precision=FP32, kappa=0.0, inner_iters=1, normalize=True, exponent="mm", gram=False) -> _Opts:
     o = _Opts()
     lib().nmf_default_opts(ctypes.byref(o))
     o.precision = PRECISIONS.get(precision, precision) if isinstance(precision, str) else int(precision)
@@ -171,6 +171,7 @@ def _opts(precision=FP32, kappa=0.0, inner_iters=1, normalize=True, exponent="mm
     o.inner_iters = int(inner_iters)
     o.normalize = 1 if normalize else 0
     o.exponent = EXPONENTS.get(exponent, exponent) if isinstance(exponent, str) else int(exponent)
+    o.gram = 1 if gram else 0
     return o
 
 
@@ -281,8 +282,11 @@ def check_step_args(F, N, K, V=0x10000000, ldv=None, W=0x50000000, ldw=None, H=0
 
 
 def step(V, W, H, beta: float, mode="joint", *, precision="fp32", kappa: float = 0.0, normalize: bool = True,
-         exponent="mm", inner_iters: int = 1, objective_out=None, stream=None, ctx: Optional[Context] = None):
+         exponent="mm", inner_iters: int = 1, gram: bool = False, objective_out=None, stream=None,
+         ctx: Optional[Context] = None):
     """One outer iteration in place on W and H (see nmf_beta_step).
+
+    ``gram``: at beta = 2, the Gram-form denominators of Table 2 (K x K products).
 
     ``exponent``: "mm" (gamma(beta)) or "one" (gamma = 1 for every beta).
     ``inner_iters``: sub-iterations L (Algorithm 1 or 2; joint mode with L > 1
@@ -298,7 +302,7 @@ def step(V, W, H, beta: float, mode="joint", *, precision="fp32", kappa: float =
     K = W.shape[1]
     if W.shape[0] != F or H.shape != (K, N):
         raise ValueError("shape mismatch: V (F,N), W (F,K), H (K,N)")
-    o = _opts(precision, kappa, inner_iters, normalize, exponent)
+    o = _opts(precision, kappa, inner_iters, normalize, exponent, gram)
     pobj = _dev_f64(objective_out, "objective_out") if objective_out is not None else None
     st = lib().nmf_beta_step(_ctx(ctx), _stream(stream), F, N, K, pv, ldv, pw, ldw, ph, ldh,
                              float(beta), m, ctypes.byref(o), pobj)
@@ -387,8 +391,8 @@ def kkt(V, W, H, beta: float, *, kappa: float = 0.0, out=None, stream=None, ctx=
 
 
 def run(V, W, H, beta: float, mode="joint", max_iters: int = 1000, eps: float = 1e-5, *, precision="fp32",
-        kappa: float = 0.0, normalize: bool = True, exponent="mm", inner_iters: int = 1, trace=None, stop=None,
-        stream=None, ctx: Optional[Context] = None):
+        kappa: float = 0.0, normalize: bool = True, exponent="mm", inner_iters: int = 1, gram: bool = False,
+        trace=None, stop=None, stream=None, ctx: Optional[Context] = None):
     """Up to max_iters outer iterations with the stopping rule of Sec. 4.1.2 on
     the device (nmf_beta_run).  Returns (trace, stop): a float64 device tensor of
     max_iters + 1 objectives (entries after the stop are left as given) and an
@@ -408,7 +412,7 @@ def run(V, W, H, beta: float, mode="joint", max_iters: int = 1000, eps: float = 
         stop = torch.empty(1, dtype=torch.int32, device=V.device)
     if stop.dtype != torch.int32 or not stop.is_cuda or stop.numel() < 1:
         raise ValueError("stop must be an int32 device tensor")
-    o = _opts(precision, kappa, inner_iters, normalize, exponent)
+    o = _opts(precision, kappa, inner_iters, normalize, exponent, gram)
     st = lib().nmf_beta_run(_ctx(ctx), _stream(stream), F, N, K, pv, ldv, pw, ldw, ph, ldh, float(beta), m,
                             ctypes.byref(o), int(max_iters), float(eps), _dev_f64(trace, "trace", int(max_iters) + 1),
                             stop.data_ptr())

@@ -312,6 +312,7 @@ nmf_status check_opts(const nmf_step_opts* o) {
   if (o->inner_iters < 1 || o->inner_iters > kMaxInnerIters) return NMF_ERR_ARG;
   if (o->normalize != 0 && o->normalize != 1) return NMF_ERR_ARG;
   if (o->exponent != NMF_EXPONENT_MM && o->exponent != NMF_EXPONENT_ONE) return NMF_ERR_ARG;
+  if (o->gram != 0 && o->gram != 1) return NMF_ERR_ARG;
   return NMF_OK;
 }
 
@@ -617,7 +618,8 @@ nmf_status step_impl(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K,
   nmf_default_opts(&o);
   if (opts) o = *opts;
   hipStream_t s = (hipStream_t)stream;
-  const int bc = beta_class(beta);
+  const bool gram = o.gram != 0;
+  const int bc = gram ? BC_B2G : beta_class(beta);
   const bool joint = (mode == NMF_JOINT);
   const bool want_obj = d_objective != nullptr || run != nullptr;
   const int prec = opts ? opts->precision : NMF_FP32;
@@ -626,30 +628,38 @@ nmf_status step_impl(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K,
   // resident (not under stream capture), else four streaming launches
   const int L = o.inner_iters;
   int fused_grid = 0;
-  if (!no_alloc && !run && c->path == NMF_PATH_FUSED && L == 1 && prec == NMF_FP32 && kblocks_for(K) <= 2 &&
+  if (!no_alloc && !run && !gram && c->path == NMF_PATH_FUSED && L == 1 && prec == NMF_FP32 && kblocks_for(K) <= 2 &&
       F * N <= kFusedMaxEntries) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess) return NMF_ERR_HIP;
     if (cs == hipStreamCaptureStatusNone) fused_grid = fused_capacity(c, bc, kblocks_for(K), joint, want_obj);
   }
-  if (!no_alloc && !run && c->path == NMF_PATH_FUSED && fused_grid <= 0) return NMF_ERR_UNSUPPORTED;
-  bool use_pq = joint && fused_grid == 0 && F * N <= kPQMaxEntries;
-  const int cols_occ = sweep_cols_occupancy(bc, kblocks_for(K), KIND_UPDATE, joint);
+  if (!no_alloc && !run && !gram && c->path == NMF_PATH_FUSED && fused_grid <= 0) return NMF_ERR_UNSUPPORTED;
+  // the Gram form at beta = 2 keeps nothing between the passes (P = V)
+  bool use_pq = joint && !gram && fused_grid == 0 && F * N <= kPQMaxEntries;
+  const bool dual = joint && !gram;
+  const int cols_occ = sweep_cols_occupancy(bc, kblocks_for(K), KIND_UPDATE, dual);
   Plan p = make_plan(c, F, N, K, cols_occ, fused_grid, use_pq, joint && L > 1);
+  // Gram region after the plan: G(H~) and G2 ([KP][KP] float64 each) and the
+  // Gram kernels' block partials
+  const size_t gram_bytes = gram ? sizeof(double) * (size_t)(2 + gram_parts()) * p.KP * p.KP : 0;
   char* ws = nullptr;
   if (no_alloc) {
-    if (p.total > kScratchBytes && use_pq && L == 1) {
+    if (p.total + gram_bytes > kScratchBytes && use_pq && L == 1) {
       use_pq = false;  // the H pass forms Lambda~ again instead of reading kept P, Q
       p = make_plan(c, F, N, K, cols_occ, 0, false, false);
     }
-    if (p.total > kScratchBytes) return NMF_ERR_WORKSPACE;
+    if (align_up(p.total) + gram_bytes > kScratchBytes) return NMF_ERR_WORKSPACE;
     if (!c->scratch) return NMF_ERR_HIP;
     ws = c->scratch;
   } else {
-    if ((st = ensure_ws(c, s, p.total)) != NMF_OK) return st;
+    if ((st = ensure_ws(c, s, align_up(p.total) + gram_bytes)) != NMF_OK) return st;
     ws = c->ws;
     flags = flags_ptr(c);
   }
+  double* const G1 = gram ? (double*)(ws + align_up(p.total)) : nullptr;
+  double* const G2 = G1 ? G1 + (size_t)p.KP * p.KP : nullptr;
+  double* const Gpart = G2 ? G2 + (size_t)p.KP * p.KP : nullptr;
   const bool quiet = no_alloc;
 
   StepArgs sa = make_step_args(p, ws, flags, F, N, K, V, ldv, W, ldw, H, ldh, beta, joint, prec, o, d_objective);
@@ -660,6 +670,10 @@ nmf_status step_impl(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K,
   if (run) {
     ra.halt = ua.halt = ca.halt = ha.halt = run->halt;
     ha.d_obj = nullptr;  // the decide kernel writes the trace
+  }
+  if (gram) {
+    ua.gram = G1;
+    ha.gram = G2;
   }
   const int sw_grid = sa.sw_grid, sh_grid = sa.sh_grid;
 
@@ -693,6 +707,10 @@ nmf_status step_impl(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K,
   if (L > 1)
     return joint ? inner_steps_joint(c, s, p, sa, bc, want_obj, L, ws, quiet, run)
                  : inner_steps(c, s, p, sa, bc, want_obj, L, prec, quiet, run);
+  if (gram) {  // H~ H~^T for the W-step denominators
+    if (launch_gram(true, s, H, ldh, H, ldh, (int)K, p.KP, N, Gpart, G1) != hipSuccess)
+      return NMF_ERR_HIP;
+  }
   hipError_t e = run_k(c, quiet, NMF_KERNEL_SWEEP_W, s, [&] {
     return prec == NMF_FP32 ? launch_sweep_rows(bc, p.KB, KIND_UPDATE, want_obj, p.pq, sw_grid, s, ra)
                             : launch_sweep_rows_lp(prec, bc, p.KB, want_obj, p.pq, sw_grid, s, ra);
@@ -701,8 +719,13 @@ nmf_status step_impl(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t K,
   if (e != hipSuccess) return NMF_ERR_HIP;
   e = run_k(c, quiet, NMF_KERNEL_UPDATE_W, s, [&] { return launch_update_w(p.KB, p.uw_blocks, s, ua); });
   if (e != hipSuccess) return NMF_ERR_HIP;
+  if (gram) {  // G2 = chi_2^T W~ (joint) or W_new^T W_new (alternating) for the H-step denominators
+    e = joint ? launch_gram(false, s, ua.C2, p.KP, W, ldw, (int)K, p.KP, F, Gpart, G2)
+              : launch_gram(false, s, ua.Wn, p.KP, ua.Wn, p.KP, (int)K, p.KP, F, Gpart, G2);
+    if (e != hipSuccess) return NMF_ERR_HIP;
+  }
   e = run_k(c, quiet, NMF_KERNEL_SWEEP_H, s, [&] {
-    return prec == NMF_FP32 ? launch_sweep_cols(bc, p.KB, KIND_UPDATE, joint, p.pq, sh_grid, s, ca)
+    return prec == NMF_FP32 ? launch_sweep_cols(bc, p.KB, KIND_UPDATE, dual, p.pq, sh_grid, s, ca)
                             : launch_sweep_cols_lp(prec, bc, p.KB, joint, p.pq, sh_grid, s, ca);
   });
   if (e != hipSuccess) return NMF_ERR_HIP;
@@ -815,6 +838,7 @@ void nmf_default_opts(nmf_step_opts* o) {
   o->inner_iters = 1;
   o->normalize = 1;
   o->exponent = NMF_EXPONENT_MM;
+  o->gram = 0;
 }
 
 const char* nmf_version(void) { return "nmfbeta 0.1 (gfx950)"; }
@@ -891,6 +915,10 @@ nmf_status nmf_check_step_args(int64_t F, int64_t N, int64_t K, const float* V, 
   st = check_opts(opts);
   if (st != NMF_OK) return st;
   if (opts && opts->precision != NMF_FP32 && K > 64) return NMF_ERR_UNSUPPORTED;
+  // Gram-form denominators: beta = 2, kappa = 0, float32, one sub-iteration, K <= 64
+  if (opts && opts->gram &&
+      (beta != 2.0 || opts->kappa != 0.f || opts->precision != NMF_FP32 || opts->inner_iters != 1 || K > 64))
+    return NMF_ERR_UNSUPPORTED;
   // L > 1 sub-iterations of joint MM: float32 products, P and Q kept between the passes
   if (opts && opts->inner_iters > 1 && mode == NMF_JOINT &&
       (opts->precision != NMF_FP32 || F * N > kPQMaxEntries))

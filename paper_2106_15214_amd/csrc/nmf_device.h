@@ -41,7 +41,7 @@ __device__ __forceinline__ int acc_row(int r, int hi) { return 8 * (r >> 2) + 4 
 // Lambda^(beta-2) for a smoothed Lambda (> 0).
 template <int BC>
 __device__ __forceinline__ float pow_bm2(float lam, float bm2) {
-  if (BC == BC_B2) return 1.f;
+  if (BC == BC_B2 || BC == BC_B2G) return 1.f;
   if (BC == BC_B1) return __builtin_amdgcn_rcpf(lam);
   if (BC == BC_B0) { float r = __builtin_amdgcn_rcpf(lam); return r * r; }
   if (BC == BC_B05) { float s = __builtin_amdgcn_rsqf(lam); return s * s * s; }
@@ -54,6 +54,7 @@ __device__ __forceinline__ float pow_bm2(float lam, float bm2) {
 template <int BC>
 __device__ __forceinline__ void beta_terms(float v, float lam, float bm2, float& P, float& Q) {
   if (BC == BC_B2) { P = v; Q = lam; return; }
+  if (BC == BC_B2G) { P = v; Q = 0.f; return; }  // Q H~^T comes from the Gram form
   if (BC == BC_B1) { P = v * __builtin_amdgcn_rcpf(lam); Q = 1.f; return; }
   if (BC == BC_B0) { float r = __builtin_amdgcn_rcpf(lam); Q = r; P = v * r * r; return; }
   if (BC == BC_B05) { float s = __builtin_amdgcn_rsqf(lam); Q = s; P = v * (s * s * s); return; }
@@ -74,7 +75,7 @@ __device__ __noinline__ inline double d_beta_general(double v, double l, double 
 // the limit of the expression.
 template <int BC>
 __device__ __forceinline__ double d_beta(double v, double l, double beta) {
-  if (BC == BC_B2) { double t = v - l; return 0.5 * t * t; }
+  if (BC == BC_B2 || BC == BC_B2G) { double t = v - l; return 0.5 * t * t; }
   if (BC == BC_B1) {  // v log(v / l) - v + l, and the limit l at v = 0
     const double t = v * log64(div64(v, l)) - v + l;
     return v > 0.0 ? t : l;
@@ -348,8 +349,10 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
   constexpr int KP = 32 * KB;
   constexpr int K2MAX = KP / 2;
   constexpr bool CONTRACT = (KIND != KIND_OBJ);
-  constexpr bool NEED_DEN = (KIND == KIND_UPDATE) && (BC != BC_B1);
+  constexpr bool NEED_DEN = (KIND == KIND_UPDATE) && (BC != BC_B1) && (BC != BC_B2G);
   constexpr bool ROWSUM = (KIND == KIND_UPDATE) && (BC == BC_B1);
+  // Gram form at beta = 2: P = V needs no Lambda; it is formed for the objective only
+  constexpr bool NEED_LAM = !(BC == BC_B2G && KIND == KIND_UPDATE && !OBJ);
   float* const Hs0 = lds;
   float* const Hs1 = lds + KP * kHS;
 
@@ -467,7 +470,7 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
       f32x16 lam;
 #pragma unroll
       for (int r = 0; r < 16; ++r) lam[r] = 0.f;
-      {
+      if (NEED_LAM) {
         // operands read one block of 4 steps ahead; blocks past K2 skipped
         float av[4], an[4];
 #pragma unroll
@@ -1480,8 +1483,11 @@ __device__ __forceinline__ void cols_item(const SweepColsArgs& a, int item, floa
   constexpr int KP = 32 * KB;
   constexpr int K2MAX = KP / 2;
   constexpr int CS = KP + 4;  // LDS row stride of [f][KP] tiles
-  constexpr bool NEED_DEN = (KIND == KIND_UPDATE) && (BC != BC_B1);
+  constexpr bool NEED_DEN = (KIND == KIND_UPDATE) && (BC != BC_B1) && (BC != BC_B2G);
   constexpr bool C2_TILE = DUAL && NEED_DEN;
+  // Lambda is formed from the staged factor unless P, Q are read (kept tiles)
+  // or P = V needs no Lambda (Gram form at beta = 2)
+  constexpr bool USE_LAM = !LOAD_PQ && (BC != BC_B2G);
   float* const Ws0 = lds;
   float* const Ws1 = lds + KP * kHS;
   float* const C1s0 = lds + 2 * KP * kHS;
@@ -1501,8 +1507,8 @@ __device__ __forceinline__ void cols_item(const SweepColsArgs& a, int item, floa
   const int K2 = (K + 1) >> 1;
 
   // B operand of Lambda = W H~: lane holds H~[2s + hi][ncol]
-  float hB[LOAD_PQ ? 1 : K2MAX];
-  if (!LOAD_PQ) {
+  float hB[USE_LAM ? K2MAX : 1];
+  if (USE_LAM) {
 #pragma unroll
     for (int s = 0; s < K2MAX; ++s) hB[s] = ldc(a.H, (int64_t)(2 * s + hi) * a.ldh + ncol, ncol_ok && 2 * s + hi < K);
 #pragma unroll
@@ -1517,13 +1523,13 @@ __device__ __forceinline__ void cols_item(const SweepColsArgs& a, int item, floa
 
   // staging: WT tile float4 j -> row k = e4 / 8, columns f0 + 4 (e4 % 8);
   //          chi tile float4 j -> row i = e4 / (KP/4), columns 4 (e4 % (KP/4))
-  float4 wreg[LOAD_PQ ? 1 : KB], c1reg[KB], c2reg[C2_TILE ? KB : 1];
+  float4 wreg[USE_LAM ? KB : 1], c1reg[KB], c2reg[C2_TILE ? KB : 1];
   auto load_tiles = [&](int f0) {
     const bool full = f0 + kTile <= F;
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
       const int e4 = tid + kBlock * j;
-      if (!LOAD_PQ) {
+      if (USE_LAM) {
         const int k = e4 >> 3, f = f0 + 4 * (e4 & 7);
         const int64_t o = (int64_t)k * a.ldwt + f;
         if (full) {
@@ -1546,7 +1552,7 @@ __device__ __forceinline__ void cols_item(const SweepColsArgs& a, int item, floa
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
       const int e4 = tid + kBlock * j;
-      if (!LOAD_PQ) *reinterpret_cast<float4*>(&(buf ? Ws1 : Ws0)[(e4 >> 3) * kHS + 4 * (e4 & 7)]) = wreg[j];
+      if (USE_LAM) *reinterpret_cast<float4*>(&(buf ? Ws1 : Ws0)[(e4 >> 3) * kHS + 4 * (e4 & 7)]) = wreg[j];
       const int i = e4 / (KP / 4), c = 4 * (e4 % (KP / 4));
       *reinterpret_cast<float4*>(&(buf ? C1s1 : C1s0)[i * CS + c]) = c1reg[j];
       if (C2_TILE) *reinterpret_cast<float4*>(&(buf ? C2s1 : C2s0)[i * CS + c]) = c2reg[j];
@@ -1618,6 +1624,13 @@ __device__ __forceinline__ void cols_item(const SweepColsArgs& a, int item, floa
             P[r] = vcur[r];
           }
           Q[r] = NEED_DEN ? wcur[r] : 0.f;
+        }
+      } else if (!USE_LAM) {  // Gram form at beta = 2: P = V + kappa
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const bool ok = ncol_ok && f0 + acc_row(r, hi) < F;
+          P[r] = ok ? vcur[r] + a.kappa : 0.f;
+          Q[r] = 0.f;
         }
       } else {
         const float* ws = buf ? Ws1 : Ws0;
@@ -1765,7 +1778,19 @@ __device__ __forceinline__ void update_w_unit(const UpdateWArgs& a, int unit, bo
     }
     float wn = 0.f, c1 = 0.f, c2 = 0.f;
     if (fok && k < a.K) {
-      const double dsum = a.beta_one ? den1 : den;
+      double gden = 0.0;
+      if (a.gram) {  // Gram form at beta = 2: (W~ (H~ H~^T))[f][k], eight terms in flight
+        const float* wr = a.W + (int64_t)f * a.ldw;
+        double g8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int l = 0;
+        for (; l + 8 <= a.K; l += 8) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) g8[j] = fma((double)wr[l + j], a.gram[(l + j) * KP + k], g8[j]);
+        }
+        for (; l < a.K; ++l) g8[0] = fma((double)wr[l], a.gram[l * KP + k], g8[0]);
+        gden = ((g8[0] + g8[1]) + (g8[2] + g8[3])) + ((g8[4] + g8[5]) + (g8[6] + g8[7]));
+      }
+      const double dsum = a.beta_one ? den1 : (a.gram ? gden : den);
       const double ratio = num / dsum;
       if (!(dsum > 0.0) || !isfinite(ratio)) set_flag(a.flags, 1u);
       const double rr = pow_gamma(ratio, a.gamma);

@@ -8,7 +8,9 @@ namespace nmf {
 
 // Classes of beta with specialised element-wise terms (the general class uses
 // exp2/log2 for Lambda^(beta-2)).
-enum BetaClass { BC_GEN = 0, BC_B2 = 1, BC_B1 = 2, BC_B0 = 3, BC_B05 = 4, BC_B15 = 5 };
+// BC_B2G: beta = 2 with the Gram-form denominators of Table 2 (Q H~^T = W~ (H~ H~^T)
+// and chi_2^T Q = (chi_2^T W~) H~): the passes contract P = V only.
+enum BetaClass { BC_GEN = 0, BC_B2 = 1, BC_B1 = 2, BC_B0 = 3, BC_B05 = 4, BC_B15 = 5, BC_B2G = 6 };
 
 // What a pass over V accumulates.
 enum Kind {
@@ -98,6 +100,7 @@ struct UpdateWArgs {
   double* pcol;                    // [grid][2][KP] column norm^2 and sum partials
   unsigned* flags;
   const unsigned* halt;            // nullable: the launch does nothing when *halt != 0
+  const double* gram;              // nullable: [KP][KP] H~ H~^T; the denominator is W~ (H~ H~^T) (beta = 2)
 };
 
 struct UpdateHArgs {
@@ -114,6 +117,8 @@ struct UpdateHArgs {
   // chi_1(H_new, H~) and chi_2(H_new, H~) ([K][ldc]) for the next W step
   float* C1h; float* C2h; int64_t ldc; double beta;
   const unsigned* halt;            // nullable: the launch does nothing when *halt != 0
+  const double* gram;              // nullable: [KP][KP] G2 = chi_2^T W~ (joint) or W_new^T W_new
+                                   // (alternating); the denominator is G2 H~ (beta = 2)
 };
 
 // launchers (nmf_kernels.hip)
@@ -239,6 +244,15 @@ int kkt_parts();
 hipError_t launch_kkt(int kb, hipStream_t s, const float* pnumw, int n_groups, const float* pnumh, int f_groups,
                       const float* W, int64_t ldw, const float* H, int64_t ldh, int F, int N, int K, double* part,
                       double* res);
+
+// Gram matrix G[k][l] = sum_i x_i[k] y_i[l] (float64), k, l < K <= 64, stored
+// [KP][KP]: COLS, the i-th columns of K x N matrices (H~ H~^T); otherwise the
+// i-th rows of F x K row-major matrices (chi_2^T W~, W_new^T W_new).  Two
+// launches: block partials in `part` ([gram_parts()][KP][KP]), then their sum
+// in a fixed order.
+int gram_parts();
+hipError_t launch_gram(bool cols, hipStream_t s, const float* X, int64_t ldx, const float* Y, int64_t ldy, int K,
+                       int KP, int64_t len, double* part, double* G);
 
 hipError_t launch_validate(hipStream_t s, const float* V, int64_t ldv, const float* W, int64_t ldw,
                            const float* H, int64_t ldh, int F, int N, int K, int zero_bad, unsigned* flags);

@@ -3,6 +3,8 @@
 // objective finalization and the domain scan.  The passes over V are in
 // nmf_sweep_rows.hip and nmf_sweep_cols.hip; the device building blocks live in
 // nmf_device.h.
+#include <algorithm>
+
 #include "nmf_device.h"
 
 namespace nmf {
@@ -98,7 +100,18 @@ __global__ __launch_bounds__(kBlock) void update_h_kernel(UpdateHArgs a) {
     }
   }
   if (!ok) return;
-  const double dd = a.beta_one ? (double)csum_s[k] : den;
+  double gden = 0.0;
+  if (a.gram) {  // Gram form at beta = 2: (G2 H~)[k][n], eight terms in flight
+    double g8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int l = 0;
+    for (; l + 8 <= a.K; l += 8) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) g8[j] = fma(a.gram[k * KP + l + j], (double)a.H[(int64_t)(l + j) * a.ldh + n], g8[j]);
+    }
+    for (; l < a.K; ++l) g8[0] = fma(a.gram[k * KP + l], (double)a.H[(int64_t)l * a.ldh + n], g8[0]);
+    gden = ((g8[0] + g8[1]) + (g8[2] + g8[3])) + ((g8[4] + g8[5]) + (g8[6] + g8[7]));
+  }
+  const double dd = a.beta_one ? (double)csum_s[k] : (a.gram ? gden : den);
   const double ratio = num / dd;
   if (!(dd > 0.0) || !isfinite(ratio)) set_flag(a.flags, 1u);
   if (a.C1h) {  // sub-iteration: chi terms of H_new against H~ (no normalization)
@@ -241,6 +254,86 @@ hipError_t launch_update_h(int kb, int grid, hipStream_t s, const UpdateHArgs& a
     case 4: hipLaunchKernelGGL(update_h_kernel<4>, dim3(grid), dim3(kBlock), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gram matrices of the beta = 2 Gram form (Table 2).  gram_kernel: block b
+// takes a range of i (32 at a time staged in LDS) and writes its float64
+// partial [KP][KP]; gram_finalize_kernel adds the partials in block order (one
+// thread per entry, eight loads in flight).  Deterministic, no atomics.
+// ---------------------------------------------------------------------------
+constexpr int kGramBlocks = 64;
+int gram_parts() { return kGramBlocks; }
+
+template <bool COLS>
+__global__ __launch_bounds__(kBlock) void gram_kernel(const float* X, int64_t ldx, const float* Y, int64_t ldy, int K,
+                                                      int KP, int64_t len, double* part) {
+  __shared__ float xs[32][65], ys[32][65];
+  const int tid = threadIdx.x;
+  const int64_t chunk = (len + gridDim.x - 1) / gridDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = min(len, i0 + chunk);
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int64_t b = i0; b < i1; b += 32) {
+    __syncthreads();
+    for (int e = tid; e < 32 * 64; e += kBlock) {
+      int r, k;
+      if (COLS) { k = e / 32; r = e % 32; }  // consecutive threads read consecutive columns of a row
+      else { r = e / 64; k = e % 64; }       // consecutive threads read consecutive entries of a row
+      const int64_t i = b + r;
+      const bool ok = i < i1 && k < K;
+      float x = 0.f, y = 0.f;
+      if (ok) {
+        x = COLS ? X[(int64_t)k * ldx + i] : X[i * ldx + k];
+        y = COLS ? Y[(int64_t)k * ldy + i] : Y[i * ldy + k];
+      }
+      xs[r][k] = x;
+      ys[r][k] = y;
+    }
+    __syncthreads();
+    // thread owns pairs (k, l) = (4 (tid / 16) + q / 4, 4 (tid % 16) + q % 4), q < 16
+#pragma unroll 4
+    for (int r = 0; r < 32; ++r) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int k = (tid >> 4) * 4 + (q >> 2), l = (tid & 15) * 4 + (q & 3);
+        acc[q] = fma((double)xs[r][k], (double)ys[r][l], acc[q]);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int k = (tid >> 4) * 4 + (q >> 2), l = (tid & 15) * 4 + (q & 3);
+    if (k < KP && l < KP) part[(int64_t)blockIdx.x * KP * KP + k * KP + l] = acc[q];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void gram_finalize_kernel(const double* part, int nparts, int KP, double* G) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= KP * KP) return;
+  double s = 0.0;
+  int b = 0;
+  for (; b + 8 <= nparts; b += 8) {
+    double x[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) x[r] = part[(int64_t)(b + r) * KP * KP + e];
+    s += ((x[0] + x[1]) + (x[2] + x[3])) + ((x[4] + x[5]) + (x[6] + x[7]));
+  }
+  for (; b < nparts; ++b) s += part[(int64_t)b * KP * KP + e];
+  G[e] = s;
+}
+
+hipError_t launch_gram(bool cols, hipStream_t s, const float* X, int64_t ldx, const float* Y, int64_t ldy, int K,
+                       int KP, int64_t len, double* part, double* G) {
+  if (K > 64 || KP > 64) return hipErrorInvalidValue;
+  // about 64 entries of i per block, at most kGramBlocks blocks
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(kGramBlocks, (len + 63) / 64));
+  if (cols) hipLaunchKernelGGL(gram_kernel<true>, dim3(grid), dim3(kBlock), 0, s, X, ldx, Y, ldy, K, KP, len, part);
+  else hipLaunchKernelGGL(gram_kernel<false>, dim3(grid), dim3(kBlock), 0, s, X, ldx, Y, ldy, K, KP, len, part);
+  hipLaunchKernelGGL(gram_finalize_kernel, dim3((KP * KP + kBlock - 1) / kBlock), dim3(kBlock), 0, s, part, grid,
+                     KP, G);
   return hipGetLastError();
 }
 

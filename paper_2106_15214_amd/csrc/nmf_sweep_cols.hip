@@ -40,6 +40,12 @@ static hipError_t cols_bc(int kb, int kind, bool dual, bool pq, int grid, hipStr
 
 hipError_t launch_sweep_cols(int bc, int kb, int kind, bool dual, bool pq, int grid, hipStream_t s,
                              const SweepColsArgs& a) {
+  if (bc == BC_B2G) {  // Gram form at beta = 2: numerators chi_1^T V only (C1 = W_new in both modes)
+    if (kind != KIND_UPDATE || pq || kb > 2) return hipErrorInvalidValue;
+    if (kb == 1) hipLaunchKernelGGL((sweep_cols_kernel<BC_B2G, 1, KIND_UPDATE, false, false>), dim3(grid), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((sweep_cols_kernel<BC_B2G, 2, KIND_UPDATE, false, false>), dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+  }
   switch (bc) {
     case BC_GEN: return cols_bc<BC_GEN>(kb, kind, dual, pq, grid, s, a);
     case BC_B2: return cols_bc<BC_B2>(kb, kind, dual, pq, grid, s, a);

@@ -81,6 +81,17 @@ static hipError_t rows_bc(int kb, int kind, bool obj, bool pq, int grid, hipStre
 
 hipError_t launch_sweep_rows(int bc, int kb, int kind, bool obj, bool pq, int grid, hipStream_t s,
                              const SweepRowsArgs& a) {
+  if (bc == BC_B2G) {  // Gram form at beta = 2: update passes with K <= 64, no kept P, Q
+    if (kind != KIND_UPDATE || pq || kb > 2) return hipErrorInvalidValue;
+    if (kb == 1) {
+      if (obj) hipLaunchKernelGGL((sweep_rows_kernel<BC_B2G, 1, KIND_UPDATE, true, false>), dim3(grid), dim3(kBlock), 0, s, a);
+      else hipLaunchKernelGGL((sweep_rows_kernel<BC_B2G, 1, KIND_UPDATE, false, false>), dim3(grid), dim3(kBlock), 0, s, a);
+    } else {
+      if (obj) hipLaunchKernelGGL((sweep_rows_kernel<BC_B2G, 2, KIND_UPDATE, true, false>), dim3(grid), dim3(kBlock), 0, s, a);
+      else hipLaunchKernelGGL((sweep_rows_kernel<BC_B2G, 2, KIND_UPDATE, false, false>), dim3(grid), dim3(kBlock), 0, s, a);
+    }
+    return hipGetLastError();
+  }
   switch (bc) {
     case BC_GEN: return rows_bc<BC_GEN>(kb, kind, obj, pq, grid, s, a);
     case BC_B2: return rows_bc<BC_B2>(kb, kind, obj, pq, grid, s, a);

@@ -524,3 +524,62 @@ def test_autograd_backward_uses_device_scale():
     sW, sH = _grad_tol_scale(p.V, p.W, p.H, 0.5)
     assert np.linalg.norm(W.grad.cpu().numpy() - 2.5 * gW) <= 3e-5 * sW
     assert np.linalg.norm(H.grad.cpu().numpy() - 2.5 * gH) <= 3e-5 * sH
+
+
+GRAM_SHAPES = [(64, 100, 5), (257, 300, 49), (130, 70, 64), (33, 1000, 8), (1, 40, 3), (40, 1, 3), (129, 129, 1),
+               (361, 2429, 49)]
+
+
+@pytest.mark.parametrize("shape", GRAM_SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("mode", ["joint", "alternating"])
+@pytest.mark.parametrize("obj", [True, False])
+def test_gram_form_beta2_parity(shape, mode, obj):
+    # beta = 2 with the Gram-form denominators of Table 2: the same iteration as
+    # the oracle's (whose beta = 2 step is pinned to the textbook Gram-form rules)
+    F, N, K = shape
+    p = synth.random_positive(F, N, K, seed=F + 2 * N + K, zeros=0.1)
+    print(f"[parity] gram F={F} N={N} K={K} mode={mode} obj={obj}", flush=True)
+    Vd, Wd, Hd = dev(p.V), dev(p.W), dev(p.H)
+    o = torch.full((1,), float("nan"), dtype=torch.float64, device=DEV) if obj else None
+    ctx = ctx_for("auto")
+    nb.step(Vd, Wd, Hd, 2.0, mode, gram=True, objective_out=o, ctx=ctx)
+    torch.cuda.synchronize()
+    assert nb.get_flags(clear=True, ctx=ctx) == 0
+    Wr, Hr = ref_step(p.V, p.W, p.H, 2.0, mode)
+    check_pair(Wd.cpu().numpy(), Hd.cpu().numpy(), Wr, Hr, tag=f"gram {mode}")
+    if obj:
+        d0 = ref_obj(p.V, p.W, p.H, 2.0)
+        assert abs(o.item() - d0) <= TOL_OBJ * abs(d0)
+
+
+def test_gram_form_trajectory_matches_contraction_form():
+    p = synth.make_problem("faces_euc")
+    V = dev(p.V)
+    Wa, Ha, Wb, Hb = dev(p.W), dev(p.H), dev(p.W), dev(p.H)
+    oa = torch.zeros(1, dtype=torch.float64, device=DEV)
+    ob = torch.zeros(1, dtype=torch.float64, device=DEV)
+    ta, tb = [], []
+    for _ in range(50):
+        nb.step(V, Wa, Ha, 2.0, "joint", gram=True, objective_out=oa)
+        nb.step(V, Wb, Hb, 2.0, "joint", objective_out=ob)
+        ta.append(oa.item())
+        tb.append(ob.item())
+    assert nb.get_flags(clear=True) == 0
+    assert np.all(np.diff(ta) <= 2e-7 * np.abs(ta[1:]))
+    assert np.allclose(ta, tb, rtol=1e-5)
+    check_pair(Wa.cpu().numpy(), Ha.cpu().numpy(), Wb.cpu().numpy().astype(np.float64),
+               Hb.cpu().numpy().astype(np.float64), tag="gram vs contraction after 50 steps", fro=1e-4, el=1e-3)
+
+
+def test_gram_form_rejected_where_unsupported():
+    p = synth.random_positive(40, 50, 6, seed=66)
+    V, W, H = dev(p.V), dev(p.W), dev(p.H)
+    for kw in (dict(beta=1.0), dict(beta=2.0, kappa=0.1), dict(beta=2.0, precision="bf16"),
+               dict(beta=2.0, inner_iters=2)):
+        beta = kw.pop("beta")
+        with pytest.raises(nb.NmfError):
+            nb.step(V, W, H, beta, "joint", gram=True, **kw)
+    q = synth.random_positive(40, 50, 65, seed=67)
+    with pytest.raises(nb.NmfError):
+        nb.step(dev(q.V), dev(q.W), dev(q.H), 2.0, "joint", gram=True)
+    assert torch.equal(W, dev(p.W))
