@@ -374,7 +374,7 @@ typedef struct {
 } nmf_problem;
 
 typedef struct {
-  int32_t tiles_per_item;   /* 32-wide tiles each pass item walks (0: default 8) */
+  int32_t tiles_per_item;   /* 32-wide tiles each pass item walks (0: default 128) */
   int32_t workers;          /* persistent workgroups (0: as many as fit on the GPU) */
 } nmf_batch_config;
 

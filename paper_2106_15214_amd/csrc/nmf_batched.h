@@ -40,8 +40,13 @@ __device__ __forceinline__ T load_const(const __attribute__((address_space(4))) 
   return r;
 }
 
+// One work item.  Not inlined: each (beta class, K block, phase) path is its
+// own function with its own register allocation, so the persistent kernel's
+// budget is the largest single path and not the union of all of them inlined
+// into one body (which spilled heavily); this is what lets two workgroups share
+// a compute unit.
 template <int BC, int KB, int PREC, bool JOINT, bool OBJ>
-__device__ __forceinline__ void batch_item(ConstProblemPtr P, int prob, int phase, int item, const BatchArgs& b,
+__device__ __noinline__ void batch_item(ConstProblemPtr P, int prob, int phase, int item, const BatchArgs& b,
                                            float* lds, double* red, float* norm_s, float* csum_s) {
   if (phase == PH_WPASS) {
     const SweepRowsArgs ra = load_const(&P->ra);
@@ -106,7 +111,7 @@ __device__ __forceinline__ void batch_item_bc(int bc, ConstProblemPtr P, int pro
 }
 
 template <int PREC, bool JOINT, bool OBJ>
-__global__ __launch_bounds__(kBlock, 1) void batched_step_kernel(BatchArgs b) {
+__global__ __launch_bounds__(kBlock, 2) void batched_step_kernel(BatchArgs b) {
   __shared__ __align__(16) float lds[kBatchLdsBytes / 4];
   __shared__ double red[kWaves];
   __shared__ float norm_s[64], csum_s[64];
