@@ -173,6 +173,7 @@ def main(argv=None):
     ap.add_argument("--problems", type=int, default=512, help="batched workload: number of problems")
     ap.add_argument("--tune", default=None, help="batched workload: autotune, caching results in this JSON file")
     ap.add_argument("--tiles", type=int, default=0, help="batched workload: tiles per pass item (0: library default)")
+    ap.add_argument("--lag", type=int, default=0, help="batched workload: queue order (0 phase-major, d pipelined)")
     ap.add_argument("--inner-iters", type=int, default=1,
                     help="sub-iterations L per outer iteration (both methods; L > 1: float32)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"],
@@ -574,7 +575,7 @@ def main_batched(args, nb, synth, torch, np, dev):
     print(f"# batched: {len(probs)} problems, sum FN = {fn:.3e}, sum FNK = {fnk:.3e} "
           f"(generated in {time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
     ctx = nb.Context(0)
-    cfg = {"tiles_per_item": args.tiles, "workers": 0}
+    cfg = {"tiles_per_item": args.tiles, "workers": 0, "lag": args.lag}
     tuned_ms = None
     if args.tune:
         cfg, tuned_ms = nb.batch_tune(probs, "joint", precision=args.precision, iters=3, cache=args.tune, ctx=ctx)

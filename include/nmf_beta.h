@@ -376,6 +376,11 @@ typedef struct {
 typedef struct {
   int32_t tiles_per_item;   /* 32-wide tiles each pass item walks (0: default 128) */
   int32_t workers;          /* persistent workgroups (0: as many as fit on the GPU) */
+  int32_t lag;              /* order of the work queue.  0 (default): phase by phase
+                               over all problems.  d > 0: problems pipelined d apart,
+                               problem j's phase q listed with problem j + q d's W
+                               pass, so a problem's kept P, Q are read back by its H
+                               pass while fewer problems' tiles are in flight. */
 } nmf_batch_config;
 
 /* Validates every problem (as nmf_beta_step would; opts->precision FP32 or BF16,

@@ -77,7 +77,7 @@ class _SparseV(ctypes.Structure):
 
 
 class _BatchConfig(ctypes.Structure):
-    _fields_ = [("tiles_per_item", ctypes.c_int32), ("workers", ctypes.c_int32)]
+    _fields_ = [("tiles_per_item", ctypes.c_int32), ("workers", ctypes.c_int32), ("lag", ctypes.c_int32)]
 
 
 _lib = None
@@ -588,12 +588,13 @@ class Batch:
     (V, W, H, beta) device tensors; W and H are updated in place by step()."""
 
     def __init__(self, problems, mode="joint", *, precision="fp32", kappa: float = 0.0, normalize: bool = True,
-                 exponent="mm", tiles_per_item: int = 0, workers: int = 0, ctx: Optional[Context] = None):
+                 exponent="mm", tiles_per_item: int = 0, workers: int = 0, lag: int = 0,
+                 ctx: Optional[Context] = None):
         self._tensors = list(problems)  # keep the caller's tensors alive
         self.count = len(problems)
         arr = _problems(problems)
         o = _opts(precision, kappa, 1, normalize, exponent)
-        cfg = _BatchConfig(int(tiles_per_item), int(workers))
+        cfg = _BatchConfig(int(tiles_per_item), int(workers), int(lag))
         h = _vp()
         _check(lib().nmf_batch_create(_ctx(ctx), arr, self.count, MODES[mode], ctypes.byref(o), ctypes.byref(cfg),
                                       ctypes.byref(h)), "nmf_batch_create")
@@ -663,14 +664,14 @@ def batch_tune(problems, mode="joint", *, precision="fp32", kappa: float = 0.0, 
             table = json.load(f)
         if key in table:
             e = table[key]
-            return {"tiles_per_item": e["tiles_per_item"], "workers": e["workers"]}, e["ms"]
+            return {"tiles_per_item": e["tiles_per_item"], "workers": e["workers"], "lag": e.get("lag", 0)}, e["ms"]
     arr = _problems(problems)
     o = _opts(precision, kappa, 1, normalize)
     cfg = _BatchConfig()
     ms = _dbl()
     _check(lib().nmf_batch_tune(_ctx(ctx), arr, len(problems), MODES[mode], ctypes.byref(o), _stream(stream),
                                 int(iters), ctypes.byref(cfg), ctypes.byref(ms)), "nmf_batch_tune")
-    best = {"tiles_per_item": cfg.tiles_per_item, "workers": cfg.workers}
+    best = {"tiles_per_item": cfg.tiles_per_item, "workers": cfg.workers, "lag": cfg.lag}
     if cache:
         table[key] = dict(best, ms=ms.value)
         tmp = cache + ".tmp"

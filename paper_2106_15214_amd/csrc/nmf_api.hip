@@ -1322,7 +1322,9 @@ nmf_status nmf_batch_create(nmf_ctx_t c, const nmf_problem* pr, int32_t count, i
     d.per_item[PH_HUPDATE] = batch_h_units(p.KB);
     for (int ph = 0; ph < 4; ++ph) d.items[ph] = (int)cdiv(d.units[ph], d.per_item[ph]);
   }
-  // queue: phase-major; within a phase the larger problems first
+  // queue, larger problems first: phase-major (lag 0), or pipelined with phase q
+  // of the problem at position j listed at step j + q lag.  Either way every
+  // item is listed after all the items it waits for.
   std::vector<int> order(count);
   for (int i = 0; i < count; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int bb) {
@@ -1330,9 +1332,20 @@ nmf_status nmf_batch_create(nmf_ctx_t c, const nmf_problem* pr, int32_t count, i
   });
   std::vector<int2> list;
   list.reserve((size_t)total);
-  for (int ph = 0; ph < 4; ++ph)
-    for (int i : order)
-      for (int it = 0; it < desc[i].items[ph]; ++it) list.push_back(make_int2(i, (ph << 24) | it));
+  auto emit = [&](int i, int ph) {
+    for (int it = 0; it < desc[i].items[ph]; ++it) list.push_back(make_int2(i, (ph << 24) | it));
+  };
+  const int lag = cfg ? std::max(0, cfg->lag) : 0;
+  if (lag == 0) {
+    for (int ph = 0; ph < 4; ++ph)
+      for (int i : order) emit(i, ph);
+  } else {
+    for (int64_t step = 0; step < (int64_t)count + 3 * (int64_t)lag; ++step)
+      for (int ph = 0; ph < 4; ++ph) {
+        const int64_t j = step - (int64_t)ph * lag;
+        if (j >= 0 && j < count) emit(order[j], ph);
+      }
+  }
 
   hipError_t e = hipMemset(mem, 0, o_desc);
   if (e == hipSuccess) e = hipMemcpy(mem + o_desc, desc.data(), sizeof(BatchProblem) * count, hipMemcpyHostToDevice);
@@ -1430,14 +1443,14 @@ nmf_status nmf_batch_tune(nmf_ctx_t c, const nmf_problem* pr, int32_t count, int
   };
   nmf_status result = NMF_OK;
   double best_t = 1e300;
-  nmf_batch_config best_cfg{kBatchTilesDefault, 0};
+  nmf_batch_config best_cfg{kBatchTilesDefault, 0, 0};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess || copy_all(true) != hipSuccess) {
     result = NMF_ERR_HIP;
   }
   static const int kCandidates[] = {4, 8, 16, 32, 64, 128};
   for (int ci = 0; result == NMF_OK && ci < (int)(sizeof(kCandidates) / sizeof(int)); ++ci) {
-    nmf_batch_config cfg{kCandidates[ci], 0};
+    nmf_batch_config cfg{kCandidates[ci], 0, 0};
     nmf_batch_t b = nullptr;
     nmf_status st = nmf_batch_create(c, pr, count, mode, opts, &cfg, &b);
     if (st != NMF_OK) { result = st; break; }
