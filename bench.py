@@ -171,7 +171,8 @@ def main(argv=None):
     ap.add_argument("--target-blocks", type=int, default=0)
     ap.add_argument("--min-tiles", type=int, default=0)
     ap.add_argument("--problems", type=int, default=512, help="batched workload: number of problems")
-    ap.add_argument("--tune", default=None, help="batched workload: autotune, caching results in this JSON file")
+    ap.add_argument("--tune", default=None,
+                    help="batched workload: tune the per-bucket tile table, caching it in this text file")
     ap.add_argument("--tiles", type=int, default=0, help="batched workload: tiles per pass item (0: library default)")
     ap.add_argument("--lag", type=int, default=0, help="batched workload: queue order (0 phase-major, d pipelined)")
     ap.add_argument("--inner-iters", type=int, default=1,
@@ -578,8 +579,10 @@ def main_batched(args, nb, synth, torch, np, dev):
     cfg = {"tiles_per_item": args.tiles, "workers": 0, "lag": args.lag}
     tuned_ms = None
     if args.tune:
-        cfg, tuned_ms = nb.batch_tune(probs, "joint", precision=args.precision, iters=3, cache=args.tune, ctx=ctx)
-        print(f"# tuned: {cfg} ({tuned_ms:.3f} ms/step)", file=sys.stderr, flush=True)
+        tiles, tuned_ms, hit = nb.tune(probs, "joint", precision=args.precision, iters=3, cache=args.tune, ctx=ctx)
+        print(f"# tuned bucket tiles {tiles} ({tuned_ms:.3f} ms/step, {'cached' if hit else 'measured'})",
+              file=sys.stderr, flush=True)
+    bucket_tiles = nb.get_batch_tiles(ctx)
     res, traces = {}, {}
     W0 = [(W.clone(), H.clone()) for _, W, H, _ in probs]
 
@@ -623,6 +626,8 @@ def main_batched(args, nb, synth, torch, np, dev):
         if b.flags(clear=True):
             print(f"# warning: flags raised in the {mode} trajectory", file=sys.stderr, flush=True)
         b.close()
+        if args.tiles == 0 and args.lag == 0:
+            res[mode]["device_planned_ms_per_step"] = device_planned_ms(nb, torch, probs, mode, args, ctx, reset)
     tto = batched_time_to_objective(np, host, traces, {m: res[m]["ms_per_step"] for m in res}, T)
 
     t = res["joint"]["ms_per_step"] * 1e-3
@@ -651,7 +656,7 @@ def main_batched(args, nb, synth, torch, np, dev):
         "data": "synthetic",
         "config": {"workload": "batched", "problems": len(probs), "sum_FN": fn, "sum_FNK": fnk, "mode": "joint",
                    "precision": args.precision, "objective_every_step": True, "launches_per_step": 1,
-                   "graph_replay": True, **cfg},
+                   "graph_replay": True, **cfg, "bucket_tiles": bucket_tiles},
         "problem_iterations_per_s": len(probs) * res["joint"]["steps_per_s"],
         "alternating": {"value": res["alternating"]["steps_per_s"], "ms_per_step": res["alternating"]["ms_per_step"],
                         "roofline_frac": alt_frac},
@@ -669,6 +674,41 @@ def main_batched(args, nb, synth, torch, np, dev):
     print(json.dumps(out), flush=True)
     ctx.close()
     return 0
+
+
+def device_planned_ms(nb, torch, probs, mode, args, ctx, reset):
+    """Time per step of the same batch through nmf_beta_step_batched (the
+    descriptors in device memory, planned on the device each step: a planning
+    launch plus the persistent launch), replayed from a graph."""
+    reset()
+    shapes = [(V.shape[0], V.shape[1], W.shape[1]) for V, W, H, _ in probs]
+    tiles = nb.get_batch_tiles(ctx)
+    ctx = nb.Context(0)  # its own region: a captured region is never re-reserved
+    nb.set_batch_tiles(tiles, ctx=ctx)
+    items, nbytes = nb.batch_requirements(shapes, mode, tiles)
+    nb.reserve_batched(len(probs), items, nbytes, ctx=ctx)
+    dp = nb.DeviceProblems(len(probs))
+    dp.set(probs)
+    obj = torch.zeros(len(probs), dtype=torch.float64, device=probs[0][0].device)
+    s = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        nb.step_batched(dp, mode, precision=args.precision, objectives=obj, stream=s, ctx=ctx)
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    fl = nb.get_flags(clear=True, ctx=ctx)
+    print(f"# {mode}: {ms:.3f} ms/step device-planned (graph replays), flags {fl}", file=sys.stderr, flush=True)
+    del graph
+    ctx.close()
+    return ms
 
 
 def batched_time_to_objective(np, host, traces, ms_per_iter, T):

@@ -51,7 +51,8 @@ typedef enum {
   NMF_ERR_HIP = 6,         /* a HIP runtime call failed */
   NMF_ERR_UNSUPPORTED = 7, /* K > 128, unknown precision, an unsupported inner_iters > 1 case */
   NMF_ERR_ARG = 8,         /* other invalid argument (mode, opts field) */
-  NMF_ERR_NO_DEVICE = 9    /* no usable GPU */
+  NMF_ERR_NO_DEVICE = 9,   /* no usable GPU */
+  NMF_ERR_IO = 10          /* nmf_tune could not write its cache file */
 } nmf_status;
 
 typedef enum {
@@ -81,6 +82,9 @@ typedef enum {
 #define NMF_FLAG_RANGE 8u     /* NMF_FP16 mode: an operand of a float16 product was
                                  outside the float16 range or not finite (the step's
                                  result is then not meaningful) */
+#define NMF_FLAG_SKIPPED 16u  /* nmf_beta_step_batched updated nothing: a descriptor
+                                 was invalid, two problems' matrices overlapped, or
+                                 the batch needed more than the reserved region */
 
 /* exponent of the multiplicative updates (nmf_step_opts.exponent) */
 #define NMF_EXPONENT_MM 0  /* gamma(beta) of eq. (def_gamma): the MM step, whose
@@ -251,7 +255,8 @@ nmf_status nmf_beta_validate(nmf_ctx_t ctx, void* stream, int64_t F, int64_t N, 
                              const float* V, int64_t ldv, const float* W, int64_t ldw,
                              const float* H, int64_t ldh, double beta, float kappa);
 
-/* Reads (synchronizing `stream`) and optionally clears the sticky flags. */
+/* Reads (synchronizing `stream`) and optionally clears the sticky flags: those of
+ * the context's steps and of its nmf_beta_step_batched calls, OR-ed together. */
 nmf_status nmf_get_flags(nmf_ctx_t ctx, void* stream, uint32_t* flags, int32_t clear);
 
 /* Per-kernel timing with HIP events recorded on the launch stream around each
@@ -374,7 +379,9 @@ typedef struct {
 } nmf_problem;
 
 typedef struct {
-  int32_t tiles_per_item;   /* 32-wide tiles each pass item walks (0: default 128) */
+  int32_t tiles_per_item;   /* 32-wide tiles each pass item walks (0: the context's
+                               per-bucket table, 128 in every bucket unless set by
+                               nmf_set_batch_tiles or nmf_tune) */
   int32_t workers;          /* persistent workgroups (0: as many as fit on the GPU) */
   int32_t lag;              /* order of the work queue.  0 (default): phase by phase
                                over all problems.  d > 0: problems pipelined d apart,
@@ -404,14 +411,100 @@ nmf_status nmf_batch_info(nmf_batch_t batch, int64_t* work_items, int32_t* worke
 /* Frees the batch (synchronizes the device first). */
 nmf_status nmf_batch_destroy(nmf_batch_t batch);
 
-/* Autotuner: times `iters` batch steps (after one warm-up step) for each
- * candidate tiles_per_item in {4, 8, 16, 32, 64, 128} on the given problems and
- * returns the fastest configuration and its time per step in milliseconds.
- * The problems' W and H are saved before and restored after every candidate, so
- * they are unchanged on return.  Synchronous. */
-nmf_status nmf_batch_tune(nmf_ctx_t ctx, const nmf_problem* problems, int32_t count, int32_t mode,
-                          const nmf_step_opts* opts, void* stream, int32_t iters, nmf_batch_config* best,
-                          double* best_ms);
+/* Per-bucket tile counts.  A problem of a batch falls in bucket
+ *   (K <= 32 ? 0 : 4) + (T <= 32 ? 0 : T <= 64 ? 1 : T <= 128 ? 2 : 3),
+ *   T = max(ceil(F / 32), ceil(N / 32)),
+ * and walks the tiles_per_item of its bucket.  The context holds one table
+ * (128 in every bucket at creation), used by nmf_batch_create when
+ * cfg->tiles_per_item is 0 and by every nmf_beta_step_batched. */
+#define NMF_BATCH_BUCKETS 8
+
+/* Bucket of a problem of sizes F, N, K (host only); -1 if a size is out of
+ * range (F, N < 1, K outside 1..64). */
+int32_t nmf_batch_bucket(int64_t F, int64_t N, int64_t K);
+
+/* Sets (copies in) or reads (copies out) the context's table of
+ * NMF_BATCH_BUCKETS tile counts, each in 1..4096 (else NMF_ERR_ARG).  Setting
+ * also updates the reserved batched region if there is one (a blocking copy):
+ * graphs that replay nmf_beta_step_batched plan with the new table from their
+ * next replay on. */
+nmf_status nmf_set_batch_tiles(nmf_ctx_t ctx, const int32_t* tiles);
+nmf_status nmf_get_batch_tiles(nmf_ctx_t ctx, int32_t* tiles);
+
+/* Autotuner of the context's bucket table for a representative set of
+ * problems (host descriptors of device matrices, as nmf_batch_create).
+ *
+ * Key: the device's architecture and compute-unit count, the mode and
+ * opts->precision.  If `cache_path` (may be NULL) holds an entry for this key
+ * that covers every bucket the problems fall in, its tiles are installed and
+ * nothing is measured (*from_cache = 1).  Otherwise, starting from that entry
+ * (else from the context's table), each uncovered bucket in turn takes the
+ * candidate of {4, 8, 16, 32, 64, 128} with the smallest time per batched step
+ * of the whole set (one warm-up step, then `iters` timed steps; candidates
+ * that split every problem of the bucket as an already timed one are skipped),
+ * the others held fixed.  The problems' W and H are saved before and restored
+ * after every timing, so they are unchanged on return.  The result is
+ * installed in the context (as nmf_set_batch_tiles) and, with a cache_path,
+ * written to the file (one text line per key, other lines kept; written to a
+ * temporary file and renamed; NMF_ERR_IO if that fails).
+ *
+ * tiles (host int32[NMF_BATCH_BUCKETS], required) receives the table; ms
+ * (nullable) the time per step of the set with it (the cached time on a cache
+ * hit); from_cache (nullable) 1 on a cache hit, else 0.  Synchronous; not
+ * during stream capture. */
+nmf_status nmf_tune(nmf_ctx_t ctx, void* stream, const nmf_problem* problems, int32_t count, int32_t mode,
+                    const nmf_step_opts* opts, int32_t iters, const char* cache_path, int32_t* tiles, double* ms,
+                    int32_t* from_cache);
+
+/* ---------------------------------------------------------------------------
+ * Batched step with descriptors in device memory.
+ *
+ * For callers whose problem set changes between steps without a host round
+ * trip: a graph replayed over new matrices, shapes or betas, or a serving loop
+ * that cannot call hipMalloc.  nmf_reserve_batched sizes the context's batched
+ * region once; nmf_beta_step_batched then allocates nothing and never waits on
+ * the host, so it may be captured into a HIP graph.  Each call launches a
+ * planning kernel (one workgroup: it reads the descriptors, checks them, plans
+ * every problem with the context's bucket table exactly as nmf_batch_create
+ * does, lays the workspaces out, and lists the work items phase by phase,
+ * larger problems first) and then the persistent kernel of nmf_batch_step.  The
+ * results are those of nmf_batch_create + nmf_batch_step on the same problems
+ * with the same tile counts and lag 0.
+ * ------------------------------------------------------------------------- */
+
+/* Items per step and workspace bytes that `count` problems (host descriptors;
+ * only the sizes are read) need in `mode` under `tiles` (host
+ * int32[NMF_BATCH_BUCKETS]; NULL: 128 in every bucket).  Host only, no GPU.
+ * NMF_ERR_SHAPE / NMF_ERR_UNSUPPORTED for a size out of range (K > 64). */
+nmf_status nmf_batch_requirements(const nmf_problem* problems, int32_t count, int32_t mode, const int32_t* tiles,
+                                  int64_t* items, int64_t* workspace_bytes);
+
+/* Allocates the context's batched region (blocking; frees a previous one):
+ * max_problems descriptors (>= 1), max_items work items per step (1 .. 2^31 - 1)
+ * and workspace_bytes (>= 0) of problem workspaces.  NMF_ERR_WORKSPACE once a
+ * nmf_beta_step_batched call was captured (a graph may point into the region). */
+nmf_status nmf_reserve_batched(nmf_ctx_t ctx, int32_t max_problems, int64_t max_items, int64_t workspace_bytes);
+
+/* One outer iteration of every problem described by d_problems (device array
+ * of `count` nmf_problem, count <= max_problems), in place on their W and H.
+ * d_count (device int32, nullable): the number of descriptors used this call,
+ * read on the device (0 <= *d_count <= count), so a captured call can be
+ * replayed on fewer problems; NULL uses all `count`.  opts: FP32 or BF16,
+ * inner_iters 1, gram 0 (else NMF_ERR_UNSUPPORTED).  d_objectives (device
+ * double[count], nullable) receives each problem's entry objective.
+ *
+ * Status covers the host arguments: NMF_ERR_NULL, NMF_ERR_ARG (count < 1, mode,
+ * opts), NMF_ERR_WORKSPACE (no batched region, or count > max_problems).  The
+ * descriptors are checked on the device (as nmf_beta_step's arguments, K <= 64,
+ * and the W and H of every problem overlapping no other W, H and no V; V may
+ * be shared):
+ * if one fails, or the plan needs more items or workspace than reserved, the
+ * call updates nothing, writes no objective and sets NMF_FLAG_SKIPPED.  Flags
+ * of these calls are read and cleared with nmf_get_flags.  Calls on one
+ * context share the region: calls that overlap in time race. */
+nmf_status nmf_beta_step_batched(nmf_ctx_t ctx, void* stream, int32_t count, const nmf_problem* d_problems,
+                                 int32_t mode, const nmf_step_opts* opts, double* d_objectives,
+                                 const int32_t* d_count);
 
 #ifdef __cplusplus
 }

@@ -26,7 +26,9 @@ __all__ = [
     "ALTERNATING", "JOINT", "FP32", "BF16", "FP16", "EXPONENTS",
     "FLAG_NONFINITE", "FLAG_DOMAIN", "FLAG_BARRIER", "FLAG_RANGE", "KERNELS",
     "step", "step_noalloc", "run", "kkt", "objective", "grad", "SparseV", "kl_step_sparse", "kl_objective_sparse",
-    "sparse_validate", "validate", "get_flags", "check_step_args", "Batch", "batch_tune",
+    "sparse_validate", "validate", "get_flags", "check_step_args", "Batch", "BATCH_BUCKETS", "batch_bucket",
+    "set_batch_tiles", "get_batch_tiles", "tune", "batch_requirements", "reserve_batched", "DeviceProblems",
+    "step_batched", "FLAG_SKIPPED",
     "BetaDivergence", "beta_divergence",
 ]
 
@@ -38,6 +40,8 @@ KERNELS = {"sweep_w": 0, "update_w": 1, "sweep_h": 2, "update_h": 3, "fused_step
 PATHS = {"auto": 0, "stream": 1, "fused": 2}
 FLAG_BARRIER = 4
 FLAG_RANGE = 8  # float16 mode: an operand outside the float16 range
+FLAG_SKIPPED = 16  # step_batched updated nothing (invalid descriptor, overlap, over capacity)
+BATCH_BUCKETS = 8
 MODES = {"alternating": ALTERNATING, "bmm": ALTERNATING, "joint": JOINT, "jmm": JOINT}
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16}
 # update exponent: gamma(beta) (the MM step) or 1 (the heuristic of Sec. 3.3.3)
@@ -137,14 +141,24 @@ def lib() -> ctypes.CDLL:
         L.nmf_batch_get_flags.argtypes = [_vp, _vp, ctypes.POINTER(_u32), _i32]
         L.nmf_batch_info.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_i64)]
         L.nmf_batch_destroy.argtypes = [_vp]
-        L.nmf_batch_tune.argtypes = [_vp, PP, _i32, _i32, ctypes.POINTER(_Opts), _vp, _i32, PC,
-                                     ctypes.POINTER(_dbl)]
+        PI = ctypes.POINTER(_i32)
+        L.nmf_batch_bucket.argtypes = [_i64, _i64, _i64]
+        L.nmf_batch_bucket.restype = _i32
+        L.nmf_set_batch_tiles.argtypes = [_vp, PI]
+        L.nmf_get_batch_tiles.argtypes = [_vp, PI]
+        L.nmf_tune.argtypes = [_vp, _vp, PP, _i32, _i32, ctypes.POINTER(_Opts), _i32, ctypes.c_char_p, PI,
+                               ctypes.POINTER(_dbl), PI]
+        L.nmf_batch_requirements.argtypes = [PP, _i32, _i32, PI, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
+        L.nmf_reserve_batched.argtypes = [_vp, _i32, _i64, _i64]
+        L.nmf_beta_step_batched.argtypes = [_vp, _vp, _i32, _vp, _i32, ctypes.POINTER(_Opts), _vp, _vp]
         for name in ("nmf_create", "nmf_destroy", "nmf_reserve", "nmf_check_step_args", "nmf_beta_step",
                      "nmf_beta_step_noalloc", "nmf_beta_kkt", "nmf_beta_run",
                      "nmf_beta_objective", "nmf_beta_grad", "nmf_beta_validate", "nmf_get_flags",
                      "nmf_profile_enable", "nmf_profile_read", "nmf_set_launch", "nmf_set_path",
                      "nmf_profile_phases", "nmf_batch_create", "nmf_batch_step", "nmf_batch_get_flags",
-                     "nmf_batch_info", "nmf_batch_destroy", "nmf_batch_tune", "nmf_kl_step_sparse",
+                     "nmf_batch_info", "nmf_batch_destroy", "nmf_set_batch_tiles", "nmf_get_batch_tiles",
+                     "nmf_tune", "nmf_batch_requirements", "nmf_reserve_batched", "nmf_beta_step_batched",
+                     "nmf_kl_step_sparse",
                      "nmf_kl_objective_sparse", "nmf_sparse_validate"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -634,48 +648,126 @@ class Batch:
             pass
 
 
-def _batch_signature(problems, mode, precision) -> str:
-    """Tuning-cache key: device architecture, mode, precision and a histogram of
-    problem shape buckets (log2 of F, N; K in steps of 16; beta)."""
-    import hashlib
-    import math
-    import torch
-    arch = getattr(torch.cuda.get_device_properties(0), "gcnArchName", "gpu").split(":")[0]
-    hist = {}
-    for V, W, H, beta in problems:
-        F, N = V.shape
-        key = (int(math.log2(F)), int(math.log2(N)), (W.shape[1] - 1) // 16, float(beta))
-        hist[key] = hist.get(key, 0) + 1
-    digest = hashlib.sha1(repr(sorted(hist.items())).encode()).hexdigest()[:16]
-    return f"{arch}/{mode}/{precision}/{len(problems)}/{digest}"
+def batch_bucket(F: int, N: int, K: int) -> int:
+    """Tile-table bucket of a batched problem of sizes F, N, K (nmf_batch_bucket)."""
+    return int(lib().nmf_batch_bucket(int(F), int(N), int(K)))
 
 
-def batch_tune(problems, mode="joint", *, precision="fp32", kappa: float = 0.0, normalize: bool = True,
-               iters: int = 3, cache: Optional[str] = None, stream=None, ctx: Optional[Context] = None):
-    """Autotunes the batch configuration (nmf_batch_tune) and returns
-    (config dict, ms per step).  With ``cache`` (a JSON file) a configuration
-    measured before for the same device, mode, precision and shape histogram is
-    returned without measuring; new results are added to the file."""
-    import json
-    key = _batch_signature(problems, mode, precision)
-    table = {}
-    if cache and os.path.exists(cache):
-        with open(cache) as f:
-            table = json.load(f)
-        if key in table:
-            e = table[key]
-            return {"tiles_per_item": e["tiles_per_item"], "workers": e["workers"], "lag": e.get("lag", 0)}, e["ms"]
+def set_batch_tiles(tiles, ctx: Optional[Context] = None):
+    """Sets the context's tiles per pass item of each bucket (nmf_set_batch_tiles)."""
+    arr = (_i32 * BATCH_BUCKETS)(*[int(t) for t in tiles])
+    if len(tiles) != BATCH_BUCKETS:
+        raise ValueError(f"{BATCH_BUCKETS} tile counts expected")
+    _check(lib().nmf_set_batch_tiles(_ctx(ctx), arr), "nmf_set_batch_tiles")
+
+
+def get_batch_tiles(ctx: Optional[Context] = None):
+    arr = (_i32 * BATCH_BUCKETS)()
+    _check(lib().nmf_get_batch_tiles(_ctx(ctx), arr), "nmf_get_batch_tiles")
+    return list(arr)
+
+
+def tune(problems, mode="joint", *, precision="fp32", kappa: float = 0.0, normalize: bool = True,
+         iters: int = 3, cache: Optional[str] = None, stream=None, ctx: Optional[Context] = None):
+    """Tunes the context's per-bucket tile table on ``problems`` (nmf_tune) and
+    returns (tiles, ms per step, from_cache).  With ``cache`` (a text file) a
+    table measured before for the same device, mode and precision covering
+    these problems' buckets is installed without measuring; new results are
+    written to the file."""
     arr = _problems(problems)
     o = _opts(precision, kappa, 1, normalize)
-    cfg = _BatchConfig()
-    ms = _dbl()
-    _check(lib().nmf_batch_tune(_ctx(ctx), arr, len(problems), MODES[mode], ctypes.byref(o), _stream(stream),
-                                int(iters), ctypes.byref(cfg), ctypes.byref(ms)), "nmf_batch_tune")
-    best = {"tiles_per_item": cfg.tiles_per_item, "workers": cfg.workers, "lag": cfg.lag}
-    if cache:
-        table[key] = dict(best, ms=ms.value)
-        tmp = cache + ".tmp"
-        with open(tmp, "w") as f:
-            json.dump(table, f, indent=1, sort_keys=True)
-        os.replace(tmp, cache)
-    return best, ms.value
+    tiles = (_i32 * BATCH_BUCKETS)()
+    ms, hit = _dbl(), _i32()
+    path = os.fsencode(cache) if cache else None
+    _check(lib().nmf_tune(_ctx(ctx), _stream(stream), arr, len(problems), MODES[mode], ctypes.byref(o), int(iters),
+                          path, tiles, ctypes.byref(ms), ctypes.byref(hit)), "nmf_tune")
+    return list(tiles), ms.value, bool(hit.value)
+
+
+def batch_requirements(shapes, mode="joint", tiles=None):
+    """(work items per step, workspace bytes) that problems of the given
+    (F, N, K) sizes need in a batch under ``tiles`` (None: 128 in every bucket).
+    Host only."""
+    arr = (_Problem * len(shapes))()
+    for i, (F, N, K) in enumerate(shapes):
+        arr[i] = _Problem(int(F), int(N), int(K), None, 0, None, 0, None, 0, 1.0)
+    t = (_i32 * BATCH_BUCKETS)(*[int(x) for x in tiles]) if tiles is not None else None
+    n, b = _i64(), _i64()
+    _check(lib().nmf_batch_requirements(arr, len(shapes), MODES[mode], t, ctypes.byref(n), ctypes.byref(b)),
+           "nmf_batch_requirements")
+    return n.value, b.value
+
+
+def reserve_batched(max_problems: int, max_items: int, workspace_bytes: int, ctx: Optional[Context] = None):
+    """Allocates the context's region for step_batched (nmf_reserve_batched)."""
+    _check(lib().nmf_reserve_batched(_ctx(ctx), int(max_problems), int(max_items), int(workspace_bytes)),
+           "nmf_reserve_batched")
+
+
+class DeviceProblems:
+    """Problem descriptors (nmf_problem) in device memory for step_batched.
+    ``capacity`` slots; set() writes (V, W, H, beta) device tensors into them
+    with one host-to-device copy on ``stream`` (the tensors are kept alive)."""
+
+    def __init__(self, capacity: int, device: int = 0):
+        import torch
+        self.capacity = int(capacity)
+        self.buf = torch.zeros(ctypes.sizeof(_Problem) * self.capacity, dtype=torch.uint8,
+                               device=f"cuda:{device}")
+        self._tensors = []
+        self.count = 0
+
+    def set(self, problems, stream=None):
+        import torch
+        if len(problems) > self.capacity:
+            raise ValueError(f"{len(problems)} problems for {self.capacity} slots")
+        arr = _problems(problems)
+        host = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8)
+        n = host.numel()
+        if n:
+            if stream is None:
+                self.buf[:n].copy_(host)
+            else:
+                with torch.cuda.stream(stream):
+                    self.buf[:n].copy_(host)
+        self._tensors = list(problems)
+        self.count = len(problems)
+
+    def set_raw(self, descriptors: bytes, stream=None):
+        """Writes packed nmf_problem bytes as they are (no checks), for tests of
+        the device-side checks."""
+        import torch
+        host = torch.frombuffer(bytearray(descriptors), dtype=torch.uint8)
+        self.buf[:host.numel()].copy_(host)
+
+    @staticmethod
+    def pack(problems) -> bytes:
+        return bytes(_problems(problems))
+
+    def ptr(self) -> int:
+        return self.buf.data_ptr()
+
+
+def step_batched(dp: DeviceProblems, mode="joint", *, count: Optional[int] = None, precision="fp32",
+                 kappa: float = 0.0, normalize: bool = True, exponent="mm", objectives=None, d_count=None,
+                 stream=None, ctx: Optional[Context] = None):
+    """One outer iteration of every problem described in device memory
+    (nmf_beta_step_batched).  ``count`` descriptors are passed (default: those
+    set last); ``d_count`` (an int32 device tensor, optional) limits the number
+    used on the device; ``objectives`` (float64 device tensor) receives the
+    entry objectives."""
+    import torch
+    n = dp.count if count is None else int(count)
+    optr = None
+    if objectives is not None:
+        if objectives.dtype != torch.float64 or not objectives.is_cuda or objectives.numel() < n:
+            raise ValueError("objectives must be a float64 device tensor with one entry per problem")
+        optr = objectives.data_ptr()
+    cptr = None
+    if d_count is not None:
+        if d_count.dtype != torch.int32 or not d_count.is_cuda:
+            raise ValueError("d_count must be an int32 device tensor")
+        cptr = d_count.data_ptr()
+    o = _opts(precision, kappa, 1, normalize, exponent)
+    _check(lib().nmf_beta_step_batched(_ctx(ctx), _stream(stream), n, dp.ptr(), MODES[mode], ctypes.byref(o), optr,
+                                       cptr), "nmf_beta_step_batched")

@@ -2,24 +2,27 @@
 // launch planning and the C ABI declared in include/nmf_beta.h.
 #include <hip/hip_runtime.h>
 
+#include <unistd.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
+#include "nmf_batched_plan.h"
 #include "nmf_beta.h"
 #include "nmf_internal.h"
+#include "nmf_plan.h"
 
 using namespace nmf;
 
 namespace {
 
-constexpr size_t kAlign = 256;
-inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 struct TimedLaunch {
   hipEvent_t start, stop;
@@ -56,6 +59,18 @@ struct nmf_ctx_s {
   std::vector<hipEvent_t> event_pool;
   double prof_ms[NMF_KERNEL_COUNT] = {};
   int64_t prof_count[NMF_KERNEL_COUNT] = {};
+  int batch_tiles[kBatchBuckets] = {};  // tiles per pass item of each batch bucket (set at creation)
+  int batch_grid[2][2] = {};            // persistent batched grid per (precision, mode), 0 = not yet known
+  // batched region of nmf_beta_step_batched (nmf_reserve_batched): header
+  // (flags, queue position, exits, counts) | tile table | done counters |
+  // descriptors | queue | planner scratch | problem workspaces
+  char* bmem = nullptr;
+  size_t bbytes = 0;
+  int b_max_problems = 0;
+  int64_t b_max_items = 0, b_work_bytes = 0;
+  size_t bo_tiles = 0, bo_done = 0, bo_desc = 0, bo_list = 0, bo_sbytes = 0, bo_sitems = 0, bo_soff = 0,
+         bo_sorder = 0, bo_work = 0;
+  bool b_captured = false;  // a batched call was captured: the region never moves again
 };
 
 struct nmf_batch_s {
@@ -72,37 +87,11 @@ struct nmf_batch_s {
 
 namespace {
 
-// Workspace header (zeroed at allocation): the sticky flags word at byte 0,
-// the fused kernel's grid-barrier words (arrivals, generation) at bytes 8, 12,
-// its eight phase stamps (uint64) at bytes 64..127, and the halt word of the
-// device-side outer loop at byte 128.
-constexpr size_t kHeaderBytes = 256;
 constexpr size_t kHaltOffset = 128;  // halt word of the device-side outer loop (nmf_beta_run)
 constexpr int kFusedMaxPerCU = 8;      // bound on co-resident fused workgroups per CU (workspace sizing)
 constexpr int kUpdateWBlocks = 4096;  // W-update workgroups at most (one unit of rows each, or more)
-constexpr int kColChunkRows = 512;  // rows of W_new per column-partial workgroup of the H pass
 
-struct Plan {
-  int KB, KP;
-  int row_blocks, n_groups, tiles_n;  // sweep_rows grid = row_blocks * n_groups
-  int col_blocks, f_groups, tiles_f;  // sweep_cols grid = col_blocks * f_groups
-  int uw_blocks, uh_blocks;
-  int col_parts, col_chunk;           // column partials of W_new formed in the H pass
-  int64_t ldt;                        // leading dimension of the transposed factor (K x F)
-  bool fused;                         // one cooperative launch (grid = fused_grid)
-  bool pq;                            // joint streaming path keeps P, Q between the passes
-  int fused_grid;
-  // byte offsets inside the workspace
-  size_t o_pobj, o_pnum, o_pden, o_prs, o_wn, o_c1, o_c2, o_c0, o_wt, o_pcol, o_pnumh, o_pdenh, o_colsum, o_pst,
-      o_qst, o_c1h, o_c2h, total;
-  int64_t ldc;                        // leading dimension of the chi(H) terms of joint sub-iterations
-};
 
-int kblocks_for(int64_t K) {
-  if (K <= 32) return 1;
-  if (K <= 64) return 2;
-  return 4;
-}
 
 // Number of groups the contracted dimension (`tiles` 32-wide tiles) is split
 // into, for `blocks` workgroups along the other dimension.  Minimizes a cost in
@@ -133,34 +122,7 @@ int choose_groups(const nmf_ctx_s* c, int64_t tiles, int64_t blocks, int64_t out
   return (int)cdiv(tiles, tpg);
 }
 
-// Region sizes (bytes) of the workspace; offsets are assigned in this order.
-struct Sizes {
-  size_t pobj, pnum, prs, fk, wt, pcol, pnumh, pq, kn;
-};
 
-Plan layout(const Sizes& z, Plan p) {
-  size_t o = kHeaderBytes;
-  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
-  p.o_pobj = take(z.pobj);
-  p.o_pnum = take(z.pnum);
-  p.o_pden = take(z.pnum);
-  p.o_prs = take(z.prs);
-  p.o_wn = take(z.fk);
-  p.o_c1 = take(z.fk);
-  p.o_c2 = take(z.fk);
-  p.o_c0 = take(z.fk);
-  p.o_wt = take(z.wt);
-  p.o_pcol = take(z.pcol);
-  p.o_pnumh = take(z.pnumh);
-  p.o_pdenh = take(z.pnumh);
-  p.o_colsum = take(sizeof(float) * 2 * 128);
-  p.o_pst = take(z.pq);
-  p.o_qst = take(z.pq);
-  p.o_c1h = take(z.kn);
-  p.o_c2h = take(z.kn);
-  p.total = o;
-  return p;
-}
 
 // Largest problem (F N entries) run as one fused launch: its P and Q tiles
 // (8 bytes per entry) stay well inside the 256 MB last-level cache.
@@ -171,10 +133,6 @@ constexpr int64_t kFusedMaxEntries = int64_t(1) << 24;
 constexpr int64_t kPQMaxEntries = int64_t(1) << 28;
 // Largest number of sub-iterations L accepted in one step.
 constexpr int kMaxInnerIters = 1000;
-// V (bytes) above which the W pass loads it with the nontemporal hint: a V this
-// large does not stay in the 256 MB last-level cache between passes anyway.
-constexpr int64_t kStreamVBytes = int64_t(128) << 20;
-inline int stream_v(int64_t F, int64_t N) { return F * N * (int64_t)sizeof(float) > kStreamVBytes; }
 
 int fused_capacity(nmf_ctx_s* c, int bc, int kb, bool joint, bool obj) {
   int& slot = c->fused_grid[kb - 1][bc][joint][obj];
@@ -182,30 +140,6 @@ int fused_capacity(nmf_ctx_s* c, int bc, int kb, bool joint, bool obj) {
   return slot - 1;
 }
 
-// `cols_occ`: workgroups per CU of the streaming column pass.  `fused_grid` > 0
-// plans the single-launch path with that many workgroups.
-// Column-partial split, transposed leading dimension and workspace offsets of
-// a plan whose splits are set.
-Plan finish_plan(Plan p, int64_t F, int64_t N, bool inner = false) {
-  {
-    const int64_t rows = (int64_t)p.tiles_f * kTile;
-    p.col_parts = (int)std::min<int64_t>(p.col_blocks, cdiv(rows, kColChunkRows));
-    p.col_chunk = (int)cdiv(rows, p.col_parts);
-  }
-  p.ldt = cdiv(F, 4) * 4;
-  Sizes z;
-  z.pobj = sizeof(double) * (size_t)std::max<int64_t>((int64_t)p.row_blocks * p.n_groups, p.fused_grid);
-  z.pnum = sizeof(float) * (size_t)p.n_groups * F * p.KP;
-  z.prs = sizeof(float) * (size_t)p.n_groups * p.KP;
-  z.fk = sizeof(float) * (size_t)F * p.KP;
-  z.wt = sizeof(float) * (size_t)p.KP * p.ldt;
-  z.pcol = sizeof(double) * (size_t)(p.fused ? p.uw_blocks : (int64_t)p.f_groups * p.col_parts) * 2 * p.KP;
-  z.pnumh = sizeof(float) * (size_t)p.f_groups * N * p.KP;
-  z.pq = (p.fused || p.pq) ? sizeof(float) * (size_t)cdiv(F, kTile) * cdiv(N, kTile) * kTile * kTile : 0;
-  p.ldc = cdiv(N, 4) * 4;
-  z.kn = inner ? sizeof(float) * (size_t)p.KP * p.ldc : 0;
-  return layout(z, p);
-}
 
 Plan make_plan(const nmf_ctx_s* c, int64_t F, int64_t N, int64_t K, int cols_occ = 2, int fused_grid = 0,
                bool pq = false, bool inner = false) {
@@ -227,27 +161,6 @@ Plan make_plan(const nmf_ctx_s* c, int64_t F, int64_t N, int64_t K, int cols_occ
   return finish_plan(p, F, N, inner);
 }
 
-// Splits of a problem inside a batch: every row (column) group covers about
-// `tiles` column (row) tiles; one W-update unit of rows and one H-update unit
-// of columns per work item.
-Plan make_batch_plan(int64_t F, int64_t N, int64_t K, int tiles, bool pq) {
-  Plan p{};
-  p.pq = pq;
-  p.KB = kblocks_for(K);
-  p.KP = 32 * p.KB;
-  const int64_t tn = cdiv(N, kTile), tf = cdiv(F, kTile);
-  p.row_blocks = (int)cdiv(F, kBlockRows);
-  p.n_groups = (int)cdiv(tn, tiles);
-  p.tiles_n = (int)cdiv(tn, p.n_groups);
-  p.n_groups = (int)cdiv(tn, p.tiles_n);
-  p.col_blocks = (int)cdiv(N, kBlockRows);
-  p.f_groups = (int)cdiv(tf, tiles);
-  p.tiles_f = (int)cdiv(tf, p.f_groups);
-  p.f_groups = (int)cdiv(tf, p.tiles_f);
-  p.uw_blocks = (int)cdiv(F, update_w_unit_rows(p.KB));
-  p.uh_blocks = (int)cdiv(N, kBlock / p.KP);
-  return finish_plan(p, F, N);
-}
 
 // Workspace size covering every call with F <= maxF, N <= maxN, K <= maxK under
 // the current launch settings.  choose_groups keeps blocks * groups <= 4 * slots
@@ -392,73 +305,6 @@ hipError_t timed(nmf_ctx_s* c, int kernel, hipStream_t s, Fn&& launch) {
   return e;
 }
 
-// Kernel arguments of one outer iteration of a problem whose workspace regions
-// (offsets of `p`) start at `ws`.
-struct StepArgs {
-  SweepRowsArgs ra;
-  UpdateWArgs ua;
-  SweepColsArgs ca;
-  UpdateHArgs ha;
-  int sw_grid, sh_grid;
-};
-
-StepArgs make_step_args(const Plan& p, char* ws, unsigned* flags, int64_t F, int64_t N, int64_t K, const float* V,
-                        int64_t ldv, float* W, int64_t ldw, float* H, int64_t ldh, double beta, bool joint, int prec,
-                        const nmf_step_opts& o, double* d_objective) {
-  const int bc = beta_class(beta);
-  const bool beta_one = (bc == BC_B1);
-  float* Wn = (float*)(ws + p.o_wn);
-  float* C1 = (float*)(ws + p.o_c1);
-  float* C2 = (float*)(ws + p.o_c2);
-  StepArgs sa{};
-  SweepRowsArgs& ra = sa.ra;
-  ra.V = V; ra.ldv = ldv; ra.W = W; ra.ldw = ldw; ra.H = H; ra.ldh = ldh;
-  ra.F = (int)F; ra.N = (int)N; ra.K = (int)K;
-  ra.bm2 = (float)(beta - 2.0); ra.kappa = o.kappa; ra.beta = beta;
-  ra.n_groups = p.n_groups; ra.tiles_per_group = p.tiles_n;
-  ra.pnum = (float*)(ws + p.o_pnum); ra.pden = (float*)(ws + p.o_pden); ra.prs = (float*)(ws + p.o_prs);
-  ra.pobj = (double*)(ws + p.o_pobj);
-  ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
-  ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
-  ra.vstream = stream_v(F, N);
-  ra.flags = flags;
-  sa.sw_grid = p.row_blocks * p.n_groups;
-
-  UpdateWArgs& ua = sa.ua;
-  ua.W = W; ua.ldw = ldw; ua.pnum = ra.pnum; ua.pden = ra.pden; ua.prs = ra.prs;
-  ua.F = (int)F; ua.K = (int)K; ua.n_groups = p.n_groups;
-  const double gamma = o.exponent == NMF_EXPONENT_ONE ? 1.0 : gamma_of(beta);
-  ua.beta = beta; ua.gamma = gamma; ua.joint = joint; ua.beta_one = beta_one;
-  ua.Wn = Wn; ua.C1 = C1; ua.C2 = C2; ua.pcol = (double*)(ws + p.o_pcol);
-  ua.WT = (float*)(ws + p.o_wt); ua.ldt = p.ldt;
-  ua.C0 = (prec != NMF_FP32 && joint && !p.pq) ? (float*)(ws + p.o_c0) : nullptr;
-  ua.flags = flags;
-
-  SweepColsArgs& ca = sa.ca;
-  ca.V = V; ca.ldv = ldv;
-  ca.WT = ua.WT; ca.ldwt = p.ldt;
-  ca.C0 = ua.C0;
-  ca.flags = flags;
-  if (joint) { ca.C1 = C1; ca.C2 = C2; }
-  else { ca.C1 = Wn; ca.C2 = Wn; }
-  ca.H = H; ca.ldh = ldh;
-  ca.F = (int)F; ca.N = (int)N; ca.K = (int)K;
-  ca.bm2 = (float)(beta - 2.0); ca.kappa = o.kappa;
-  ca.f_groups = p.f_groups; ca.tiles_per_group = p.tiles_f;
-  ca.pnum = (float*)(ws + p.o_pnumh); ca.pden = (float*)(ws + p.o_pdenh);
-  sa.sh_grid = p.col_blocks * p.f_groups;
-
-  UpdateHArgs& ha = sa.ha;
-  ha.H = H; ha.ldh = ldh; ha.pnum = ca.pnum; ha.pden = ca.pden;
-  ha.F = (int)F; ha.N = (int)N; ha.K = (int)K; ha.f_groups = p.f_groups;
-  ha.gamma = gamma; ha.beta_one = beta_one; ha.normalize = o.normalize;
-  ha.pcol = ua.pcol; ha.pcol_blocks = p.fused ? p.uw_blocks : p.f_groups * p.col_parts;
-  if (!p.fused) { ca.Wn = Wn; ca.pcol = ua.pcol; ca.col_parts = p.col_parts; ca.col_chunk = p.col_chunk; }
-  ha.pobj = ra.pobj; ha.nobj = sa.sw_grid; ha.d_obj = d_objective;
-  ha.Wn = Wn; ha.W = W; ha.ldw = ldw; ha.flags = flags;
-  ha.beta = beta;
-  return sa;
-}
 
 // Byte ranges [lo, hi) of caller memory written (W, H) or read (V) by a batch.
 struct Span {
@@ -487,12 +333,6 @@ nmf_status check_batch_alias(const nmf_problem* pr, int count) {
 }
 
 constexpr int kBatchTilesDefault = 128;  // measured best on the 512-problem workload (16..128)
-constexpr int kBatchUpdateRows = 32;   // rows of W per W-update work item
-constexpr int kBatchUpdateCols = 64;   // columns of H per H-update work item
-// the batched W update uses one thread slice per row: kBlock / KP rows per unit
-inline int batch_unit_rows(int KB) { return kBlock / (32 * KB); }
-inline int batch_w_units(int KB) { return std::max(1, kBatchUpdateRows / batch_unit_rows(KB)); }
-inline int batch_h_units(int KB) { return std::max(1, kBatchUpdateCols / (kBlock / (32 * KB))); }
 constexpr unsigned kBatchSpinLimit = 1u << 22;
 
 // Alternating MU with L > 1 sub-iterations (Algorithm 1, any product type): L W
@@ -850,11 +690,12 @@ const char* nmf_status_string(nmf_status s) {
     case NMF_ERR_SHAPE: return "NMF_ERR_SHAPE: bad size or leading dimension";
     case NMF_ERR_BETA: return "NMF_ERR_BETA: beta or kappa not finite (or kappa < 0)";
     case NMF_ERR_ALIAS: return "NMF_ERR_ALIAS: matrices overlap";
-    case NMF_ERR_WORKSPACE: return "NMF_ERR_WORKSPACE: workspace too small during or after stream capture";
+    case NMF_ERR_WORKSPACE: return "NMF_ERR_WORKSPACE: workspace (or batched region) too small, missing, or fixed by a capture";
     case NMF_ERR_HIP: return "NMF_ERR_HIP: HIP runtime error";
     case NMF_ERR_UNSUPPORTED: return "NMF_ERR_UNSUPPORTED: unsupported size or option";
     case NMF_ERR_ARG: return "NMF_ERR_ARG: invalid argument";
     case NMF_ERR_NO_DEVICE: return "NMF_ERR_NO_DEVICE: no usable GPU";
+    case NMF_ERR_IO: return "NMF_ERR_IO: the tuning cache file could not be written";
   }
   return "unknown nmf_status";
 }
@@ -868,6 +709,7 @@ nmf_status nmf_create(nmf_ctx_t* out, int device) {
   nmf_ctx_s* c = new (std::nothrow) nmf_ctx_s();
   if (!c) return NMF_ERR_HIP;
   c->device = device;
+  for (int b = 0; b < kBatchBuckets; ++b) c->batch_tiles[b] = kBatchTilesDefault;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->num_cus = prop.multiProcessorCount;
@@ -893,6 +735,7 @@ nmf_status nmf_destroy(nmf_ctx_t c) {
     for (auto& t : v) { (void)hipEventDestroy(t.start); (void)hipEventDestroy(t.stop); }
   for (auto e : c->event_pool) (void)hipEventDestroy(e);
   if (c->ws) (void)hipFree(c->ws);
+  if (c->bmem) (void)hipFree(c->bmem);
   delete c;
   return NMF_OK;
 }
@@ -1158,14 +1001,22 @@ nmf_status nmf_beta_validate(nmf_ctx_t c, void* stream, int64_t F, int64_t N, in
 nmf_status nmf_get_flags(nmf_ctx_t c, void* stream, uint32_t* flags, int32_t clear) {
   if (!c || !flags) return NMF_ERR_NULL;
   *flags = 0;
-  if (!c->ws) return NMF_OK;
+  if (!c->ws && !c->bmem) return NMF_OK;
   if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
   hipStream_t s = (hipStream_t)stream;
-  if (hipMemcpyAsync(flags, c->ws, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess) return NMF_ERR_HIP;
+  // the step workspace's word and the batched region's word
+  char* words[2] = {c->ws, c->bmem};
+  uint32_t got[2] = {0, 0};
+  for (int k = 0; k < 2; ++k)
+    if (words[k] && hipMemcpyAsync(&got[k], words[k], sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+      return NMF_ERR_HIP;
   if (hipStreamSynchronize(s) != hipSuccess) return NMF_ERR_HIP;
+  *flags = got[0] | got[1];
   if (clear) {
     const uint32_t z = 0;
-    if (hipMemcpyAsync(c->ws, &z, sizeof(uint32_t), hipMemcpyHostToDevice, s) != hipSuccess) return NMF_ERR_HIP;
+    for (int k = 0; k < 2; ++k)
+      if (words[k] && hipMemcpyAsync(words[k], &z, sizeof(uint32_t), hipMemcpyHostToDevice, s) != hipSuccess)
+        return NMF_ERR_HIP;
     if (hipStreamSynchronize(s) != hipSuccess) return NMF_ERR_HIP;
   }
   return NMF_OK;
@@ -1225,34 +1076,45 @@ nmf_status nmf_set_launch(nmf_ctx_t c, int32_t target_blocks, int32_t min_tiles)
   return NMF_OK;
 }
 
-nmf_status nmf_batch_create(nmf_ctx_t c, const nmf_problem* pr, int32_t count, int32_t mode,
-                            const nmf_step_opts* opts, const nmf_batch_config* cfg, nmf_batch_t* out) {
-  if (!out) return NMF_ERR_NULL;
-  *out = nullptr;
-  if (!c || !pr) return NMF_ERR_NULL;
-  if (count < 1) return NMF_ERR_ARG;
-  if (mode != NMF_ALTERNATING && mode != NMF_JOINT) return NMF_ERR_ARG;
+}  // extern "C"
+
+namespace {
+
+// Validated options of a batch (precision FP32 or BF16, one sub-iteration, no
+// Gram form); NMF_OK or the status to return.
+nmf_status batch_opts(const nmf_step_opts* opts, nmf_step_opts* o) {
   nmf_status st = check_opts(opts);
   if (st != NMF_OK) return st;
-  nmf_step_opts o;
-  nmf_default_opts(&o);
-  if (opts) o = *opts;
-  if (o.precision != NMF_FP32 && o.precision != NMF_BF16) return NMF_ERR_UNSUPPORTED;
-  if (o.inner_iters != 1) return NMF_ERR_UNSUPPORTED;
-  const int tiles = cfg && cfg->tiles_per_item > 0 ? cfg->tiles_per_item : kBatchTilesDefault;
-  if (cfg && cfg->workers < 0) return NMF_ERR_ARG;
+  nmf_default_opts(o);
+  if (opts) *o = *opts;
+  if (o->precision != NMF_FP32 && o->precision != NMF_BF16) return NMF_ERR_UNSUPPORTED;
+  if (o->inner_iters != 1 || o->gram) return NMF_ERR_UNSUPPORTED;
+  return NMF_OK;
+}
+
+int batch_grid(nmf_ctx_s* c, int prec, bool joint) {
+  int& g = c->batch_grid[prec == NMF_BF16][joint];
+  if (g <= 0) g = batched_max_blocks(prec, joint, c->num_cus);
+  return g;
+}
+
+// nmf_batch_create with an explicit tile count per bucket.
+nmf_status batch_create(nmf_ctx_s* c, const nmf_problem* pr, int count, int mode, const nmf_step_opts& o,
+                        const int* tiles, int workers, int lag, nmf_batch_t* out) {
+  *out = nullptr;
   for (int i = 0; i < count; ++i) {
     const nmf_problem& q = pr[i];
-    st = nmf_check_step_args(q.F, q.N, q.K, q.V, q.ldv, q.W, q.ldw, q.H, q.ldh, q.beta, mode, &o);
+    nmf_status st = nmf_check_step_args(q.F, q.N, q.K, q.V, q.ldv, q.W, q.ldw, q.H, q.ldh, q.beta, mode, &o);
     if (st != NMF_OK) return st;
     if (q.K > 64) return NMF_ERR_UNSUPPORTED;
   }
-  if ((st = check_batch_alias(pr, count)) != NMF_OK) return st;
+  nmf_status st = check_batch_alias(pr, count);
+  if (st != NMF_OK) return st;
   if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
   const bool joint = mode == NMF_JOINT;
-  const int max_grid = batched_max_blocks(o.precision, joint, c->num_cus);
+  const int max_grid = batch_grid(c, o.precision, joint);
   if (max_grid <= 0) return NMF_ERR_HIP;
-  const int grid = cfg && cfg->workers > 0 ? std::min(cfg->workers, max_grid) : max_grid;
+  const int grid = workers > 0 ? std::min(workers, max_grid) : max_grid;
 
   // plans and memory layout
   std::vector<Plan> plans(count);
@@ -1264,10 +1126,9 @@ nmf_status nmf_batch_create(nmf_ctx_t c, const nmf_problem* pr, int32_t count, i
   off = align_up(off + sizeof(BatchProblem) * (size_t)count);
   int64_t total = 0;
   for (int i = 0; i < count; ++i) {
-    plans[i] = make_batch_plan(pr[i].F, pr[i].N, pr[i].K, tiles, joint);
-    const Plan& p = plans[i];
-    total += (int64_t)p.row_blocks * p.n_groups + cdiv(cdiv(pr[i].F, batch_unit_rows(p.KB)), batch_w_units(p.KB)) +
-             (int64_t)p.col_blocks * p.f_groups + cdiv(p.uh_blocks, batch_h_units(p.KB));
+    const nmf_problem& q = pr[i];
+    plans[i] = make_batch_plan(q.F, q.N, q.K, tiles[bucket_of(q.F, q.N, q.K)], joint);
+    total += batch_items(plans[i], q.F);
   }
   if (total >= (int64_t)1 << 31) return NMF_ERR_UNSUPPORTED;
   const size_t o_list = off;
@@ -1295,33 +1156,7 @@ nmf_status nmf_batch_create(nmf_ctx_t c, const nmf_problem* pr, int32_t count, i
   // descriptors (V is loaded with the nontemporal hint by the size rule of each
   // problem: the hint measured no gain on a batch of cache-sized problems)
   std::vector<BatchProblem> desc(count);
-  for (int i = 0; i < count; ++i) {
-    const nmf_problem& q = pr[i];
-    const Plan& p = plans[i];
-    StepArgs sa = make_step_args(p, mem + base[i], flags, q.F, q.N, q.K, q.V, q.ldv, q.W, q.ldw, q.H, q.ldh,
-                                 q.beta, joint, o.precision, o, nullptr);
-    if (p.pq) {  // joint: the H pass contracts the kept P, Q tiles
-      sa.ra.NT = (int)cdiv(q.N, kTile);
-      sa.ra.Pst = (float*)(mem + base[i] + p.o_pst);
-      sa.ra.Qst = (float*)(mem + base[i] + p.o_qst);
-      sa.ca.NT = sa.ra.NT; sa.ca.Pst = sa.ra.Pst; sa.ca.Qst = sa.ra.Qst;
-    }
-    BatchProblem& d = desc[i];
-    d.ra = sa.ra;
-    d.ua = sa.ua;
-    d.ca = sa.ca;
-    d.ha = sa.ha;
-    d.bc = beta_class(q.beta);
-    d.kb = p.KB;
-    for (int ph = 0; ph < 4; ++ph) d.per_item[ph] = 1;
-    d.units[PH_WPASS] = p.row_blocks * p.n_groups;
-    d.units[PH_WUPDATE] = (int)cdiv(q.F, batch_unit_rows(p.KB));
-    d.units[PH_HPASS] = p.col_blocks * p.f_groups;
-    d.units[PH_HUPDATE] = p.uh_blocks;
-    d.per_item[PH_WUPDATE] = batch_w_units(p.KB);
-    d.per_item[PH_HUPDATE] = batch_h_units(p.KB);
-    for (int ph = 0; ph < 4; ++ph) d.items[ph] = (int)cdiv(d.units[ph], d.per_item[ph]);
-  }
+  for (int i = 0; i < count; ++i) desc[i] = make_batch_problem(plans[i], mem + base[i], flags, pr[i], joint, o);
   // queue, larger problems first: phase-major (lag 0), or pipelined with phase q
   // of the problem at position j listed at step j + q lag.  Either way every
   // item is listed after all the items it waits for.
@@ -1335,7 +1170,6 @@ nmf_status nmf_batch_create(nmf_ctx_t c, const nmf_problem* pr, int32_t count, i
   auto emit = [&](int i, int ph) {
     for (int it = 0; it < desc[i].items[ph]; ++it) list.push_back(make_int2(i, (ph << 24) | it));
   };
-  const int lag = cfg ? std::max(0, cfg->lag) : 0;
   if (lag == 0) {
     for (int ph = 0; ph < 4; ++ph)
       for (int i : order) emit(i, ph);
@@ -1359,6 +1193,7 @@ nmf_status nmf_batch_create(nmf_ctx_t c, const nmf_problem* pr, int32_t count, i
   a.probs = (const BatchProblem*)(mem + o_desc);
   a.list = (const int2*)(mem + o_list);
   a.total = (int)total;
+  a.counts = nullptr;
   a.next = (unsigned*)(mem + 8);
   a.exited = (unsigned*)(mem + 12);
   a.done = (unsigned*)(mem + o_done);
@@ -1368,6 +1203,125 @@ nmf_status nmf_batch_create(nmf_ctx_t c, const nmf_problem* pr, int32_t count, i
   a.spin_limit = kBatchSpinLimit;
   *out = b;
   return NMF_OK;
+}
+
+// ---- tuning cache: one text line per key ----
+//   nmf_tune 1 <arch> <compute units> <mode> <precision> <bucket mask> <tiles x 8> <ms>
+struct TuneKey {
+  char arch[64];
+  int cus, mode, prec;
+};
+
+struct TuneEntry {
+  unsigned mask = 0;
+  int tiles[kBatchBuckets] = {};
+  double ms = 0.0;
+};
+
+bool parse_tune_line(const char* line, TuneKey* k, TuneEntry* e) {
+  int ver = 0;
+  int t[kBatchBuckets];
+  unsigned mask = 0;
+  double ms = 0.0;
+  const int n = sscanf(line, "nmf_tune %d %63s %d %d %d %x %d %d %d %d %d %d %d %d %lf", &ver, k->arch, &k->cus,
+                       &k->mode, &k->prec, &mask, &t[0], &t[1], &t[2], &t[3], &t[4], &t[5], &t[6], &t[7], &ms);
+  if (n != 7 + kBatchBuckets || ver != 1) return false;
+  for (int b = 0; b < kBatchBuckets; ++b)
+    if (t[b] < 1 || t[b] > 4096) return false;
+  e->mask = mask & ((1u << kBatchBuckets) - 1);
+  std::memcpy(e->tiles, t, sizeof(t));
+  e->ms = ms;
+  return true;
+}
+
+bool same_key(const TuneKey& a, const TuneKey& b) {
+  return std::strcmp(a.arch, b.arch) == 0 && a.cus == b.cus && a.mode == b.mode && a.prec == b.prec;
+}
+
+// Lines of the cache file (none if it does not exist or cannot be read).
+std::vector<std::string> read_lines(const char* path) {
+  std::vector<std::string> lines;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return lines;
+  char buf[512];
+  std::string cur;
+  while (std::fgets(buf, sizeof(buf), f)) {
+    cur += buf;
+    if (!cur.empty() && cur.back() == '\n') {
+      cur.pop_back();
+      lines.push_back(cur);
+      cur.clear();
+    }
+  }
+  if (!cur.empty()) lines.push_back(cur);
+  std::fclose(f);
+  return lines;
+}
+
+bool cache_lookup(const char* path, const TuneKey& key, TuneEntry* out) {
+  bool found = false;
+  for (const std::string& l : read_lines(path)) {
+    TuneKey k;
+    TuneEntry e;
+    if (parse_tune_line(l.c_str(), &k, &e) && same_key(k, key)) {
+      *out = e;  // the last entry of a key wins
+      found = true;
+    }
+  }
+  return found;
+}
+
+nmf_status cache_store(const char* path, const TuneKey& key, const TuneEntry& e) {
+  std::vector<std::string> keep;
+  for (const std::string& l : read_lines(path)) {
+    TuneKey k;
+    TuneEntry old;
+    if (!(parse_tune_line(l.c_str(), &k, &old) && same_key(k, key))) keep.push_back(l);
+  }
+  char line[512];
+  std::snprintf(line, sizeof(line), "nmf_tune 1 %s %d %d %d 0x%02x %d %d %d %d %d %d %d %d %.6f", key.arch, key.cus,
+                key.mode, key.prec, e.mask, e.tiles[0], e.tiles[1], e.tiles[2], e.tiles[3], e.tiles[4], e.tiles[5],
+                e.tiles[6], e.tiles[7], e.ms);
+  keep.push_back(line);
+  const std::string tmp = std::string(path) + ".tmp." + std::to_string((long)getpid());
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return NMF_ERR_IO;
+  bool ok = true;
+  for (const std::string& l : keep) ok = ok && std::fprintf(f, "%s\n", l.c_str()) > 0;
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok || std::rename(tmp.c_str(), path) != 0) {
+    (void)std::remove(tmp.c_str());
+    return NMF_ERR_IO;
+  }
+  return NMF_OK;
+}
+
+nmf_status upload_tiles(nmf_ctx_s* c) {
+  if (!c->bmem) return NMF_OK;
+  if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
+  return hip_status(hipMemcpy(c->bmem + c->bo_tiles, c->batch_tiles, sizeof(int) * kBatchBuckets,
+                              hipMemcpyHostToDevice));
+}
+
+}  // namespace
+
+extern "C" {
+
+nmf_status nmf_batch_create(nmf_ctx_t c, const nmf_problem* pr, int32_t count, int32_t mode,
+                            const nmf_step_opts* opts, const nmf_batch_config* cfg, nmf_batch_t* out) {
+  if (!out) return NMF_ERR_NULL;
+  *out = nullptr;
+  if (!c || !pr) return NMF_ERR_NULL;
+  if (count < 1) return NMF_ERR_ARG;
+  if (mode != NMF_ALTERNATING && mode != NMF_JOINT) return NMF_ERR_ARG;
+  nmf_step_opts o;
+  nmf_status st = batch_opts(opts, &o);
+  if (st != NMF_OK) return st;
+  if (cfg && (cfg->workers < 0 || cfg->tiles_per_item < 0 || cfg->lag < 0)) return NMF_ERR_ARG;
+  int tiles[kBatchBuckets];
+  for (int b = 0; b < kBatchBuckets; ++b)
+    tiles[b] = cfg && cfg->tiles_per_item > 0 ? cfg->tiles_per_item : c->batch_tiles[b];
+  return batch_create(c, pr, count, mode, o, tiles, cfg ? cfg->workers : 0, cfg ? cfg->lag : 0, out);
 }
 
 nmf_status nmf_batch_step(nmf_batch_t b, void* stream, double* d_objectives) {
@@ -1410,14 +1364,216 @@ nmf_status nmf_batch_destroy(nmf_batch_t b) {
   return NMF_OK;
 }
 
-nmf_status nmf_batch_tune(nmf_ctx_t c, const nmf_problem* pr, int32_t count, int32_t mode,
-                          const nmf_step_opts* opts, void* stream, int32_t iters, nmf_batch_config* best,
-                          double* best_ms) {
-  if (!c || !pr || !best) return NMF_ERR_NULL;
-  if (iters < 1) return NMF_ERR_ARG;
+int32_t nmf_batch_bucket(int64_t F, int64_t N, int64_t K) {
+  if (F < 1 || N < 1 || K < 1 || K > 64) return -1;
+  return bucket_of(F, N, K);
+}
+
+nmf_status nmf_set_batch_tiles(nmf_ctx_t c, const int32_t* tiles) {
+  if (!c || !tiles) return NMF_ERR_NULL;
+  for (int b = 0; b < kBatchBuckets; ++b)
+    if (tiles[b] < 1 || tiles[b] > 4096) return NMF_ERR_ARG;
+  for (int b = 0; b < kBatchBuckets; ++b) c->batch_tiles[b] = tiles[b];
+  return upload_tiles(c);
+}
+
+nmf_status nmf_get_batch_tiles(nmf_ctx_t c, int32_t* tiles) {
+  if (!c || !tiles) return NMF_ERR_NULL;
+  for (int b = 0; b < kBatchBuckets; ++b) tiles[b] = c->batch_tiles[b];
+  return NMF_OK;
+}
+
+nmf_status nmf_batch_requirements(const nmf_problem* pr, int32_t count, int32_t mode, const int32_t* tiles,
+                                  int64_t* items, int64_t* workspace_bytes) {
+  if (!pr || !items || !workspace_bytes) return NMF_ERR_NULL;
+  *items = 0;
+  *workspace_bytes = 0;
+  if (count < 1) return NMF_ERR_ARG;
+  if (mode != NMF_ALTERNATING && mode != NMF_JOINT) return NMF_ERR_ARG;
+  if (tiles)
+    for (int b = 0; b < kBatchBuckets; ++b)
+      if (tiles[b] < 1 || tiles[b] > 4096) return NMF_ERR_ARG;
+  int64_t n = 0, bytes = 0;
+  for (int i = 0; i < count; ++i) {
+    const nmf_problem& q = pr[i];
+    if (q.F < 1 || q.N < 1 || q.K < 1 || q.F > INT32_MAX || q.N > INT32_MAX) return NMF_ERR_SHAPE;
+    if (q.K > 64) return NMF_ERR_UNSUPPORTED;
+    const int b = bucket_of(q.F, q.N, q.K);
+    const Plan p = make_batch_plan(q.F, q.N, q.K, tiles ? tiles[b] : kBatchTilesDefault, mode == NMF_JOINT);
+    n += batch_items(p, q.F);
+    bytes += (int64_t)align_up(p.total);
+  }
+  *items = n;
+  *workspace_bytes = bytes;
+  return NMF_OK;
+}
+
+nmf_status nmf_reserve_batched(nmf_ctx_t c, int32_t max_problems, int64_t max_items, int64_t workspace_bytes) {
+  if (!c) return NMF_ERR_NULL;
+  if (max_problems < 1 || max_items < 1 || max_items > INT32_MAX || workspace_bytes < 0) return NMF_ERR_ARG;
+  if (c->b_captured) return NMF_ERR_WORKSPACE;
+  if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
+  // the persistent grids, so that a captured step makes no occupancy query
+  for (int prec : {NMF_FP32, NMF_BF16})
+    for (bool joint : {false, true})
+      if (batch_grid(c, prec, joint) <= 0) return NMF_ERR_HIP;
+  const size_t P = (size_t)max_problems;
+  size_t off = kHeaderBytes;  // flags @0, queue position @8, exits @12, counts @16
+  auto take = [&](size_t bytes) { size_t r = off; off = align_up(off + bytes); return r; };
+  const size_t o_tiles = take(sizeof(int) * kBatchBuckets);
+  const size_t o_done = take(sizeof(unsigned) * 4 * P);
+  const size_t o_desc = take(sizeof(BatchProblem) * P);
+  const size_t o_list = take(sizeof(int2) * (size_t)max_items);
+  const size_t o_sbytes = take(sizeof(int64_t) * P);
+  const size_t o_sitems = take(sizeof(int64_t) * 4 * P);
+  const size_t o_soff = take(sizeof(int64_t) * 4 * P);
+  const size_t o_sorder = take(sizeof(int) * P);
+  const size_t o_work = take((size_t)workspace_bytes);
+  uint32_t flags_keep = 0;
+  if (c->bmem) {
+    if (hipDeviceSynchronize() != hipSuccess) return NMF_ERR_HIP;
+    (void)hipMemcpy(&flags_keep, c->bmem, sizeof(uint32_t), hipMemcpyDeviceToHost);
+    (void)hipFree(c->bmem);
+    c->bmem = nullptr;
+    c->bbytes = 0;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, off) != hipSuccess) return NMF_ERR_HIP;
+  char* m = (char*)p;
+  hipError_t e = hipMemset(m, 0, o_desc);  // header, tile table, done counters
+  if (e == hipSuccess) e = hipMemcpy(m, &flags_keep, sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m + o_tiles, c->batch_tiles, sizeof(int) * kBatchBuckets, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(p);
+    return NMF_ERR_HIP;
+  }
+  c->bmem = m;
+  c->bbytes = off;
+  c->b_max_problems = max_problems;
+  c->b_max_items = max_items;
+  c->b_work_bytes = workspace_bytes;
+  c->bo_tiles = o_tiles;
+  c->bo_done = o_done;
+  c->bo_desc = o_desc;
+  c->bo_list = o_list;
+  c->bo_sbytes = o_sbytes;
+  c->bo_sitems = o_sitems;
+  c->bo_soff = o_soff;
+  c->bo_sorder = o_sorder;
+  c->bo_work = o_work;
+  return NMF_OK;
+}
+
+nmf_status nmf_beta_step_batched(nmf_ctx_t c, void* stream, int32_t count, const nmf_problem* d_problems,
+                                 int32_t mode, const nmf_step_opts* opts, double* d_objectives,
+                                 const int32_t* d_count) {
+  if (!c || !d_problems) return NMF_ERR_NULL;
+  if (count < 1) return NMF_ERR_ARG;
+  if (mode != NMF_ALTERNATING && mode != NMF_JOINT) return NMF_ERR_ARG;
+  nmf_step_opts o;
+  nmf_status st = batch_opts(opts, &o);
+  if (st != NMF_OK) return st;
+  if (!c->bmem || count > c->b_max_problems) return NMF_ERR_WORKSPACE;
   if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
   hipStream_t s = (hipStream_t)stream;
-  // save W and H of every problem (packed) to restore them after each candidate
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return NMF_ERR_HIP;
+  if (cs != hipStreamCaptureStatusNone) c->b_captured = true;
+  const bool joint = mode == NMF_JOINT;
+  const int grid = batch_grid(c, o.precision, joint);
+  if (grid <= 0) return NMF_ERR_HIP;
+  char* m = c->bmem;
+  BatchPlanArgs pa{};
+  pa.problems = d_problems;
+  pa.count = count;
+  pa.d_count = d_count;
+  pa.tiles = (const int*)(m + c->bo_tiles);
+  pa.joint = joint;
+  pa.opts = o;
+  pa.work = m + c->bo_work;
+  pa.work_bytes = c->b_work_bytes;
+  pa.max_items = c->b_max_items;
+  pa.s_bytes = (int64_t*)(m + c->bo_sbytes);
+  pa.s_items = (int64_t*)(m + c->bo_sitems);
+  pa.s_off = (int64_t*)(m + c->bo_soff);
+  pa.s_order = (int*)(m + c->bo_sorder);
+  pa.desc = (BatchProblem*)(m + c->bo_desc);
+  pa.list = (int2*)(m + c->bo_list);
+  pa.done = (unsigned*)(m + c->bo_done);
+  pa.next = (unsigned*)(m + 8);
+  pa.exited = (unsigned*)(m + 12);
+  pa.counts = (int*)(m + 16);
+  pa.flags = (unsigned*)m;
+  hipError_t e = launch_batch_plan(s, pa);
+  if (e != hipSuccess) return NMF_ERR_HIP;
+  BatchArgs a{};
+  a.probs = pa.desc;
+  a.list = pa.list;
+  a.total = 0;
+  a.counts = pa.counts;
+  a.next = pa.next;
+  a.exited = pa.exited;
+  a.done = pa.done;
+  a.nprob = 0;
+  a.d_obj = d_objectives;
+  a.flags = pa.flags;
+  a.spin_limit = kBatchSpinLimit;
+  return hip_status(launch_batched(o.precision, joint, grid, s, a));
+}
+
+nmf_status nmf_tune(nmf_ctx_t c, void* stream, const nmf_problem* pr, int32_t count, int32_t mode,
+                    const nmf_step_opts* opts, int32_t iters, const char* cache_path, int32_t* tiles_out,
+                    double* ms_out, int32_t* from_cache) {
+  if (!c || !pr || !tiles_out) return NMF_ERR_NULL;
+  if (count < 1 || iters < 1) return NMF_ERR_ARG;
+  if (mode != NMF_ALTERNATING && mode != NMF_JOINT) return NMF_ERR_ARG;
+  nmf_step_opts o;
+  nmf_status st = batch_opts(opts, &o);
+  if (st != NMF_OK) return st;
+  for (int i = 0; i < count; ++i) {
+    const nmf_problem& q = pr[i];
+    if ((st = nmf_check_step_args(q.F, q.N, q.K, q.V, q.ldv, q.W, q.ldw, q.H, q.ldh, q.beta, mode, &o)) != NMF_OK)
+      return st;
+    if (q.K > 64) return NMF_ERR_UNSUPPORTED;
+  }
+  if ((st = check_batch_alias(pr, count)) != NMF_OK) return st;
+  if (from_cache) *from_cache = 0;
+  if (hipSetDevice(c->device) != hipSuccess) return NMF_ERR_HIP;
+  const bool joint = mode == NMF_JOINT;
+
+  TuneKey key{};
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return NMF_ERR_HIP;
+    size_t n = 0;
+    while (n + 1 < sizeof(key.arch) && prop.gcnArchName[n] && prop.gcnArchName[n] != ':' &&
+           prop.gcnArchName[n] != ' ')
+      ++n;
+    std::memcpy(key.arch, prop.gcnArchName, n);
+    key.arch[n] = 0;
+    if (n == 0) std::strcpy(key.arch, "gpu");
+    key.cus = c->num_cus;
+    key.mode = mode;
+    key.prec = o.precision;
+  }
+  unsigned needed = 0;
+  for (int i = 0; i < count; ++i) needed |= 1u << bucket_of(pr[i].F, pr[i].N, pr[i].K);
+  TuneEntry cached;
+  const bool have = cache_path && cache_lookup(cache_path, key, &cached);
+  int table[kBatchBuckets];
+  for (int b = 0; b < kBatchBuckets; ++b)
+    table[b] = have && (cached.mask >> b & 1u) ? cached.tiles[b] : c->batch_tiles[b];
+  if (have && (needed & ~cached.mask) == 0) {
+    for (int b = 0; b < kBatchBuckets; ++b) c->batch_tiles[b] = table[b];
+    if ((st = upload_tiles(c)) != NMF_OK) return st;
+    for (int b = 0; b < kBatchBuckets; ++b) tiles_out[b] = table[b];
+    if (ms_out) *ms_out = cached.ms;
+    if (from_cache) *from_cache = 1;
+    return NMF_OK;
+  }
+
+  // save W and H of every problem (packed) to restore them after each timing
+  hipStream_t s = (hipStream_t)stream;
   size_t words = 0;
   for (int i = 0; i < count; ++i) words += (size_t)(pr[i].F * pr[i].K + pr[i].K * pr[i].N);
   float* save = nullptr;
@@ -1441,45 +1597,79 @@ nmf_status nmf_batch_tune(nmf_ctx_t c, const nmf_problem* pr, int32_t count, int
     }
     return hipStreamSynchronize(s);
   };
-  nmf_status result = NMF_OK;
-  double best_t = 1e300;
-  nmf_batch_config best_cfg{kBatchTilesDefault, 0, 0};
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess || copy_all(true) != hipSuccess) {
-    result = NMF_ERR_HIP;
-  }
-  static const int kCandidates[] = {4, 8, 16, 32, 64, 128};
-  for (int ci = 0; result == NMF_OK && ci < (int)(sizeof(kCandidates) / sizeof(int)); ++ci) {
-    nmf_batch_config cfg{kCandidates[ci], 0, 0};
+  // time per step of the whole set under `t`; +inf if a work item gave up waiting
+  auto time_table = [&](const int* t, double* ms) -> nmf_status {
     nmf_batch_t b = nullptr;
-    nmf_status st = nmf_batch_create(c, pr, count, mode, opts, &cfg, &b);
-    if (st != NMF_OK) { result = st; break; }
-    float ms = 0.f;
-    hipError_t e = launch_batched(b->prec, b->mode == NMF_JOINT, b->grid, s, b->args);
+    nmf_status r = batch_create(c, pr, count, mode, o, t, 0, 0, &b);
+    if (r != NMF_OK) return r;
+    float el = 0.f;
+    hipError_t e = launch_batched(b->prec, joint, b->grid, s, b->args);
     if (e == hipSuccess) e = hipEventRecord(e0, s);
-    for (int t = 0; e == hipSuccess && t < iters; ++t) e = launch_batched(b->prec, b->mode == NMF_JOINT, b->grid, s, b->args);
+    for (int k = 0; e == hipSuccess && k < iters; ++k) e = launch_batched(b->prec, joint, b->grid, s, b->args);
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&el, e0, e1);
     uint32_t fl = 0;
     if (e == hipSuccess && nmf_batch_get_flags(b, stream, &fl, 1) != NMF_OK) e = hipErrorUnknown;
     (void)nmf_batch_destroy(b);
     if (e == hipSuccess) e = copy_all(false);
-    if (e != hipSuccess) { result = NMF_ERR_HIP; break; }
-    const double t = (double)ms / iters;
-    if (fl == 0 && t < best_t) {
-      best_t = t;
-      best_cfg = cfg;
+    if (e != hipSuccess) return NMF_ERR_HIP;
+    *ms = (fl & NMF_FLAG_BARRIER) ? HUGE_VAL : (double)el / iters;
+    return NMF_OK;
+  };
+  // how the problems of bucket `b` are split under `t` tiles per item
+  auto split_of = [&](int b, int t) {
+    std::vector<int> sig;
+    for (int i = 0; i < count; ++i) {
+      const nmf_problem& q = pr[i];
+      if (bucket_of(q.F, q.N, q.K) != b) continue;
+      const Plan p = make_batch_plan(q.F, q.N, q.K, t, joint);
+      sig.insert(sig.end(), {p.n_groups, p.tiles_n, p.f_groups, p.tiles_f});
+    }
+    return sig;
+  };
+  static const int kCandidates[] = {4, 8, 16, 32, 64, 128};
+  double best = HUGE_VAL;
+  st = NMF_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess || copy_all(true) != hipSuccess)
+    st = NMF_ERR_HIP;
+  if (st == NMF_OK) st = time_table(table, &best);
+  const unsigned todo = needed & ~(have ? cached.mask : 0u);
+  for (int b = 0; st == NMF_OK && b < kBatchBuckets; ++b) {
+    if (!(todo >> b & 1u)) continue;
+    std::vector<std::vector<int>> seen{split_of(b, table[b])};
+    for (int cand : kCandidates) {
+      std::vector<int> sig = split_of(b, cand);
+      if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
+      seen.push_back(sig);
+      int trial[kBatchBuckets];
+      std::memcpy(trial, table, sizeof(trial));
+      trial[b] = cand;
+      double ms = HUGE_VAL;
+      if ((st = time_table(trial, &ms)) != NMF_OK) break;
+      if (ms < best) {
+        best = ms;
+        table[b] = cand;
+      }
     }
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)hipFree(save);
-  if (result == NMF_OK) {
-    *best = best_cfg;
-    if (best_ms) *best_ms = best_t;
+  if (st != NMF_OK) return st;
+  for (int b = 0; b < kBatchBuckets; ++b) c->batch_tiles[b] = table[b];
+  if ((st = upload_tiles(c)) != NMF_OK) return st;
+  for (int b = 0; b < kBatchBuckets; ++b) tiles_out[b] = table[b];
+  if (ms_out) *ms_out = best;
+  if (cache_path) {
+    TuneEntry e;
+    e.mask = needed | (have ? cached.mask : 0u);
+    std::memcpy(e.tiles, table, sizeof(table));
+    e.ms = best;
+    if ((st = cache_store(cache_path, key, e)) != NMF_OK) return st;
   }
-  return result;
+  return NMF_OK;
 }
 
 }  // extern "C"

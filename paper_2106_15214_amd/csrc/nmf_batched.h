@@ -119,12 +119,15 @@ __global__ __launch_bounds__(kBlock, 2) void batched_step_kernel(BatchArgs b) {
   __shared__ int last;
   const int tid = threadIdx.x;
   const ConstProblemPtr probs = (ConstProblemPtr)b.probs;
+  // a batch planned on the device publishes its sizes in memory
+  const int total = b.counts ? b.counts[0] : b.total;
+  const int nprob = b.counts ? b.counts[1] : b.nprob;
 
   for (;;) {
     __syncthreads();  // every thread has read the previous entry
     if (tid == 0) {
       const unsigned idx = atomicAdd(b.next, 1u);
-      entry = idx < (unsigned)b.total ? b.list[idx] : make_int2(-1, 0);
+      entry = idx < (unsigned)total ? b.list[idx] : make_int2(-1, 0);
     }
     __syncthreads();
     const int prob = __builtin_amdgcn_readfirstlane(entry.x);
@@ -179,7 +182,7 @@ __global__ __launch_bounds__(kBlock, 2) void batched_step_kernel(BatchArgs b) {
   if (last) {
     __threadfence();
     // atomic exchanges: the counters are only ever accessed atomically
-    for (int i = tid; i < 4 * b.nprob; i += kBlock)
+    for (int i = tid; i < 4 * nprob; i += kBlock)
       (void)__hip_atomic_exchange(b.done + i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (tid == 0) {
       (void)__hip_atomic_exchange(b.next, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -34,7 +34,7 @@ constexpr int sweep_cols_occupancy(int bc, int KB, int kind, bool dual) {
   return (KB >= 4 || (dual && kind == KIND_UPDATE && bc != BC_B1)) ? 1 : 2;
 }
 
-inline int beta_class(double beta) {
+__host__ __device__ inline int beta_class(double beta) {
   if (beta == 2.0) return BC_B2;
   if (beta == 1.0) return BC_B1;
   if (beta == 0.0) return BC_B0;
@@ -44,7 +44,7 @@ inline int beta_class(double beta) {
 }
 
 // gamma(beta), paper eq. (def_gamma)
-inline double gamma_of(double beta) {
+__host__ __device__ inline double gamma_of(double beta) {
   if (beta < 1.0) return 1.0 / (2.0 - beta);
   if (beta <= 2.0) return 1.0;
   return 1.0 / (beta - 1.0);
@@ -183,6 +183,7 @@ struct BatchArgs {
   const BatchProblem* probs;
   const int2* list;     // [total]: (problem, phase << 24 | item), phase-major
   int total;
+  const int* counts;    // nullable: total and the problem count read from [0], [1] instead
   unsigned* next;       // queue position (zero at launch; reset by the last workgroup)
   unsigned* exited;     // workgroups that left the queue loop
   unsigned* done;       // [problems][4] finished items per phase (reset at exit)

@@ -12,7 +12,7 @@ import paper_2106_15214_amd as nb
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "nmf_beta.h")
 
-OK, E_NULL, E_SHAPE, E_BETA, E_ALIAS, E_WS, E_HIP, E_UNSUP, E_ARG, E_NODEV = range(10)
+OK, E_NULL, E_SHAPE, E_BETA, E_ALIAS, E_WS, E_HIP, E_UNSUP, E_ARG, E_NODEV, E_IO = range(11)
 
 
 def _declared():
@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     L = nb.lib()
-    for st in range(10):
+    for st in range(11):
         s = L.nmf_status_string(st).decode()
         assert s.startswith("NMF_")
     assert L.nmf_status_string(99).decode() == "unknown nmf_status"
@@ -110,3 +110,79 @@ def test_binding_rejects_host_tensors():
     H = torch.ones(2, 5)
     with pytest.raises((ValueError, nb.NmfError, RuntimeError)):
         nb.step(V, W, H, 1.0, "joint", ctx=object.__new__(nb.Context))
+
+
+# ---------------------------------------------------------------------------
+# batched step with device descriptors: host-only parts
+# ---------------------------------------------------------------------------
+def _bucket_from_rule(F, N, K):
+    """The bucket rule as the header states it."""
+    T = max(-(-F // 32), -(-N // 32))
+    cls = 0 if T <= 32 else 1 if T <= 64 else 2 if T <= 128 else 3
+    return (0 if K <= 32 else 4) + cls
+
+
+def test_batch_bucket_rule():
+    for F, N, K in [(1, 1, 1), (1024, 1024, 32), (1025, 100, 32), (100, 2048, 33), (2049, 10, 64),
+                    (4096, 4096, 64), (4097, 1, 1), (128, 5000, 17), (1000, 200, 64), (20000, 10000, 50)]:
+        assert nb.batch_bucket(F, N, K) == _bucket_from_rule(F, N, K), (F, N, K)
+    for F, N, K in [(0, 5, 5), (5, 0, 5), (5, 5, 0), (5, 5, 65)]:
+        assert nb.batch_bucket(F, N, K) == -1
+
+
+def _shapes(n, seed=3):
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    return [(int(rng.integers(128, 1026)), int(rng.integers(200, 5001)), int(rng.integers(8, 65))) for _ in range(n)]
+
+
+def test_batch_requirements_invariants():
+    shapes = _shapes(40)
+    items, bytes_ = nb.batch_requirements(shapes, "joint")
+    assert items > 0 and bytes_ > 0
+    # additive over problems
+    i1, b1 = nb.batch_requirements(shapes[:17], "joint")
+    i2, b2 = nb.batch_requirements(shapes[17:], "joint")
+    assert (i1 + i2, b1 + b2) == (items, bytes_)
+    # the default table is 128 in every bucket
+    assert nb.batch_requirements(shapes, "joint", [128] * 8) == (items, bytes_)
+    # joint keeps P and Q per problem: more workspace, the same items
+    ia, ba = nb.batch_requirements(shapes, "alternating")
+    assert ia == items and ba < bytes_
+    # fewer tiles per item: more items, never fewer bytes
+    it, bt = nb.batch_requirements(shapes, "joint", [8] * 8)
+    assert it > items and bt >= bytes_
+    # a single problem: items are whole row / column blocks of 128 per pass
+    (F, N, K) = (1000, 3000, 20)
+    i, _ = nb.batch_requirements([(F, N, K)], "joint", [4096] * 8)
+    rb, cb = -(-F // 128), -(-N // 128)
+    assert i >= rb + cb and i <= rb + cb + F + N
+
+
+def test_batch_requirements_checks():
+    with pytest.raises(nb.NmfError) as e:
+        nb.batch_requirements([(10, 10, 65)])
+    assert e.value.status == E_UNSUP
+    with pytest.raises(nb.NmfError) as e:
+        nb.batch_requirements([(0, 10, 5)])
+    assert e.value.status == E_SHAPE
+    with pytest.raises(nb.NmfError) as e:
+        nb.batch_requirements([(10, 10, 5)], "joint", [0] * 8)
+    assert e.value.status == E_ARG
+    L = nb.lib()
+    n, b = ctypes.c_int64(), ctypes.c_int64()
+    assert L.nmf_batch_requirements(None, 1, 1, None, ctypes.byref(n), ctypes.byref(b)) == E_NULL
+    arr = (nb._Problem * 1)(nb._Problem(10, 10, 5, None, 0, None, 0, None, 0, 1.0))
+    assert L.nmf_batch_requirements(arr, 0, 1, None, ctypes.byref(n), ctypes.byref(b)) == E_ARG
+    assert L.nmf_batch_requirements(arr, 1, 5, None, ctypes.byref(n), ctypes.byref(b)) == E_ARG
+
+
+def test_batched_entry_points_null_context():
+    L = nb.lib()
+    t = (ctypes.c_int32 * 8)()
+    assert L.nmf_reserve_batched(None, 1, 1, 1) == E_NULL
+    assert L.nmf_beta_step_batched(None, None, 1, 1, 1, None, None, None) == E_NULL
+    assert L.nmf_set_batch_tiles(None, t) == E_NULL
+    assert L.nmf_get_batch_tiles(None, t) == E_NULL
+    arr = (nb._Problem * 1)()
+    assert L.nmf_tune(None, None, arr, 1, 1, None, 1, None, t, None, None) == E_NULL

@@ -239,20 +239,3 @@ def test_batched_rejects_aliasing_and_large_k():
     p = synth.random_positive(40, 50, 65, seed=3)
     with pytest.raises(nb.NmfError):
         nb.Batch([(dev(p.V), dev(p.W), dev(p.H), 1.0)], "joint", ctx=ctx())
-
-
-def test_batch_tune_restores_state_and_caches(tmp_path):
-    probs = to_dev(make_set(WELL_POSED, seed0=1100))
-    before = [(W.clone(), H.clone()) for _, W, H, _ in probs]
-    cache = str(tmp_path / "tune.json")
-    cfg, ms = nb.batch_tune(probs, "joint", iters=2, cache=cache, ctx=ctx())
-    assert cfg["tiles_per_item"] in (4, 8, 16, 32, 64, 128) and ms > 0
-    for (W0, H0), (_, W, H, _) in zip(before, probs):
-        assert torch.equal(W0, W) and torch.equal(H0, H)
-    cfg2, ms2 = nb.batch_tune(probs, "joint", iters=2, cache=cache, ctx=ctx())
-    assert cfg2 == cfg and ms2 == ms
-    b = nb.Batch(probs, "joint", ctx=ctx(), **cfg)
-    b.step()
-    torch.cuda.synchronize()
-    assert b.flags() == 0
-    b.close()
