@@ -3,7 +3,8 @@
 // phase-major over all problems:
 //   W-pass items  (rows items: Lambda~ tiles, P, Q, W-step partials, objective;
 //                  in joint mode P and Q are kept for the H pass)
-//   W-update units (partials reduced, W_new, chi terms)
+//   W-update items (partials reduced, W_new, chi terms; 64 rows each, all loads
+//                  in flight together)
 //   H-pass items  (cols items: H-step partials from the kept P, Q in joint mode,
 //                  column sums of W_new)
 //   H-update units (H_new, normalization, W write-back, objective total)
@@ -14,6 +15,7 @@
 #pragma once
 
 #include "nmf_device.h"
+#include "nmf_plan.h"
 
 namespace nmf {
 
@@ -22,6 +24,7 @@ constexpr int kBatchLdsBytes = cols_item_lds<2, true>();
 static_assert(cols_item_lp_lds<2, true>() <= kBatchLdsBytes, "batched LDS");
 static_assert(rows_item_lds<2>() <= kBatchLdsBytes, "batched LDS");
 static_assert(2 * kBlock * 8 <= kBatchLdsBytes, "batched LDS");
+static_assert(kBatchWRows * (64 + 1) * 4 <= kBatchLdsBytes, "batched LDS");
 
 // Descriptors never change during the launch: reading them through the
 // constant address space lets the compiler keep their fields in scalar
@@ -59,12 +62,10 @@ __device__ __noinline__ void batch_item(ConstProblemPtr P, int prob, int phase, 
       if (threadIdx.x == 0) ra.pobj[item] = sum;
     }
   } else if (phase == PH_WUPDATE) {
+    // the joint H pass contracts the kept P, Q tiles and never forms Lambda
+    // again, so only alternating MU needs the transposed factor
     const UpdateWArgs ua = load_const(&P->ua);
-    const double den1 = row_sum_den<KB>(ua);
-    double nrm = 0.0, cs = 0.0;
-    const int per = P->per_item[PH_WUPDATE];
-    const int u1 = min(P->units[PH_WUPDATE], (item + 1) * per);
-    for (int u = item * per; u < u1; ++u) update_w_unit<KB, 1>(ua, u, true, lds, den1, nrm, cs);
+    update_w_rows<KB, kBatchWRows>(ua, item * kBatchWRows, !JOINT, row_sum_den<KB>(ua), lds);
   } else if (phase == PH_HPASS) {
     const SweepColsArgs ca = load_const(&P->ca);
     cols_prologue<KB>(ca, item, lds);

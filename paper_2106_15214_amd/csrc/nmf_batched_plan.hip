@@ -107,10 +107,9 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(BatchPlanArgs 
     } else {
       const Plan p = make_batch_plan(q.F, q.N, q.K, a.tiles[bucket_of(q.F, q.N, q.K)], a.joint != 0);
       bytes = (int64_t)align_up(p.total);
-      items[PH_WPASS] = (int64_t)p.row_blocks * p.n_groups;
-      items[PH_WUPDATE] = cdiv(cdiv(q.F, batch_unit_rows(p.KB)), batch_w_units(p.KB));
-      items[PH_HPASS] = (int64_t)p.col_blocks * p.f_groups;
-      items[PH_HUPDATE] = cdiv(p.uh_blocks, batch_h_units(p.KB));
+      int units[4], per_item[4], it[4];
+      batch_phases(p, q.F, units, per_item, it);
+      for (int ph = 0; ph < 4; ++ph) items[ph] = it[ph];
     }
     a.s_bytes[i] = bytes;
     for (int ph = 0; ph < 4; ++ph) a.s_items[4 * (int64_t)i + ph] = items[ph];

@@ -1811,6 +1811,77 @@ __device__ __forceinline__ void update_w_unit(const UpdateWArgs& a, int unit, bo
   }
 }
 
+// W update of rows [f0, f0 + R) with every load of the rows in flight at once
+// (the batched step's W-update item): thread (r, k) owns rows f0 + r + i RU,
+// i < R / RU (RU = kBlock / KP), and sums each row's partial groups in order in
+// float64, so the result equals update_w_unit's.  With `write_wt` the factor
+// that forms Lambda in the H pass (W~ joint, W_new alternating) is written to
+// the transposed copy through LDS ([R][KP + 1] floats), 32 consecutive rows of
+// one column per wave store.
+template <int KB, int R>
+__device__ __forceinline__ void update_w_rows(const UpdateWArgs& a, int f0, bool write_wt, double den1,
+                                              float* lds) {
+  constexpr int KP = 32 * KB;
+  constexpr int RU = kBlock / KP;
+  constexpr int PER = R / RU;
+  static_assert(PER * RU == R, "rows per item");
+  const int tid = threadIdx.x;
+  const int k = tid % KP, r = tid / KP;
+  const bool kok = k < a.K;
+  const int64_t gstride = (int64_t)a.F * KP;
+  float wt[PER];
+  bool ok[PER];
+  double num[PER], den[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int f = f0 + r + i * RU;
+    ok[i] = f < a.F;
+    wt[i] = ldz(a.W, (int64_t)f * a.ldw + k, ok[i] && kok);
+    num[i] = 0.0;
+    den[i] = 0.0;
+  }
+  for (int g = 0; g < a.n_groups; ++g) {
+    float xn[PER], xd[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int64_t o = (int64_t)g * gstride + (int64_t)(f0 + r + i * RU) * KP + k;
+      xn[i] = ldc(a.pnum, o, ok[i]);
+      xd[i] = a.beta_one ? 0.f : ldc(a.pden, o, ok[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) { num[i] += (double)xn[i]; den[i] += (double)xd[i]; }
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int f = f0 + r + i * RU;
+    float wn = 0.f, c1 = 0.f, c2 = 0.f;
+    if (ok[i] && kok) {
+      const double dsum = a.beta_one ? den1 : den[i];
+      const double ratio = num[i] / dsum;
+      if (!(dsum > 0.0) || !isfinite(ratio)) set_flag(a.flags, 1u);
+      const double rr = pow_gamma(ratio, a.gamma);
+      const double w0 = (double)wt[i];
+      const double wnew = w0 * rr;
+      wn = (float)wnew;
+      if (a.joint) chi_terms(a.beta, w0, rr, wnew, c1, c2);
+    }
+    if (ok[i]) {
+      const int64_t o = (int64_t)f * KP + k;
+      a.Wn[o] = wn;
+      if (a.joint) { a.C1[o] = c1; a.C2[o] = c2; }
+      if (a.C0) a.C0[o] = wt[i];
+    }
+    if (write_wt) lds[(r + i * RU) * (KP + 1) + k] = a.joint ? wt[i] : wn;
+  }
+  if (write_wt) {
+    __syncthreads();
+    for (int e = tid; e < KP * R; e += kBlock) {
+      const int kk = e / R, j = e % R;
+      if (f0 + j < a.F) a.WT[(int64_t)kk * a.ldt + f0 + j] = lds[j * (KP + 1) + kk];
+    }
+  }
+}
+
 // Sum over groups of the beta = 1 row-sum partials of H~ (the W-step denominator).
 template <int KB>
 __device__ __forceinline__ double row_sum_den(const UpdateWArgs& a) {

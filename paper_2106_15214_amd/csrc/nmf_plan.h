@@ -20,11 +20,10 @@ NMF_PLAN_HD inline int64_t max64(int64_t a, int64_t b) { return a > b ? a : b; }
 constexpr size_t kHeaderBytes = 256;
 constexpr int kColChunkRows = 512;  // rows of W_new per column-partial workgroup of the H pass
 
-// the batched W update uses one thread slice per row: kBlock / KP rows per unit
-constexpr int kBatchUpdateRows = 32;   // rows of W per W-update work item
-constexpr int kBatchUpdateCols = 64;   // columns of H per H-update work item
-NMF_PLAN_HD inline int batch_unit_rows(int KB) { return kBlock / (32 * KB); }
-NMF_PLAN_HD inline int batch_w_units(int KB) { return (int)max64(1, kBatchUpdateRows / batch_unit_rows(KB)); }
+// batched update items: rows of W per W-update item (all of them loaded at
+// once), columns of H per H-update item (units of kBlock / KP columns)
+constexpr int kBatchWRows = 64;
+constexpr int kBatchUpdateCols = 256;
 NMF_PLAN_HD inline int batch_h_units(int KB) { return (int)max64(1, kBatchUpdateCols / (kBlock / (32 * KB))); }
 
 constexpr size_t kAlign = 256;
@@ -214,6 +213,21 @@ NMF_PLAN_HD inline int bucket_of(int64_t F, int64_t N, int64_t K) {
   return (kblocks_for(K) - 1) * 4 + cls;
 }
 
+// Update units and work items per phase of a problem in a batch: W-pass items
+// (row block x column group), W-update items of kBatchWRows rows, H-pass items
+// (column block x row group), H-update items of batch_h_units column units.
+NMF_PLAN_HD inline void batch_phases(const Plan& p, int64_t F, int units[4], int per_item[4], int items[4]) {
+  units[PH_WPASS] = p.row_blocks * p.n_groups;
+  units[PH_WUPDATE] = (int)cdiv(F, kBatchWRows);
+  units[PH_HPASS] = p.col_blocks * p.f_groups;
+  units[PH_HUPDATE] = p.uh_blocks;
+  per_item[PH_WPASS] = 1;
+  per_item[PH_WUPDATE] = 1;
+  per_item[PH_HPASS] = 1;
+  per_item[PH_HUPDATE] = batch_h_units(p.KB);
+  for (int ph = 0; ph < 4; ++ph) items[ph] = (int)cdiv(units[ph], per_item[ph]);
+}
+
 // Kernel descriptor of one problem of a batch (workspace at `ws`): the four
 // phases' arguments, and for each phase its update units and work items.
 NMF_PLAN_HD inline BatchProblem make_batch_problem(const Plan& p, char* ws, unsigned* flags, const nmf_problem& q,
@@ -235,22 +249,15 @@ NMF_PLAN_HD inline BatchProblem make_batch_problem(const Plan& p, char* ws, unsi
   d.ha = sa.ha;
   d.bc = beta_class(q.beta);
   d.kb = p.KB;
-  d.units[PH_WPASS] = p.row_blocks * p.n_groups;
-  d.units[PH_WUPDATE] = (int)cdiv(q.F, batch_unit_rows(p.KB));
-  d.units[PH_HPASS] = p.col_blocks * p.f_groups;
-  d.units[PH_HUPDATE] = p.uh_blocks;
-  d.per_item[PH_WPASS] = 1;
-  d.per_item[PH_WUPDATE] = batch_w_units(p.KB);
-  d.per_item[PH_HPASS] = 1;
-  d.per_item[PH_HUPDATE] = batch_h_units(p.KB);
-  for (int ph = 0; ph < 4; ++ph) d.items[ph] = (int)cdiv(d.units[ph], d.per_item[ph]);
+  batch_phases(p, q.F, d.units, d.per_item, d.items);
   return d;
 }
 
 // Work items of one problem's outer iteration in a batch (all four phases).
 NMF_PLAN_HD inline int64_t batch_items(const Plan& p, int64_t F) {
-  return (int64_t)p.row_blocks * p.n_groups + cdiv(cdiv(F, batch_unit_rows(p.KB)), batch_w_units(p.KB)) +
-         (int64_t)p.col_blocks * p.f_groups + cdiv(p.uh_blocks, batch_h_units(p.KB));
+  int units[4], per_item[4], items[4];
+  batch_phases(p, F, units, per_item, items);
+  return (int64_t)items[0] + items[1] + items[2] + items[3];
 }
 
 }  // namespace nmf
