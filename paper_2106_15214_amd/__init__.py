@@ -48,7 +48,9 @@ PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16}
 EXPONENTS = {"mm": 0, "one": 1}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-library_path = os.path.join(_HERE, "libnmfbeta.so")
+# NMF_BETA_LIBRARY selects another build of the same library (the host-side
+# sanitizer build of the CPU tests); by default the in-tree libnmfbeta.so
+library_path = os.environ.get("NMF_BETA_LIBRARY") or os.path.join(_HERE, "libnmfbeta.so")
 
 
 class NmfError(RuntimeError):

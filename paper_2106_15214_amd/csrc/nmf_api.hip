@@ -684,7 +684,11 @@ void nmf_default_opts(nmf_step_opts* o) {
 const char* nmf_version(void) { return "nmfbeta 0.1 (gfx950)"; }
 
 const char* nmf_status_string(nmf_status s) {
-  switch (s) {
+  // a C caller may pass any int: read it as one (an out-of-range enumerator
+  // value must not be loaded as the enum type)
+  int v = 0;
+  std::memcpy(&v, &s, sizeof(v));
+  switch (v) {
     case NMF_OK: return "NMF_OK";
     case NMF_ERR_NULL: return "NMF_ERR_NULL: required pointer is NULL";
     case NMF_ERR_SHAPE: return "NMF_ERR_SHAPE: bad size or leading dimension";
