@@ -14,13 +14,16 @@ namespace nmf {
 
 namespace {
 
-constexpr int kPlanThreads = 256;
+constexpr int kPlanThreads = 1024;
+constexpr int kPlanWaves = kPlanThreads / 64;
+constexpr int kStage = 256;  // descriptors staged in LDS per round of the pairwise checks
 
 // Exclusive prefix sum of x[0..n) in place, by the whole workgroup: one
-// contiguous segment per thread, the segment totals scanned by thread 0 in
-// LDS, the offsets added back.  *total receives the sum.
+// contiguous segment per thread, the segment totals scanned across each wave
+// with shuffles and across the waves by one wave, the offsets added back.
+// *total receives the sum.  seg holds kPlanWaves values.
 __device__ void block_exclusive_scan(int64_t* x, int n, int64_t* seg, int64_t* total) {
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int per = (n + kPlanThreads - 1) / kPlanThreads;
   const int i0 = min(n, tid * per), i1 = min(n, i0 + per);
   int64_t s = 0;
@@ -29,19 +32,28 @@ __device__ void block_exclusive_scan(int64_t* x, int n, int64_t* seg, int64_t* t
     x[i] = s;
     s += v;
   }
-  seg[tid] = s;
+  // inclusive scan of the segment totals within the wave
+  int64_t inc = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int64_t y = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += y;
+  }
+  if (lane == 63) seg[wave] = inc;
   __syncthreads();
-  if (tid == 0) {
-    int64_t run = 0;
-    for (int t = 0; t < kPlanThreads; ++t) {
-      const int64_t v = seg[t];
-      seg[t] = run;
-      run += v;
+  if (wave == 0) {
+    const int64_t w = lane < kPlanWaves ? seg[lane] : 0;
+    int64_t wi = w;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int64_t y = __shfl_up(wi, d, 64);
+      if (lane >= d) wi += y;
     }
-    *total = run;
+    if (lane < kPlanWaves) seg[lane] = wi - w;  // exclusive wave offsets
+    if (lane == 63) *total = wi;
   }
   __syncthreads();
-  const int64_t off = seg[tid];
+  const int64_t off = seg[wave] + inc - s;
   for (int i = i0; i < i1; ++i) x[i] += off;
   __syncthreads();
 }
@@ -79,8 +91,8 @@ __device__ Spans spans_of(const nmf_problem& q) {
 }
 
 __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(BatchPlanArgs a) {
-  __shared__ Spans stage[kPlanThreads];
-  __shared__ int64_t seg[kPlanThreads];
+  __shared__ Spans stage[kStage];
+  __shared__ int64_t seg[kPlanWaves];
   __shared__ int64_t tot_bytes, tot_items[4];
   __shared__ int bad;
   const int tid = threadIdx.x;
@@ -116,18 +128,20 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(BatchPlanArgs 
   }
 
   // rank by size (larger first, ties by index) and cross-problem overlaps, with
-  // the other problems' spans staged through LDS 256 at a time
+  // the other problems' spans staged through LDS kStage at a time
   for (int ib = 0; ib < P; ib += kPlanThreads) {
     const int i = ib + tid;
     const Spans me = i < P ? spans_of(a.problems[i]) : Spans{-1, 0, 0, 0, 0, 0, 0};
     int r = 0;
     bool ov = false;
-    for (int jb = 0; jb < P; jb += kPlanThreads) {
+    for (int jb = 0; jb < P; jb += kStage) {
       __syncthreads();
-      const int j = jb + tid;
-      stage[tid] = j < P ? spans_of(a.problems[j]) : Spans{-2, 0, 0, 0, 0, 0, 0};
+      if (tid < kStage) {
+        const int j = jb + tid;
+        stage[tid] = j < P ? spans_of(a.problems[j]) : Spans{-2, 0, 0, 0, 0, 0, 0};
+      }
       __syncthreads();
-      const int nj = min(kPlanThreads, P - jb);
+      const int nj = min(kStage, P - jb);
       for (int t = 0; t < nj; ++t) {
         const Spans& o = stage[t];
         const int j2 = jb + t;
