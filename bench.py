@@ -418,7 +418,7 @@ def main_sparse(args, nb, synth, torch, np, dev):
     nbytes = 2 * nnz * 8
     roof = {"bound": "alu", "achieved": flops / t_dom / 1e12, "peak": PEAK_VALU_F32 / 1e12, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(args.workload + "_sparse", "fp32", "sparse_pass")
+    roof["traffic"] = measured_traffic(args.workload + "_csr", "fp32", "sparse_pass")
     roof["kernel"] = "sparse_pass"
     roof["algorithmic_flops_per_launch"] = flops
     roof["algorithmic_bytes_per_launch"] = nbytes
