@@ -92,11 +92,12 @@ def source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, precision: str, kernel: str, beta=None):
+def measured_traffic(workload: str, precision: str, kernel: str, beta=None, field: str = "traffic_joint"):
     """Calibrated HBM bytes per launch of `kernel` in the joint step, from the
     committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of this workload, or None
     when there is none, it was taken at another beta (another kernel
-    instantiation), or the kernels changed since it was taken."""
+    instantiation), or the kernels changed since it was taken.  `field`
+    "mfma_busy" reads the matrix-core utilization of the same summary instead."""
     name = f"kernels_{workload}" + ("" if precision == "fp32" else f"_precision_{precision}") + ".txt"
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
@@ -109,7 +110,7 @@ def measured_traffic(workload: str, precision: str, kernel: str, beta=None):
                 digest = parts[1]
             elif len(parts) == 2 and parts[0] == "beta":
                 pbeta = float(parts[1])
-            elif len(parts) == 3 and parts[0] == "traffic_joint" and parts[1] == kernel:
+            elif len(parts) == 3 and parts[0] == field and parts[1] == kernel:
                 value = float(parts[2])
     if digest != source_digest():
         return None
@@ -276,6 +277,7 @@ def main(argv=None):
         roof = {"bound": "hbm", "achieved": vbytes / t_dom / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = measured_traffic(args.workload, args.precision, dom, beta)
+    roof["mfma_busy_profiled"] = measured_traffic(args.workload, args.precision, dom, beta, field="mfma_busy")
     roof["kernel"] = dom
     roof["algorithmic_flops_per_launch"] = flops
     roof["algorithmic_bytes_per_launch"] = vbytes
@@ -639,6 +641,7 @@ def main_batched(args, nb, synth, torch, np, dev):
         roof = {"bound": "hbm", "achieved": vbytes / t / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = measured_traffic("batched", args.precision, "batched_step")
+    roof["mfma_busy_profiled"] = measured_traffic("batched", args.precision, "batched_step", field="mfma_busy")
     roof["kernel"] = "batched_step"
     roof["algorithmic_flops_per_launch"] = flops
     roof["algorithmic_bytes_per_launch"] = vbytes
