@@ -453,6 +453,8 @@ def main_sparse(args, nb, synth, torch, np, dev):
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_sparse(p, (rp, ci, rv), args.cpu_seconds, res["joint"]["iters_per_s"])
+    if args.calib_copy:
+        out["calib_copy_bytes"] = calib_copy(torch, dev)
     print(json.dumps(out), flush=True)
     ctx.close()
     return 0
