@@ -54,21 +54,23 @@ PAPER_CPU_REFERENCE = {
 }
 
 
-def _flops_bytes(F, N, K, beta, mode):
+def _flops_bytes(F, N, K, beta, mode, gram=False):
     """Algorithmic work per launch of each kernel (one outer iteration).
 
     sweep_w    : Lambda = W~H~ (2FNK) + P H~^T (2FNK) + Q H~^T (2FNK; omitted at
-                 beta = 1, where the denominator is a row sum); reads V once (4FN bytes).
-    sweep_h    : the two H-step contractions (4FNK; 2FNK at beta = 1).  Re-forming
-                 Lambda costs another 2FNK: algorithmic for the alternating method
-                 (Lambda' = W_new H~), implementation overhead for the joint one.
+                 beta = 1, where the denominator is a row sum, and in the Gram
+                 form at beta = 2, where it is W~ (H~ H~^T)); reads V once (4FN bytes).
+    sweep_h    : the two H-step contractions (4FNK; 2FNK at beta = 1 and in the
+                 Gram form).  Re-forming Lambda costs another 2FNK: algorithmic
+                 for the alternating method (Lambda' = W_new H~; not needed in the
+                 Gram form), implementation overhead for the joint one.
     fused_step : the whole iteration: joint 10FNK (6FNK at beta = 1) reading V
                  once; alternating 12FNK (8FNK) reading V twice.
     """
     b1 = (beta == 1.0)
     fnk = F * N * K
-    sw = (4 if b1 else 6) * fnk
-    sh = (2 if b1 else 4) * fnk + (2 * fnk if mode == "alternating" else 0)
+    sw = (4 if b1 or gram else 6) * fnk
+    sh = (2 if b1 or gram else 4) * fnk + (2 * fnk if mode == "alternating" and not gram else 0)
     vb = 4 * F * N
     return {"sweep_w": (sw, vb), "sweep_h": (sh, vb),
             "fused_step": (sw + sh, vb if mode == "joint" else 2 * vb)}
@@ -164,6 +166,9 @@ def main(argv=None):
     ap.add_argument("--tto-iters", type=int, default=None,
                     help="iterations of the time-to-objective runs (default: the workload's own count)")
     ap.add_argument("--beta", type=float, default=None)
+    ap.add_argument("--kappa", type=float, default=None,
+                    help="batched workload: smoothing constant of Sec. 4.1.3 (default 1e-9: its count data with "
+                         "zeros at beta < 1 drive entries of WH to zero at kappa = 0)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle timing sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -264,7 +269,7 @@ def main(argv=None):
             phases[mode] = dict(zip(["w_pass", "barrier1", "w_update", "barrier2", "h_pass", "barrier3", "h_update"],
                                     [round(x, 2) for x in ctx.profile_phases()]))
         ctx.profile([])
-    fb = _flops_bytes(F, N, K, beta, "joint")
+    fb = _flops_bytes(F, N, K, beta, "joint", gram=args.gram)
     dom = max((k for k in kern["joint"] if k in fb), key=lambda k: kern["joint"][k]["avg_us"])
     flops, vbytes = fb[dom]
     t_dom = kern["joint"][dom]["avg_us"] * 1e-6
@@ -560,6 +565,11 @@ def main_batched(args, nb, synth, torch, np, dev):
     persistent launch per outer iteration, replayed from a HIP graph.  A step is
     one outer iteration of every problem; `value` is steps per second."""
     specs = synth.batched_specs(args.problems)
+    # Sec. 4.1.3's smoothing: at kappa = 0 the count-data problems with zeros at
+    # beta < 1 drive entries of WH to zero within ~130 iterations (in float64 as
+    # well) until an update ratio is undefined
+    kappa = 1e-9 if args.kappa is None else float(args.kappa)
+    args.kappa_batched = kappa
     t0 = time.perf_counter()
     probs, host = [], []
     for sp in specs:
@@ -583,7 +593,8 @@ def main_batched(args, nb, synth, torch, np, dev):
     cfg = {"tiles_per_item": args.tiles, "workers": 0, "lag": args.lag}
     tuned_ms = None
     if args.tune:
-        tiles, tuned_ms, hit = nb.tune(probs, "joint", precision=args.precision, iters=3, cache=args.tune, ctx=ctx)
+        tiles, tuned_ms, hit = nb.tune(probs, "joint", precision=args.precision, kappa=kappa, iters=3, cache=args.tune,
+                                      ctx=ctx)
         print(f"# tuned bucket tiles {tiles} ({tuned_ms:.3f} ms/step, {'cached' if hit else 'measured'})",
               file=sys.stderr, flush=True)
     bucket_tiles = nb.get_batch_tiles(ctx)
@@ -598,7 +609,7 @@ def main_batched(args, nb, synth, torch, np, dev):
     T = args.tto_iters
     for mode in ("joint", "alternating"):
         reset()
-        b = nb.Batch(probs, mode, precision=args.precision, ctx=ctx, **cfg)
+        b = nb.Batch(probs, mode, precision=args.precision, kappa=kappa, ctx=ctx, **cfg)
         obj = torch.zeros(len(probs), dtype=torch.float64, device=dev)
         for _ in range(args.warmup):
             b.step(objectives=obj)
@@ -660,7 +671,7 @@ def main_batched(args, nb, synth, torch, np, dev):
         "dtype": {"fp32": "f32", "bf16": "bf16", "fp16": "f16"}[args.precision],
         "data": "synthetic",
         "config": {"workload": "batched", "problems": len(probs), "sum_FN": fn, "sum_FNK": fnk, "mode": "joint",
-                   "precision": args.precision, "objective_every_step": True, "launches_per_step": 1,
+                   "precision": args.precision, "kappa": kappa, "objective_every_step": True, "launches_per_step": 1,
                    "graph_replay": True, **cfg, "bucket_tiles": bucket_tiles},
         "problem_iterations_per_s": len(probs) * res["joint"]["steps_per_s"],
         "alternating": {"value": res["alternating"]["steps_per_s"], "ms_per_step": res["alternating"]["ms_per_step"],
@@ -675,7 +686,7 @@ def main_batched(args, nb, synth, torch, np, dev):
     if args.calib_copy:
         out["calib_copy_bytes"] = calib_copy(torch, dev)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_batched(host, args.cpu_seconds, res["joint"]["steps_per_s"])
+        out["cpu_baseline"] = cpu_baseline_batched(host, args.cpu_seconds, res["joint"]["steps_per_s"], kappa)
     print(json.dumps(out), flush=True)
     ctx.close()
     return 0
@@ -686,7 +697,7 @@ def device_planned_ms(nb, torch, probs, mode, args, ctx, reset):
     descriptors in device memory, planned on the device each step: a planning
     launch plus the persistent launch), replayed from a graph."""
     reset()
-    shapes = [(V.shape[0], V.shape[1], W.shape[1]) for V, W, H, _ in probs]
+    shapes = [(V.shape[0], V.shape[1], W.shape[1], beta) for V, W, H, beta in probs]
     tiles = nb.get_batch_tiles(ctx)
     ctx = nb.Context(0)  # its own region: a captured region is never re-reserved
     nb.set_batch_tiles(tiles, ctx=ctx)
@@ -698,7 +709,7 @@ def device_planned_ms(nb, torch, probs, mode, args, ctx, reset):
     s = torch.cuda.Stream()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph, stream=s):
-        nb.step_batched(dp, mode, precision=args.precision, objectives=obj, stream=s, ctx=ctx)
+        nb.step_batched(dp, mode, precision=args.precision, kappa=args.kappa_batched, objectives=obj, stream=s, ctx=ctx)
     for _ in range(args.warmup):
         graph.replay()
     torch.cuda.synchronize()
@@ -783,7 +794,7 @@ def _timed_oracle(fn, budget_s, threads=None):
     return n, el, used
 
 
-def cpu_baseline_batched(host, budget_s, gpu_value):
+def cpu_baseline_batched(host, budget_s, gpu_value, kappa=0.0):
     """The FP64 oracle's joint iteration (objective + update + normalization) on a
     fixed random sample of 16 of the problems, timed with all host cores and with
     one thread (about budget_s / 2 seconds each), scaled to one iteration of the
@@ -799,8 +810,8 @@ def cpu_baseline_batched(host, budget_s, gpu_value):
 
     def sweep():
         for V, W, H, beta in sample:
-            oracle.objective(V, W, H, beta)
-            oracle.jmm_iteration(V, W, H, beta)
+            oracle.objective(V, W, H, beta, kappa=kappa)
+            oracle.jmm_iteration(V, W, H, beta, kappa=kappa)
 
     n_all, el_all, th_all = _timed_oracle(sweep, budget_s / 2)
     n_one, el_one, _ = _timed_oracle(sweep, budget_s / 2, threads=1)

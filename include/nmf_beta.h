@@ -412,16 +412,19 @@ nmf_status nmf_batch_info(nmf_batch_t batch, int64_t* work_items, int32_t* worke
 nmf_status nmf_batch_destroy(nmf_batch_t batch);
 
 /* Per-bucket tile counts.  A problem of a batch falls in bucket
- *   (K <= 32 ? 0 : 4) + (T <= 32 ? 0 : T <= 64 ? 1 : T <= 128 ? 2 : 3),
- *   T = max(ceil(F / 32), ceil(N / 32)),
+ *   6 (4 k + s) + c,
+ *   k = (K <= 32 ? 0 : 1),
+ *   s = (T <= 32 ? 0 : T <= 64 ? 1 : T <= 128 ? 2 : 3), T = max(ceil(F / 32), ceil(N / 32)),
+ *   c = the beta class: 0 general, 1 beta = 2, 2 beta = 1, 3 beta = 0, 4 beta = 1/2,
+ *       5 beta = 3/2 (the classes the kernels are compiled for),
  * and walks the tiles_per_item of its bucket.  The context holds one table
  * (128 in every bucket at creation), used by nmf_batch_create when
  * cfg->tiles_per_item is 0 and by every nmf_beta_step_batched. */
-#define NMF_BATCH_BUCKETS 8
+#define NMF_BATCH_BUCKETS 48
 
-/* Bucket of a problem of sizes F, N, K (host only); -1 if a size is out of
- * range (F, N < 1, K outside 1..64). */
-int32_t nmf_batch_bucket(int64_t F, int64_t N, int64_t K);
+/* Bucket of a problem of sizes F, N, K and divergence beta (host only); -1 if
+ * a size is out of range (F, N < 1, K outside 1..64) or beta is not finite. */
+int32_t nmf_batch_bucket(int64_t F, int64_t N, int64_t K, double beta);
 
 /* Sets (copies in) or reads (copies out) the context's table of
  * NMF_BATCH_BUCKETS tile counts, each in 1..4096 (else NMF_ERR_ARG).  Setting
@@ -473,9 +476,10 @@ nmf_status nmf_tune(nmf_ctx_t ctx, void* stream, const nmf_problem* problems, in
  * ------------------------------------------------------------------------- */
 
 /* Items per step and workspace bytes that `count` problems (host descriptors;
- * only the sizes are read) need in `mode` under `tiles` (host
+ * only the sizes and beta are read) need in `mode` under `tiles` (host
  * int32[NMF_BATCH_BUCKETS]; NULL: 128 in every bucket).  Host only, no GPU.
- * NMF_ERR_SHAPE / NMF_ERR_UNSUPPORTED for a size out of range (K > 64). */
+ * NMF_ERR_SHAPE / NMF_ERR_UNSUPPORTED for a size out of range (K > 64),
+ * NMF_ERR_BETA for a beta that is not finite. */
 nmf_status nmf_batch_requirements(const nmf_problem* problems, int32_t count, int32_t mode, const int32_t* tiles,
                                   int64_t* items, int64_t* workspace_bytes);
 

@@ -41,7 +41,7 @@ PATHS = {"auto": 0, "stream": 1, "fused": 2}
 FLAG_BARRIER = 4
 FLAG_RANGE = 8  # float16 mode: an operand outside the float16 range
 FLAG_SKIPPED = 16  # step_batched updated nothing (invalid descriptor, overlap, over capacity)
-BATCH_BUCKETS = 8
+BATCH_BUCKETS = 48
 MODES = {"alternating": ALTERNATING, "bmm": ALTERNATING, "joint": JOINT, "jmm": JOINT}
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16}
 # update exponent: gamma(beta) (the MM step) or 1 (the heuristic of Sec. 3.3.3)
@@ -144,7 +144,7 @@ def lib() -> ctypes.CDLL:
         L.nmf_batch_info.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_i64)]
         L.nmf_batch_destroy.argtypes = [_vp]
         PI = ctypes.POINTER(_i32)
-        L.nmf_batch_bucket.argtypes = [_i64, _i64, _i64]
+        L.nmf_batch_bucket.argtypes = [_i64, _i64, _i64, _dbl]
         L.nmf_batch_bucket.restype = _i32
         L.nmf_set_batch_tiles.argtypes = [_vp, PI]
         L.nmf_get_batch_tiles.argtypes = [_vp, PI]
@@ -650,16 +650,17 @@ class Batch:
             pass
 
 
-def batch_bucket(F: int, N: int, K: int) -> int:
-    """Tile-table bucket of a batched problem of sizes F, N, K (nmf_batch_bucket)."""
-    return int(lib().nmf_batch_bucket(int(F), int(N), int(K)))
+def batch_bucket(F: int, N: int, K: int, beta: float) -> int:
+    """Tile-table bucket of a batched problem of sizes F, N, K and divergence
+    beta (nmf_batch_bucket)."""
+    return int(lib().nmf_batch_bucket(int(F), int(N), int(K), float(beta)))
 
 
 def set_batch_tiles(tiles, ctx: Optional[Context] = None):
     """Sets the context's tiles per pass item of each bucket (nmf_set_batch_tiles)."""
-    arr = (_i32 * BATCH_BUCKETS)(*[int(t) for t in tiles])
     if len(tiles) != BATCH_BUCKETS:
         raise ValueError(f"{BATCH_BUCKETS} tile counts expected")
+    arr = (_i32 * BATCH_BUCKETS)(*[int(t) for t in tiles])
     _check(lib().nmf_set_batch_tiles(_ctx(ctx), arr), "nmf_set_batch_tiles")
 
 
@@ -688,11 +689,11 @@ def tune(problems, mode="joint", *, precision="fp32", kappa: float = 0.0, normal
 
 def batch_requirements(shapes, mode="joint", tiles=None):
     """(work items per step, workspace bytes) that problems of the given
-    (F, N, K) sizes need in a batch under ``tiles`` (None: 128 in every bucket).
-    Host only."""
+    (F, N, K, beta) sizes need in a batch under ``tiles`` (None: 128 in every
+    bucket).  Host only."""
     arr = (_Problem * len(shapes))()
-    for i, (F, N, K) in enumerate(shapes):
-        arr[i] = _Problem(int(F), int(N), int(K), None, 0, None, 0, None, 0, 1.0)
+    for i, (F, N, K, beta) in enumerate(shapes):
+        arr[i] = _Problem(int(F), int(N), int(K), None, 0, None, 0, None, 0, float(beta))
     t = (_i32 * BATCH_BUCKETS)(*[int(x) for x in tiles]) if tiles is not None else None
     n, b = _i64(), _i64()
     _check(lib().nmf_batch_requirements(arr, len(shapes), MODES[mode], t, ctypes.byref(n), ctypes.byref(b)),

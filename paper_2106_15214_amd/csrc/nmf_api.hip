@@ -1131,7 +1131,7 @@ nmf_status batch_create(nmf_ctx_s* c, const nmf_problem* pr, int count, int mode
   int64_t total = 0;
   for (int i = 0; i < count; ++i) {
     const nmf_problem& q = pr[i];
-    plans[i] = make_batch_plan(q.F, q.N, q.K, tiles[bucket_of(q.F, q.N, q.K)], joint);
+    plans[i] = make_batch_plan(q.F, q.N, q.K, tiles[bucket_of(q.F, q.N, q.K, q.beta)], joint);
     total += batch_items(plans[i], q.F);
   }
   if (total >= (int64_t)1 << 31) return NMF_ERR_UNSUPPORTED;
@@ -1210,31 +1210,38 @@ nmf_status batch_create(nmf_ctx_s* c, const nmf_problem* pr, int count, int mode
 }
 
 // ---- tuning cache: one text line per key ----
-//   nmf_tune 1 <arch> <compute units> <mode> <precision> <bucket mask> <tiles x 8> <ms>
+//   nmf_tune 2 <arch> <compute units> <mode> <precision> <bucket mask, hex> <tiles x NMF_BATCH_BUCKETS> <ms>
 struct TuneKey {
   char arch[64];
   int cus, mode, prec;
 };
 
 struct TuneEntry {
-  unsigned mask = 0;
+  uint64_t mask = 0;
   int tiles[kBatchBuckets] = {};
   double ms = 0.0;
 };
 
+constexpr int kTuneVersion = 2;
+
 bool parse_tune_line(const char* line, TuneKey* k, TuneEntry* e) {
-  int ver = 0;
-  int t[kBatchBuckets];
-  unsigned mask = 0;
-  double ms = 0.0;
-  const int n = sscanf(line, "nmf_tune %d %63s %d %d %d %x %d %d %d %d %d %d %d %d %lf", &ver, k->arch, &k->cus,
-                       &k->mode, &k->prec, &mask, &t[0], &t[1], &t[2], &t[3], &t[4], &t[5], &t[6], &t[7], &ms);
-  if (n != 7 + kBatchBuckets || ver != 1) return false;
-  for (int b = 0; b < kBatchBuckets; ++b)
-    if (t[b] < 1 || t[b] > 4096) return false;
-  e->mask = mask & ((1u << kBatchBuckets) - 1);
-  std::memcpy(e->tiles, t, sizeof(t));
-  e->ms = ms;
+  int ver = 0, used = 0;
+  unsigned long long mask = 0;
+  if (sscanf(line, "nmf_tune %d %63s %d %d %d %llx%n", &ver, k->arch, &k->cus, &k->mode, &k->prec, &mask, &used) != 6 ||
+      ver != kTuneVersion)
+    return false;
+  const char* p = line + used;
+  for (int b = 0; b < kBatchBuckets; ++b) {
+    char* end = nullptr;
+    const long t = std::strtol(p, &end, 10);
+    if (end == p || t < 1 || t > 4096) return false;
+    e->tiles[b] = (int)t;
+    p = end;
+  }
+  char* end = nullptr;
+  e->ms = std::strtod(p, &end);
+  if (end == p) return false;
+  e->mask = (uint64_t)mask & ((kBatchBuckets >= 64) ? ~0ull : ((1ull << kBatchBuckets) - 1));
   return true;
 }
 
@@ -1282,10 +1289,14 @@ nmf_status cache_store(const char* path, const TuneKey& key, const TuneEntry& e)
     TuneEntry old;
     if (!(parse_tune_line(l.c_str(), &k, &old) && same_key(k, key))) keep.push_back(l);
   }
-  char line[512];
-  std::snprintf(line, sizeof(line), "nmf_tune 1 %s %d %d %d 0x%02x %d %d %d %d %d %d %d %d %.6f", key.arch, key.cus,
-                key.mode, key.prec, e.mask, e.tiles[0], e.tiles[1], e.tiles[2], e.tiles[3], e.tiles[4], e.tiles[5],
-                e.tiles[6], e.tiles[7], e.ms);
+  std::string line = "nmf_tune " + std::to_string(kTuneVersion) + " " + key.arch + " " + std::to_string(key.cus) +
+                     " " + std::to_string(key.mode) + " " + std::to_string(key.prec);
+  char buf[64];
+  std::snprintf(buf, sizeof(buf), " 0x%012llx", (unsigned long long)e.mask);
+  line += buf;
+  for (int b = 0; b < kBatchBuckets; ++b) line += " " + std::to_string(e.tiles[b]);
+  std::snprintf(buf, sizeof(buf), " %.6f", e.ms);
+  line += buf;
   keep.push_back(line);
   const std::string tmp = std::string(path) + ".tmp." + std::to_string((long)getpid());
   FILE* f = std::fopen(tmp.c_str(), "w");
@@ -1368,9 +1379,9 @@ nmf_status nmf_batch_destroy(nmf_batch_t b) {
   return NMF_OK;
 }
 
-int32_t nmf_batch_bucket(int64_t F, int64_t N, int64_t K) {
-  if (F < 1 || N < 1 || K < 1 || K > 64) return -1;
-  return bucket_of(F, N, K);
+int32_t nmf_batch_bucket(int64_t F, int64_t N, int64_t K, double beta) {
+  if (F < 1 || N < 1 || K < 1 || K > 64 || !std::isfinite(beta)) return -1;
+  return bucket_of(F, N, K, beta);
 }
 
 nmf_status nmf_set_batch_tiles(nmf_ctx_t c, const int32_t* tiles) {
@@ -1402,7 +1413,8 @@ nmf_status nmf_batch_requirements(const nmf_problem* pr, int32_t count, int32_t 
     const nmf_problem& q = pr[i];
     if (q.F < 1 || q.N < 1 || q.K < 1 || q.F > INT32_MAX || q.N > INT32_MAX) return NMF_ERR_SHAPE;
     if (q.K > 64) return NMF_ERR_UNSUPPORTED;
-    const int b = bucket_of(q.F, q.N, q.K);
+    if (!std::isfinite(q.beta)) return NMF_ERR_BETA;
+    const int b = bucket_of(q.F, q.N, q.K, q.beta);
     const Plan p = make_batch_plan(q.F, q.N, q.K, tiles ? tiles[b] : kBatchTilesDefault, mode == NMF_JOINT);
     n += batch_items(p, q.F);
     bytes += (int64_t)align_up(p.total);
@@ -1560,13 +1572,13 @@ nmf_status nmf_tune(nmf_ctx_t c, void* stream, const nmf_problem* pr, int32_t co
     key.mode = mode;
     key.prec = o.precision;
   }
-  unsigned needed = 0;
-  for (int i = 0; i < count; ++i) needed |= 1u << bucket_of(pr[i].F, pr[i].N, pr[i].K);
+  uint64_t needed = 0;
+  for (int i = 0; i < count; ++i) needed |= 1ull << bucket_of(pr[i].F, pr[i].N, pr[i].K, pr[i].beta);
   TuneEntry cached;
   const bool have = cache_path && cache_lookup(cache_path, key, &cached);
   int table[kBatchBuckets];
   for (int b = 0; b < kBatchBuckets; ++b)
-    table[b] = have && (cached.mask >> b & 1u) ? cached.tiles[b] : c->batch_tiles[b];
+    table[b] = have && (cached.mask >> b & 1ull) ? cached.tiles[b] : c->batch_tiles[b];
   if (have && (needed & ~cached.mask) == 0) {
     for (int b = 0; b < kBatchBuckets; ++b) c->batch_tiles[b] = table[b];
     if ((st = upload_tiles(c)) != NMF_OK) return st;
@@ -1627,7 +1639,7 @@ nmf_status nmf_tune(nmf_ctx_t c, void* stream, const nmf_problem* pr, int32_t co
     std::vector<int> sig;
     for (int i = 0; i < count; ++i) {
       const nmf_problem& q = pr[i];
-      if (bucket_of(q.F, q.N, q.K) != b) continue;
+      if (bucket_of(q.F, q.N, q.K, q.beta) != b) continue;
       const Plan p = make_batch_plan(q.F, q.N, q.K, t, joint);
       sig.insert(sig.end(), {p.n_groups, p.tiles_n, p.f_groups, p.tiles_f});
     }
@@ -1639,9 +1651,9 @@ nmf_status nmf_tune(nmf_ctx_t c, void* stream, const nmf_problem* pr, int32_t co
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess || copy_all(true) != hipSuccess)
     st = NMF_ERR_HIP;
   if (st == NMF_OK) st = time_table(table, &best);
-  const unsigned todo = needed & ~(have ? cached.mask : 0u);
+  const uint64_t todo = needed & ~(have ? cached.mask : 0ull);
   for (int b = 0; st == NMF_OK && b < kBatchBuckets; ++b) {
-    if (!(todo >> b & 1u)) continue;
+    if (!(todo >> b & 1ull)) continue;
     std::vector<std::vector<int>> seen{split_of(b, table[b])};
     for (int cand : kCandidates) {
       std::vector<int> sig = split_of(b, cand);
@@ -1668,7 +1680,7 @@ nmf_status nmf_tune(nmf_ctx_t c, void* stream, const nmf_problem* pr, int32_t co
   if (ms_out) *ms_out = best;
   if (cache_path) {
     TuneEntry e;
-    e.mask = needed | (have ? cached.mask : 0u);
+    e.mask = needed | (have ? cached.mask : 0ull);
     std::memcpy(e.tiles, table, sizeof(table));
     e.ms = best;
     if ((st = cache_store(cache_path, key, e)) != NMF_OK) return st;

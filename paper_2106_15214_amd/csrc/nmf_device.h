@@ -50,18 +50,21 @@ __device__ __forceinline__ float pow_bm2(float lam, float bm2) {
 }
 
 // P = v lam^(beta-2), Q = lam^(beta-1) (v and lam include kappa), the two
-// element-wise terms of eqs. (alt_update) / (jnt_update).
+// element-wise terms of eqs. (alt_update) / (jnt_update).  P is exactly 0 where
+// v = 0: for beta < 2 the power of a small positive lam overflows float32
+// (lam^(-3/2) beyond the range below lam = 2e-26, lam^(-2) below 5e-20), and
+// 0 * inf would turn an entry whose value is 0 into a NaN.
 template <int BC>
 __device__ __forceinline__ void beta_terms(float v, float lam, float bm2, float& P, float& Q) {
   if (BC == BC_B2) { P = v; Q = lam; return; }
   if (BC == BC_B2G) { P = v; Q = 0.f; return; }  // Q H~^T comes from the Gram form
-  if (BC == BC_B1) { P = v * __builtin_amdgcn_rcpf(lam); Q = 1.f; return; }
-  if (BC == BC_B0) { float r = __builtin_amdgcn_rcpf(lam); Q = r; P = v * r * r; return; }
-  if (BC == BC_B05) { float s = __builtin_amdgcn_rsqf(lam); Q = s; P = v * (s * s * s); return; }
-  if (BC == BC_B15) { float s = __builtin_amdgcn_rsqf(lam); P = v * s; Q = lam * s; return; }
-  float e = __builtin_amdgcn_exp2f(bm2 * __builtin_amdgcn_logf(lam));
-  P = v * e;
-  Q = lam * e;
+  float e;
+  if (BC == BC_B1) { e = __builtin_amdgcn_rcpf(lam); Q = 1.f; }
+  else if (BC == BC_B0) { const float r = __builtin_amdgcn_rcpf(lam); Q = r; e = r * r; }
+  else if (BC == BC_B05) { const float s = __builtin_amdgcn_rsqf(lam); Q = s; e = s * s * s; }
+  else if (BC == BC_B15) { const float s = __builtin_amdgcn_rsqf(lam); e = s; Q = lam * s; }
+  else { e = __builtin_amdgcn_exp2f(bm2 * __builtin_amdgcn_logf(lam)); Q = lam * e; }
+  P = v != 0.f ? v * e : 0.f;
 }
 
 // General-beta term of eq. (beta-div) (out of line: three float64 pows).

@@ -201,16 +201,18 @@ NMF_PLAN_HD inline StepArgs make_step_args(const Plan& p, char* ws, unsigned* fl
   return sa;
 }
 
-// Per-bucket tile counts of batched problems: bucket (K block, size class),
-// the class by the larger of the problem's row and column tile counts (<= 32,
-// <= 64, <= 128, more).  The tile count only changes how a pass splits its
-// contraction into items, not the arithmetic, so beta does not enter.
+// Per-bucket tile counts of batched problems: bucket (K block, size class, beta
+// class), the size class by the larger of the problem's row and column tile
+// counts (<= 32, <= 64, <= 128, more).  The tile count changes how a pass
+// splits its contraction into items, not the arithmetic; the beta class sets
+// the cost of an item's element-wise work and so the best split.
+constexpr int kBatchBetaClasses = 6;  // BC_GEN .. BC_B15
 constexpr int kBatchBuckets = NMF_BATCH_BUCKETS;
-static_assert(kBatchBuckets == 8, "two K blocks x four size classes");
-NMF_PLAN_HD inline int bucket_of(int64_t F, int64_t N, int64_t K) {
+static_assert(kBatchBuckets == 2 * 4 * kBatchBetaClasses, "K blocks x size classes x beta classes");
+NMF_PLAN_HD inline int bucket_of(int64_t F, int64_t N, int64_t K, double beta) {
   const int64_t t = max64(cdiv(F, kTile), cdiv(N, kTile));
   const int cls = t <= 32 ? 0 : t <= 64 ? 1 : t <= 128 ? 2 : 3;
-  return (kblocks_for(K) - 1) * 4 + cls;
+  return ((kblocks_for(K) - 1) * 4 + cls) * kBatchBetaClasses + beta_class(beta);
 }
 
 // Update units and work items per phase of a problem in a batch: W-pass items

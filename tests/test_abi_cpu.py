@@ -115,25 +115,39 @@ def test_binding_rejects_host_tensors():
 # ---------------------------------------------------------------------------
 # batched step with device descriptors: host-only parts
 # ---------------------------------------------------------------------------
-def _bucket_from_rule(F, N, K):
+# beta classes of the bucket rule as the header numbers them
+_BETA_CLASS = {2.0: 1, 1.0: 2, 0.0: 3, 0.5: 4, 1.5: 5}
+
+
+def _bucket_from_rule(F, N, K, beta):
     """The bucket rule as the header states it."""
     T = max(-(-F // 32), -(-N // 32))
-    cls = 0 if T <= 32 else 1 if T <= 64 else 2 if T <= 128 else 3
-    return (0 if K <= 32 else 4) + cls
+    s = 0 if T <= 32 else 1 if T <= 64 else 2 if T <= 128 else 3
+    k = 0 if K <= 32 else 1
+    return 6 * (4 * k + s) + _BETA_CLASS.get(beta, 0)
 
 
 def test_batch_bucket_rule():
+    seen = set()
     for F, N, K in [(1, 1, 1), (1024, 1024, 32), (1025, 100, 32), (100, 2048, 33), (2049, 10, 64),
-                    (4096, 4096, 64), (4097, 1, 1), (128, 5000, 17), (1000, 200, 64), (20000, 10000, 50)]:
-        assert nb.batch_bucket(F, N, K) == _bucket_from_rule(F, N, K), (F, N, K)
-    for F, N, K in [(0, 5, 5), (5, 0, 5), (5, 5, 0), (5, 5, 65)]:
-        assert nb.batch_bucket(F, N, K) == -1
+                    (4096, 4096, 64), (4097, 1, 1), (128, 5000, 17), (1000, 200, 64), (20000, 10000, 50),
+                    (3000, 100, 10)]:
+        for beta in (0.0, 0.5, 1.0, 1.5, 2.0, -0.5, 1.2, 2.5):
+            b = nb.batch_bucket(F, N, K, beta)
+            assert b == _bucket_from_rule(F, N, K, beta), (F, N, K, beta)
+            seen.add(b)
+    assert seen <= set(range(nb.BATCH_BUCKETS)) and len(seen) == nb.BATCH_BUCKETS
+    for F, N, K, beta in [(0, 5, 5, 1.0), (5, 0, 5, 1.0), (5, 5, 0, 1.0), (5, 5, 65, 1.0), (5, 5, 5, float("nan")),
+                          (5, 5, 5, float("inf"))]:
+        assert nb.batch_bucket(F, N, K, beta) == -1
 
 
 def _shapes(n, seed=3):
     import numpy as np
     rng = np.random.default_rng(seed)
-    return [(int(rng.integers(128, 1026)), int(rng.integers(200, 5001)), int(rng.integers(8, 65))) for _ in range(n)]
+    betas = (0.0, 0.5, 1.0, 1.5, 2.0)
+    return [(int(rng.integers(128, 1026)), int(rng.integers(200, 5001)), int(rng.integers(8, 65)),
+             betas[int(rng.integers(0, 5))]) for _ in range(n)]
 
 
 def test_batch_requirements_invariants():
@@ -145,30 +159,41 @@ def test_batch_requirements_invariants():
     i2, b2 = nb.batch_requirements(shapes[17:], "joint")
     assert (i1 + i2, b1 + b2) == (items, bytes_)
     # the default table is 128 in every bucket
-    assert nb.batch_requirements(shapes, "joint", [128] * 8) == (items, bytes_)
+    assert nb.batch_requirements(shapes, "joint", [128] * 48) == (items, bytes_)
+    # a table changed in one bucket changes the plans of that bucket's problems only
+    b0 = _bucket_from_rule(*shapes[0])
+    t = [128] * 48
+    t[b0] = 4
+    for sh in shapes:
+        changed = nb.batch_requirements([sh], "joint", t) != nb.batch_requirements([sh], "joint")
+        assert not changed or _bucket_from_rule(*sh) == b0, sh
+    assert nb.batch_requirements(shapes[:1], "joint", t)[0] > nb.batch_requirements(shapes[:1], "joint")[0]
     # joint keeps P and Q per problem: more workspace, the same items
     ia, ba = nb.batch_requirements(shapes, "alternating")
     assert ia == items and ba < bytes_
     # fewer tiles per item: more items, never fewer bytes
-    it, bt = nb.batch_requirements(shapes, "joint", [8] * 8)
+    it, bt = nb.batch_requirements(shapes, "joint", [8] * 48)
     assert it > items and bt >= bytes_
     # a single problem: items are whole row / column blocks of 128 per pass
     (F, N, K) = (1000, 3000, 20)
-    i, _ = nb.batch_requirements([(F, N, K)], "joint", [4096] * 8)
+    i, _ = nb.batch_requirements([(F, N, K, 1.0)], "joint", [4096] * 48)
     rb, cb = -(-F // 128), -(-N // 128)
     assert i >= rb + cb and i <= rb + cb + F + N
 
 
 def test_batch_requirements_checks():
     with pytest.raises(nb.NmfError) as e:
-        nb.batch_requirements([(10, 10, 65)])
+        nb.batch_requirements([(10, 10, 65, 1.0)])
     assert e.value.status == E_UNSUP
     with pytest.raises(nb.NmfError) as e:
-        nb.batch_requirements([(0, 10, 5)])
+        nb.batch_requirements([(0, 10, 5, 1.0)])
     assert e.value.status == E_SHAPE
     with pytest.raises(nb.NmfError) as e:
-        nb.batch_requirements([(10, 10, 5)], "joint", [0] * 8)
+        nb.batch_requirements([(10, 10, 5, 1.0)], "joint", [0] * 48)
     assert e.value.status == E_ARG
+    with pytest.raises(nb.NmfError) as e:
+        nb.batch_requirements([(10, 10, 5, float("nan"))])
+    assert e.value.status == E_BETA
     L = nb.lib()
     n, b = ctypes.c_int64(), ctypes.c_int64()
     assert L.nmf_batch_requirements(None, 1, 1, None, ctypes.byref(n), ctypes.byref(b)) == E_NULL
@@ -179,7 +204,7 @@ def test_batch_requirements_checks():
 
 def test_batched_entry_points_null_context():
     L = nb.lib()
-    t = (ctypes.c_int32 * 8)()
+    t = (ctypes.c_int32 * nb.BATCH_BUCKETS)()
     assert L.nmf_reserve_batched(None, 1, 1, 1) == E_NULL
     assert L.nmf_beta_step_batched(None, None, 1, 1, 1, None, None, None) == E_NULL
     assert L.nmf_set_batch_tiles(None, t) == E_NULL

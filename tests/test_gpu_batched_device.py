@@ -58,7 +58,7 @@ def reserve_for(ctx, shapes, mode, slots=None):
 
 
 def shapes_of(probs):
-    return [(V.shape[0], V.shape[1], W.shape[1]) for V, W, H, _ in probs]
+    return [(V.shape[0], V.shape[1], W.shape[1], beta) for V, W, H, beta in probs]
 
 
 def bits(t):
@@ -276,7 +276,7 @@ def test_tile_table_changes_plans_not_results():
     probs = make_set([(1100, 2100, 40, 1.0), (700, 4500, 12, 0.5), (300, 97, 33, 0.0)], seed0=2800)
     a, b = to_dev(probs), to_dev(probs)
     ctx = nb.Context(0)
-    tiles = [4, 8, 16, 32, 8, 16, 4, 64]
+    tiles = [(4, 8, 16, 32, 64, 128)[b % 6] for b in range(nb.BATCH_BUCKETS)]
     nb.set_batch_tiles(tiles, ctx=ctx)
     assert nb.get_batch_tiles(ctx) == tiles
     reserve_for(ctx, shapes_of(probs), "joint")
@@ -290,16 +290,18 @@ def test_tile_table_changes_plans_not_results():
     host.close()
     for (V, W, H, beta), (_, Wd, Hd, _) in zip(probs, a):
         Wr, Hr = O.jmm_iteration(V.astype(np.float64), W.astype(np.float64), H.astype(np.float64), beta)
-        check_pair(Wd.cpu().numpy(), Hd.cpu().numpy(), Wr, Hr, tag=f"table {tiles}")
+        check_pair(Wd.cpu().numpy(), Hd.cpu().numpy(), Wr, Hr, tag=f"custom table, beta={beta}")
     with pytest.raises(nb.NmfError):
-        nb.set_batch_tiles([0] * 8, ctx=ctx)
+        nb.set_batch_tiles([0] * nb.BATCH_BUCKETS, ctx=ctx)
+    with pytest.raises(ValueError):
+        nb.set_batch_tiles([128] * 8, ctx=ctx)
     ctx.close()
 
 
 def test_tune_writes_and_reads_its_cache(tmp_path):
     probs = to_dev(make_set(WELL_POSED, seed0=2900))
     before = [(W.clone(), H.clone()) for _, W, H, _ in probs]
-    buckets = {nb.batch_bucket(V.shape[0], V.shape[1], W.shape[1]) for V, W, H, _ in probs}
+    buckets = {nb.batch_bucket(V.shape[0], V.shape[1], W.shape[1], beta) for V, W, H, beta in probs}
     assert len(buckets) >= 2
     cache = str(tmp_path / "tiles.txt")
     with open(cache, "w") as f:
@@ -315,10 +317,10 @@ def test_tune_writes_and_reads_its_cache(tmp_path):
     lines = open(cache).read().splitlines()
     assert lines[0] == "a line of another tool"
     entries = [l.split() for l in lines if l.startswith("nmf_tune ")]
-    assert len(entries) == 1 and entries[0][1] == "1"
+    assert len(entries) == 1 and entries[0][1] == "2"
     mask = int(entries[0][6], 16)
     assert mask == sum(1 << b for b in buckets)
-    assert [int(x) for x in entries[0][7:15]] == tiles
+    assert [int(x) for x in entries[0][7:7 + nb.BATCH_BUCKETS]] == tiles
     # a second context reads the entry and measures nothing
     ctx2 = nb.Context(0)
     tiles2, ms2, hit2 = nb.tune(probs, "joint", iters=1, cache=cache, ctx=ctx2)
@@ -333,7 +335,7 @@ def test_tune_writes_and_reads_its_cache(tmp_path):
     # a problem in a bucket the entry does not cover: that bucket is tuned, the
     # others keep the cached tiles
     extra = to_dev(make_set([(5000, 300, 60, 1.0)], seed0=2950))
-    b_extra = nb.batch_bucket(5000, 300, 60)
+    b_extra = nb.batch_bucket(5000, 300, 60, 1.0)
     assert b_extra not in buckets
     tiles4, _, hit4 = nb.tune(probs + extra, "joint", iters=1, cache=cache, ctx=ctx2)
     assert not hit4
