@@ -239,3 +239,60 @@ def test_batched_rejects_aliasing_and_large_k():
     p = synth.random_positive(40, 50, 65, seed=3)
     with pytest.raises(nb.NmfError):
         nb.Batch([(dev(p.V), dev(p.W), dev(p.H), 1.0)], "joint", ctx=ctx())
+
+
+def test_long_trajectory_kappa_reading():
+    """Problem 152 of the batched workload (569 x 369, K = 8, beta = 0.5, Poisson V
+    with about 40 % zeros): at kappa = 0 the iterates drive entries of WH to zero
+    at the zeros of V until an update ratio is undefined, on the GPU and in the
+    float64 oracle alike, near the same iteration; at kappa = 1e-9 (Sec. 4.1.3)
+    both run 200 iterations with a non-increasing objective, and the GPU's
+    objective trace follows the oracle's."""
+    spec = synth.batched_specs(512)[152]
+    q = synth.make_batched_problem(spec)
+    assert spec["beta"] == 0.5 and np.mean(q.V == 0) > 0.3
+    V64 = q.V.astype(np.float64)
+    T = 200
+
+    def oracle_run(kappa):
+        W, H = q.W.astype(np.float64), q.H.astype(np.float64)
+        trace = [O.objective(V64, W, H, 0.5, kappa=kappa)]
+        for t in range(T):
+            try:
+                W, H = O.jmm_iteration(V64, W, H, 0.5, kappa=kappa)
+            except FloatingPointError:
+                return trace, t
+            trace.append(O.objective(V64, W, H, 0.5, kappa=kappa))
+        return trace, None
+
+    def gpu_run(kappa):
+        V, W, H = dev(q.V), dev(q.W), dev(q.H)
+        b = nb.Batch([(V, W, H, 0.5)], "joint", kappa=kappa, ctx=ctx())
+        tr = torch.zeros((T + 1, 1), dtype=torch.float64, device=DEV)
+        first_flag = None
+        for t in range(T + 1):
+            b.step(objectives=tr[t])
+            if first_flag is None and t % 5 == 4 and b.flags(clear=True):
+                first_flag = t
+        b.close()
+        torch.cuda.synchronize()
+        return tr[:, 0].cpu().numpy(), first_flag
+
+    print("[batched] long trajectory, kappa = 0", flush=True)
+    _, o_fail = oracle_run(0.0)
+    g_trace, g_flag = gpu_run(0.0)
+    assert o_fail is not None and g_flag is not None, (o_fail, g_flag)
+    # the same breakdown near the same iteration (flags are polled every 5 steps)
+    assert abs(g_flag - o_fail) <= 25, (g_flag, o_fail)
+
+    print("[batched] long trajectory, kappa = 1e-9", flush=True)
+    o_trace, o_fail = oracle_run(1e-9)
+    g_trace, g_flag = gpu_run(1e-9)
+    assert o_fail is None and g_flag is None, (o_fail, g_flag)
+    g = g_trace[:T + 1]  # objective of iterates 0..T (the step at t reports iterate t)
+    assert np.all(np.isfinite(g))
+    assert np.all(np.diff(g) <= 1e-6 * g[1:]), "objective increased"
+    o = np.asarray(o_trace)
+    rel_dev = np.abs(g - o) / o
+    print(f"[batched] trajectory deviation from the oracle: max {rel_dev.max():.2e}", flush=True)
+    assert rel_dev.max() <= 1e-4
