@@ -650,7 +650,6 @@ GradParts grad_passes(nmf_ctx_s* c, hipStream_t s, const Plan& p, int64_t F, int
   ra.pnum = (float*)(ws + p.o_pnum); ra.pobj = (double*)(ws + p.o_pobj);
   ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
   ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
-  ra.vstream = stream_v(F, N);
   GradParts g{hipSuccess, ra.pnum, (float*)(ws + p.o_pnumh), ra.pobj, p.row_blocks * p.n_groups};
   g.e = launch_sweep_rows(bc, p.KB, KIND_GRAD, want_obj, false, g.sw_grid, s, ra);
   if (g.e != hipSuccess) return g;
@@ -807,7 +806,6 @@ nmf_status nmf_beta_objective(nmf_ctx_t c, void* stream, int64_t F, int64_t N, i
   ra.pobj = (double*)(c->ws + p.o_pobj);
   ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
   ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
-  ra.vstream = stream_v(F, N);
   const int grid = p.row_blocks * p.n_groups;
   hipError_t e = launch_sweep_rows(beta_class(beta), p.KB, KIND_OBJ, true, false, grid, s, ra);
   if (e != hipSuccess) return NMF_ERR_HIP;
@@ -905,7 +903,6 @@ nmf_status nmf_beta_run(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t
   ra.pobj = (double*)(c->ws + p.o_pobj);
   ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
   ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
-  ra.vstream = stream_v(F, N);
   ra.halt = run.halt;
   const int grid = p.row_blocks * p.n_groups;
   hipError_t e = launch_sweep_rows(beta_class(beta), p.KB, KIND_OBJ, true, false, grid, s, ra);
@@ -1157,8 +1154,7 @@ nmf_status batch_create(nmf_ctx_s* c, const nmf_problem* pr, int count, int mode
   char* mem = b->mem;
   unsigned* flags = (unsigned*)mem;
 
-  // descriptors (V is loaded with the nontemporal hint by the size rule of each
-  // problem: the hint measured no gain on a batch of cache-sized problems)
+  // descriptors
   std::vector<BatchProblem> desc(count);
   for (int i = 0; i < count; ++i) desc[i] = make_batch_problem(plans[i], mem + base[i], flags, pr[i], joint, o);
   // queue, larger problems first: phase-major (lag 0), or pipelined with phase q

@@ -115,22 +115,6 @@ __device__ __forceinline__ float ldc(const float* __restrict__ p, int64_t idx, b
 __device__ __forceinline__ float4 ldc4(const float* __restrict__ p, int64_t idx, bool ok) {
   return *reinterpret_cast<const float4*>(p + (ok ? idx : 0));
 }
-// V as streamed by the W pass when it is larger than the last-level cache: every
-// entry is read once per pass, so the loads carry the nontemporal hint and the
-// F x N stream does not evict from the cache what the pass reuses (the H~ tiles
-// every workgroup stages, the W~ rows).  Measured on the 20000 x 10000 count
-// workload: W pass 917 -> 762 us.  A V that fits in the cache is loaded without
-// the hint: it is read again by the H pass (beta = 2) and the next iteration,
-// and the hint slowed the 361 x 2429 W pass from 15 to 18 us.  Same selection
-// of the address as ldc / ldc4.
-typedef float f32x4v __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ float ldc_nt(const float* __restrict__ p, int64_t idx, bool ok) {
-  return __builtin_nontemporal_load(p + (ok ? idx : 0));
-}
-__device__ __forceinline__ float4 ldc4_nt(const float* __restrict__ p, int64_t idx, bool ok) {
-  const f32x4v y = __builtin_nontemporal_load(reinterpret_cast<const f32x4v*>(p + (ok ? idx : 0)));
-  return make_float4(y[0], y[1], y[2], y[3]);
-}
 
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
@@ -432,13 +416,13 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
     for (int q = 0; q < 4; ++q) {
       const int nb = n0 + 8 * q + 4 * hi;
       if (full) {
-        const float4 x = a.vstream ? ldc4_nt(a.V, vrow + nb, frow_ok) : ldc4(a.V, vrow + nb, frow_ok);
+        const float4 x = ldc4(a.V, vrow + nb, frow_ok);
         v[4 * q + 0] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
       } else {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const bool ok = frow_ok && nb + j < N;
-          v[4 * q + j] = a.vstream ? ldc_nt(a.V, vrow + nb + j, ok) : ldc(a.V, vrow + nb + j, ok);
+          v[4 * q + j] = ldc(a.V, vrow + nb + j, ok);
         }
       }
     }
@@ -915,13 +899,13 @@ __device__ __forceinline__ void rows_item_lp(const SweepRowsArgs& a, int item, f
     for (int q = 0; q < 4; ++q) {
       const int nb = n0 + 8 * q + 4 * hi;
       if (full) {
-        const float4 x = a.vstream ? ldc4_nt(a.V, vrow + nb, frow_ok) : ldc4(a.V, vrow + nb, frow_ok);
+        const float4 x = ldc4(a.V, vrow + nb, frow_ok);
         v[4 * q + 0] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
       } else {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const bool ok = frow_ok && nb + j < N;
-          v[4 * q + j] = a.vstream ? ldc_nt(a.V, vrow + nb + j, ok) : ldc(a.V, vrow + nb + j, ok);
+          v[4 * q + j] = ldc(a.V, vrow + nb + j, ok);
         }
       }
     }

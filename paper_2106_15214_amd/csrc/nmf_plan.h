@@ -81,11 +81,6 @@ NMF_PLAN_HD inline Plan layout(const Sizes& z, Plan p) {
   return p;
 }
 
-// V (bytes) above which the W pass loads it with the nontemporal hint: a V this
-// large does not stay in the 256 MB last-level cache between passes anyway.
-constexpr int64_t kStreamVBytes = int64_t(128) << 20;
-NMF_PLAN_HD inline int stream_v(int64_t F, int64_t N) { return F * N * (int64_t)sizeof(float) > kStreamVBytes; }
-
 // `cols_occ`: workgroups per CU of the streaming column pass.  `fused_grid` > 0
 // plans the single-launch path with that many workgroups.
 // Column-partial split, transposed leading dimension and workspace offsets of
@@ -161,7 +156,6 @@ NMF_PLAN_HD inline StepArgs make_step_args(const Plan& p, char* ws, unsigned* fl
   ra.pobj = (double*)(ws + p.o_pobj);
   ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
   ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
-  ra.vstream = stream_v(F, N);
   ra.flags = flags;
   sa.sw_grid = p.row_blocks * p.n_groups;
 

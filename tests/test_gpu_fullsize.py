@@ -2,8 +2,8 @@
 
 * The 20000 x 10000 (K = 50, beta = 1) count workload: one outer iteration on
   the whole matrix, every entry of W and H compared entry-wise (and in
-  Frobenius norm), and the objective and gradient calls.  This is the size at which the W pass streams V with the
-  nontemporal hint (V is 800 MB), the launch configuration the benchmark times.
+  Frobenius norm), and the objective and gradient calls, in the launch
+  configuration the benchmark times (V is 800 MB, larger than the cache).
 * A joint step just above 2^28 entries of V (16449 x 16353, ragged edges,
   beta = 0.5): beyond that size the joint step does not keep the P and Q tiles,
   and its H pass forms Lambda~ and its powers again from V, W~, H~.  Float32
