@@ -650,6 +650,7 @@ GradParts grad_passes(nmf_ctx_s* c, hipStream_t s, const Plan& p, int64_t F, int
   ra.pnum = (float*)(ws + p.o_pnum); ra.pobj = (double*)(ws + p.o_pobj);
   ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
   ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
+  ra.vstream = 0;
   GradParts g{hipSuccess, ra.pnum, (float*)(ws + p.o_pnumh), ra.pobj, p.row_blocks * p.n_groups};
   g.e = launch_sweep_rows(bc, p.KB, KIND_GRAD, want_obj, false, g.sw_grid, s, ra);
   if (g.e != hipSuccess) return g;
@@ -806,6 +807,7 @@ nmf_status nmf_beta_objective(nmf_ctx_t c, void* stream, int64_t F, int64_t N, i
   ra.pobj = (double*)(c->ws + p.o_pobj);
   ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
   ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
+  ra.vstream = 0;
   const int grid = p.row_blocks * p.n_groups;
   hipError_t e = launch_sweep_rows(beta_class(beta), p.KB, KIND_OBJ, true, false, grid, s, ra);
   if (e != hipSuccess) return NMF_ERR_HIP;
@@ -903,6 +905,7 @@ nmf_status nmf_beta_run(nmf_ctx_t c, void* stream, int64_t F, int64_t N, int64_t
   ra.pobj = (double*)(c->ws + p.o_pobj);
   ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
   ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
+  ra.vstream = 0;
   ra.halt = run.halt;
   const int grid = p.row_blocks * p.n_groups;
   hipError_t e = launch_sweep_rows(beta_class(beta), p.KB, KIND_OBJ, true, false, grid, s, ra);

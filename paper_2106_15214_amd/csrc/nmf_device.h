@@ -116,6 +116,23 @@ __device__ __forceinline__ float4 ldc4(const float* __restrict__ p, int64_t idx,
   return *reinterpret_cast<const float4*>(p + (ok ? idx : 0));
 }
 
+// V loads of the W pass with the nontemporal hint, selected per launch by
+// SweepRowsArgs::vstream (same selection of the address as ldc / ldc4).  The
+// launch plans leave it off: on the 20000 x 10000 count workload the hinted
+// 32-byte pieces of a row's 128-byte segment re-fetch lines (1.4 GB for 0.8 GB
+// of V) and the W pass took 760 us (FP32) and 525 us (BF16) against 737 and
+// 481 us with ordinary loads.  The per-launch choice itself stays: the tile
+// loop compiled without it (ordinary loads only) measured slower still, 804
+// and 551 us, from a different placement of the next tile's loads.
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float ldc_nt(const float* __restrict__ p, int64_t idx, bool ok) {
+  return __builtin_nontemporal_load(p + (ok ? idx : 0));
+}
+__device__ __forceinline__ float4 ldc4_nt(const float* __restrict__ p, int64_t idx, bool ok) {
+  const f32x4v y = __builtin_nontemporal_load(reinterpret_cast<const f32x4v*>(p + (ok ? idx : 0)));
+  return make_float4(y[0], y[1], y[2], y[3]);
+}
+
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
@@ -416,13 +433,13 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
     for (int q = 0; q < 4; ++q) {
       const int nb = n0 + 8 * q + 4 * hi;
       if (full) {
-        const float4 x = ldc4(a.V, vrow + nb, frow_ok);
+        const float4 x = a.vstream ? ldc4_nt(a.V, vrow + nb, frow_ok) : ldc4(a.V, vrow + nb, frow_ok);
         v[4 * q + 0] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
       } else {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const bool ok = frow_ok && nb + j < N;
-          v[4 * q + j] = ldc(a.V, vrow + nb + j, ok);
+          v[4 * q + j] = a.vstream ? ldc_nt(a.V, vrow + nb + j, ok) : ldc(a.V, vrow + nb + j, ok);
         }
       }
     }
@@ -899,13 +916,13 @@ __device__ __forceinline__ void rows_item_lp(const SweepRowsArgs& a, int item, f
     for (int q = 0; q < 4; ++q) {
       const int nb = n0 + 8 * q + 4 * hi;
       if (full) {
-        const float4 x = ldc4(a.V, vrow + nb, frow_ok);
+        const float4 x = a.vstream ? ldc4_nt(a.V, vrow + nb, frow_ok) : ldc4(a.V, vrow + nb, frow_ok);
         v[4 * q + 0] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
       } else {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const bool ok = frow_ok && nb + j < N;
-          v[4 * q + j] = ldc(a.V, vrow + nb + j, ok);
+          v[4 * q + j] = a.vstream ? ldc_nt(a.V, vrow + nb + j, ok) : ldc(a.V, vrow + nb + j, ok);
         }
       }
     }

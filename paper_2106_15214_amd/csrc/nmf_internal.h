@@ -63,6 +63,7 @@ struct SweepRowsArgs {
   double* pobj;                    // [grid] objective partials (nullable)
   int vec4;                        // V rows 16-byte aligned
   int hvec;                        // H rows 16-byte aligned
+  int vstream;                     // V loads with the nontemporal hint (load policy; 0 by default)
   unsigned* flags;                 // status word (float16 range check)
   float* Pst; float* Qst; int NT;  // P, Q tiles [row tile * NT + column tile][32 n][32 f] (fused joint pass)
   const unsigned* halt;            // nullable: the launch does nothing when *halt != 0 (stopped run)

@@ -156,6 +156,7 @@ NMF_PLAN_HD inline StepArgs make_step_args(const Plan& p, char* ws, unsigned* fl
   ra.pobj = (double*)(ws + p.o_pobj);
   ra.vec4 = ((uintptr_t)V % 16 == 0) && (ldv % 4 == 0);
   ra.hvec = ((uintptr_t)H % 16 == 0) && (ldh % 4 == 0);
+  ra.vstream = 0;  // ordinary V loads (see ldc_nt)
   ra.flags = flags;
   sa.sw_grid = p.row_blocks * p.n_groups;
 
