@@ -701,7 +701,7 @@ def device_planned_ms(nb, torch, probs, mode, args, ctx, reset):
     tiles = nb.get_batch_tiles(ctx)
     ctx = nb.Context(0)  # its own region: a captured region is never re-reserved
     nb.set_batch_tiles(tiles, ctx=ctx)
-    items, nbytes = nb.batch_requirements(shapes, mode, tiles)
+    items, nbytes = nb.batch_requirements(shapes, mode, tiles, args.precision)
     nb.reserve_batched(len(probs), items, nbytes, ctx=ctx)
     dp = nb.DeviceProblems(len(probs))
     dp.set(probs)

@@ -476,12 +476,16 @@ nmf_status nmf_tune(nmf_ctx_t ctx, void* stream, const nmf_problem* problems, in
  * ------------------------------------------------------------------------- */
 
 /* Items per step and workspace bytes that `count` problems (host descriptors;
- * only the sizes and beta are read) need in `mode` under `tiles` (host
- * int32[NMF_BATCH_BUCKETS]; NULL: 128 in every bucket).  Host only, no GPU.
- * NMF_ERR_SHAPE / NMF_ERR_UNSUPPORTED for a size out of range (K > 64),
- * NMF_ERR_BETA for a beta that is not finite. */
-nmf_status nmf_batch_requirements(const nmf_problem* problems, int32_t count, int32_t mode, const int32_t* tiles,
-                                  int64_t* items, int64_t* workspace_bytes);
+ * only the sizes and beta are read) need in `mode` and `precision`
+ * (NMF_FP32 / NMF_BF16 / NMF_FP16) under `tiles` (host
+ * int32[NMF_BATCH_BUCKETS]; NULL: 128 in every bucket).  The item count is the
+ * batch's exact one: in float32 a problem whose rows take one column group has
+ * its W update applied by its W-pass items and no W-update items.  Host only,
+ * no GPU.  NMF_ERR_ARG for a bad mode, precision or table, NMF_ERR_SHAPE /
+ * NMF_ERR_UNSUPPORTED for a size out of range (K > 64), NMF_ERR_BETA for a
+ * beta that is not finite. */
+nmf_status nmf_batch_requirements(const nmf_problem* problems, int32_t count, int32_t mode, int32_t precision,
+                                  const int32_t* tiles, int64_t* items, int64_t* workspace_bytes);
 
 /* Allocates the context's batched region (blocking; frees a previous one):
  * max_problems descriptors (>= 1), max_items work items per step (1 .. 2^31 - 1)

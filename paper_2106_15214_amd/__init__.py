@@ -150,7 +150,7 @@ def lib() -> ctypes.CDLL:
         L.nmf_get_batch_tiles.argtypes = [_vp, PI]
         L.nmf_tune.argtypes = [_vp, _vp, PP, _i32, _i32, ctypes.POINTER(_Opts), _i32, ctypes.c_char_p, PI,
                                ctypes.POINTER(_dbl), PI]
-        L.nmf_batch_requirements.argtypes = [PP, _i32, _i32, PI, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
+        L.nmf_batch_requirements.argtypes = [PP, _i32, _i32, _i32, PI, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
         L.nmf_reserve_batched.argtypes = [_vp, _i32, _i64, _i64]
         L.nmf_beta_step_batched.argtypes = [_vp, _vp, _i32, _vp, _i32, ctypes.POINTER(_Opts), _vp, _vp]
         for name in ("nmf_create", "nmf_destroy", "nmf_reserve", "nmf_check_step_args", "nmf_beta_step",
@@ -687,16 +687,17 @@ def tune(problems, mode="joint", *, precision="fp32", kappa: float = 0.0, normal
     return list(tiles), ms.value, bool(hit.value)
 
 
-def batch_requirements(shapes, mode="joint", tiles=None):
+def batch_requirements(shapes, mode="joint", tiles=None, precision="fp32"):
     """(work items per step, workspace bytes) that problems of the given
-    (F, N, K, beta) sizes need in a batch under ``tiles`` (None: 128 in every
-    bucket).  Host only."""
+    (F, N, K, beta) sizes need in a batch in ``mode`` and ``precision`` under
+    ``tiles`` (None: 128 in every bucket).  Host only."""
     arr = (_Problem * len(shapes))()
     for i, (F, N, K, beta) in enumerate(shapes):
         arr[i] = _Problem(int(F), int(N), int(K), None, 0, None, 0, None, 0, float(beta))
     t = (_i32 * BATCH_BUCKETS)(*[int(x) for x in tiles]) if tiles is not None else None
     n, b = _i64(), _i64()
-    _check(lib().nmf_batch_requirements(arr, len(shapes), MODES[mode], t, ctypes.byref(n), ctypes.byref(b)),
+    _check(lib().nmf_batch_requirements(arr, len(shapes), MODES[mode], PRECISIONS[precision], t, ctypes.byref(n),
+                                        ctypes.byref(b)),
            "nmf_batch_requirements")
     return n.value, b.value
 

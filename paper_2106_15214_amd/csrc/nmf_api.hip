@@ -1132,7 +1132,7 @@ nmf_status batch_create(nmf_ctx_s* c, const nmf_problem* pr, int count, int mode
   for (int i = 0; i < count; ++i) {
     const nmf_problem& q = pr[i];
     plans[i] = make_batch_plan(q.F, q.N, q.K, tiles[bucket_of(q.F, q.N, q.K, q.beta)], joint);
-    total += batch_items(plans[i], q.F);
+    total += batch_items(plans[i], q.F, batch_w_fused(plans[i], o.precision));
   }
   if (total >= (int64_t)1 << 31) return NMF_ERR_UNSUPPORTED;
   const size_t o_list = off;
@@ -1397,13 +1397,14 @@ nmf_status nmf_get_batch_tiles(nmf_ctx_t c, int32_t* tiles) {
   return NMF_OK;
 }
 
-nmf_status nmf_batch_requirements(const nmf_problem* pr, int32_t count, int32_t mode, const int32_t* tiles,
-                                  int64_t* items, int64_t* workspace_bytes) {
+nmf_status nmf_batch_requirements(const nmf_problem* pr, int32_t count, int32_t mode, int32_t precision,
+                                  const int32_t* tiles, int64_t* items, int64_t* workspace_bytes) {
   if (!pr || !items || !workspace_bytes) return NMF_ERR_NULL;
   *items = 0;
   *workspace_bytes = 0;
   if (count < 1) return NMF_ERR_ARG;
   if (mode != NMF_ALTERNATING && mode != NMF_JOINT) return NMF_ERR_ARG;
+  if (precision != NMF_FP32 && precision != NMF_BF16 && precision != NMF_FP16) return NMF_ERR_ARG;
   if (tiles)
     for (int b = 0; b < kBatchBuckets; ++b)
       if (tiles[b] < 1 || tiles[b] > 4096) return NMF_ERR_ARG;
@@ -1415,7 +1416,7 @@ nmf_status nmf_batch_requirements(const nmf_problem* pr, int32_t count, int32_t 
     if (!std::isfinite(q.beta)) return NMF_ERR_BETA;
     const int b = bucket_of(q.F, q.N, q.K, q.beta);
     const Plan p = make_batch_plan(q.F, q.N, q.K, tiles ? tiles[b] : kBatchTilesDefault, mode == NMF_JOINT);
-    n += batch_items(p, q.F);
+    n += batch_items(p, q.F, batch_w_fused(p, precision));
     bytes += (int64_t)align_up(p.total);
   }
   *items = n;

@@ -4,12 +4,14 @@
 //   W-pass items  (rows items: Lambda~ tiles, P, Q, W-step partials, objective;
 //                  in joint mode P and Q are kept for the H pass)
 //   W-update items (partials reduced, W_new, chi terms; 64 rows each, all loads
-//                  in flight together)
+//                  in flight together); none for a float32 problem whose W-pass
+//                  items each cover whole rows: those apply the update themselves
 //   H-pass items  (cols items: H-step partials from the kept P, Q in joint mode,
 //                  column sums of W_new)
 //   H-update units (H_new, normalization, W write-back, objective total)
 // A per-problem counter of finished items per phase replaces grid barriers: an
-// item of phase q waits until its problem's phase q - 1 is complete.  Every
+// item of phase q waits until its problem's nearest earlier phase with items is
+// complete.  Every
 // item it can wait for was taken from the queue before it by a running
 // workgroup, so the wait ends without co-residency of the grid.
 #pragma once
@@ -48,6 +50,19 @@ __device__ __forceinline__ T load_const(const __attribute__((address_space(4))) 
 // budget is the largest single path and not the union of all of them inlined
 // into one body (which spilled heavily); this is what lets two workgroups share
 // a compute unit.
+// W-pass item of a float32 problem whose rows take one column group: the item
+// applies the W update from its accumulators; its objective terms are added to
+// the caller's objsum.  A function of its own, so that its registers are
+// allocated apart from the other phases'.  (Like batch_item it is handed a
+// reference into its caller's frame, which keeps the call from being marked as
+// one that could skip the caller's frame; such calls make the callee save the
+// callee-saved registers it uses, hundreds of bytes per lane per item.)
+template <int BC, int KB, bool JOINT, bool OBJ>
+__device__ __noinline__ void batch_wpass_fused(ConstProblemPtr P, int item, float* lds, double& objsum) {
+  const SweepRowsArgs ra = load_const(&P->ra);
+  rows_item<BC, KB, KIND_UPDATE, OBJ, JOINT, true>(ra, item, lds, objsum, &P->ua);
+}
+
 template <int BC, int KB, int PREC, bool JOINT, bool OBJ>
 __device__ __noinline__ void batch_item(ConstProblemPtr P, int prob, int phase, int item, const BatchArgs& b,
                                            float* lds, double* red, float* norm_s, float* csum_s) {
@@ -111,6 +126,19 @@ __device__ __forceinline__ void batch_item_bc(int bc, ConstProblemPtr P, int pro
   }
 }
 
+template <int KB, bool JOINT, bool OBJ>
+__device__ __forceinline__ void batch_wpass_fused_bc(int bc, ConstProblemPtr P, int item, float* lds,
+                                                     double& objsum) {
+  switch (bc) {
+    case BC_GEN: batch_wpass_fused<BC_GEN, KB, JOINT, OBJ>(P, item, lds, objsum); break;
+    case BC_B2: batch_wpass_fused<BC_B2, KB, JOINT, OBJ>(P, item, lds, objsum); break;
+    case BC_B1: batch_wpass_fused<BC_B1, KB, JOINT, OBJ>(P, item, lds, objsum); break;
+    case BC_B0: batch_wpass_fused<BC_B0, KB, JOINT, OBJ>(P, item, lds, objsum); break;
+    case BC_B05: batch_wpass_fused<BC_B05, KB, JOINT, OBJ>(P, item, lds, objsum); break;
+    default: batch_wpass_fused<BC_B15, KB, JOINT, OBJ>(P, item, lds, objsum); break;
+  }
+}
+
 template <int PREC, bool JOINT, bool OBJ>
 __global__ __launch_bounds__(kBlock, 2) void batched_step_kernel(BatchArgs b) {
   __shared__ __align__(16) float lds[kBatchLdsBytes / 4];
@@ -137,11 +165,14 @@ __global__ __launch_bounds__(kBlock, 2) void batched_step_kernel(BatchArgs b) {
     const int phase = code >> 24, item = code & 0xffffff;
     ConstProblemPtr P = probs + prob;
 
-    // wait until the previous phase of this problem is complete (bounded)
+    // wait until the nearest earlier phase of this problem that has items is
+    // complete (bounded)
     if (phase > 0) {
       if (tid == 0) {
-        const unsigned need = (unsigned)P->items[phase - 1];
-        unsigned* cnt = b.done + 4 * prob + phase - 1;
+        int pq = phase - 1;
+        while (pq > 0 && P->items[pq] == 0) --pq;
+        const unsigned need = (unsigned)P->items[pq];
+        unsigned* cnt = b.done + 4 * prob + pq;
         unsigned polls = 0;
         // polled with read-modify-write atomics, which are performed where the
         // producers' increments are, never served from a cached copy
@@ -162,7 +193,15 @@ __global__ __launch_bounds__(kBlock, 2) void batched_step_kernel(BatchArgs b) {
     }
 
     const int kb = P->kb, bc = P->bc;
-    if (kb == 1) batch_item_bc<1, PREC, JOINT, OBJ>(bc, P, prob, phase, item, b, lds, red, norm_s, csum_s);
+    if (PREC == 0 && phase == PH_WPASS && P->wfused) {
+      double objsum = 0.0;
+      if (kb == 1) batch_wpass_fused_bc<1, JOINT, OBJ>(bc, P, item, lds, objsum);
+      else batch_wpass_fused_bc<2, JOINT, OBJ>(bc, P, item, lds, objsum);
+      if (OBJ) {
+        const double sum = block_sum(objsum, red);
+        if (tid == 0) P->ra.pobj[item] = sum;
+      }
+    } else if (kb == 1) batch_item_bc<1, PREC, JOINT, OBJ>(bc, P, prob, phase, item, b, lds, red, norm_s, csum_s);
     else batch_item_bc<2, PREC, JOINT, OBJ>(bc, P, prob, phase, item, b, lds, red, norm_s, csum_s);
 
     // nothing in the launch waits for the H update (its writes are read by the

@@ -348,8 +348,15 @@ __device__ __forceinline__ KlQueue kl_queue_of(float* lds, int wave) {
 // a later H pass that reuses them (joint MM: V~ and its element-wise terms are
 // formed once per outer iteration).
 // ---------------------------------------------------------------------------
-template <int BC, int KB, int KIND, bool OBJ, bool STORE_PQ>
-__device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, float* lds, double& objsum) {
+// FINISH (one column group: the item's accumulators hold the whole W-step
+// contractions of its rows): the item applies the W update itself from the
+// accumulators (W_new, and chi_1, chi_2 in joint mode or the transposed W_new in
+// alternating mode, as update_w_rows writes them) instead of writing partials;
+// `u` points to the update's arguments (read where they are used).
+template <int BC, int KB, int KIND, bool OBJ, bool STORE_PQ, bool FINISH = false,
+          class UPtr = const UpdateWArgs*>
+__device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, float* lds, double& objsum,
+                                          UPtr u = nullptr) {
   constexpr int KP = 32 * KB;
   constexpr int K2MAX = KP / 2;
   constexpr bool CONTRACT = (KIND != KIND_OBJ);
@@ -564,6 +571,76 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
   }
 
   if (OBJ && BC == BC_B1 && wave_on) klq.drain(objsum);
+  if constexpr (FINISH) {
+    // the beta = 1 denominator: row sums of H~ over all N (this item's single
+    // group), gathered per k through LDS
+    float* const rs_s = lds;  // [KP]
+    if (ROWSUM) {
+      __syncthreads();  // the staged tiles are no longer read
+#pragma unroll
+      for (int j = 0; j < KB; ++j) {
+        float x = rsum[j];
+        x += __shfl_xor(x, 1, 64);
+        x += __shfl_xor(x, 2, 64);
+        x += __shfl_xor(x, 4, 64);
+        const int e4 = tid + kBlock * j;
+        if ((e4 & 7) == 0) rs_s[e4 >> 3] = x;
+      }
+      __syncthreads();
+    }
+    if (wave_on) {
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        const int k = kb * 32 + li;
+        const bool kok = k < K;
+        const double den1 = ROWSUM ? (double)rs_s[k] : 0.0;
+        float wt[16], wn[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int f = f0 + acc_row(r, hi);
+          wt[r] = ldz(u->W, (int64_t)f * u->ldw + k, f < a.F && kok);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int f = f0 + acc_row(r, hi);
+          float w1 = 0.f, c1 = 0.f, c2 = 0.f;
+          if (f < a.F && kok) {
+            const double num = (double)accN[kb][r];
+            const double den = ROWSUM ? den1 : (double)accD[kb][r];
+            const double ratio = num / den;
+            if (!(den > 0.0) || !isfinite(ratio)) set_flag(u->flags, 1u);
+            const double rr = pow_gamma(ratio, u->gamma);
+            const double w0 = (double)wt[r];
+            const double wnew = w0 * rr;
+            w1 = (float)wnew;
+            if (u->joint) chi_terms(u->beta, w0, rr, wnew, c1, c2);
+          }
+          wn[r] = w1;
+          if (f < a.F) {
+            const int64_t o = (int64_t)f * KP + k;
+            u->Wn[o] = w1;
+            if (u->joint) { u->C1[o] = c1; u->C2[o] = c2; }
+          }
+        }
+        if (!u->joint) {
+          // W_new^T: registers 4q..4q+3 are four consecutive rows of one column
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int fb = f0 + 8 * q + 4 * hi;
+            float* const dst = u->WT + (int64_t)k * u->ldt + fb;
+            if (fb + 3 < a.F) {
+              *reinterpret_cast<float4*>(dst) = make_float4(wn[4 * q], wn[4 * q + 1], wn[4 * q + 2], wn[4 * q + 3]);
+            } else {
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                if (fb + i < a.F) dst[i] = wn[4 * q + i];
+            }
+          }
+        }
+      }
+    }
+    return;
+  }
   if (CONTRACT && wave_on) {
     // accumulator (i = row offset f, j = li = column k); each wave owns its rows
 #pragma unroll

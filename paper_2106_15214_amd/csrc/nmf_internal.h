@@ -175,6 +175,7 @@ struct BatchProblem {
   SweepColsArgs ca;
   UpdateHArgs ha;
   int bc, kb;
+  int wfused;    // the W-pass items apply the W update (no W-update items)
   int items[4];  // work items per phase
   int units[4];  // update units per phase (W rows / H columns groups); an item covers `per_item` of them
   int per_item[4];

@@ -210,12 +210,19 @@ NMF_PLAN_HD inline int bucket_of(int64_t F, int64_t N, int64_t K, double beta) {
   return ((kblocks_for(K) - 1) * 4 + cls) * kBatchBetaClasses + beta_class(beta);
 }
 
+// A float32 problem whose rows take one column group has the whole W-step
+// contractions of a row block in one W-pass item, which then applies the W
+// update itself: the problem has no W-update items.
+NMF_PLAN_HD inline bool batch_w_fused(const Plan& p, int prec) { return p.n_groups == 1 && prec == NMF_FP32; }
+
 // Update units and work items per phase of a problem in a batch: W-pass items
-// (row block x column group), W-update items of kBatchWRows rows, H-pass items
-// (column block x row group), H-update items of batch_h_units column units.
-NMF_PLAN_HD inline void batch_phases(const Plan& p, int64_t F, int units[4], int per_item[4], int items[4]) {
+// (row block x column group), W-update items of kBatchWRows rows (none if
+// w_fused), H-pass items (column block x row group), H-update items of
+// batch_h_units column units.
+NMF_PLAN_HD inline void batch_phases(const Plan& p, int64_t F, bool w_fused, int units[4], int per_item[4],
+                                     int items[4]) {
   units[PH_WPASS] = p.row_blocks * p.n_groups;
-  units[PH_WUPDATE] = (int)cdiv(F, kBatchWRows);
+  units[PH_WUPDATE] = w_fused ? 0 : (int)cdiv(F, kBatchWRows);
   units[PH_HPASS] = p.col_blocks * p.f_groups;
   units[PH_HUPDATE] = p.uh_blocks;
   per_item[PH_WPASS] = 1;
@@ -246,14 +253,15 @@ NMF_PLAN_HD inline BatchProblem make_batch_problem(const Plan& p, char* ws, unsi
   d.ha = sa.ha;
   d.bc = beta_class(q.beta);
   d.kb = p.KB;
-  batch_phases(p, q.F, d.units, d.per_item, d.items);
+  d.wfused = batch_w_fused(p, o.precision);
+  batch_phases(p, q.F, d.wfused != 0, d.units, d.per_item, d.items);
   return d;
 }
 
 // Work items of one problem's outer iteration in a batch (all four phases).
-NMF_PLAN_HD inline int64_t batch_items(const Plan& p, int64_t F) {
+NMF_PLAN_HD inline int64_t batch_items(const Plan& p, int64_t F, bool w_fused) {
   int units[4], per_item[4], items[4];
-  batch_phases(p, F, units, per_item, items);
+  batch_phases(p, F, w_fused, units, per_item, items);
   return (int64_t)items[0] + items[1] + items[2] + items[3];
 }
 

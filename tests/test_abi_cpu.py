@@ -179,6 +179,17 @@ def test_batch_requirements_invariants():
     i, _ = nb.batch_requirements([(F, N, K, 1.0)], "joint", [4096] * 48)
     rb, cb = -(-F // 128), -(-N // 128)
     assert i >= rb + cb and i <= rb + cb + F + N
+    # float32 applies the W update of a problem whose rows take one column group
+    # (here N / 32 = 94 tiles <= 128) in its W-pass items: ceil(F / 64) W-update
+    # items fewer than in bfloat16, the same workspace
+    lo = nb.batch_requirements([(F, N, K, 1.0)], "joint")
+    hi = nb.batch_requirements([(F, N, K, 1.0)], "joint", precision="bf16")
+    assert hi[0] - lo[0] == -(-F // 64) and hi[1] == lo[1]
+    # two column groups (4 tiles per item): no difference
+    assert (nb.batch_requirements([(F, N, K, 1.0)], "joint", [4] * 48)
+            == nb.batch_requirements([(F, N, K, 1.0)], "joint", [4] * 48, precision="bf16"))
+    ib, bb = nb.batch_requirements(shapes, "joint", precision="fp16")
+    assert ib >= items and bb == bytes_
 
 
 def test_batch_requirements_checks():
@@ -196,10 +207,11 @@ def test_batch_requirements_checks():
     assert e.value.status == E_BETA
     L = nb.lib()
     n, b = ctypes.c_int64(), ctypes.c_int64()
-    assert L.nmf_batch_requirements(None, 1, 1, None, ctypes.byref(n), ctypes.byref(b)) == E_NULL
+    assert L.nmf_batch_requirements(None, 1, 1, 0, None, ctypes.byref(n), ctypes.byref(b)) == E_NULL
     arr = (nb._Problem * 1)(nb._Problem(10, 10, 5, None, 0, None, 0, None, 0, 1.0))
-    assert L.nmf_batch_requirements(arr, 0, 1, None, ctypes.byref(n), ctypes.byref(b)) == E_ARG
-    assert L.nmf_batch_requirements(arr, 1, 5, None, ctypes.byref(n), ctypes.byref(b)) == E_ARG
+    assert L.nmf_batch_requirements(arr, 0, 1, 0, None, ctypes.byref(n), ctypes.byref(b)) == E_ARG
+    assert L.nmf_batch_requirements(arr, 1, 5, 0, None, ctypes.byref(n), ctypes.byref(b)) == E_ARG
+    assert L.nmf_batch_requirements(arr, 1, 1, 7, None, ctypes.byref(n), ctypes.byref(b)) == E_ARG
 
 
 def test_batched_entry_points_null_context():

@@ -51,8 +51,8 @@ def to_dev(probs):
     return [(dev(V), dev(W), dev(H), b) for V, W, H, b in probs]
 
 
-def reserve_for(ctx, shapes, mode, slots=None):
-    items, nbytes = nb.batch_requirements(shapes, mode, nb.get_batch_tiles(ctx))
+def reserve_for(ctx, shapes, mode, slots=None, precision="fp32"):
+    items, nbytes = nb.batch_requirements(shapes, mode, nb.get_batch_tiles(ctx), precision)
     nb.reserve_batched(slots or len(shapes), items, nbytes, ctx=ctx)
     return items, nbytes
 
@@ -79,7 +79,7 @@ def test_device_planned_equals_host_planned(mode, precision):
     print(f"[device batch] {mode} {precision} problems={len(a)}", flush=True)
     ctx = nb.Context(0)
     ctx.set_path("stream")
-    reserve_for(ctx, shapes_of(probs), mode)
+    reserve_for(ctx, shapes_of(probs), mode, precision=precision)
     dp = nb.DeviceProblems(len(a))
     dp.set(a)
     host = nb.Batch(b, mode, precision=precision, ctx=ctx)
