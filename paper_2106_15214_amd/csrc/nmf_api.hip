@@ -1132,7 +1132,7 @@ nmf_status batch_create(nmf_ctx_s* c, const nmf_problem* pr, int count, int mode
   for (int i = 0; i < count; ++i) {
     const nmf_problem& q = pr[i];
     plans[i] = make_batch_plan(q.F, q.N, q.K, tiles[bucket_of(q.F, q.N, q.K, q.beta)], joint);
-    total += batch_items(plans[i], q.F, batch_w_fused(plans[i], o.precision));
+    total += batch_items(plans[i], q.F, o.precision);
   }
   if (total >= (int64_t)1 << 31) return NMF_ERR_UNSUPPORTED;
   const size_t o_list = off;
@@ -1416,7 +1416,7 @@ nmf_status nmf_batch_requirements(const nmf_problem* pr, int32_t count, int32_t 
     if (!std::isfinite(q.beta)) return NMF_ERR_BETA;
     const int b = bucket_of(q.F, q.N, q.K, q.beta);
     const Plan p = make_batch_plan(q.F, q.N, q.K, tiles ? tiles[b] : kBatchTilesDefault, mode == NMF_JOINT);
-    n += batch_items(p, q.F, batch_w_fused(p, precision));
+    n += batch_items(p, q.F, precision);
     bytes += (int64_t)align_up(p.total);
   }
   *items = n;

@@ -4,16 +4,18 @@
 //   W-pass items  (rows items: Lambda~ tiles, P, Q, W-step partials, objective;
 //                  in joint mode P and Q are kept for the H pass)
 //   W-update items (partials reduced, W_new, chi terms; 64 rows each, all loads
-//                  in flight together); none for a float32 problem whose W-pass
-//                  items each cover whole rows: those apply the update themselves
+//                  in flight together)
 //   H-pass items  (cols items: H-step partials from the kept P, Q in joint mode,
 //                  column sums of W_new)
 //   H-update units (H_new, normalization, W write-back, objective total)
+// A float32 problem whose rows take one column group has no W-update items: its
+// W-pass items apply the W update.  If its columns also take one row group it
+// has no H-update items either: its W-pass items also write the column
+// partials of W_new and its H-pass items apply the H update and write W back.
 // A per-problem counter of finished items per phase replaces grid barriers: an
-// item of phase q waits until its problem's nearest earlier phase with items is
-// complete.  Every
-// item it can wait for was taken from the queue before it by a running
-// workgroup, so the wait ends without co-residency of the grid.
+// item waits until its problem's nearest earlier phase that has items is
+// complete.  Every item it can wait for was taken from the queue before it by a
+// running workgroup, so the wait ends without co-residency of the grid.
 #pragma once
 
 #include "nmf_device.h"
@@ -61,6 +63,33 @@ template <int BC, int KB, bool JOINT, bool OBJ>
 __device__ __noinline__ void batch_wpass_fused(ConstProblemPtr P, int item, float* lds, double& objsum) {
   const SweepRowsArgs ra = load_const(&P->ra);
   rows_item<BC, KB, KIND_UPDATE, OBJ, JOINT, true>(ra, item, lds, objsum, &P->ua);
+}
+
+// H-pass item of a float32 problem whose W-pass items applied the W update and
+// whose columns take one row group: the column norms and sums of W_new from
+// the W pass's row-block partials, the H-step contractions of the item's
+// columns, the H update of those columns, this item's share of the W
+// write-back, and (item 0) the objective total.
+template <int BC, int KB, bool JOINT, bool OBJ>
+__device__ __noinline__ void batch_hpass_fused(ConstProblemPtr P, int prob, int item, const BatchArgs& b,
+                                               float* lds, double* red, float* norm_s, float* csum_s) {
+  reduce_columns<KB>(P->ha.pcol, P->ha.pcol_blocks, reinterpret_cast<double*>(lds), norm_s, csum_s);
+  {
+    const SweepColsArgs ca = load_const(&P->ca);
+    cols_item<BC, KB, KIND_UPDATE, JOINT, JOINT, true>(ca, item, lds, &P->ha, norm_s, csum_s);
+  }
+  const UpdateHArgs ha = load_const(&P->ha);
+  const int items = P->items[PH_HPASS];
+  write_w<KB>(ha, norm_s, (int64_t)item * kBlock + threadIdx.x, (int64_t)items * kBlock);
+  if (OBJ && item == 0 && b.d_obj) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < ha.nobj; i += kBlock) s += ha.pobj[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) {
+      b.d_obj[prob] = s;
+      if (!isfinite(s)) set_flag(b.flags, 1u);
+    }
+  }
 }
 
 template <int BC, int KB, int PREC, bool JOINT, bool OBJ>
@@ -139,6 +168,20 @@ __device__ __forceinline__ void batch_wpass_fused_bc(int bc, ConstProblemPtr P, 
   }
 }
 
+template <int KB, bool JOINT, bool OBJ>
+__device__ __forceinline__ void batch_hpass_fused_bc(int bc, ConstProblemPtr P, int prob, int item,
+                                                     const BatchArgs& b, float* lds, double* red, float* norm_s,
+                                                     float* csum_s) {
+  switch (bc) {
+    case BC_GEN: batch_hpass_fused<BC_GEN, KB, JOINT, OBJ>(P, prob, item, b, lds, red, norm_s, csum_s); break;
+    case BC_B2: batch_hpass_fused<BC_B2, KB, JOINT, OBJ>(P, prob, item, b, lds, red, norm_s, csum_s); break;
+    case BC_B1: batch_hpass_fused<BC_B1, KB, JOINT, OBJ>(P, prob, item, b, lds, red, norm_s, csum_s); break;
+    case BC_B0: batch_hpass_fused<BC_B0, KB, JOINT, OBJ>(P, prob, item, b, lds, red, norm_s, csum_s); break;
+    case BC_B05: batch_hpass_fused<BC_B05, KB, JOINT, OBJ>(P, prob, item, b, lds, red, norm_s, csum_s); break;
+    default: batch_hpass_fused<BC_B15, KB, JOINT, OBJ>(P, prob, item, b, lds, red, norm_s, csum_s); break;
+  }
+}
+
 template <int PREC, bool JOINT, bool OBJ>
 __global__ __launch_bounds__(kBlock, 2) void batched_step_kernel(BatchArgs b) {
   __shared__ __align__(16) float lds[kBatchLdsBytes / 4];
@@ -193,16 +236,27 @@ __global__ __launch_bounds__(kBlock, 2) void batched_step_kernel(BatchArgs b) {
     }
 
     const int kb = P->kb, bc = P->bc;
-    if (PREC == 0 && phase == PH_WPASS && P->wfused) {
-      double objsum = 0.0;
-      if (kb == 1) batch_wpass_fused_bc<1, JOINT, OBJ>(bc, P, item, lds, objsum);
-      else batch_wpass_fused_bc<2, JOINT, OBJ>(bc, P, item, lds, objsum);
-      if (OBJ) {
-        const double sum = block_sum(objsum, red);
-        if (tid == 0) P->ra.pobj[item] = sum;
+    bool fused_item = false;
+    if constexpr (PREC == 0) {
+      if (phase == PH_WPASS && P->wfused) {
+        double objsum = 0.0;
+        if (kb == 1) batch_wpass_fused_bc<1, JOINT, OBJ>(bc, P, item, lds, objsum);
+        else batch_wpass_fused_bc<2, JOINT, OBJ>(bc, P, item, lds, objsum);
+        if (OBJ) {
+          const double sum = block_sum(objsum, red);
+          if (tid == 0) P->ra.pobj[item] = sum;
+        }
+        fused_item = true;
+      } else if (phase == PH_HPASS && P->hfused) {
+        if (kb == 1) batch_hpass_fused_bc<1, JOINT, OBJ>(bc, P, prob, item, b, lds, red, norm_s, csum_s);
+        else batch_hpass_fused_bc<2, JOINT, OBJ>(bc, P, prob, item, b, lds, red, norm_s, csum_s);
+        fused_item = true;
       }
-    } else if (kb == 1) batch_item_bc<1, PREC, JOINT, OBJ>(bc, P, prob, phase, item, b, lds, red, norm_s, csum_s);
-    else batch_item_bc<2, PREC, JOINT, OBJ>(bc, P, prob, phase, item, b, lds, red, norm_s, csum_s);
+    }
+    if (!fused_item) {
+      if (kb == 1) batch_item_bc<1, PREC, JOINT, OBJ>(bc, P, prob, phase, item, b, lds, red, norm_s, csum_s);
+      else batch_item_bc<2, PREC, JOINT, OBJ>(bc, P, prob, phase, item, b, lds, red, norm_s, csum_s);
+    }
 
     // nothing in the launch waits for the H update (its writes are read by the
     // next launch), so only the first three phases publish their items

@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(BatchPlanArgs 
       const Plan p = make_batch_plan(q.F, q.N, q.K, a.tiles[bucket_of(q.F, q.N, q.K, q.beta)], a.joint != 0);
       bytes = (int64_t)align_up(p.total);
       int units[4], per_item[4], it[4];
-      batch_phases(p, q.F, batch_w_fused(p, a.opts.precision), units, per_item, it);
+      batch_phases(p, q.F, a.opts.precision, units, per_item, it);
       for (int ph = 0; ph < 4; ++ph) items[ph] = it[ph];
     }
     a.s_bytes[i] = bytes;

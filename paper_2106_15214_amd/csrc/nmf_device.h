@@ -352,7 +352,9 @@ __device__ __forceinline__ KlQueue kl_queue_of(float* lds, int wave) {
 // contractions of its rows): the item applies the W update itself from the
 // accumulators (W_new, and chi_1, chi_2 in joint mode or the transposed W_new in
 // alternating mode, as update_w_rows writes them) instead of writing partials;
-// `u` points to the update's arguments (read where they are used).
+// `u` points to the update's arguments (read where they are used).  With
+// u->pcol set it also writes the column sums of W_new^2 and W_new over its 128
+// rows to u->pcol[rb][2][KP] (the normalization's partials, one per row block).
 template <int BC, int KB, int KIND, bool OBJ, bool STORE_PQ, bool FINISH = false,
           class UPtr = const UpdateWArgs*>
 __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, float* lds, double& objsum,
@@ -588,6 +590,9 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
       }
       __syncthreads();
     }
+    double csq[KB], csm[KB];  // this lane's column sums of W_new^2 and W_new
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) { csq[kb] = 0.0; csm[kb] = 0.0; }
     if (wave_on) {
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
@@ -621,6 +626,8 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
             u->Wn[o] = w1;
             if (u->joint) { u->C1[o] = c1; u->C2[o] = c2; }
           }
+          csq[kb] += (double)w1 * (double)w1;
+          csm[kb] += (double)w1;
         }
         if (!u->joint) {
           // W_new^T: registers 4q..4q+3 are four consecutive rows of one column
@@ -637,6 +644,28 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
             }
           }
         }
+      }
+    }
+    if (u->pcol) {
+      // lanes hi = 0, 1 hold the same column; the four waves' sums are added
+      // in wave order through LDS (rows past F hold W_new = 0)
+      double* const cs = reinterpret_cast<double*>(lds + 2 * KP);  // [kWaves][2][KP]
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        const double q2 = csq[kb] + __shfl_xor(csq[kb], 32, 64);
+        const double q1 = csm[kb] + __shfl_xor(csm[kb], 32, 64);
+        if (hi == 0) {
+          cs[(wave * 2 + 0) * KP + kb * 32 + li] = q2;
+          cs[(wave * 2 + 1) * KP + kb * 32 + li] = q1;
+        }
+      }
+      __syncthreads();
+      if (tid < 2 * KP) {
+        const int part = tid / KP, k = tid % KP;
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) t += cs[(w * 2 + part) * KP + k];
+        u->pcol[(int64_t)rb * 2 * KP + tid] = t;
       }
     }
     return;
@@ -1558,9 +1587,15 @@ constexpr int cols_item_lds() {
 // LOAD_PQ) and chi_1, chi_2 (32 x KP, row-major with ld KP).  With LOAD_PQ the
 // element-wise terms P, Q come from the tiles a rows item stored (no Lambda
 // re-formation, no V pass).
+// FINISH (one row group: the accumulators hold the whole H-step contractions of
+// the item's columns): the item applies the H update to its columns in place,
+// as update_h_cols_multi does, from the accumulators and the column norms and
+// sums of W_new in norm_s / csum_s; `uh` points to the update's arguments.
 // ---------------------------------------------------------------------------
-template <int BC, int KB, int KIND, bool DUAL, bool LOAD_PQ>
-__device__ __forceinline__ void cols_item(const SweepColsArgs& a, int item, float* lds) {
+template <int BC, int KB, int KIND, bool DUAL, bool LOAD_PQ, bool FINISH = false,
+          class UHPtr = const UpdateHArgs*>
+__device__ __forceinline__ void cols_item(const SweepColsArgs& a, int item, float* lds, UHPtr uh = nullptr,
+                                          const float* norm_s = nullptr, const float* csum_s = nullptr) {
   constexpr int KP = 32 * KB;
   constexpr int K2MAX = KP / 2;
   constexpr int CS = KP + 4;  // LDS row stride of [f][KP] tiles
@@ -1770,6 +1805,67 @@ __device__ __forceinline__ void cols_item(const SweepColsArgs& a, int item, floa
     __syncthreads();
   }
 
+  if constexpr (FINISH) {
+    if (!wave_on) return;
+    float* const Hw = uh->H;
+    const int64_t ldh = uh->ldh;
+    const bool h4 = ((uintptr_t)Hw % 16 == 0) && (ldh % 4 == 0);
+    const int N = a.N;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      const int k = kb * 32 + li;
+      const bool kok = k < K;
+      double nk = 1.0;
+      if (uh->normalize && kok) {
+        const float x = norm_s[k];
+        if (x > 0.f) nk = (double)x;
+      }
+      const double den1 = uh->beta_one && kok ? (double)csum_s[k] : 0.0;
+      // H~ at the accumulator positions: registers 4q..4q+3 are columns
+      // n0w + 8q + 4hi + 0..3 of row k
+      float hv[16];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int nb = n0w + 8 * q + 4 * hi;
+        const int64_t o = (int64_t)k * ldh + nb;
+        if (h4 && nb + 3 < N) {
+          const float4 x = ldc4(Hw, o, kok);
+          hv[4 * q + 0] = x.x; hv[4 * q + 1] = x.y; hv[4 * q + 2] = x.z; hv[4 * q + 3] = x.w;
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) hv[4 * q + j] = ldc(Hw, o + j, kok && nb + j < N);
+        }
+      }
+      float hn[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int n = n0w + acc_row(r, hi);
+        hn[r] = 0.f;
+        if (kok && n < N) {
+          const double num = (double)accN[kb][r];
+          const double dd = uh->beta_one ? den1 : (double)accD[kb][r];
+          const double ratio = num / dd;
+          if (!(dd > 0.0) || !isfinite(ratio)) set_flag(uh->flags, 1u);
+          hn[r] = (float)((double)hv[r] * (pow_gamma(ratio, uh->gamma) * nk));
+        }
+      }
+      if (kok) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int nb = n0w + 8 * q + 4 * hi;
+          float* const dst = Hw + (int64_t)k * ldh + nb;
+          if (h4 && nb + 3 < N) {
+            *reinterpret_cast<float4*>(dst) = make_float4(hn[4 * q], hn[4 * q + 1], hn[4 * q + 2], hn[4 * q + 3]);
+          } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              if (nb + j < N) dst[j] = hn[4 * q + j];
+          }
+        }
+      }
+    }
+    return;
+  }
   if (wave_on) {
     // accumulator (i = column offset n, j = li = k); each wave owns its columns
 #pragma unroll

@@ -176,6 +176,7 @@ struct BatchProblem {
   UpdateHArgs ha;
   int bc, kb;
   int wfused;    // the W-pass items apply the W update (no W-update items)
+  int hfused;    // ... and the H-pass items the H update (no H-update items)
   int items[4];  // work items per phase
   int units[4];  // update units per phase (W rows / H columns groups); an item covers `per_item` of them
   int per_item[4];

@@ -39,6 +39,7 @@ struct Plan {
   int64_t ldt;                        // leading dimension of the transposed factor (K x F)
   bool fused;                         // one cooperative launch (grid = fused_grid)
   bool pq;                            // joint streaming path keeps P, Q between the passes
+  bool row_pcol;                      // batch: room for one column partial per row block
   int fused_grid;
   // byte offsets inside the workspace
   size_t o_pobj, o_pnum, o_pden, o_prs, o_wn, o_c1, o_c2, o_c0, o_wt, o_pcol, o_pnumh, o_pdenh, o_colsum, o_pst,
@@ -98,7 +99,10 @@ NMF_PLAN_HD inline Plan finish_plan(Plan p, int64_t F, int64_t N, bool inner = f
   z.prs = sizeof(float) * (size_t)p.n_groups * p.KP;
   z.fk = sizeof(float) * (size_t)F * p.KP;
   z.wt = sizeof(float) * (size_t)p.KP * p.ldt;
-  z.pcol = sizeof(double) * (size_t)(p.fused ? p.uw_blocks : (int64_t)p.f_groups * p.col_parts) * 2 * p.KP;
+  z.pcol = sizeof(double) *
+           (size_t)(p.fused ? p.uw_blocks
+                            : max64((int64_t)p.f_groups * p.col_parts, p.row_pcol ? p.row_blocks : 0)) *
+           2 * p.KP;
   z.pnumh = sizeof(float) * (size_t)p.f_groups * N * p.KP;
   z.pq = (p.fused || p.pq) ? sizeof(float) * (size_t)cdiv(F, kTile) * cdiv(N, kTile) * kTile * kTile : 0;
   p.ldc = cdiv(N, 4) * 4;
@@ -125,6 +129,7 @@ NMF_PLAN_HD inline Plan make_batch_plan(int64_t F, int64_t N, int64_t K, int til
   p.f_groups = (int)cdiv(tf, p.tiles_f);
   p.uw_blocks = (int)cdiv(F, update_w_unit_rows(p.KB));
   p.uh_blocks = (int)cdiv(N, kBlock / p.KP);
+  p.row_pcol = true;
   return finish_plan(p, F, N);
 }
 
@@ -214,17 +219,21 @@ NMF_PLAN_HD inline int bucket_of(int64_t F, int64_t N, int64_t K, double beta) {
 // contractions of a row block in one W-pass item, which then applies the W
 // update itself: the problem has no W-update items.
 NMF_PLAN_HD inline bool batch_w_fused(const Plan& p, int prec) { return p.n_groups == 1 && prec == NMF_FP32; }
+// If its columns also take one row group, the W-pass items write the column
+// partials of W_new (one per row block) and the H-pass items apply the H
+// update and write W back: the problem has no H-update items either.
+NMF_PLAN_HD inline bool batch_h_fused(const Plan& p, int prec) { return batch_w_fused(p, prec) && p.f_groups == 1; }
 
-// Update units and work items per phase of a problem in a batch: W-pass items
-// (row block x column group), W-update items of kBatchWRows rows (none if
-// w_fused), H-pass items (column block x row group), H-update items of
-// batch_h_units column units.
-NMF_PLAN_HD inline void batch_phases(const Plan& p, int64_t F, bool w_fused, int units[4], int per_item[4],
+// Update units and work items per phase of a problem in a batch of precision
+// `prec`: W-pass items (row block x column group), W-update items of
+// kBatchWRows rows (none if batch_w_fused), H-pass items (column block x row
+// group), H-update items of batch_h_units column units (none if batch_h_fused).
+NMF_PLAN_HD inline void batch_phases(const Plan& p, int64_t F, int prec, int units[4], int per_item[4],
                                      int items[4]) {
   units[PH_WPASS] = p.row_blocks * p.n_groups;
-  units[PH_WUPDATE] = w_fused ? 0 : (int)cdiv(F, kBatchWRows);
+  units[PH_WUPDATE] = batch_w_fused(p, prec) ? 0 : (int)cdiv(F, kBatchWRows);
   units[PH_HPASS] = p.col_blocks * p.f_groups;
-  units[PH_HUPDATE] = p.uh_blocks;
+  units[PH_HUPDATE] = batch_h_fused(p, prec) ? 0 : p.uh_blocks;
   per_item[PH_WPASS] = 1;
   per_item[PH_WUPDATE] = 1;
   per_item[PH_HPASS] = 1;
@@ -254,14 +263,21 @@ NMF_PLAN_HD inline BatchProblem make_batch_problem(const Plan& p, char* ws, unsi
   d.bc = beta_class(q.beta);
   d.kb = p.KB;
   d.wfused = batch_w_fused(p, o.precision);
-  batch_phases(p, q.F, d.wfused != 0, d.units, d.per_item, d.items);
+  d.hfused = batch_h_fused(p, o.precision);
+  if (d.hfused) {  // column partials from the W pass, one per row block
+    d.ca.pcol = nullptr;
+    d.ha.pcol_blocks = p.row_blocks;
+  } else {
+    d.ua.pcol = nullptr;
+  }
+  batch_phases(p, q.F, o.precision, d.units, d.per_item, d.items);
   return d;
 }
 
 // Work items of one problem's outer iteration in a batch (all four phases).
-NMF_PLAN_HD inline int64_t batch_items(const Plan& p, int64_t F, bool w_fused) {
+NMF_PLAN_HD inline int64_t batch_items(const Plan& p, int64_t F, int prec) {
   int units[4], per_item[4], items[4];
-  batch_phases(p, F, w_fused, units, per_item, items);
+  batch_phases(p, F, prec, units, per_item, items);
   return (int64_t)items[0] + items[1] + items[2] + items[3];
 }
 

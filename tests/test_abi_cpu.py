@@ -180,11 +180,18 @@ def test_batch_requirements_invariants():
     rb, cb = -(-F // 128), -(-N // 128)
     assert i >= rb + cb and i <= rb + cb + F + N
     # float32 applies the W update of a problem whose rows take one column group
-    # (here N / 32 = 94 tiles <= 128) in its W-pass items: ceil(F / 64) W-update
-    # items fewer than in bfloat16, the same workspace
+    # (here N / 32 = 94 tiles <= 128) in its W-pass items, and with one row group
+    # (F / 32 = 32 tiles) the H update in its H-pass items: ceil(F / 64)
+    # W-update items and ceil(ceil(N / 8) / 32) H-update items (K = 20: 8
+    # columns of 32 k per 256 threads, 32 such units an item) fewer than in
+    # bfloat16, the same workspace
     lo = nb.batch_requirements([(F, N, K, 1.0)], "joint")
     hi = nb.batch_requirements([(F, N, K, 1.0)], "joint", precision="bf16")
-    assert hi[0] - lo[0] == -(-F // 64) and hi[1] == lo[1]
+    assert hi[0] - lo[0] == -(-F // 64) + -(-(-(-N // 8)) // 32) and hi[1] == lo[1]
+    # W update only: two row groups (F = 5000 rows, 157 tiles)
+    lo = nb.batch_requirements([(5000, N, K, 1.0)], "joint")
+    hi = nb.batch_requirements([(5000, N, K, 1.0)], "joint", precision="bf16")
+    assert hi[0] - lo[0] == -(-5000 // 64)
     # two column groups (4 tiles per item): no difference
     assert (nb.batch_requirements([(F, N, K, 1.0)], "joint", [4] * 48)
             == nb.batch_requirements([(F, N, K, 1.0)], "joint", [4] * 48, precision="bf16"))
