@@ -380,7 +380,7 @@ typedef struct {
 
 typedef struct {
   int32_t tiles_per_item;   /* 32-wide tiles each pass item walks (0: the context's
-                               per-bucket table, 128 in every bucket unless set by
+                               per-bucket table, 256 in every bucket unless set by
                                nmf_set_batch_tiles or nmf_tune) */
   int32_t workers;          /* persistent workgroups (0: as many as fit on the GPU) */
   int32_t lag;              /* order of the work queue.  0 (default): phase by phase
@@ -418,7 +418,7 @@ nmf_status nmf_batch_destroy(nmf_batch_t batch);
  *   c = the beta class: 0 general, 1 beta = 2, 2 beta = 1, 3 beta = 0, 4 beta = 1/2,
  *       5 beta = 3/2 (the classes the kernels are compiled for),
  * and walks the tiles_per_item of its bucket.  The context holds one table
- * (128 in every bucket at creation), used by nmf_batch_create when
+ * (256 in every bucket at creation), used by nmf_batch_create when
  * cfg->tiles_per_item is 0 and by every nmf_beta_step_batched. */
 #define NMF_BATCH_BUCKETS 48
 
@@ -442,7 +442,7 @@ nmf_status nmf_get_batch_tiles(nmf_ctx_t ctx, int32_t* tiles);
  * that covers every bucket the problems fall in, its tiles are installed and
  * nothing is measured (*from_cache = 1).  Otherwise, starting from that entry
  * (else from the context's table), each uncovered bucket in turn takes the
- * candidate of {4, 8, 16, 32, 64, 128} with the smallest time per batched step
+ * candidate of {4, 8, 16, 32, 64, 128, 256} with the smallest time per batched step
  * of the whole set (one warm-up step, then `iters` timed steps; candidates
  * that split every problem of the bucket as an already timed one are skipped),
  * the others held fixed.  The problems' W and H are saved before and restored
@@ -478,7 +478,7 @@ nmf_status nmf_tune(nmf_ctx_t ctx, void* stream, const nmf_problem* problems, in
 /* Items per step and workspace bytes that `count` problems (host descriptors;
  * only the sizes and beta are read) need in `mode` and `precision`
  * (NMF_FP32 / NMF_BF16 / NMF_FP16) under `tiles` (host
- * int32[NMF_BATCH_BUCKETS]; NULL: 128 in every bucket).  The item count is the
+ * int32[NMF_BATCH_BUCKETS]; NULL: 256 in every bucket).  The item count is the
  * batch's exact one: in float32 a problem whose rows take one column group has
  * its W update applied by its W-pass items and no W-update items.  Host only,
  * no GPU.  NMF_ERR_ARG for a bad mode, precision or table, NMF_ERR_SHAPE /

@@ -690,7 +690,7 @@ def tune(problems, mode="joint", *, precision="fp32", kappa: float = 0.0, normal
 def batch_requirements(shapes, mode="joint", tiles=None, precision="fp32"):
     """(work items per step, workspace bytes) that problems of the given
     (F, N, K, beta) sizes need in a batch in ``mode`` and ``precision`` under
-    ``tiles`` (None: 128 in every bucket).  Host only."""
+    ``tiles`` (None: 256 in every bucket).  Host only."""
     arr = (_Problem * len(shapes))()
     for i, (F, N, K, beta) in enumerate(shapes):
         arr[i] = _Problem(int(F), int(N), int(K), None, 0, None, 0, None, 0, float(beta))

@@ -332,7 +332,9 @@ nmf_status check_batch_alias(const nmf_problem* pr, int count) {
   return NMF_OK;
 }
 
-constexpr int kBatchTilesDefault = 128;  // measured best on the 512-problem workload (16..128)
+// measured best on the 512-problem workload among 96..256 (160 and 256 tie):
+// more problems take one group per pass and skip the update phases
+constexpr int kBatchTilesDefault = 256;
 constexpr unsigned kBatchSpinLimit = 1u << 22;
 
 // Alternating MU with L > 1 sub-iterations (Algorithm 1, any product type): L W
@@ -1645,7 +1647,7 @@ nmf_status nmf_tune(nmf_ctx_t c, void* stream, const nmf_problem* pr, int32_t co
     }
     return sig;
   };
-  static const int kCandidates[] = {4, 8, 16, 32, 64, 128};
+  static const int kCandidates[] = {4, 8, 16, 32, 64, 128, 256};
   double best = HUGE_VAL;
   st = NMF_OK;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess || copy_all(true) != hipSuccess)

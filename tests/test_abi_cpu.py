@@ -158,11 +158,11 @@ def test_batch_requirements_invariants():
     i1, b1 = nb.batch_requirements(shapes[:17], "joint")
     i2, b2 = nb.batch_requirements(shapes[17:], "joint")
     assert (i1 + i2, b1 + b2) == (items, bytes_)
-    # the default table is 128 in every bucket
-    assert nb.batch_requirements(shapes, "joint", [128] * 48) == (items, bytes_)
+    # the default table is 256 in every bucket
+    assert nb.batch_requirements(shapes, "joint", [256] * 48) == (items, bytes_)
     # a table changed in one bucket changes the plans of that bucket's problems only
     b0 = _bucket_from_rule(*shapes[0])
-    t = [128] * 48
+    t = [256] * 48
     t[b0] = 4
     for sh in shapes:
         changed = nb.batch_requirements([sh], "joint", t) != nb.batch_requirements([sh], "joint")
@@ -188,9 +188,9 @@ def test_batch_requirements_invariants():
     lo = nb.batch_requirements([(F, N, K, 1.0)], "joint")
     hi = nb.batch_requirements([(F, N, K, 1.0)], "joint", precision="bf16")
     assert hi[0] - lo[0] == -(-F // 64) + -(-(-(-N // 8)) // 32) and hi[1] == lo[1]
-    # W update only: two row groups (F = 5000 rows, 157 tiles)
-    lo = nb.batch_requirements([(5000, N, K, 1.0)], "joint")
-    hi = nb.batch_requirements([(5000, N, K, 1.0)], "joint", precision="bf16")
+    # W update only: two row groups (F = 5000 rows, 157 tiles, 128 per item)
+    lo = nb.batch_requirements([(5000, N, K, 1.0)], "joint", [128] * 48)
+    hi = nb.batch_requirements([(5000, N, K, 1.0)], "joint", [128] * 48, precision="bf16")
     assert hi[0] - lo[0] == -(-5000 // 64)
     # two column groups (4 tiles per item): no difference
     assert (nb.batch_requirements([(F, N, K, 1.0)], "joint", [4] * 48)

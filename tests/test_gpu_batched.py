@@ -62,8 +62,12 @@ def oracle_step(V, W, H, beta, mode):
     return f(V.astype(np.float64), W.astype(np.float64), H.astype(np.float64), beta)
 
 
+# tiles 0: the context's table (every problem here one group per pass: in
+# float32 no update phases); 1, 3: several groups (all four phases); 12: a mix
+# of both and of problems that skip only the W-update phase (F = 500: two row
+# groups, N = 260: one column group)
 @pytest.mark.parametrize("mode", ["joint", "alternating"])
-@pytest.mark.parametrize("tiles", [0, 1, 3])
+@pytest.mark.parametrize("tiles", [0, 1, 3, 12])
 def test_batched_step_matches_oracle(mode, tiles):
     probs = make_set(SPECS)
     d = to_dev(probs)

@@ -310,7 +310,7 @@ def test_tune_writes_and_reads_its_cache(tmp_path):
     print("[tune] first call", flush=True)
     tiles, ms, hit = nb.tune(probs, "joint", iters=1, cache=cache, ctx=ctx)
     assert not hit and ms > 0 and len(tiles) == nb.BATCH_BUCKETS
-    assert all(t in (4, 8, 16, 32, 64, 128) for t in tiles)
+    assert all(t in (4, 8, 16, 32, 64, 128, 256) for t in tiles)
     for (W0, H0), (_, W, H, _) in zip(before, probs):
         assert torch.equal(W0, W) and torch.equal(H0, H)
     assert nb.get_batch_tiles(ctx) == tiles
