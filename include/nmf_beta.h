@@ -360,7 +360,10 @@ nmf_status nmf_sparse_validate(nmf_ctx_t ctx, void* stream, const nmf_sparse_v* 
  * computation as nmf_beta_step in the batch's mode -- in ONE persistent kernel
  * launch.  Work items of all problems (W pass, W update, H pass, H update) are
  * taken from a queue listed phase by phase; a per-problem completion counter
- * lets an item start once its problem's previous phase has finished.
+ * lets an item start once its problem's previous phase that has items has
+ * finished.  A problem whose rows take one column group has no W-update items
+ * (its W-pass items apply the W update), and if its columns also take one row
+ * group no H-update items either (its H-pass items apply the H update).
  *
  * The batch owns its own device memory (descriptors, queue, workspace, status
  * word), allocated by nmf_batch_create; nmf_batch_step allocates nothing and
@@ -476,14 +479,15 @@ nmf_status nmf_tune(nmf_ctx_t ctx, void* stream, const nmf_problem* problems, in
  * ------------------------------------------------------------------------- */
 
 /* Items per step and workspace bytes that `count` problems (host descriptors;
- * only the sizes and beta are read) need in `mode` and `precision`
- * (NMF_FP32 / NMF_BF16 / NMF_FP16) under `tiles` (host
- * int32[NMF_BATCH_BUCKETS]; NULL: 256 in every bucket).  The item count is the
- * batch's exact one: in float32 a problem whose rows take one column group has
- * its W update applied by its W-pass items and no W-update items.  Host only,
- * no GPU.  NMF_ERR_ARG for a bad mode, precision or table, NMF_ERR_SHAPE /
- * NMF_ERR_UNSUPPORTED for a size out of range (K > 64), NMF_ERR_BETA for a
- * beta that is not finite. */
+ * only the sizes and beta are read) need in `mode` and `precision` (NMF_FP32 or
+ * NMF_BF16) under `tiles` (host int32[NMF_BATCH_BUCKETS]; NULL: 256 in every
+ * bucket).  The item count is the batch's exact one: a problem whose rows take
+ * one column group has its W update applied by its W-pass items (no W-update
+ * items), and if its columns also take one row group its H update by its
+ * H-pass items (no H-update items).  Host only, no GPU.  NMF_ERR_ARG for a bad
+ * mode, precision or table, NMF_ERR_UNSUPPORTED for NMF_FP16 or K > 64,
+ * NMF_ERR_SHAPE for a size out of range, NMF_ERR_BETA for a beta that is not
+ * finite. */
 nmf_status nmf_batch_requirements(const nmf_problem* problems, int32_t count, int32_t mode, int32_t precision,
                                   const int32_t* tiles, int64_t* items, int64_t* workspace_bytes);
 

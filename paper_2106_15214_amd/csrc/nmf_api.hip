@@ -1407,6 +1407,7 @@ nmf_status nmf_batch_requirements(const nmf_problem* pr, int32_t count, int32_t 
   if (count < 1) return NMF_ERR_ARG;
   if (mode != NMF_ALTERNATING && mode != NMF_JOINT) return NMF_ERR_ARG;
   if (precision != NMF_FP32 && precision != NMF_BF16 && precision != NMF_FP16) return NMF_ERR_ARG;
+  if (precision == NMF_FP16) return NMF_ERR_UNSUPPORTED;  // batches run float32 or bfloat16 products
   if (tiles)
     for (int b = 0; b < kBatchBuckets; ++b)
       if (tiles[b] < 1 || tiles[b] > 4096) return NMF_ERR_ARG;

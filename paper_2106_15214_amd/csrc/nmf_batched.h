@@ -8,8 +8,8 @@
 //   H-pass items  (cols items: H-step partials from the kept P, Q in joint mode,
 //                  column sums of W_new)
 //   H-update units (H_new, normalization, W write-back, objective total)
-// A float32 problem whose rows take one column group has no W-update items: its
-// W-pass items apply the W update.  If its columns also take one row group it
+// A problem whose rows take one column group has no W-update items: its W-pass
+// items apply the W update.  If its columns also take one row group it
 // has no H-update items either: its W-pass items also write the column
 // partials of W_new and its H-pass items apply the H update and write W back.
 // A per-problem counter of finished items per phase replaces grid barriers: an
@@ -52,31 +52,34 @@ __device__ __forceinline__ T load_const(const __attribute__((address_space(4))) 
 // budget is the largest single path and not the union of all of them inlined
 // into one body (which spilled heavily); this is what lets two workgroups share
 // a compute unit.
-// W-pass item of a float32 problem whose rows take one column group: the item
-// applies the W update from its accumulators; its objective terms are added to
+// W-pass item of a problem whose rows take one column group: the item applies
+// the W update from its accumulators; its objective terms are added to
 // the caller's objsum.  A function of its own, so that its registers are
 // allocated apart from the other phases'.  (Like batch_item it is handed a
 // reference into its caller's frame, which keeps the call from being marked as
 // one that could skip the caller's frame; such calls make the callee save the
 // callee-saved registers it uses, hundreds of bytes per lane per item.)
-template <int BC, int KB, bool JOINT, bool OBJ>
+template <int BC, int KB, int PREC, bool JOINT, bool OBJ>
 __device__ __noinline__ void batch_wpass_fused(ConstProblemPtr P, int item, float* lds, double& objsum) {
   const SweepRowsArgs ra = load_const(&P->ra);
-  rows_item<BC, KB, KIND_UPDATE, OBJ, JOINT, true>(ra, item, lds, objsum, &P->ua);
+  if constexpr (PREC == 0) rows_item<BC, KB, KIND_UPDATE, OBJ, JOINT, true>(ra, item, lds, objsum, &P->ua);
+  else rows_item_lp<BC, KB, OBJ, __bf16, JOINT, true>(ra, item, lds, objsum, &P->ua);
 }
 
-// H-pass item of a float32 problem whose W-pass items applied the W update and
+// H-pass item of a problem whose W-pass items applied the W update and
 // whose columns take one row group: the column norms and sums of W_new from
 // the W pass's row-block partials, the H-step contractions of the item's
 // columns, the H update of those columns, this item's share of the W
 // write-back, and (item 0) the objective total.
-template <int BC, int KB, bool JOINT, bool OBJ>
+template <int BC, int KB, int PREC, bool JOINT, bool OBJ>
 __device__ __noinline__ void batch_hpass_fused(ConstProblemPtr P, int prob, int item, const BatchArgs& b,
                                                float* lds, double* red, float* norm_s, float* csum_s) {
   reduce_columns<KB>(P->ha.pcol, P->ha.pcol_blocks, reinterpret_cast<double*>(lds), norm_s, csum_s);
   {
     const SweepColsArgs ca = load_const(&P->ca);
-    cols_item<BC, KB, KIND_UPDATE, JOINT, JOINT, true>(ca, item, lds, &P->ha, norm_s, csum_s);
+    if constexpr (PREC == 0) cols_item<BC, KB, KIND_UPDATE, JOINT, JOINT, true>(ca, item, lds, &P->ha, norm_s, csum_s);
+    else if constexpr (JOINT) cols_item_lp_pq<BC, KB, __bf16, true>(ca, item, lds, &P->ha, norm_s, csum_s);
+    else cols_item_lp<BC, KB, false, __bf16, true>(ca, item, lds, &P->ha, norm_s, csum_s);
   }
   const UpdateHArgs ha = load_const(&P->ha);
   const int items = P->items[PH_HPASS];
@@ -155,30 +158,30 @@ __device__ __forceinline__ void batch_item_bc(int bc, ConstProblemPtr P, int pro
   }
 }
 
-template <int KB, bool JOINT, bool OBJ>
+template <int KB, int PREC, bool JOINT, bool OBJ>
 __device__ __forceinline__ void batch_wpass_fused_bc(int bc, ConstProblemPtr P, int item, float* lds,
                                                      double& objsum) {
   switch (bc) {
-    case BC_GEN: batch_wpass_fused<BC_GEN, KB, JOINT, OBJ>(P, item, lds, objsum); break;
-    case BC_B2: batch_wpass_fused<BC_B2, KB, JOINT, OBJ>(P, item, lds, objsum); break;
-    case BC_B1: batch_wpass_fused<BC_B1, KB, JOINT, OBJ>(P, item, lds, objsum); break;
-    case BC_B0: batch_wpass_fused<BC_B0, KB, JOINT, OBJ>(P, item, lds, objsum); break;
-    case BC_B05: batch_wpass_fused<BC_B05, KB, JOINT, OBJ>(P, item, lds, objsum); break;
-    default: batch_wpass_fused<BC_B15, KB, JOINT, OBJ>(P, item, lds, objsum); break;
+    case BC_GEN: batch_wpass_fused<BC_GEN, KB, PREC, JOINT, OBJ>(P, item, lds, objsum); break;
+    case BC_B2: batch_wpass_fused<BC_B2, KB, PREC, JOINT, OBJ>(P, item, lds, objsum); break;
+    case BC_B1: batch_wpass_fused<BC_B1, KB, PREC, JOINT, OBJ>(P, item, lds, objsum); break;
+    case BC_B0: batch_wpass_fused<BC_B0, KB, PREC, JOINT, OBJ>(P, item, lds, objsum); break;
+    case BC_B05: batch_wpass_fused<BC_B05, KB, PREC, JOINT, OBJ>(P, item, lds, objsum); break;
+    default: batch_wpass_fused<BC_B15, KB, PREC, JOINT, OBJ>(P, item, lds, objsum); break;
   }
 }
 
-template <int KB, bool JOINT, bool OBJ>
+template <int KB, int PREC, bool JOINT, bool OBJ>
 __device__ __forceinline__ void batch_hpass_fused_bc(int bc, ConstProblemPtr P, int prob, int item,
                                                      const BatchArgs& b, float* lds, double* red, float* norm_s,
                                                      float* csum_s) {
   switch (bc) {
-    case BC_GEN: batch_hpass_fused<BC_GEN, KB, JOINT, OBJ>(P, prob, item, b, lds, red, norm_s, csum_s); break;
-    case BC_B2: batch_hpass_fused<BC_B2, KB, JOINT, OBJ>(P, prob, item, b, lds, red, norm_s, csum_s); break;
-    case BC_B1: batch_hpass_fused<BC_B1, KB, JOINT, OBJ>(P, prob, item, b, lds, red, norm_s, csum_s); break;
-    case BC_B0: batch_hpass_fused<BC_B0, KB, JOINT, OBJ>(P, prob, item, b, lds, red, norm_s, csum_s); break;
-    case BC_B05: batch_hpass_fused<BC_B05, KB, JOINT, OBJ>(P, prob, item, b, lds, red, norm_s, csum_s); break;
-    default: batch_hpass_fused<BC_B15, KB, JOINT, OBJ>(P, prob, item, b, lds, red, norm_s, csum_s); break;
+    case BC_GEN: batch_hpass_fused<BC_GEN, KB, PREC, JOINT, OBJ>(P, prob, item, b, lds, red, norm_s, csum_s); break;
+    case BC_B2: batch_hpass_fused<BC_B2, KB, PREC, JOINT, OBJ>(P, prob, item, b, lds, red, norm_s, csum_s); break;
+    case BC_B1: batch_hpass_fused<BC_B1, KB, PREC, JOINT, OBJ>(P, prob, item, b, lds, red, norm_s, csum_s); break;
+    case BC_B0: batch_hpass_fused<BC_B0, KB, PREC, JOINT, OBJ>(P, prob, item, b, lds, red, norm_s, csum_s); break;
+    case BC_B05: batch_hpass_fused<BC_B05, KB, PREC, JOINT, OBJ>(P, prob, item, b, lds, red, norm_s, csum_s); break;
+    default: batch_hpass_fused<BC_B15, KB, PREC, JOINT, OBJ>(P, prob, item, b, lds, red, norm_s, csum_s); break;
   }
 }
 
@@ -237,19 +240,19 @@ __global__ __launch_bounds__(kBlock, 2) void batched_step_kernel(BatchArgs b) {
 
     const int kb = P->kb, bc = P->bc;
     bool fused_item = false;
-    if constexpr (PREC == 0) {
+    if constexpr (PREC <= 1) {
       if (phase == PH_WPASS && P->wfused) {
         double objsum = 0.0;
-        if (kb == 1) batch_wpass_fused_bc<1, JOINT, OBJ>(bc, P, item, lds, objsum);
-        else batch_wpass_fused_bc<2, JOINT, OBJ>(bc, P, item, lds, objsum);
+        if (kb == 1) batch_wpass_fused_bc<1, PREC, JOINT, OBJ>(bc, P, item, lds, objsum);
+        else batch_wpass_fused_bc<2, PREC, JOINT, OBJ>(bc, P, item, lds, objsum);
         if (OBJ) {
           const double sum = block_sum(objsum, red);
           if (tid == 0) P->ra.pobj[item] = sum;
         }
         fused_item = true;
       } else if (phase == PH_HPASS && P->hfused) {
-        if (kb == 1) batch_hpass_fused_bc<1, JOINT, OBJ>(bc, P, prob, item, b, lds, red, norm_s, csum_s);
-        else batch_hpass_fused_bc<2, JOINT, OBJ>(bc, P, prob, item, b, lds, red, norm_s, csum_s);
+        if (kb == 1) batch_hpass_fused_bc<1, PREC, JOINT, OBJ>(bc, P, prob, item, b, lds, red, norm_s, csum_s);
+        else batch_hpass_fused_bc<2, PREC, JOINT, OBJ>(bc, P, prob, item, b, lds, red, norm_s, csum_s);
         fused_item = true;
       }
     }

@@ -342,6 +342,196 @@ __device__ __forceinline__ KlQueue kl_queue_of(float* lds, int wave) {
 }
 
 // ---------------------------------------------------------------------------
+// W update applied by a rows item of a problem whose rows take one column group
+// (its accumulators hold the whole W-step contractions of rows f0 .. f0 + 31 of
+// its wave): W_new, and chi_1, chi_2 in joint mode or the transposed W_new in
+// alternating mode, as update_w_rows writes them, with the same float64
+// arithmetic.  ROWSUM: the beta = 1 denominator is the row sums of H~ (rsum, as
+// the rows item accumulates them), gathered per k through LDS.  With u->pcol set
+// it also writes the column sums of W_new^2 and W_new over the item's 128 rows
+// to u->pcol[rb][2][KP].  Every thread of the workgroup calls it, after the
+// item's last barrier.
+// ---------------------------------------------------------------------------
+template <int KB, bool ROWSUM, class UPtr>
+__device__ __forceinline__ void finish_w_rows(const SweepRowsArgs& a, UPtr u, const f32x16 (&accN)[KB],
+                                              const f32x16 (&accD)[KB], const float (&rsum)[KB], float* lds,
+                                              int rb, int f0, bool wave_on) {
+  constexpr int KP = 32 * KB;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, hi = lane >> 5;
+  const int K = a.K;
+  // the beta = 1 denominator: row sums of H~ over all N (this item's single
+  // group), gathered per k through LDS
+  float* const rs_s = lds;  // [KP]
+  if (ROWSUM) {
+    __syncthreads();  // the staged tiles are no longer read
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      float x = rsum[j];
+      x += __shfl_xor(x, 1, 64);
+      x += __shfl_xor(x, 2, 64);
+      x += __shfl_xor(x, 4, 64);
+      const int e4 = tid + kBlock * j;
+      if ((e4 & 7) == 0) rs_s[e4 >> 3] = x;
+    }
+    __syncthreads();
+  }
+  double csq[KB], csm[KB];  // this lane's column sums of W_new^2 and W_new
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) { csq[kb] = 0.0; csm[kb] = 0.0; }
+  if (wave_on) {
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      const int k = kb * 32 + li;
+      const bool kok = k < K;
+      const double den1 = ROWSUM ? (double)rs_s[k] : 0.0;
+      float wt[16], wn[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int f = f0 + acc_row(r, hi);
+        wt[r] = ldz(u->W, (int64_t)f * u->ldw + k, f < a.F && kok);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int f = f0 + acc_row(r, hi);
+        float w1 = 0.f, c1 = 0.f, c2 = 0.f;
+        if (f < a.F && kok) {
+          const double num = (double)accN[kb][r];
+          const double den = ROWSUM ? den1 : (double)accD[kb][r];
+          const double ratio = num / den;
+          if (!(den > 0.0) || !isfinite(ratio)) set_flag(u->flags, 1u);
+          const double rr = pow_gamma(ratio, u->gamma);
+          const double w0 = (double)wt[r];
+          const double wnew = w0 * rr;
+          w1 = (float)wnew;
+          if (u->joint) chi_terms(u->beta, w0, rr, wnew, c1, c2);
+        }
+        wn[r] = w1;
+        if (f < a.F) {
+          const int64_t o = (int64_t)f * KP + k;
+          u->Wn[o] = w1;
+          if (u->joint) { u->C1[o] = c1; u->C2[o] = c2; }
+        }
+        csq[kb] += (double)w1 * (double)w1;
+        csm[kb] += (double)w1;
+      }
+      if (!u->joint) {
+        // W_new^T: registers 4q..4q+3 are four consecutive rows of one column
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int fb = f0 + 8 * q + 4 * hi;
+          float* const dst = u->WT + (int64_t)k * u->ldt + fb;
+          if (fb + 3 < a.F) {
+            *reinterpret_cast<float4*>(dst) = make_float4(wn[4 * q], wn[4 * q + 1], wn[4 * q + 2], wn[4 * q + 3]);
+          } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              if (fb + i < a.F) dst[i] = wn[4 * q + i];
+          }
+        }
+      }
+    }
+  }
+  if (u->pcol) {
+    // lanes hi = 0, 1 hold the same column; the four waves' sums are added
+    // in wave order through LDS (rows past F hold W_new = 0)
+    double* const cs = reinterpret_cast<double*>(lds + 2 * KP);  // [kWaves][2][KP]
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      const double q2 = csq[kb] + __shfl_xor(csq[kb], 32, 64);
+      const double q1 = csm[kb] + __shfl_xor(csm[kb], 32, 64);
+      if (hi == 0) {
+        cs[(wave * 2 + 0) * KP + kb * 32 + li] = q2;
+        cs[(wave * 2 + 1) * KP + kb * 32 + li] = q1;
+      }
+    }
+    __syncthreads();
+    if (tid < 2 * KP) {
+      const int part = tid / KP, k = tid % KP;
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) t += cs[(w * 2 + part) * KP + k];
+      u->pcol[(int64_t)rb * 2 * KP + tid] = t;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// H update applied by one wave of a cols item of a problem whose columns take
+// one row group (its accumulators hold the whole H-step contractions of columns
+// n0w .. n0w + 31), in place, as update_h_cols_multi computes it: H_new = H~
+// (num/den)^gamma, times the column norm of W_new when normalizing, with den =
+// the column sums of W_new at beta = 1; norm_s / csum_s hold those norms and
+// sums.  No other item reads these columns of H~.
+// ---------------------------------------------------------------------------
+template <int KB, class UHPtr>
+__device__ __forceinline__ void finish_h_cols(const SweepColsArgs& a, UHPtr uh, const f32x16 (&accN)[KB],
+                                              const f32x16 (&accD)[KB], const float* norm_s, const float* csum_s,
+                                              int n0w) {
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 31, hi = lane >> 5;
+  const int K = a.K;
+  float* const Hw = uh->H;
+  const int64_t ldh = uh->ldh;
+  const bool h4 = ((uintptr_t)Hw % 16 == 0) && (ldh % 4 == 0);
+  const int N = a.N;
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    const int k = kb * 32 + li;
+    const bool kok = k < K;
+    double nk = 1.0;
+    if (uh->normalize && kok) {
+      const float x = norm_s[k];
+      if (x > 0.f) nk = (double)x;
+    }
+    const double den1 = uh->beta_one && kok ? (double)csum_s[k] : 0.0;
+    // H~ at the accumulator positions: registers 4q..4q+3 are columns
+    // n0w + 8q + 4hi + 0..3 of row k
+    float hv[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int nb = n0w + 8 * q + 4 * hi;
+      const int64_t o = (int64_t)k * ldh + nb;
+      if (h4 && nb + 3 < N) {
+        const float4 x = ldc4(Hw, o, kok);
+        hv[4 * q + 0] = x.x; hv[4 * q + 1] = x.y; hv[4 * q + 2] = x.z; hv[4 * q + 3] = x.w;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) hv[4 * q + j] = ldc(Hw, o + j, kok && nb + j < N);
+      }
+    }
+    float hn[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int n = n0w + acc_row(r, hi);
+      hn[r] = 0.f;
+      if (kok && n < N) {
+        const double num = (double)accN[kb][r];
+        const double dd = uh->beta_one ? den1 : (double)accD[kb][r];
+        const double ratio = num / dd;
+        if (!(dd > 0.0) || !isfinite(ratio)) set_flag(uh->flags, 1u);
+        hn[r] = (float)((double)hv[r] * (pow_gamma(ratio, uh->gamma) * nk));
+      }
+    }
+    if (kok) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int nb = n0w + 8 * q + 4 * hi;
+        float* const dst = Hw + (int64_t)k * ldh + nb;
+        if (h4 && nb + 3 < N) {
+          *reinterpret_cast<float4*>(dst) = make_float4(hn[4 * q], hn[4 * q + 1], hn[4 * q + 2], hn[4 * q + 3]);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (nb + j < N) dst[j] = hn[4 * q + j];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // rows item: W-step contractions (reduction over n) for 128 rows of V over the
 // column tiles of one group.  Optional objective terms (added to objsum), and
 // optionally P and Q stored tile by tile ([tile][n][f], tile = ti * NT + tj) for
@@ -574,100 +764,7 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
 
   if (OBJ && BC == BC_B1 && wave_on) klq.drain(objsum);
   if constexpr (FINISH) {
-    // the beta = 1 denominator: row sums of H~ over all N (this item's single
-    // group), gathered per k through LDS
-    float* const rs_s = lds;  // [KP]
-    if (ROWSUM) {
-      __syncthreads();  // the staged tiles are no longer read
-#pragma unroll
-      for (int j = 0; j < KB; ++j) {
-        float x = rsum[j];
-        x += __shfl_xor(x, 1, 64);
-        x += __shfl_xor(x, 2, 64);
-        x += __shfl_xor(x, 4, 64);
-        const int e4 = tid + kBlock * j;
-        if ((e4 & 7) == 0) rs_s[e4 >> 3] = x;
-      }
-      __syncthreads();
-    }
-    double csq[KB], csm[KB];  // this lane's column sums of W_new^2 and W_new
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) { csq[kb] = 0.0; csm[kb] = 0.0; }
-    if (wave_on) {
-#pragma unroll
-      for (int kb = 0; kb < KB; ++kb) {
-        const int k = kb * 32 + li;
-        const bool kok = k < K;
-        const double den1 = ROWSUM ? (double)rs_s[k] : 0.0;
-        float wt[16], wn[16];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int f = f0 + acc_row(r, hi);
-          wt[r] = ldz(u->W, (int64_t)f * u->ldw + k, f < a.F && kok);
-        }
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int f = f0 + acc_row(r, hi);
-          float w1 = 0.f, c1 = 0.f, c2 = 0.f;
-          if (f < a.F && kok) {
-            const double num = (double)accN[kb][r];
-            const double den = ROWSUM ? den1 : (double)accD[kb][r];
-            const double ratio = num / den;
-            if (!(den > 0.0) || !isfinite(ratio)) set_flag(u->flags, 1u);
-            const double rr = pow_gamma(ratio, u->gamma);
-            const double w0 = (double)wt[r];
-            const double wnew = w0 * rr;
-            w1 = (float)wnew;
-            if (u->joint) chi_terms(u->beta, w0, rr, wnew, c1, c2);
-          }
-          wn[r] = w1;
-          if (f < a.F) {
-            const int64_t o = (int64_t)f * KP + k;
-            u->Wn[o] = w1;
-            if (u->joint) { u->C1[o] = c1; u->C2[o] = c2; }
-          }
-          csq[kb] += (double)w1 * (double)w1;
-          csm[kb] += (double)w1;
-        }
-        if (!u->joint) {
-          // W_new^T: registers 4q..4q+3 are four consecutive rows of one column
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int fb = f0 + 8 * q + 4 * hi;
-            float* const dst = u->WT + (int64_t)k * u->ldt + fb;
-            if (fb + 3 < a.F) {
-              *reinterpret_cast<float4*>(dst) = make_float4(wn[4 * q], wn[4 * q + 1], wn[4 * q + 2], wn[4 * q + 3]);
-            } else {
-#pragma unroll
-              for (int i = 0; i < 4; ++i)
-                if (fb + i < a.F) dst[i] = wn[4 * q + i];
-            }
-          }
-        }
-      }
-    }
-    if (u->pcol) {
-      // lanes hi = 0, 1 hold the same column; the four waves' sums are added
-      // in wave order through LDS (rows past F hold W_new = 0)
-      double* const cs = reinterpret_cast<double*>(lds + 2 * KP);  // [kWaves][2][KP]
-#pragma unroll
-      for (int kb = 0; kb < KB; ++kb) {
-        const double q2 = csq[kb] + __shfl_xor(csq[kb], 32, 64);
-        const double q1 = csm[kb] + __shfl_xor(csm[kb], 32, 64);
-        if (hi == 0) {
-          cs[(wave * 2 + 0) * KP + kb * 32 + li] = q2;
-          cs[(wave * 2 + 1) * KP + kb * 32 + li] = q1;
-        }
-      }
-      __syncthreads();
-      if (tid < 2 * KP) {
-        const int part = tid / KP, k = tid % KP;
-        double t = 0.0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) t += cs[(w * 2 + part) * KP + k];
-        u->pcol[(int64_t)rb * 2 * KP + tid] = t;
-      }
-    }
+    finish_w_rows<KB, ROWSUM>(a, u, accN, accD, rsum, lds, rb, f0, wave_on);
     return;
   }
   if (CONTRACT && wave_on) {
@@ -929,9 +1026,12 @@ __device__ __forceinline__ void split_low(const float (&x)[8], typename LowP<T>:
 }
 
 // rows item with low-precision products (update kind).  The H~ tile is staged
-// in LDS in float32 as in rows_item; operands are converted when read.
-template <int BC, int KB, bool OBJ, class T, bool STORE_PQ = false>
-__device__ __forceinline__ void rows_item_lp(const SweepRowsArgs& a, int item, float* lds, double& objsum) {
+// in LDS in float32 as in rows_item; operands are converted when read.  FINISH
+// and `u` as in rows_item.
+template <int BC, int KB, bool OBJ, class T, bool STORE_PQ = false, bool FINISH = false,
+          class UPtr = const UpdateWArgs*>
+__device__ __forceinline__ void rows_item_lp(const SweepRowsArgs& a, int item, float* lds, double& objsum,
+                                             UPtr u = nullptr) {
   typedef typename LowP<T>::v8 v8;
   constexpr int KP = 32 * KB;
   constexpr int KS = KP / 16;  // 16-deep steps of Lambda
@@ -1140,6 +1240,11 @@ __device__ __forceinline__ void rows_item_lp(const SweepRowsArgs& a, int item, f
   }
 
   if (OBJ && BC == BC_B1 && wave_on) klq.drain(objsum);
+  if (!rok) set_flag(a.flags, 8u);  // operand outside the float16 range
+  if constexpr (FINISH) {
+    finish_w_rows<KB, ROWSUM>(a, u, accN, accD, rsum, lds, rb, f0, wave_on);
+    return;
+  }
   if (wave_on) {
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
@@ -1154,7 +1259,6 @@ __device__ __forceinline__ void rows_item_lp(const SweepRowsArgs& a, int item, f
       }
     }
   }
-  if (!rok) set_flag(a.flags, 8u);  // operand outside the float16 range
   if (ROWSUM) {
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
@@ -1177,9 +1281,11 @@ constexpr int cols_item_lp_lds() {
 
 // cols item with low-precision products (update kind).  The factor forming
 // Lambda is read row-major (C0, ld KP): W~ (joint) or W_new (alternating, then
-// C0 == C1 and its tile is staged once).
-template <int BC, int KB, bool DUAL, class T>
-__device__ __forceinline__ void cols_item_lp(const SweepColsArgs& a, int item, float* lds) {
+// C0 == C1 and its tile is staged once).  FINISH, uh, norm_s and csum_s as in
+// cols_item.
+template <int BC, int KB, bool DUAL, class T, bool FINISH = false, class UHPtr = const UpdateHArgs*>
+__device__ __forceinline__ void cols_item_lp(const SweepColsArgs& a, int item, float* lds, UHPtr uh = nullptr,
+                                             const float* norm_s = nullptr, const float* csum_s = nullptr) {
   typedef typename LowP<T>::v8 v8;
   constexpr int KP = 32 * KB;
   constexpr int KS = KP / 16;
@@ -1343,6 +1449,11 @@ __device__ __forceinline__ void cols_item_lp(const SweepColsArgs& a, int item, f
     __syncthreads();
   }
 
+  if (!rok) set_flag(a.flags, 8u);  // operand outside the float16 range
+  if constexpr (FINISH) {
+    if (wave_on) finish_h_cols<KB>(a, uh, accN, accD, norm_s, csum_s, n0w);
+    return;
+  }
   if (wave_on) {
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
@@ -1357,7 +1468,6 @@ __device__ __forceinline__ void cols_item_lp(const SweepColsArgs& a, int item, f
       }
     }
   }
-  if (!rok) set_flag(a.flags, 8u);  // operand outside the float16 range
 }
 
 // Column sums of W_new^2 and W_new over rows [f0, f1) of the row-major W_new
@@ -1417,8 +1527,10 @@ __device__ __forceinline__ void cols_prologue(const SweepColsArgs& a, int item, 
 // P, Q tiles the W pass kept in the product type (no Lambda~, no powers): lane
 // (li, hi) reads, for column n0w + li, the eight rows acc_row(8 st + e, hi) of
 // step st as two 4-entry runs.  At beta = 2, P = V + kappa is read from V.
-template <int BC, int KB, class T>
-__device__ __forceinline__ void cols_item_lp_pq(const SweepColsArgs& a, int item, float* lds) {
+// FINISH, uh, norm_s and csum_s as in cols_item.
+template <int BC, int KB, class T, bool FINISH = false, class UHPtr = const UpdateHArgs*>
+__device__ __forceinline__ void cols_item_lp_pq(const SweepColsArgs& a, int item, float* lds, UHPtr uh = nullptr,
+                                                const float* norm_s = nullptr, const float* csum_s = nullptr) {
   typedef typename LowP<T>::v8 v8;
   constexpr int KP = 32 * KB;
   constexpr int CS = KP + 4;
@@ -1557,6 +1669,11 @@ __device__ __forceinline__ void cols_item_lp_pq(const SweepColsArgs& a, int item
     __syncthreads();
   }
 
+  if (!rok) set_flag(a.flags, 8u);  // operand outside the float16 range
+  if constexpr (FINISH) {
+    if (wave_on) finish_h_cols<KB>(a, uh, accN, accD, norm_s, csum_s, n0w);
+    return;
+  }
   if (wave_on) {
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
@@ -1571,7 +1688,6 @@ __device__ __forceinline__ void cols_item_lp_pq(const SweepColsArgs& a, int item
       }
     }
   }
-  if (!rok) set_flag(a.flags, 8u);  // operand outside the float16 range
 }
 
 // LDS bytes a cols item needs.
@@ -1806,64 +1922,7 @@ __device__ __forceinline__ void cols_item(const SweepColsArgs& a, int item, floa
   }
 
   if constexpr (FINISH) {
-    if (!wave_on) return;
-    float* const Hw = uh->H;
-    const int64_t ldh = uh->ldh;
-    const bool h4 = ((uintptr_t)Hw % 16 == 0) && (ldh % 4 == 0);
-    const int N = a.N;
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
-      const int k = kb * 32 + li;
-      const bool kok = k < K;
-      double nk = 1.0;
-      if (uh->normalize && kok) {
-        const float x = norm_s[k];
-        if (x > 0.f) nk = (double)x;
-      }
-      const double den1 = uh->beta_one && kok ? (double)csum_s[k] : 0.0;
-      // H~ at the accumulator positions: registers 4q..4q+3 are columns
-      // n0w + 8q + 4hi + 0..3 of row k
-      float hv[16];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int nb = n0w + 8 * q + 4 * hi;
-        const int64_t o = (int64_t)k * ldh + nb;
-        if (h4 && nb + 3 < N) {
-          const float4 x = ldc4(Hw, o, kok);
-          hv[4 * q + 0] = x.x; hv[4 * q + 1] = x.y; hv[4 * q + 2] = x.z; hv[4 * q + 3] = x.w;
-        } else {
-#pragma unroll
-          for (int j = 0; j < 4; ++j) hv[4 * q + j] = ldc(Hw, o + j, kok && nb + j < N);
-        }
-      }
-      float hn[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int n = n0w + acc_row(r, hi);
-        hn[r] = 0.f;
-        if (kok && n < N) {
-          const double num = (double)accN[kb][r];
-          const double dd = uh->beta_one ? den1 : (double)accD[kb][r];
-          const double ratio = num / dd;
-          if (!(dd > 0.0) || !isfinite(ratio)) set_flag(uh->flags, 1u);
-          hn[r] = (float)((double)hv[r] * (pow_gamma(ratio, uh->gamma) * nk));
-        }
-      }
-      if (kok) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int nb = n0w + 8 * q + 4 * hi;
-          float* const dst = Hw + (int64_t)k * ldh + nb;
-          if (h4 && nb + 3 < N) {
-            *reinterpret_cast<float4*>(dst) = make_float4(hn[4 * q], hn[4 * q + 1], hn[4 * q + 2], hn[4 * q + 3]);
-          } else {
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-              if (nb + j < N) dst[j] = hn[4 * q + j];
-          }
-        }
-      }
-    }
+    if (wave_on) finish_h_cols<KB>(a, uh, accN, accD, norm_s, csum_s, n0w);
     return;
   }
   if (wave_on) {

@@ -215,10 +215,13 @@ NMF_PLAN_HD inline int bucket_of(int64_t F, int64_t N, int64_t K, double beta) {
   return ((kblocks_for(K) - 1) * 4 + cls) * kBatchBetaClasses + beta_class(beta);
 }
 
-// A float32 problem whose rows take one column group has the whole W-step
+// A problem whose rows take one column group has the whole W-step
 // contractions of a row block in one W-pass item, which then applies the W
-// update itself: the problem has no W-update items.
-NMF_PLAN_HD inline bool batch_w_fused(const Plan& p, int prec) { return p.n_groups == 1 && prec == NMF_FP32; }
+// update itself: the problem has no W-update items (batches run float32 or
+// bfloat16 products).
+NMF_PLAN_HD inline bool batch_w_fused(const Plan& p, int prec) {
+  return p.n_groups == 1 && (prec == NMF_FP32 || prec == NMF_BF16);
+}
 // If its columns also take one row group, the W-pass items write the column
 // partials of W_new (one per row block) and the H-pass items apply the H
 // update and write W back: the problem has no H-update items either.

@@ -179,24 +179,31 @@ def test_batch_requirements_invariants():
     i, _ = nb.batch_requirements([(F, N, K, 1.0)], "joint", [4096] * 48)
     rb, cb = -(-F // 128), -(-N // 128)
     assert i >= rb + cb and i <= rb + cb + F + N
-    # float32 applies the W update of a problem whose rows take one column group
-    # (here N / 32 = 94 tiles <= 128) in its W-pass items, and with one row group
-    # (F / 32 = 32 tiles) the H update in its H-pass items: ceil(F / 64)
-    # W-update items and ceil(ceil(N / 8) / 32) H-update items (K = 20: 8
-    # columns of 32 k per 256 threads, 32 such units an item) fewer than in
-    # bfloat16, the same workspace
-    lo = nb.batch_requirements([(F, N, K, 1.0)], "joint")
-    hi = nb.batch_requirements([(F, N, K, 1.0)], "joint", precision="bf16")
-    assert hi[0] - lo[0] == -(-F // 64) + -(-(-(-N // 8)) // 32) and hi[1] == lo[1]
-    # W update only: two row groups (F = 5000 rows, 157 tiles, 128 per item)
-    lo = nb.batch_requirements([(5000, N, K, 1.0)], "joint", [128] * 48)
-    hi = nb.batch_requirements([(5000, N, K, 1.0)], "joint", [128] * 48, precision="bf16")
-    assert hi[0] - lo[0] == -(-5000 // 64)
-    # two column groups (4 tiles per item): no difference
-    assert (nb.batch_requirements([(F, N, K, 1.0)], "joint", [4] * 48)
-            == nb.batch_requirements([(F, N, K, 1.0)], "joint", [4] * 48, precision="bf16"))
-    ib, bb = nb.batch_requirements(shapes, "joint", precision="fp16")
-    assert ib >= items and bb == bytes_
+    # the item count phase by phase (row blocks of 128 x column groups, W-update
+    # items of 64 rows, column blocks x row groups, H-update items of KP column
+    # units of 256 / KP columns), written out from the splits: a problem whose
+    # rows take one column group has no W-update items, and if its columns also
+    # take one row group no H-update items either
+    for (F2, N2, K2, t) in [(1000, 3000, 20, 256), (1000, 3000, 20, 128), (5000, 3000, 20, 128),
+                            (1000, 3000, 20, 4), (700, 4500, 50, 100), (33, 1000, 8, 12)]:
+        assert nb.batch_requirements([(F2, N2, K2, 0.5)], "joint", [t] * 48)[0] == _items_from_splits(F2, N2, K2, t)
+        assert (nb.batch_requirements([(F2, N2, K2, 0.5)], "alternating", [t] * 48, precision="bf16")[0]
+                == _items_from_splits(F2, N2, K2, t))
+
+
+def _groups(tiles_total, tiles):
+    g = -(-tiles_total // tiles)
+    per = -(-tiles_total // g)
+    return -(-tiles_total // per)
+
+
+def _items_from_splits(F, N, K, tiles):
+    KP = 32 if K <= 32 else 64
+    ng, fg = _groups(-(-N // 32), tiles), _groups(-(-F // 32), tiles)
+    w_pass, h_pass = -(-F // 128) * ng, -(-N // 128) * fg
+    w_update = 0 if ng == 1 else -(-F // 64)
+    h_update = 0 if ng == 1 and fg == 1 else -(-(-(-N // (256 // KP))) // KP)
+    return w_pass + w_update + h_pass + h_update
 
 
 def test_batch_requirements_checks():
@@ -219,6 +226,7 @@ def test_batch_requirements_checks():
     assert L.nmf_batch_requirements(arr, 0, 1, 0, None, ctypes.byref(n), ctypes.byref(b)) == E_ARG
     assert L.nmf_batch_requirements(arr, 1, 5, 0, None, ctypes.byref(n), ctypes.byref(b)) == E_ARG
     assert L.nmf_batch_requirements(arr, 1, 1, 7, None, ctypes.byref(n), ctypes.byref(b)) == E_ARG
+    assert L.nmf_batch_requirements(arr, 1, 1, 2, None, ctypes.byref(n), ctypes.byref(b)) == E_UNSUP  # FP16
 
 
 def test_batched_entry_points_null_context():
