@@ -352,7 +352,7 @@ __device__ __forceinline__ KlQueue kl_queue_of(float* lds, int wave) {
 // to u->pcol[rb][2][KP].  Every thread of the workgroup calls it, after the
 // item's last barrier.
 // ---------------------------------------------------------------------------
-template <int KB, bool ROWSUM, class UPtr>
+template <int KB, bool ROWSUM, bool WT_TILDE, class UPtr>
 __device__ __forceinline__ void finish_w_rows(const SweepRowsArgs& a, UPtr u, const f32x16 (&accN)[KB],
                                               const f32x16 (&accD)[KB], const float (&rsum)[KB], float* lds,
                                               int rb, int f0, bool wave_on) {
@@ -416,18 +416,21 @@ __device__ __forceinline__ void finish_w_rows(const SweepRowsArgs& a, UPtr u, co
         csq[kb] += (double)w1 * (double)w1;
         csm[kb] += (double)w1;
       }
-      if (!u->joint) {
-        // W_new^T: registers 4q..4q+3 are four consecutive rows of one column
+      if (WT_TILDE || !u->joint) {
+        // the transposed factor that forms Lambda in the H pass: W~^T
+        // (WT_TILDE: joint MM re-forming Lambda~) or W_new^T; registers
+        // 4q..4q+3 are four consecutive rows of one column
+        const float* const tr = WT_TILDE ? wt : wn;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int fb = f0 + 8 * q + 4 * hi;
           float* const dst = u->WT + (int64_t)k * u->ldt + fb;
           if (fb + 3 < a.F) {
-            *reinterpret_cast<float4*>(dst) = make_float4(wn[4 * q], wn[4 * q + 1], wn[4 * q + 2], wn[4 * q + 3]);
+            *reinterpret_cast<float4*>(dst) = make_float4(tr[4 * q], tr[4 * q + 1], tr[4 * q + 2], tr[4 * q + 3]);
           } else {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-              if (fb + i < a.F) dst[i] = wn[4 * q + i];
+              if (fb + i < a.F) dst[i] = tr[4 * q + i];
           }
         }
       }
@@ -539,13 +542,11 @@ __device__ __forceinline__ void finish_h_cols(const SweepColsArgs& a, UHPtr uh, 
 // formed once per outer iteration).
 // ---------------------------------------------------------------------------
 // FINISH (one column group: the item's accumulators hold the whole W-step
-// contractions of its rows): the item applies the W update itself from the
-// accumulators (W_new, and chi_1, chi_2 in joint mode or the transposed W_new in
-// alternating mode, as update_w_rows writes them) instead of writing partials;
-// `u` points to the update's arguments (read where they are used).  With
-// u->pcol set it also writes the column sums of W_new^2 and W_new over its 128
-// rows to u->pcol[rb][2][KP] (the normalization's partials, one per row block).
-template <int BC, int KB, int KIND, bool OBJ, bool STORE_PQ, bool FINISH = false,
+// contractions of its rows): the item applies the W update itself
+// (finish_w_rows) instead of writing partials; `u` points to the update's
+// arguments (read where they are used).  WT_TILDE: the transposed factor it
+// writes is W~ (joint MM whose H pass forms Lambda~ again).
+template <int BC, int KB, int KIND, bool OBJ, bool STORE_PQ, bool FINISH = false, bool WT_TILDE = false,
           class UPtr = const UpdateWArgs*>
 __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, float* lds, double& objsum,
                                           UPtr u = nullptr) {
@@ -764,7 +765,7 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
 
   if (OBJ && BC == BC_B1 && wave_on) klq.drain(objsum);
   if constexpr (FINISH) {
-    finish_w_rows<KB, ROWSUM>(a, u, accN, accD, rsum, lds, rb, f0, wave_on);
+    finish_w_rows<KB, ROWSUM, WT_TILDE>(a, u, accN, accD, rsum, lds, rb, f0, wave_on);
     return;
   }
   if (CONTRACT && wave_on) {
@@ -1242,7 +1243,7 @@ __device__ __forceinline__ void rows_item_lp(const SweepRowsArgs& a, int item, f
   if (OBJ && BC == BC_B1 && wave_on) klq.drain(objsum);
   if (!rok) set_flag(a.flags, 8u);  // operand outside the float16 range
   if constexpr (FINISH) {
-    finish_w_rows<KB, ROWSUM>(a, u, accN, accD, rsum, lds, rb, f0, wave_on);
+    finish_w_rows<KB, ROWSUM, false>(a, u, accN, accD, rsum, lds, rb, f0, wave_on);
     return;
   }
   if (wave_on) {
