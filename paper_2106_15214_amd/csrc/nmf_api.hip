@@ -1133,7 +1133,7 @@ nmf_status batch_create(nmf_ctx_s* c, const nmf_problem* pr, int count, int mode
   int64_t total = 0;
   for (int i = 0; i < count; ++i) {
     const nmf_problem& q = pr[i];
-    plans[i] = make_batch_plan(q.F, q.N, q.K, tiles[bucket_of(q.F, q.N, q.K, q.beta)], joint, o.precision);
+    plans[i] = make_batch_plan(q.F, q.N, q.K, q.beta, tiles[bucket_of(q.F, q.N, q.K, q.beta)], joint, o.precision);
     total += batch_items(plans[i], q.F, o.precision);
   }
   if (total >= (int64_t)1 << 31) return NMF_ERR_UNSUPPORTED;
@@ -1418,7 +1418,8 @@ nmf_status nmf_batch_requirements(const nmf_problem* pr, int32_t count, int32_t 
     if (q.K > 64) return NMF_ERR_UNSUPPORTED;
     if (!std::isfinite(q.beta)) return NMF_ERR_BETA;
     const int b = bucket_of(q.F, q.N, q.K, q.beta);
-    const Plan p = make_batch_plan(q.F, q.N, q.K, tiles ? tiles[b] : kBatchTilesDefault, mode == NMF_JOINT, precision);
+    const Plan p =
+        make_batch_plan(q.F, q.N, q.K, q.beta, tiles ? tiles[b] : kBatchTilesDefault, mode == NMF_JOINT, precision);
     n += batch_items(p, q.F, precision);
     bytes += (int64_t)align_up(p.total);
   }
@@ -1643,7 +1644,7 @@ nmf_status nmf_tune(nmf_ctx_t c, void* stream, const nmf_problem* pr, int32_t co
     for (int i = 0; i < count; ++i) {
       const nmf_problem& q = pr[i];
       if (bucket_of(q.F, q.N, q.K, q.beta) != b) continue;
-      const Plan p = make_batch_plan(q.F, q.N, q.K, t, joint, o.precision);
+      const Plan p = make_batch_plan(q.F, q.N, q.K, q.beta, t, joint, o.precision);
       sig.insert(sig.end(), {p.n_groups, p.tiles_n, p.f_groups, p.tiles_f});
     }
     return sig;

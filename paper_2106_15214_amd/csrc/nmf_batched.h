@@ -31,10 +31,10 @@ static_assert(2 * kBlock * 8 <= kBatchLdsBytes, "batched LDS");
 static_assert(kBatchWRows * (64 + 1) * 4 <= kBatchLdsBytes, "batched LDS");
 
 // Joint MM keeps P, Q between its passes except with float32 products at
-// K <= 32 (one K block), where its H pass forms Lambda~ again from W~^T; the
-// same rule as batch_keeps_pq, fixed per instantiation.
-template <int KB, int PREC, bool JOINT>
-constexpr bool kKeepPQ = JOINT && (PREC != 0 || KB > 1);
+// K <= 32 (one K block) or beta = 1, where its H pass forms Lambda~ again from
+// W~^T; the same rule as batch_keeps_pq, fixed per instantiation.
+template <int BC, int KB, int PREC, bool JOINT>
+constexpr bool kKeepPQ = JOINT && (PREC != 0 || (KB > 1 && BC != BC_B1));
 
 // Descriptors never change during the launch: reading them through the
 // constant address space lets the compiler keep their fields in scalar
@@ -68,7 +68,7 @@ __device__ __forceinline__ T load_const(const __attribute__((address_space(4))) 
 template <int BC, int KB, int PREC, bool JOINT, bool OBJ>
 __device__ __noinline__ void batch_wpass_fused(ConstProblemPtr P, int item, float* lds, double& objsum) {
   const SweepRowsArgs ra = load_const(&P->ra);
-  constexpr bool KEEP = kKeepPQ<KB, PREC, JOINT>;
+  constexpr bool KEEP = kKeepPQ<BC, KB, PREC, JOINT>;
   if constexpr (PREC == 0)
     rows_item<BC, KB, KIND_UPDATE, OBJ, KEEP, true, JOINT && !KEEP>(ra, item, lds, objsum, &P->ua);
   else rows_item_lp<BC, KB, OBJ, __bf16, JOINT, true>(ra, item, lds, objsum, &P->ua);
@@ -85,7 +85,7 @@ __device__ __noinline__ void batch_hpass_fused(ConstProblemPtr P, int prob, int 
   reduce_columns<KB>(P->ha.pcol, P->ha.pcol_blocks, reinterpret_cast<double*>(lds), norm_s, csum_s);
   {
     const SweepColsArgs ca = load_const(&P->ca);
-    constexpr bool KEEP = kKeepPQ<KB, PREC, JOINT>;
+    constexpr bool KEEP = kKeepPQ<BC, KB, PREC, JOINT>;
     if constexpr (PREC == 0) cols_item<BC, KB, KIND_UPDATE, JOINT, KEEP, true>(ca, item, lds, &P->ha, norm_s, csum_s);
     else if constexpr (JOINT) cols_item_lp_pq<BC, KB, __bf16, true>(ca, item, lds, &P->ha, norm_s, csum_s);
     else cols_item_lp<BC, KB, false, __bf16, true>(ca, item, lds, &P->ha, norm_s, csum_s);
@@ -110,7 +110,7 @@ __device__ __noinline__ void batch_item(ConstProblemPtr P, int prob, int phase, 
   if (phase == PH_WPASS) {
     const SweepRowsArgs ra = load_const(&P->ra);
     double objsum = 0.0;
-    if constexpr (PREC == 0) rows_item<BC, KB, KIND_UPDATE, OBJ, kKeepPQ<KB, PREC, JOINT>>(ra, item, lds, objsum);
+    if constexpr (PREC == 0) rows_item<BC, KB, KIND_UPDATE, OBJ, kKeepPQ<BC, KB, PREC, JOINT>>(ra, item, lds, objsum);
     else if constexpr (PREC == 1) rows_item_lp<BC, KB, OBJ, __bf16, JOINT>(ra, item, lds, objsum);
     else rows_item_lp<BC, KB, OBJ, _Float16, JOINT>(ra, item, lds, objsum);
     if (OBJ) {
@@ -122,11 +122,11 @@ __device__ __noinline__ void batch_item(ConstProblemPtr P, int prob, int phase, 
     // alternating MU, W~ for joint MM without kept P, Q); a joint H pass that
     // contracts the kept P, Q never forms Lambda again
     const UpdateWArgs ua = load_const(&P->ua);
-    update_w_rows<KB, kBatchWRows>(ua, item * kBatchWRows, !kKeepPQ<KB, PREC, JOINT>, row_sum_den<KB>(ua), lds);
+    update_w_rows<KB, kBatchWRows>(ua, item * kBatchWRows, !kKeepPQ<BC, KB, PREC, JOINT>, row_sum_den<KB>(ua), lds);
   } else if (phase == PH_HPASS) {
     const SweepColsArgs ca = load_const(&P->ca);
     cols_prologue<KB>(ca, item, lds);
-    if constexpr (PREC == 0) cols_item<BC, KB, KIND_UPDATE, JOINT, kKeepPQ<KB, PREC, JOINT>>(ca, item, lds);
+    if constexpr (PREC == 0) cols_item<BC, KB, KIND_UPDATE, JOINT, kKeepPQ<BC, KB, PREC, JOINT>>(ca, item, lds);
     else if constexpr (PREC == 1) {
       if constexpr (JOINT) cols_item_lp_pq<BC, KB, __bf16>(ca, item, lds);
       else cols_item_lp<BC, KB, false, __bf16>(ca, item, lds);

@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(BatchPlanArgs 
     if (sp.key < 0) {
       atomicOr(&bad, 1);
     } else {
-      const Plan p = make_batch_plan(q.F, q.N, q.K, a.tiles[bucket_of(q.F, q.N, q.K, q.beta)], a.joint != 0,
+      const Plan p = make_batch_plan(q.F, q.N, q.K, q.beta, a.tiles[bucket_of(q.F, q.N, q.K, q.beta)], a.joint != 0,
                                    a.opts.precision);
       bytes = (int64_t)align_up(p.total);
       int units[4], per_item[4], it[4];
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(BatchPlanArgs 
   for (int r = tid; r < P; r += kPlanThreads) {
     const int i = a.s_order[r];
     const nmf_problem q = a.problems[i];
-    const Plan p = make_batch_plan(q.F, q.N, q.K, a.tiles[bucket_of(q.F, q.N, q.K, q.beta)], a.joint != 0,
+    const Plan p = make_batch_plan(q.F, q.N, q.K, q.beta, a.tiles[bucket_of(q.F, q.N, q.K, q.beta)], a.joint != 0,
                                    a.opts.precision);
     const BatchProblem d = make_batch_problem(p, a.work + a.s_bytes[i], a.flags, q, a.joint != 0, a.opts);
     a.desc[i] = d;

@@ -114,15 +114,17 @@ NMF_PLAN_HD inline Plan finish_plan(Plan p, int64_t F, int64_t N, bool inner = f
 // `tiles` column (row) tiles; one W-update unit of rows and one H-update unit
 // of columns per work item.
 // Joint MM in a batch keeps the W pass's element terms P, Q for its H pass,
-// except with float32 products at K <= 32: there the H pass forms Lambda~ again
-// from W~^T and H~ (2FNK flops against 8FN bytes of P, Q written and read back).
-NMF_PLAN_HD inline bool batch_keeps_pq(bool joint, int prec, int64_t K) {
-  return joint && (prec != NMF_FP32 || kblocks_for(K) > 1);
+// except with float32 products at K <= 32 or beta = 1: there the H pass forms
+// Lambda~ again from W~^T and H~ (2FNK flops against 8FN bytes of P, Q, 4FN at
+// beta = 1, written and read back).
+NMF_PLAN_HD inline bool batch_keeps_pq(bool joint, int prec, int64_t K, double beta) {
+  return joint && (prec != NMF_FP32 || (kblocks_for(K) > 1 && beta_class(beta) != BC_B1));
 }
 
-NMF_PLAN_HD inline Plan make_batch_plan(int64_t F, int64_t N, int64_t K, int tiles, bool joint, int prec) {
+NMF_PLAN_HD inline Plan make_batch_plan(int64_t F, int64_t N, int64_t K, double beta, int tiles, bool joint,
+                                        int prec) {
   Plan p{};
-  p.pq = batch_keeps_pq(joint, prec, K);
+  p.pq = batch_keeps_pq(joint, prec, K, beta);
   p.KB = kblocks_for(K);
   p.KP = 32 * p.KB;
   const int64_t tn = cdiv(N, kTile), tf = cdiv(F, kTile);
