@@ -30,11 +30,11 @@ static_assert(rows_item_lds<2>() <= kBatchLdsBytes, "batched LDS");
 static_assert(2 * kBlock * 8 <= kBatchLdsBytes, "batched LDS");
 static_assert(kBatchWRows * (64 + 1) * 4 <= kBatchLdsBytes, "batched LDS");
 
-// Joint MM keeps P, Q between its passes except with float32 products at
-// K <= 32 (one K block) or beta = 1, where its H pass forms Lambda~ again from
-// W~^T; the same rule as batch_keeps_pq, fixed per instantiation.
+// Joint MM keeps P, Q between its passes except at K <= 32 (one K block), and
+// with float32 products at beta = 1 too, where its H pass forms Lambda~ again
+// from a copy of W~; the same rule as batch_keeps_pq, fixed per instantiation.
 template <int BC, int KB, int PREC, bool JOINT>
-constexpr bool kKeepPQ = JOINT && (PREC != 0 || (KB > 1 && BC != BC_B1));
+constexpr bool kKeepPQ = JOINT && KB > 1 && (PREC != 0 || BC != BC_B1);
 
 // Descriptors never change during the launch: reading them through the
 // constant address space lets the compiler keep their fields in scalar
@@ -71,7 +71,7 @@ __device__ __noinline__ void batch_wpass_fused(ConstProblemPtr P, int item, floa
   constexpr bool KEEP = kKeepPQ<BC, KB, PREC, JOINT>;
   if constexpr (PREC == 0)
     rows_item<BC, KB, KIND_UPDATE, OBJ, KEEP, true, JOINT && !KEEP>(ra, item, lds, objsum, &P->ua);
-  else rows_item_lp<BC, KB, OBJ, __bf16, JOINT, true>(ra, item, lds, objsum, &P->ua);
+  else rows_item_lp<BC, KB, OBJ, __bf16, KEEP, true, JOINT && !KEEP>(ra, item, lds, objsum, &P->ua);
 }
 
 // H-pass item of a problem whose W-pass items applied the W update and
@@ -87,8 +87,8 @@ __device__ __noinline__ void batch_hpass_fused(ConstProblemPtr P, int prob, int 
     const SweepColsArgs ca = load_const(&P->ca);
     constexpr bool KEEP = kKeepPQ<BC, KB, PREC, JOINT>;
     if constexpr (PREC == 0) cols_item<BC, KB, KIND_UPDATE, JOINT, KEEP, true>(ca, item, lds, &P->ha, norm_s, csum_s);
-    else if constexpr (JOINT) cols_item_lp_pq<BC, KB, __bf16, true>(ca, item, lds, &P->ha, norm_s, csum_s);
-    else cols_item_lp<BC, KB, false, __bf16, true>(ca, item, lds, &P->ha, norm_s, csum_s);
+    else if constexpr (KEEP) cols_item_lp_pq<BC, KB, __bf16, true>(ca, item, lds, &P->ha, norm_s, csum_s);
+    else cols_item_lp<BC, KB, JOINT, __bf16, true>(ca, item, lds, &P->ha, norm_s, csum_s);
   }
   const UpdateHArgs ha = load_const(&P->ha);
   const int items = P->items[PH_HPASS];
@@ -111,7 +111,7 @@ __device__ __noinline__ void batch_item(ConstProblemPtr P, int prob, int phase, 
     const SweepRowsArgs ra = load_const(&P->ra);
     double objsum = 0.0;
     if constexpr (PREC == 0) rows_item<BC, KB, KIND_UPDATE, OBJ, kKeepPQ<BC, KB, PREC, JOINT>>(ra, item, lds, objsum);
-    else if constexpr (PREC == 1) rows_item_lp<BC, KB, OBJ, __bf16, JOINT>(ra, item, lds, objsum);
+    else if constexpr (PREC == 1) rows_item_lp<BC, KB, OBJ, __bf16, kKeepPQ<BC, KB, PREC, JOINT>>(ra, item, lds, objsum);
     else rows_item_lp<BC, KB, OBJ, _Float16, JOINT>(ra, item, lds, objsum);
     if (OBJ) {
       const double sum = block_sum(objsum, red);
@@ -128,8 +128,8 @@ __device__ __noinline__ void batch_item(ConstProblemPtr P, int prob, int phase, 
     cols_prologue<KB>(ca, item, lds);
     if constexpr (PREC == 0) cols_item<BC, KB, KIND_UPDATE, JOINT, kKeepPQ<BC, KB, PREC, JOINT>>(ca, item, lds);
     else if constexpr (PREC == 1) {
-      if constexpr (JOINT) cols_item_lp_pq<BC, KB, __bf16>(ca, item, lds);
-      else cols_item_lp<BC, KB, false, __bf16>(ca, item, lds);
+      if constexpr (kKeepPQ<BC, KB, PREC, JOINT>) cols_item_lp_pq<BC, KB, __bf16>(ca, item, lds);
+      else cols_item_lp<BC, KB, JOINT, __bf16>(ca, item, lds);
     } else {
       if constexpr (JOINT) cols_item_lp_pq<BC, KB, _Float16>(ca, item, lds);
       else cols_item_lp<BC, KB, false, _Float16>(ca, item, lds);

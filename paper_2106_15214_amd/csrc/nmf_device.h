@@ -352,7 +352,7 @@ __device__ __forceinline__ KlQueue kl_queue_of(float* lds, int wave) {
 // to u->pcol[rb][2][KP].  Every thread of the workgroup calls it, after the
 // item's last barrier.
 // ---------------------------------------------------------------------------
-template <int KB, bool ROWSUM, bool WT_TILDE, class UPtr>
+template <int KB, bool ROWSUM, bool WT_TILDE, bool C0_TILDE, class UPtr>
 __device__ __forceinline__ void finish_w_rows(const SweepRowsArgs& a, UPtr u, const f32x16 (&accN)[KB],
                                               const f32x16 (&accD)[KB], const float (&rsum)[KB], float* lds,
                                               int rb, int f0, bool wave_on) {
@@ -412,6 +412,7 @@ __device__ __forceinline__ void finish_w_rows(const SweepRowsArgs& a, UPtr u, co
           const int64_t o = (int64_t)f * KP + k;
           u->Wn[o] = w1;
           if (u->joint) { u->C1[o] = c1; u->C2[o] = c2; }
+          if (C0_TILDE) u->C0[o] = wt[r];
         }
         csq[kb] += (double)w1 * (double)w1;
         csm[kb] += (double)w1;
@@ -765,7 +766,7 @@ __device__ __forceinline__ void rows_item(const SweepRowsArgs& a, int item, floa
 
   if (OBJ && BC == BC_B1 && wave_on) klq.drain(objsum);
   if constexpr (FINISH) {
-    finish_w_rows<KB, ROWSUM, WT_TILDE>(a, u, accN, accD, rsum, lds, rb, f0, wave_on);
+    finish_w_rows<KB, ROWSUM, WT_TILDE, false>(a, u, accN, accD, rsum, lds, rb, f0, wave_on);
     return;
   }
   if (CONTRACT && wave_on) {
@@ -1028,8 +1029,9 @@ __device__ __forceinline__ void split_low(const float (&x)[8], typename LowP<T>:
 
 // rows item with low-precision products (update kind).  The H~ tile is staged
 // in LDS in float32 as in rows_item; operands are converted when read.  FINISH
-// and `u` as in rows_item.
-template <int BC, int KB, bool OBJ, class T, bool STORE_PQ = false, bool FINISH = false,
+// and `u` as in rows_item; C0_TILDE: the W update also writes the row-major
+// copy of W~ (u->C0) that forms Lambda~ again in a low-precision joint H pass.
+template <int BC, int KB, bool OBJ, class T, bool STORE_PQ = false, bool FINISH = false, bool C0_TILDE = false,
           class UPtr = const UpdateWArgs*>
 __device__ __forceinline__ void rows_item_lp(const SweepRowsArgs& a, int item, float* lds, double& objsum,
                                              UPtr u = nullptr) {
@@ -1243,7 +1245,7 @@ __device__ __forceinline__ void rows_item_lp(const SweepRowsArgs& a, int item, f
   if (OBJ && BC == BC_B1 && wave_on) klq.drain(objsum);
   if (!rok) set_flag(a.flags, 8u);  // operand outside the float16 range
   if constexpr (FINISH) {
-    finish_w_rows<KB, ROWSUM, false>(a, u, accN, accD, rsum, lds, rb, f0, wave_on);
+    finish_w_rows<KB, ROWSUM, false, C0_TILDE>(a, u, accN, accD, rsum, lds, rb, f0, wave_on);
     return;
   }
   if (wave_on) {

@@ -114,11 +114,11 @@ NMF_PLAN_HD inline Plan finish_plan(Plan p, int64_t F, int64_t N, bool inner = f
 // `tiles` column (row) tiles; one W-update unit of rows and one H-update unit
 // of columns per work item.
 // Joint MM in a batch keeps the W pass's element terms P, Q for its H pass,
-// except with float32 products at K <= 32 or beta = 1: there the H pass forms
-// Lambda~ again from W~^T and H~ (2FNK flops against 8FN bytes of P, Q, 4FN at
-// beta = 1, written and read back).
+// except at K <= 32, and with float32 products at beta = 1 too: there the H
+// pass forms Lambda~ again from a copy of W~ and H~ (2FNK flops against P, Q
+// written and read back, 8FN bytes in float32, 4FN in bfloat16 or at beta = 1).
 NMF_PLAN_HD inline bool batch_keeps_pq(bool joint, int prec, int64_t K, double beta) {
-  return joint && (prec != NMF_FP32 || (kblocks_for(K) > 1 && beta_class(beta) != BC_B1));
+  return joint && kblocks_for(K) > 1 && (prec != NMF_FP32 || beta_class(beta) != BC_B1);
 }
 
 NMF_PLAN_HD inline Plan make_batch_plan(int64_t F, int64_t N, int64_t K, double beta, int tiles, bool joint,
