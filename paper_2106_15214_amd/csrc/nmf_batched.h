@@ -53,11 +53,6 @@ __device__ __forceinline__ T load_const(const __attribute__((address_space(4))) 
   return r;
 }
 
-// One work item.  Not inlined: each (beta class, K block, phase) path is its
-// own function with its own register allocation, so the persistent kernel's
-// budget is the largest single path and not the union of all of them inlined
-// into one body (which spilled heavily); this is what lets two workgroups share
-// a compute unit.
 // W-pass item of a problem whose rows take one column group: the item applies
 // the W update from its accumulators; its objective terms are added to
 // the caller's objsum.  A function of its own, so that its registers are
@@ -104,6 +99,11 @@ __device__ __noinline__ void batch_hpass_fused(ConstProblemPtr P, int prob, int 
   }
 }
 
+// One work item.  Not inlined: each (beta class, K block, phase) path is its
+// own function with its own register allocation, so the persistent kernel's
+// budget is the largest single path and not the union of all of them inlined
+// into one body (which spilled heavily); this is what lets two workgroups share
+// a compute unit.
 template <int BC, int KB, int PREC, bool JOINT, bool OBJ>
 __device__ __noinline__ void batch_item(ConstProblemPtr P, int prob, int phase, int item, const BatchArgs& b,
                                            float* lds, double* red, float* norm_s, float* csum_s) {
