@@ -683,7 +683,7 @@ void nmf_default_opts(nmf_step_opts* o) {
   o->gram = 0;
 }
 
-const char* nmf_version(void) { return "nmfbeta 0.1 (gfx950)"; }
+const char* nmf_version(void) { return "nmfbeta 0.2 (gfx950)"; }
 
 const char* nmf_status_string(nmf_status s) {
   // a C caller may pass any int: read it as one (an out-of-range enumerator
