@@ -114,12 +114,17 @@ def test_batched_several_steps_match_single_problem_steps(mode):
         check_pair(Wb.cpu().numpy(), Hb.cpu().numpy(), Wr, Hr, tag=f"6 steps problem {i}", fro=6e-5, el=6e-4)
 
 
+# tiles as in test_batched_step_matches_oracle: folded updates, all four
+# phases, and a mix (with bfloat16 products joint problems at K <= 32 form
+# Lambda~ again from a row-major copy of W~, the others keep P, Q)
 @pytest.mark.parametrize("mode", ["joint", "alternating"])
-def test_batched_bf16_matches_oracle(mode):
+@pytest.mark.parametrize("tiles", [0, 1, 12])
+def test_batched_bf16_matches_oracle(mode, tiles):
     specs = [s for s in SPECS]
     probs = make_set(specs, seed0=500)
     d = to_dev(probs)
-    b = nb.Batch(d, mode, precision="bf16", ctx=ctx())
+    print(f"[batched bf16] mode={mode} tiles={tiles} problems={len(d)}", flush=True)
+    b = nb.Batch(d, mode, precision="bf16", tiles_per_item=tiles, ctx=ctx())
     b.step()
     torch.cuda.synchronize()
     assert b.flags(clear=True) == 0

@@ -269,28 +269,35 @@ def test_host_side_status_codes():
     ctx.close()
 
 
-def test_tile_table_changes_plans_not_results():
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_tile_table_changes_plans_not_results(precision):
     """A table with other tiles per item splits the contractions differently:
     the device-planned step then equals the host batch built with that table
     and stays within the oracle gates."""
     probs = make_set([(1100, 2100, 40, 1.0), (700, 4500, 12, 0.5), (300, 97, 33, 0.0)], seed0=2800)
     a, b = to_dev(probs), to_dev(probs)
+    print(f"[device batch] custom table {precision}", flush=True)
     ctx = nb.Context(0)
     tiles = [(4, 8, 16, 32, 64, 128)[b % 6] for b in range(nb.BATCH_BUCKETS)]
     nb.set_batch_tiles(tiles, ctx=ctx)
     assert nb.get_batch_tiles(ctx) == tiles
-    reserve_for(ctx, shapes_of(probs), "joint")
+    reserve_for(ctx, shapes_of(probs), "joint", precision=precision)
     dp = nb.DeviceProblems(len(a))
     dp.set(a)
-    nb.step_batched(dp, "joint", ctx=ctx)
-    host = nb.Batch(b, "joint", ctx=ctx)  # tiles_per_item 0: the context's table
+    nb.step_batched(dp, "joint", precision=precision, ctx=ctx)
+    host = nb.Batch(b, "joint", precision=precision, ctx=ctx)  # tiles_per_item 0: the context's table
     host.step()
     torch.cuda.synchronize()
+    assert nb.get_flags(clear=True, ctx=ctx) == 0 and host.flags() == 0
     assert_same(a, b, "custom table")
     host.close()
     for (V, W, H, beta), (_, Wd, Hd, _) in zip(probs, a):
         Wr, Hr = O.jmm_iteration(V.astype(np.float64), W.astype(np.float64), H.astype(np.float64), beta)
-        check_pair(Wd.cpu().numpy(), Hd.cpu().numpy(), Wr, Hr, tag=f"custom table, beta={beta}")
+        check_pair(Wd.cpu().numpy(), Hd.cpu().numpy(), Wr, Hr, precision, beta,
+                   tag=f"custom table {precision}, beta={beta}")
+    if precision == "bf16":
+        ctx.close()
+        return
     with pytest.raises(nb.NmfError):
         nb.set_batch_tiles([0] * nb.BATCH_BUCKETS, ctx=ctx)
     with pytest.raises(ValueError):
