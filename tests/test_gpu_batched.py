@@ -114,6 +114,20 @@ def test_batched_several_steps_match_single_problem_steps(mode):
         check_pair(Wb.cpu().numpy(), Hb.cpu().numpy(), Wr, Hr, tag=f"6 steps problem {i}", fro=6e-5, el=6e-4)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("mode", ["joint", "alternating"])
+@pytest.mark.parametrize("tiles", [0, 1, 12])
+def test_batch_items_match_requirements(precision, mode, tiles):
+    """The host's requirements count exactly the work items a batch lists."""
+    probs = to_dev(make_set(SPECS, seed0=550))
+    shapes = [(V.shape[0], V.shape[1], W.shape[1], beta) for V, W, H, beta in probs]
+    c = ctx()
+    b = nb.Batch(probs, mode, precision=precision, tiles_per_item=tiles, ctx=c)
+    table = [tiles] * nb.BATCH_BUCKETS if tiles else nb.get_batch_tiles(c)
+    assert b.info()["work_items"] == nb.batch_requirements(shapes, mode, table, precision)[0]
+    b.close()
+
+
 # tiles as in test_batched_step_matches_oracle: folded updates, all four
 # phases, and a mix (with bfloat16 products joint problems at K <= 32 form
 # Lambda~ again from a row-major copy of W~, the others keep P, Q)
