@@ -92,6 +92,7 @@ __device__ Spans spans_of(const nmf_problem& q) {
 
 __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(BatchPlanArgs a) {
   __shared__ Spans stage[kStage];
+  __shared__ int rpart[kPlanThreads];
   __shared__ int64_t seg[kPlanWaves];
   __shared__ int64_t tot_bytes, tot_items[4];
   __shared__ int bad;
@@ -129,10 +130,16 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(BatchPlanArgs 
   }
 
   // rank by size (larger first, ties by index) and cross-problem overlaps, with
-  // the other problems' spans staged through LDS kStage at a time
-  for (int ib = 0; ib < P; ib += kPlanThreads) {
-    const int i = ib + tid;
-    const Spans me = i < P ? spans_of(a.problems[i]) : Spans{-1, 0, 0, 0, 0, 0, 0};
+  // the other problems' spans staged through LDS kStage at a time.  With at
+  // most kPlanThreads / 2 problems two threads share a problem, each checking
+  // every other staged descriptor; their rank counts are added through LDS.
+  const int split = P <= kPlanThreads / 2 ? 2 : 1;
+  const int span = kPlanThreads / split;  // problems per round
+  const int part = tid / span, lt = tid % span;
+  for (int ib = 0; ib < P; ib += span) {
+    const int i = ib + lt;
+    const bool act = i < P;
+    const Spans me = act ? spans_of(a.problems[i]) : Spans{-1, 0, 0, 0, 0, 0, 0};
     int r = 0;
     bool ov = false;
     for (int jb = 0; jb < P; jb += kStage) {
@@ -143,20 +150,26 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(BatchPlanArgs 
       }
       __syncthreads();
       const int nj = min(kStage, P - jb);
-      for (int t = 0; t < nj; ++t) {
-        const Spans& o = stage[t];
-        const int j2 = jb + t;
-        r += (o.key > me.key) || (o.key == me.key && j2 < i);
-        if (j2 != i)
-          ov |= overlap(me.wlo, me.whi, o.wlo, o.whi) || overlap(me.wlo, me.whi, o.hlo, o.hhi) ||
-                overlap(me.hlo, me.hhi, o.hlo, o.hhi) || overlap(me.vlo, me.vhi, o.wlo, o.whi) ||
-                overlap(me.vlo, me.vhi, o.hlo, o.hhi);
-      }
+      if (act)
+        for (int t = part; t < nj; t += split) {
+          const Spans& o = stage[t];
+          const int j2 = jb + t;
+          r += (o.key > me.key) || (o.key == me.key && j2 < i);
+          if (j2 != i)
+            ov |= overlap(me.wlo, me.whi, o.wlo, o.whi) || overlap(me.wlo, me.whi, o.hlo, o.hhi) ||
+                  overlap(me.hlo, me.hhi, o.hlo, o.hhi) || overlap(me.vlo, me.vhi, o.wlo, o.whi) ||
+                  overlap(me.vlo, me.vhi, o.hlo, o.hhi);
+        }
     }
-    if (i < P) {
-      a.s_order[r] = i;
-      if (ov) atomicOr(&bad, 1);
+    __syncthreads();
+    rpart[tid] = r;
+    __syncthreads();
+    if (act && part == 0) {
+      int rr = 0;
+      for (int q = 0; q < split; ++q) rr += rpart[q * span + lt];
+      a.s_order[rr] = i;
     }
+    if (act && ov) atomicOr(&bad, 1);
   }
   __syncthreads();
 
