@@ -30,11 +30,11 @@ static_assert(rows_item_lds<2>() <= kBatchLdsBytes, "batched LDS");
 static_assert(2 * kBlock * 8 <= kBatchLdsBytes, "batched LDS");
 static_assert(kBatchWRows * (64 + 1) * 4 <= kBatchLdsBytes, "batched LDS");
 
-// Joint MM keeps P, Q between its passes except at K <= 32 (one K block), and
-// with float32 products at beta = 1 too, where its H pass forms Lambda~ again
-// from a copy of W~; the same rule as batch_keeps_pq, fixed per instantiation.
+// Joint MM keeps P, Q between its passes only at K > 32 (two K blocks) and
+// beta != 1; elsewhere its H pass forms Lambda~ again from a copy of W~.  The
+// same rule as batch_keeps_pq, fixed per instantiation.
 template <int BC, int KB, int PREC, bool JOINT>
-constexpr bool kKeepPQ = JOINT && KB > 1 && (PREC != 0 || BC != BC_B1);
+constexpr bool kKeepPQ = JOINT && KB > 1 && BC != BC_B1;
 
 // Descriptors never change during the launch: reading them through the
 // constant address space lets the compiler keep their fields in scalar

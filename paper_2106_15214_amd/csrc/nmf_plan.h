@@ -113,12 +113,13 @@ NMF_PLAN_HD inline Plan finish_plan(Plan p, int64_t F, int64_t N, bool inner = f
 // Splits of a problem inside a batch: every row (column) group covers about
 // `tiles` column (row) tiles; one W-update unit of rows and one H-update unit
 // of columns per work item.
-// Joint MM in a batch keeps the W pass's element terms P, Q for its H pass,
-// except at K <= 32, and with float32 products at beta = 1 too: there the H
-// pass forms Lambda~ again from a copy of W~ and H~ (2FNK flops against P, Q
-// written and read back, 8FN bytes in float32, 4FN in bfloat16 or at beta = 1).
+// Joint MM in a batch keeps the W pass's element terms P, Q for its H pass
+// only at K > 32 and beta != 1: elsewhere the H pass forms Lambda~ again from a
+// copy of W~ and H~ (2FNK flops against P, Q written and read back: 8FN bytes
+// in float32, 4FN in bfloat16 or at beta = 1, where only P is kept).
 NMF_PLAN_HD inline bool batch_keeps_pq(bool joint, int prec, int64_t K, double beta) {
-  return joint && kblocks_for(K) > 1 && (prec != NMF_FP32 || beta_class(beta) != BC_B1);
+  (void)prec;
+  return joint && kblocks_for(K) > 1 && beta_class(beta) != BC_B1;
 }
 
 NMF_PLAN_HD inline Plan make_batch_plan(int64_t F, int64_t N, int64_t K, double beta, int tiles, bool joint,
