@@ -129,8 +129,8 @@ def test_batch_items_match_requirements(precision, mode, tiles):
 
 
 # tiles as in test_batched_step_matches_oracle: folded updates, all four
-# phases, and a mix (with bfloat16 products joint problems at K <= 32 form
-# Lambda~ again from a row-major copy of W~, the others keep P, Q)
+# phases, and a mix (joint problems at K <= 32 or beta = 1 form Lambda~ again
+# from a row-major copy of W~, the others keep P, Q)
 @pytest.mark.parametrize("mode", ["joint", "alternating"])
 @pytest.mark.parametrize("tiles", [0, 1, 12])
 def test_batched_bf16_matches_oracle(mode, tiles):
